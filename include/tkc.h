@@ -1,0 +1,186 @@
+/*
+ * tkc.h -- exact top-k closeness centrality on one AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Bergamini, Borassi, Crescenzi, Marino, Meyerhenke, "Computing
+ * top-k Closeness Centrality Faster in Unweighted Graphs", Sect. 2 and the
+ * input/output of Alg. 1): given an unweighted graph G = (V, E), directed or
+ * undirected, return the k vertices of highest closeness.  For a vertex v
+ * with reachable set R(v) (v included) and r(v) = |R(v)|,
+ *     S(v) = sum_{w in R(v)} d(v, w),
+ *     f(v) = (n-1) S(v) / (r(v)-1)^2          (farness, Eq. 1; Lin's index)
+ * and closeness c(v) = 1/f(v); a vertex that reaches nothing (r = 1) has
+ * closeness 0 (f = +inf).  Results follow the exact order
+ *     v before w  iff  f(v) < f(w), or f(v) = f(w) and v < w,
+ * (exact rational comparison; the smaller id wins a tie) and exactly
+ * min(k, n) vertices are returned.
+ *
+ * The library runs the paper's pruned search (Alg. 1) on the GPU: lower
+ * bounds on farness from degree order (Deg) or walk counts (NB, Sect. 5),
+ * breadth-first searches cut as soon as a bound proves the vertex cannot
+ * enter the top k (BFSCut, Sect. 6) or complete searches that raise the
+ * bounds of other vertices (LB, Sect. 7), and the directed, disconnected
+ * machinery of Sect. 8 (alpha/omega reachability bounds, Alg. 6).
+ *
+ * Conventions for every entry point:
+ *   - Return value: TKC_OK (0) or a negative TKC_E* code; nothing throws.
+ *     tkc_last_error() gives a message for the calling thread's last error.
+ *   - Vertex ids are int32 in [0, n); the CSR arrays are int32, so the arc
+ *     count must stay below 2^31.
+ *   - Input arrays are only read during the call; the library copies what it
+ *     keeps.  Output arrays are caller-owned with room for min(k, n) items.
+ *   - A context owns one HIP stream (the caller's, or its own) and its
+ *     device workspace; calls on one context must not overlap (one thread at
+ *     a time); separate contexts may be used from separate threads.
+ */
+#ifndef TKC_H
+#define TKC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define TKC_OK 0
+#define TKC_EINVAL (-1)     /* bad argument or malformed graph            */
+#define TKC_ENOMEM (-2)     /* device or host allocation failed           */
+#define TKC_EDEVICE (-3)    /* a HIP call failed                          */
+#define TKC_ENOTSUP (-4)    /* option not supported for this input        */
+#define TKC_EBUSY (-5)      /* object in use / admission refused          */
+#define TKC_ECANCELED (-6)  /* request cancelled                          */
+
+/* lower-bound strategy (Sect. 9: the four variants; Sect. 4: computeBounds /
+ * updateBounds).  AUTO picks a Cut variant for low-diameter graphs and a
+ * Bound variant for high-diameter ones, following the paper's finding that
+ * BFSCut wins on complex networks and LB on street networks (Sect. 9.1). */
+#define TKC_AUTO 0
+#define TKC_DEG_CUT 1       /* degree order + BFSCut                      */
+#define TKC_NB_CUT 2        /* neighbourhood bound + BFSCut               */
+#define TKC_DEG_BOUND 3     /* degree order + level-based updates         */
+#define TKC_NB_BOUND 4      /* neighbourhood bound + level-based updates  */
+
+/* execution mode of the searches */
+#define TKC_PLAIN 0         /* one source at a time, whole GPU per search */
+#define TKC_BATCHED 1       /* W sources per launch, one bit lane each    */
+#define TKC_HYBRID 2        /* batched seed, then one search per workgroup
+                               for short cut searches, batched tail        */
+
+/* graph flags */
+#define TKC_DIRECTED 1u     /* arcs are directed; reverse CSR required    */
+#define TKC_VALIDATE 2u     /* check CSR shape, ids, loops, repeats, symmetry */
+#define TKC_DEVICE_PTRS 4u  /* input arrays are device pointers           */
+
+typedef struct tkc_ctx tkc_ctx;
+typedef struct tkc_graph tkc_graph;
+typedef struct tkc_server tkc_server;
+
+/* per-call statistics; every field is filled on success */
+typedef struct {
+    int64_t m_vis;          /* arcs scanned by searches: sum over searched
+                               levels of the out-degrees of the level's
+                               vertices (the paper's work count, Sect. 9.1) */
+    int64_t bfs_started;    /* searches started                            */
+    int64_t bfs_exact;      /* searches that ran to completion             */
+    int64_t bfs_cut;        /* searches stopped by the BFSCut bound        */
+    int64_t skipped;        /* vertices skipped by their bound             */
+    int64_t deferred;       /* per-workgroup searches handed to batches    */
+    int32_t max_level;      /* deepest level reached                       */
+    int32_t batch_width;    /* lanes per batch (W)                         */
+    int32_t variant_used;
+    int32_t mode_used;
+    int32_t nb_rounds;      /* walk-count rounds of the NB bound           */
+    int32_t pad_;
+    double ms_reach;        /* reachability (r or alpha/omega)             */
+    double ms_bounds;       /* initial bounds and ordering                 */
+    double ms_traverse;     /* searches (all engines)                      */
+    double ms_total;        /* whole call, host clock                      */
+    double ms_kernel_main;  /* HIP-event time of the dominant traversal
+                               kernel launches (see main_kernel)            */
+    int32_t main_launches;  /* number of such launches                     */
+    int32_t main_kernel;    /* 0 plain, 1 batched, 2 per-workgroup         */
+    int64_t bytes_main;     /* algorithmic bytes of those launches         */
+} tkc_stats;
+
+/* Context on HIP device `device`; hip_stream may be NULL (library stream) or
+ * a hipStream_t the caller keeps alive.  Error: TKC_EDEVICE. */
+int tkc_ctx_create(int device, void *hip_stream, tkc_ctx **out);
+int tkc_ctx_destroy(tkc_ctx *ctx);
+
+/* Tuning knobs (0 keeps the current value).  batch_width in {32, 64, 128,
+ * 256}; td_bu_alpha / bu_td_beta are the push->pull and pull->push switch
+ * thresholds (Beamer's alpha and beta); swarm_qcap is the queue capacity of
+ * one per-workgroup search before it is handed to the batched engine. */
+int tkc_ctx_set_tuning(tkc_ctx *ctx, int32_t batch_width, int32_t td_bu_alpha,
+                       int32_t bu_td_beta, int32_t swarm_qcap, int32_t block_size);
+
+/* Copy a graph to device memory.  row_ptr[n+1], col_idx[m_arcs] give the
+ * out-arcs; rrow_ptr/rcol_idx give the in-arcs and are required iff
+ * TKC_DIRECTED (NULL otherwise).  Undirected graphs hold each edge in both
+ * rows.  The graph must be simple (no self-loops, no repeated arcs, rows
+ * need not be sorted); TKC_VALIDATE checks it (and symmetry / that the
+ * reverse CSR is the transpose) and returns TKC_EINVAL with a message.
+ * n >= 1.  Errors: TKC_EINVAL, TKC_ENOMEM, TKC_EDEVICE. */
+int tkc_graph_upload(tkc_ctx *ctx, int32_t n, int64_t m_arcs,
+                     const int32_t *row_ptr, const int32_t *col_idx,
+                     const int32_t *rrow_ptr, const int32_t *rcol_idx,
+                     uint32_t flags, tkc_graph **out);
+/* TKC_EBUSY while a server still holds the graph. */
+int tkc_graph_free(tkc_graph *g);
+
+/* Top-k closeness (Alg. 1).  k >= 1 (TKC_EINVAL otherwise); *n_out =
+ * min(k, n) results written in the exact order: ids, S (sum_dist), r
+ * (reach) and f (farness, computed as ((double)(n-1)*(double)S) /
+ * ((double)(r-1)*(double)(r-1)), +inf when r = 1).  Any output pointer
+ * except ids and n_out may be NULL.  stats may be NULL. */
+int tkc_topk_closeness(tkc_graph *g, int32_t k, int32_t variant, int32_t mode,
+                       int32_t *ids, int64_t *sum_dist, int64_t *reach, double *farness,
+                       int32_t *n_out, tkc_stats *stats);
+
+/* ---- inspection of the individual steps (host output arrays of n items) */
+/* Reachability (Sect. 4 and Sect. 8.4, Alg. 6): undirected graphs get
+ * alpha = omega = r (component size); directed graphs get the alpha/omega
+ * bounds of Alg. 6 (exact r for vertices whose bounds coincide); scc may be
+ * NULL and is filled (component ids in topological order) for directed
+ * graphs only. */
+int tkc_graph_reach(tkc_graph *g, int64_t *alpha, int64_t *omega, int32_t *scc);
+/* Initial lower bounds (Sect. 4 computeBounds): the farness bound is
+ * (n-1) * num / den, den = 0 meaning +inf.  variant TKC_DEG_* gives 0 (and
+ * +inf when r = 1), TKC_NB_* the neighbourhood bound of Sect. 5 / 8.1.
+ * order (may be NULL) receives the processing order. */
+int tkc_graph_bounds(tkc_graph *g, int32_t variant, int64_t *num, int64_t *den, int32_t *order);
+/* Level-based bound (Sect. 7): apply the LB update of complete searches
+ * from sources[0..count) to the bounds (num, den) in place (host arrays of
+ * n; den = 0 is +inf and is never lowered). */
+int tkc_graph_lb_update(tkc_graph *g, const int32_t *sources, int32_t count,
+                        int64_t *num, int64_t *den);
+/* Exact (S, r) of the given sources by full searches on the device
+ * (batched engine, no cut). */
+int tkc_graph_sums(tkc_graph *g, const int32_t *sources, int32_t count,
+                   int64_t *sum_dist, int64_t *reach);
+
+/* ---- serving: graphs stay resident, requests are batched as they arrive */
+/* hbm_budget_bytes caps the device memory the server's request slots may
+ * use (admission control); max_inflight caps concurrent requests. */
+int tkc_server_create(tkc_ctx *ctx, size_t hbm_budget_bytes, int32_t max_inflight,
+                      tkc_server **out);
+int tkc_server_add_graph(tkc_server *s, tkc_graph *g, int32_t *graph_id);
+/* Queue a request; TKC_EBUSY if it can never fit the budget. */
+int tkc_server_submit(tkc_server *s, int32_t graph_id, int32_t k, int32_t variant,
+                      uint64_t *ticket);
+int tkc_server_poll(tkc_server *s, uint64_t ticket, int32_t *done);
+/* Blocks until the request finished; results as for tkc_topk_closeness.
+ * latency_ms = completion - submission. */
+int tkc_server_result(tkc_server *s, uint64_t ticket, int32_t *ids, int64_t *sum_dist,
+                      int64_t *reach, double *farness, int32_t *n_out, double *latency_ms);
+int tkc_server_cancel(tkc_server *s, uint64_t ticket);
+int tkc_server_destroy(tkc_server *s);
+
+const char *tkc_last_error(void);
+const char *tkc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TKC_H */

@@ -1,0 +1,836 @@
+// C ABI of the top-k closeness library and the host driver of Alg. 1.
+//
+// A query runs these steps on the context's stream:
+//   1. reachability: r(v) by connected components on the device
+//      (undirected), or the alpha/omega bounds of Alg. 6 on the host
+//      (directed) -- Sect. 4 and Sect. 8.4;
+//   2. initial bounds (computeBounds): Deg (L = 0, order by degree) or NB
+//      (walk-count bound of Sect. 5 / 8.1, order by the bound);
+//   3. processing order: one stable radix sort of the order keys;
+//   4. searches (updateBounds): plain, batched or hybrid engine, BFSCut or
+//      level-based updates;
+//   5. readback of the k results (ids, S, r) and the farness doubles.
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/tkc.h"
+#include "dev_common.hpp"
+#include "engine.hpp"
+#include "internal.hpp"
+#include "reach_host.hpp"
+
+static thread_local std::string g_err;
+
+int tkc_fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return tkc_fail(TKC_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+static double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------------ arena
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct WsItem {
+    void** p;
+    size_t bytes;
+    bool zero;
+};
+// layout of every buffer a query may use
+static size_t ws_items(Workspace& ws, const WsShape& sh, std::vector<WsItem>& items) {
+    size_t n = (size_t)sh.n, nw = (size_t)sh.nw, W = (size_t)sh.W;
+    size_t words = (n + 31) / 32;
+    size_t lcap = (size_t)sh.lcap;
+    items = {
+        {(void**)&ws.alpha, 8 * n, false}, {(void**)&ws.omega, 8 * n, false},
+        {(void**)&ws.scc, 4 * n, false}, {(void**)&ws.lnum, 8 * n, false},
+        {(void**)&ws.lden, 8 * n, false}, {(void**)&ws.key, 4 * n, false},
+        {(void**)&ws.ord, 4 * n, false}, {(void**)&ws.tkey, 4 * n, false},
+        {(void**)&ws.tval, 4 * n, false},
+        {(void**)&ws.hist, 4 * (size_t)tkc_sort_hist_words(sh.n), false},
+        {(void**)&ws.mask, 64, false}, {(void**)&ws.parent, 4 * n, false},
+        {(void**)&ws.csize, 8 * n, false}, {(void**)&ws.gbuf, 24 * n, false},
+        {(void**)&ws.nbsum, 8 * n, false}, {(void**)&ws.nbvis, 8 * n, false},
+        {(void**)&ws.nbflags, n, false}, {(void**)&ws.small, 4096, false},
+        {(void**)&ws.tstate, 4096, false}, {(void**)&ws.ring, sizeof(XRec) * TKC_XRING, false},
+        {(void**)&ws.tS, 8 * (size_t)sh.kcap, false}, {(void**)&ws.tR, 8 * (size_t)sh.kcap, false},
+        {(void**)&ws.tI, 4 * (size_t)sh.kcap, false},
+        {(void**)&ws.stats, 8 * 4 * ST_COUNT, false},
+        // plain engine
+        {(void**)&ws.p_vis, 4 * words, true}, {(void**)&ws.p_fb, 12 * words, true},
+        {(void**)&ws.p_ql, 4 * n, false}, {(void**)&ws.p_qh, 4 * n, false},
+        {(void**)&ws.p_ctr, 8 * 16, true}, {(void**)&ws.p_lvl, 4 * n, false},
+        {(void**)&ws.p_levcnt, 8 * (n + 2), false}, {(void**)&ws.p_levtab, 8 * (n + 2), false},
+        // batched engine
+        {(void**)&ws.b_vis, 8 * n * nw, true}, {(void**)&ws.b_frt0, 8 * n * nw, true},
+        {(void**)&ws.b_frt1, 8 * n * nw, true}, {(void**)&ws.b_nxt, 8 * n * nw, true},
+        {(void**)&ws.b_list, 16 * n, false}, {(void**)&ws.b_mark, 4 * n, true},
+        {(void**)&ws.b_ctr, 8 * 2048, true}, {(void**)&ws.b_cand, 4 * 256, false},
+        {(void**)&ws.b_hist, sh.lb ? 8 * lcap * W : 8, false},
+        {(void**)&ws.b_levtab, sh.lb ? 8 * lcap * W : 8, false},
+        {(void**)&ws.b_lvl, sh.lb ? 2 * n * W : 8, false},
+        {(void**)&ws.b_outS, 8 * n, false}, {(void**)&ws.b_outR, 8 * n, false},
+        // per-workgroup engine
+        {(void**)&ws.s_vis, 4 * words * (size_t)sh.swarm_blocks, true},
+        {(void**)&ws.s_queue, 4 * (size_t)sh.qcap * (size_t)sh.swarm_blocks, false},
+        {(void**)&ws.s_deferred, 4 * n, false},
+    };
+    size_t total = 0;
+    for (auto& it : items) total += align_up(it.bytes);
+    return total;
+}
+
+size_t tkc_ws_bytes(const WsShape& sh) {
+    Workspace tmp;
+    std::vector<WsItem> items;
+    return ws_items(tmp, sh, items);
+}
+
+std::mutex& tkc_coop_mutex() {
+    static std::mutex m;
+    return m;
+}
+
+int tkc_ws_reserve(tkc_ctx* ctx, Workspace& ws, const WsShape& sh) {
+    std::vector<WsItem> items;
+    size_t total = ws_items(ws, sh, items);
+    if (ws.base && total <= ws.bytes && ws.shape.covers(sh)) return TKC_OK;
+    if (ws.base) {
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        hipFree(ws.base);
+        ws.base = nullptr;
+        ws.bytes = 0;
+    }
+    void* base = nullptr;
+    if (hipMalloc(&base, total) != hipSuccess) {
+        hipGetLastError();
+        return tkc_fail(TKC_ENOMEM, "device allocation of %zu bytes failed", total);
+    }
+    ws.base = (char*)base;
+    ws.bytes = total;
+    ws.shape = sh;
+    size_t off = 0;
+    for (auto& it : items) {
+        *it.p = ws.base + off;
+        if (it.zero) HIPCHK(hipMemsetAsync(ws.base + off, 0, it.bytes, ctx->stream));
+        off += align_up(it.bytes);
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return TKC_OK;
+}
+
+// ---------------------------------------------------------------- context
+extern "C" int tkc_ctx_create(int device, void* hip_stream, tkc_ctx** out) {
+    if (!out) return tkc_fail(TKC_EINVAL, "out is NULL");
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+        return tkc_fail(TKC_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= count) return tkc_fail(TKC_EINVAL, "device %d out of range", device);
+    HIPCHK(hipSetDevice(device));
+    tkc_ctx* c = new tkc_ctx();
+    c->device = device;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+        c->own_stream = false;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return tkc_fail(TKC_EDEVICE, "stream creation failed");
+        }
+        c->own_stream = true;
+    }
+    hipEventCreate(&c->ev0);
+    hipEventCreate(&c->ev1);
+    hipHostMalloc((void**)&c->pinned, 4096, hipHostMallocDefault);
+    *out = c;
+    return TKC_OK;
+}
+
+extern "C" int tkc_ctx_destroy(tkc_ctx* c) {
+    if (!c) return TKC_OK;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    if (c->ws.base) hipFree(c->ws.base);
+    if (c->pinned) hipHostFree(c->pinned);
+    hipEventDestroy(c->ev0);
+    hipEventDestroy(c->ev1);
+    if (c->own_stream) hipStreamDestroy(c->stream);
+    delete c;
+    return TKC_OK;
+}
+
+extern "C" int tkc_ctx_set_tuning(tkc_ctx* c, int32_t batch_width, int32_t td_bu_alpha, int32_t bu_td_beta,
+                                  int32_t swarm_qcap, int32_t block_size) {
+    if (!c) return tkc_fail(TKC_EINVAL, "ctx is NULL");
+    if (batch_width && batch_width != 32 && batch_width != 64 && batch_width != 128 && batch_width != 256)
+        return tkc_fail(TKC_EINVAL, "batch_width must be 32, 64, 128 or 256");
+    if (td_bu_alpha < 0 || bu_td_beta < 0 || swarm_qcap < 0 || block_size < 0)
+        return tkc_fail(TKC_EINVAL, "negative tuning value");
+    if (batch_width) c->tune.batch_width = batch_width;
+    if (td_bu_alpha) c->tune.td_bu_alpha = td_bu_alpha;
+    if (bu_td_beta) c->tune.bu_td_beta = bu_td_beta;
+    if (swarm_qcap) c->tune.swarm_qcap = swarm_qcap;
+    if (block_size) c->tune.block = block_size;
+    return TKC_OK;
+}
+
+// ------------------------------------------------------------------ graphs
+static int validate_csr(int32_t n, int64_t m, const int32_t* rp, const int32_t* ci, const char* what) {
+    if (rp[0] != 0) return tkc_fail(TKC_EINVAL, "%s: row_ptr[0] must be 0", what);
+    if ((int64_t)rp[n] != m) return tkc_fail(TKC_EINVAL, "%s: row_ptr[n] != m_arcs", what);
+    std::vector<int32_t> row;
+    for (int32_t u = 0; u < n; u++) {
+        if (rp[u + 1] < rp[u]) return tkc_fail(TKC_EINVAL, "%s: row_ptr not monotone at %d", what, u);
+        row.assign(ci + rp[u], ci + rp[u + 1]);
+        for (int32_t w : row) {
+            if (w < 0 || w >= n) return tkc_fail(TKC_EINVAL, "%s: vertex id %d out of range", what, w);
+            if (w == u) return tkc_fail(TKC_EINVAL, "%s: self-loop at %d", what, u);
+        }
+        std::sort(row.begin(), row.end());
+        for (size_t q = 1; q < row.size(); q++)
+            if (row[q] == row[q - 1]) return tkc_fail(TKC_EINVAL, "%s: repeated arc %d->%d", what, u, row[q]);
+    }
+    return TKC_OK;
+}
+
+// true when (rp2, ci2) is the transpose of (rp, ci)
+static bool is_transpose(int32_t n, int64_t m, const int32_t* rp, const int32_t* ci, const int32_t* rp2,
+                         const int32_t* ci2) {
+    std::vector<int64_t> cnt(n + 1, 0);
+    for (int64_t e = 0; e < m; e++) cnt[ci[e] + 1]++;
+    for (int32_t i = 0; i < n; i++) cnt[i + 1] += cnt[i];
+    for (int32_t i = 0; i <= n; i++)
+        if (cnt[i] != rp2[i]) return false;
+    std::vector<int32_t> t(m);
+    std::vector<int64_t> fill(cnt.begin(), cnt.end());
+    for (int32_t u = 0; u < n; u++)
+        for (int32_t e = rp[u]; e < rp[u + 1]; e++) t[fill[ci[e]]++] = u;
+    std::vector<int32_t> a, b;
+    for (int32_t v = 0; v < n; v++) {
+        a.assign(t.begin() + cnt[v], t.begin() + cnt[v + 1]);
+        b.assign(ci2 + rp2[v], ci2 + rp2[v + 1]);
+        std::sort(a.begin(), a.end());
+        std::sort(b.begin(), b.end());
+        if (a != b) return false;
+    }
+    return true;
+}
+
+extern "C" int tkc_graph_upload(tkc_ctx* c, int32_t n, int64_t m, const int32_t* row_ptr,
+                                const int32_t* col_idx, const int32_t* rrow_ptr, const int32_t* rcol_idx,
+                                uint32_t flags, tkc_graph** out) {
+    if (!c || !out || !row_ptr || (!col_idx && m > 0)) return tkc_fail(TKC_EINVAL, "NULL argument");
+    if (n < 1) return tkc_fail(TKC_EINVAL, "n must be >= 1");
+    if (m < 0 || m > 0x7fffffffLL) return tkc_fail(TKC_EINVAL, "m_arcs must be in [0, 2^31)");
+    const bool directed = (flags & TKC_DIRECTED) != 0;
+    if (directed && (!rrow_ptr || (!rcol_idx && m > 0)))
+        return tkc_fail(TKC_EINVAL, "directed graph needs the reverse CSR");
+    if (!directed && (rrow_ptr || rcol_idx))
+        return tkc_fail(TKC_EINVAL, "reverse CSR given for an undirected graph");
+    HIPCHK(hipSetDevice(c->device));
+    // host copies (the directed reachability bounds run on the host)
+    std::vector<int32_t> hrp(n + 1), hci(m), hrrp, hrci;
+    const hipMemcpyKind k = (flags & TKC_DEVICE_PTRS) ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+    HIPCHK(hipMemcpy(hrp.data(), row_ptr, 4 * (size_t)(n + 1), k));
+    if (m) HIPCHK(hipMemcpy(hci.data(), col_idx, 4 * (size_t)m, k));
+    if (directed) {
+        hrrp.resize(n + 1);
+        hrci.resize(m);
+        HIPCHK(hipMemcpy(hrrp.data(), rrow_ptr, 4 * (size_t)(n + 1), k));
+        if (m) HIPCHK(hipMemcpy(hrci.data(), rcol_idx, 4 * (size_t)m, k));
+    }
+    if ((int64_t)hrp[n] != m) return tkc_fail(TKC_EINVAL, "row_ptr[n] != m_arcs");
+    if (flags & TKC_VALIDATE) {
+        int rc = validate_csr(n, m, hrp.data(), hci.data(), "out-arcs");
+        if (rc) return rc;
+        if (directed) {
+            rc = validate_csr(n, m, hrrp.data(), hrci.data(), "in-arcs");
+            if (rc) return rc;
+            if (!is_transpose(n, m, hrp.data(), hci.data(), hrrp.data(), hrci.data()))
+                return tkc_fail(TKC_EINVAL, "reverse CSR is not the transpose of the CSR");
+        } else if (!is_transpose(n, m, hrp.data(), hci.data(), hrp.data(), hci.data())) {
+            return tkc_fail(TKC_EINVAL, "undirected CSR is not symmetric");
+        }
+    }
+    tkc_graph* g = new tkc_graph();
+    g->ctx = c;
+    g->n = n;
+    g->m = m;
+    g->directed = directed;
+    size_t bytes = 4 * (size_t)(n + 1) + 4 * (size_t)(m ? m : 1) + 4 * (size_t)n + 4 * (size_t)(n + 1);
+    if (directed) bytes += 4 * (size_t)(n + 1) + 4 * (size_t)(m ? m : 1);
+    if (hipMalloc(&g->dbase, bytes + 1024) != hipSuccess) {
+        hipGetLastError();
+        delete g;
+        return tkc_fail(TKC_ENOMEM, "graph allocation failed");
+    }
+    char* p = (char*)g->dbase;
+    auto take = [&](size_t b) { char* r = p; p += align_up(b); return r; };
+    g->rp = (int32_t*)take(4 * (size_t)(n + 1));
+    g->ci = (int32_t*)take(4 * (size_t)(m ? m : 1));
+    g->deg = (int32_t*)take(4 * (size_t)n);
+    g->heavy = (int32_t*)take(4 * (size_t)(n + 1));
+    if (directed) {
+        g->rrp = (int32_t*)take(4 * (size_t)(n + 1));
+        g->rci = (int32_t*)take(4 * (size_t)(m ? m : 1));
+    } else {
+        g->rrp = g->rp;
+        g->rci = g->ci;
+    }
+    hipStream_t s = c->stream;
+    int rc = TKC_OK;
+    if (hipMemcpyAsync(g->rp, hrp.data(), 4 * (size_t)(n + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
+        (m && hipMemcpyAsync(g->ci, hci.data(), 4 * (size_t)m, hipMemcpyHostToDevice, s) != hipSuccess))
+        rc = tkc_fail(TKC_EDEVICE, "graph copy failed");
+    if (!rc && directed &&
+        (hipMemcpyAsync(g->rrp, hrrp.data(), 4 * (size_t)(n + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
+         (m && hipMemcpyAsync(g->rci, hrci.data(), 4 * (size_t)m, hipMemcpyHostToDevice, s) != hipSuccess)))
+        rc = tkc_fail(TKC_EDEVICE, "reverse graph copy failed");
+    if (!rc) {
+        DevGraph dg = g->view();
+        int32_t* nh = (int32_t*)c->pinned;
+        int32_t* nh_dev = g->heavy + n;   // last slot holds the count
+        if (tkc_launch_degrees(dg, g->heavy, nh_dev, s) ||
+            hipMemcpyAsync(nh, nh_dev, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            rc = tkc_fail(TKC_EDEVICE, "degree kernel failed");
+        else
+            g->nheavy = *nh;
+    }
+    if (rc) {
+        hipStreamSynchronize(s);
+        hipFree(g->dbase);
+        delete g;
+        return rc;
+    }
+    if (directed) {
+        g->h_rp.swap(hrp);
+        g->h_ci.swap(hci);
+    }
+    *out = g;
+    return TKC_OK;
+}
+
+extern "C" int tkc_graph_free(tkc_graph* g) {
+    if (!g) return TKC_OK;
+    if (g->server_refs > 0) return tkc_fail(TKC_EBUSY, "graph is held by a server");
+    hipSetDevice(g->ctx->device);
+    hipStreamSynchronize(g->ctx->stream);
+    hipFree(g->dbase);
+    for (auto& p : g->prep)
+        if (p.base) hipFree(p.base);
+    delete g;
+    return TKC_OK;
+}
+
+// ------------------------------------------------------------ query steps
+WsShape tkc_shape_for(tkc_ctx* c, tkc_graph* g, int32_t k, bool lb) {
+    WsShape sh;
+    sh.n = g->n;
+    sh.W = c->tune.batch_width;
+    sh.nw = sh.W <= 64 ? 1 : sh.W / 64;
+    sh.kcap = std::max(k, 1);
+    sh.lb = lb;
+    sh.lcap = (int32_t)std::min<int64_t>((int64_t)g->n + 2, 65000);
+    sh.qcap = std::max(64, std::min(c->tune.swarm_qcap, g->n));
+    sh.swarm_blocks = std::max(1, tkc_swarm_max_blocks(256));
+    // the private bitmaps of the per-workgroup engine cost blocks * n/8 bytes;
+    // keep them under 2 GiB
+    while (sh.swarm_blocks > 64 && (int64_t)sh.swarm_blocks * ((g->n + 31) / 32) * 4 > (2ll << 30))
+        sh.swarm_blocks /= 2;
+    return sh;
+}
+
+// step 1: reachability into ws.alpha / ws.omega (/ ws.scc)
+int tkc_step_reach(tkc_ctx* c, tkc_graph* g, Workspace& ws) {
+    hipStream_t s = c->stream;
+    DevGraph dg = g->view();
+    if (!g->directed) {
+        if (tkc_launch_cc(dg, g->heavy, g->nheavy, ws.parent, ws.csize, ws.alpha, ws.omega, s))
+            return tkc_fail(TKC_EDEVICE, "components kernel failed");
+        return TKC_OK;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        if (g->h_alpha.empty())
+            tkc_host_alpha_omega(g->n, g->h_rp.data(), g->h_ci.data(), g->h_alpha, g->h_omega, g->h_scc);
+    }
+    HIPCHK(hipMemcpyAsync(ws.alpha, g->h_alpha.data(), 8 * (size_t)g->n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ws.omega, g->h_omega.data(), 8 * (size_t)g->n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ws.scc, g->h_scc.data(), 4 * (size_t)g->n, hipMemcpyHostToDevice, s));
+    return TKC_OK;
+}
+
+// step 2 + 3: bounds into ws.lnum / ws.lden, order into ws.ord / ws.key
+int tkc_step_bounds(tkc_ctx* c, tkc_graph* g, Workspace& ws, bool nb, int32_t* rounds) {
+    hipStream_t s = c->stream;
+    DevGraph dg = g->view();
+    int32_t n = g->n;
+    if (rounds) *rounds = 0;
+    if (nb) {
+        int32_t* nfin_dev = (int32_t*)ws.small;
+        int r = tkc_launch_nb(dg, g->heavy, g->nheavy, ws.alpha, ws.omega, ws.gbuf, ws.nbsum, ws.nbvis,
+                              ws.nbflags, ws.lnum, ws.lden, nfin_dev, (int32_t*)c->pinned, s);
+        if (r < 0) return tkc_fail(TKC_EDEVICE, "NB bound kernels failed");
+        if (rounds) *rounds = r;
+        if (tkc_launch_nb_keys(n, ws.lnum, ws.lden, ws.key, ws.ord, s))
+            return tkc_fail(TKC_EDEVICE, "key kernel failed");
+    } else {
+        if (tkc_launch_deg_bounds(dg, ws.omega, ws.lnum, ws.lden, ws.key, ws.ord, s))
+            return tkc_fail(TKC_EDEVICE, "degree bound kernel failed");
+    }
+    if (tkc_sort_pairs(ws.key, ws.ord, ws.tkey, ws.tval, n, ws.hist, (uint32_t*)ws.mask,
+                       (uint32_t*)c->pinned, s))
+        return tkc_fail(TKC_EDEVICE, "sort failed");
+    return TKC_OK;
+}
+
+static DevTopk topk_view(Workspace& ws) {
+    DevTopk t;
+    t.st = (TopkState*)ws.tstate;
+    t.ring = (XRec*)ws.ring;
+    t.S = ws.tS;
+    t.R = ws.tR;
+    t.I = ws.tI;
+    return t;
+}
+
+static PlainWork plain_view(Workspace& ws) {
+    PlainWork w;
+    w.vis = ws.p_vis; w.fb = ws.p_fb; w.ql = ws.p_ql; w.qh = ws.p_qh; w.ctr = ws.p_ctr;
+    w.lvl = ws.p_lvl; w.levcnt = ws.p_levcnt; w.levtab = ws.p_levtab;
+    return w;
+}
+static BatchWork batch_view(Workspace& ws) {
+    BatchWork w;
+    w.vis = ws.b_vis; w.frt0 = ws.b_frt0; w.frt1 = ws.b_frt1; w.nxt = ws.b_nxt;
+    w.list = ws.b_list; w.touched = ws.b_mark; w.ctr = ws.b_ctr; w.lanes = nullptr;
+    w.lvl = ws.b_lvl; w.hist = ws.b_hist; w.levtab = ws.b_levtab; w.lcap = ws.shape.lcap;
+    w.cand = ws.b_cand;
+    return w;
+}
+
+// time one engine launch with events on the context stream
+struct EngineTimer {
+    tkc_ctx* c;
+    double* acc;
+    int32_t* launches;
+    std::lock_guard<std::mutex> lk;
+    EngineTimer(tkc_ctx* c_, double* a, int32_t* l) : c(c_), acc(a), launches(l), lk(tkc_coop_mutex()) {
+        hipEventRecord(c->ev0, c->stream);
+    }
+    void done() {
+        hipEventRecord(c->ev1, c->stream);
+        hipEventSynchronize(c->ev1);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, c->ev0, c->ev1);
+        *acc += ms;
+        (*launches)++;
+    }
+};
+
+static int read_stats(tkc_ctx* c, const int64_t* dev, int64_t* host) {
+    HIPCHK(hipMemcpyAsync(host, dev, 8 * ST_COUNT, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return TKC_OK;
+}
+
+extern "C" int tkc_topk_closeness(tkc_graph* g, int32_t k, int32_t variant, int32_t mode, int32_t* ids,
+                                  int64_t* sum_dist, int64_t* reach, double* farness, int32_t* n_out,
+                                  tkc_stats* stats) {
+    if (!g || !ids || !n_out) return tkc_fail(TKC_EINVAL, "NULL argument");
+    if (k < 1) return tkc_fail(TKC_EINVAL, "k must be >= 1");
+    if (variant < TKC_AUTO || variant > TKC_NB_BOUND) return tkc_fail(TKC_EINVAL, "unknown variant %d", variant);
+    if (mode < TKC_PLAIN || mode > TKC_HYBRID) return tkc_fail(TKC_EINVAL, "unknown mode %d", mode);
+    tkc_ctx* c = g->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    return tkc_run_query(c, g, k, variant, mode, ids, sum_dist, reach, farness, n_out, stats);
+}
+
+int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t mode, int32_t* ids,
+                  int64_t* sum_dist, int64_t* reach, double* farness, int32_t* n_out, tkc_stats* stats) {
+    Workspace& ws = c->ws;
+    hipStream_t s = c->stream;
+    const int32_t n = g->n;
+    if (k > n) k = n;
+    double t0 = now_ms();
+    tkc_stats st;
+    memset(&st, 0, sizeof(st));
+    int rc;
+    // AUTO: high-diameter graphs favour level-based updates (Sect. 9.1)
+    if (variant == TKC_AUTO) variant = tkc_auto_variant(c, g);
+    const bool lb = (variant == TKC_DEG_BOUND || variant == TKC_NB_BOUND);
+    const bool nb = (variant == TKC_NB_CUT || variant == TKC_NB_BOUND);
+    rc = tkc_ws_reserve(c, ws, tkc_shape_for(c, g, k, lb));
+    if (rc) return rc;
+    int32_t rounds = 0;
+    double t1;
+    if (tkc_prep_cached(c, g, nb, &rounds)) {
+        t1 = now_ms();
+    } else {
+        rc = tkc_step_reach(c, g, ws);
+        if (rc) return rc;
+        HIPCHK(hipStreamSynchronize(s));
+        t1 = now_ms();
+        rc = tkc_step_bounds(c, g, ws, nb, &rounds);
+        if (rc) return rc;
+        if (g->cache_prep) {
+            rc = tkc_prep_store(c, g, nb, rounds);
+            if (rc) return rc;
+        }
+    }
+    DevTopk tk = topk_view(ws);
+    if (tkc_launch_topk_init(tk, k, s)) return tkc_fail(TKC_EDEVICE, "top-k init failed");
+    HIPCHK(hipMemsetAsync(ws.stats, 0, 8 * 4 * ST_COUNT, s));
+    HIPCHK(hipMemsetAsync(ws.p_vis, 0, 4 * (((size_t)n + 31) / 32), s));
+    HIPCHK(hipStreamSynchronize(s));
+    double t2 = now_ms();
+
+    DevGraph dg = g->view();
+    DevReach rcv{ws.alpha, ws.omega, g->directed ? ws.scc : nullptr};
+    OrderView ov{ws.ord, ws.key, n, nb};
+    BoundsView bv{ws.lnum, ws.lden};
+    int64_t* st_plain = ws.stats;
+    int64_t* st_batch = ws.stats + ST_COUNT;
+    int64_t* st_swarm = ws.stats + 2 * ST_COUNT;
+    int64_t* st_tail = ws.stats + 3 * ST_COUNT;
+    double ms_eng[3] = {0, 0, 0};
+    int32_t nl_eng[3] = {0, 0, 0};
+    int grid = 0;
+    if (lb && mode == TKC_HYBRID) mode = TKC_BATCHED;
+    if (mode == TKC_PLAIN) {
+        EngineTimer tm(c, &ms_eng[0], &nl_eng[0]);
+        if (tkc_launch_plain(dg, rcv, ov, bv, tk, plain_view(ws), st_plain, nullptr, 0, lb, c->tune, s, &grid))
+            return tkc_fail(TKC_EDEVICE, "plain engine launch failed: %s", hipGetErrorString(hipGetLastError()));
+        tm.done();
+    } else if (mode == TKC_BATCHED) {
+        EngineTimer tm(c, &ms_eng[1], &nl_eng[1]);
+        int e = tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_batch, nullptr, 0, 0, 0, lb, false,
+                                 nullptr, nullptr, c->tune, s, &grid);
+        if (e) return tkc_fail(TKC_EDEVICE, "batched engine launch failed: %s", hipGetErrorString(hipGetLastError()));
+        tm.done();
+    } else {
+        // hybrid: batched seed until x is known, then one search per workgroup,
+        // then the deferred (large) searches batched
+        int64_t hs[ST_COUNT];
+        {
+            EngineTimer tm(c, &ms_eng[1], &nl_eng[1]);
+            if (tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_batch, nullptr, 0, 0, -1, false,
+                                 false, nullptr, nullptr, c->tune, s, &grid))
+                return tkc_fail(TKC_EDEVICE, "batched seed launch failed: %s", hipGetErrorString(hipGetLastError()));
+            tm.done();
+        }
+        rc = read_stats(c, st_batch, hs);
+        if (rc) return rc;
+        int32_t cursor = (int32_t)hs[ST_CURSOR];
+        bool stopped = hs[ST_STOP] != 0;
+        if (!stopped && cursor < n) {
+            SwarmWork sw;
+            sw.vis = ws.s_vis;
+            sw.queue = ws.s_queue;
+            sw.deferred = ws.s_deferred;
+            int32_t* small = (int32_t*)ws.small;
+            sw.ndeferred = small + 4;
+            sw.cursor = small + 5;
+            sw.stop = small + 6;
+            sw.nblocks = ws.shape.swarm_blocks;
+            sw.qcap = ws.shape.qcap;
+            HIPCHK(hipMemsetAsync(small + 4, 0, 3 * sizeof(int32_t), s));
+            {
+                EngineTimer tm(c, &ms_eng[2], &nl_eng[2]);
+                if (tkc_launch_swarm(dg, rcv, ov, bv, tk, sw, st_swarm, cursor, c->tune, s))
+                    return tkc_fail(TKC_EDEVICE, "per-workgroup engine launch failed");
+                tm.done();
+            }
+            int32_t* pin = (int32_t*)c->pinned;
+            HIPCHK(hipMemcpyAsync(pin, small + 4, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            int32_t ndef = pin[0];
+            if (ndef > 0) {
+                EngineTimer tm(c, &ms_eng[1], &nl_eng[1]);
+                if (tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_tail, ws.s_deferred, ndef, 0, 0,
+                                     false, false, nullptr, nullptr, c->tune, s, &grid))
+                    return tkc_fail(TKC_EDEVICE, "batched tail launch failed");
+                tm.done();
+            }
+        }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    double t3 = now_ms();
+    // readback
+    int64_t hstat[4][ST_COUNT];
+    HIPCHK(hipMemcpyAsync(hstat, ws.stats, sizeof(hstat), hipMemcpyDeviceToHost, s));
+    TopkState hst;
+    HIPCHK(hipMemcpyAsync(&hst, ws.tstate, sizeof(hst), hipMemcpyDeviceToHost, s));
+    std::vector<int64_t> hS(k), hR(k);
+    std::vector<int32_t> hI(k);
+    HIPCHK(hipMemcpyAsync(hS.data(), ws.tS, 8 * (size_t)k, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hR.data(), ws.tR, 8 * (size_t)k, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hI.data(), ws.tI, 4 * (size_t)k, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int32_t cnt = std::min(hst.cnt, k);
+    if (cnt != k)
+        return tkc_fail(TKC_EDEVICE, "internal error: %d results for k = %d", cnt, k);
+    for (int32_t i = 0; i < cnt; i++) {
+        ids[i] = hI[i];
+        if (sum_dist) sum_dist[i] = hS[i];
+        if (reach) reach[i] = hR[i];
+        if (farness)
+            farness[i] = hR[i] <= 1 ? INFINITY
+                                    : ((double)(n - 1) * (double)hS[i]) / ((double)(hR[i] - 1) * (double)(hR[i] - 1));
+    }
+    *n_out = cnt;
+    double t4 = now_ms();
+    if (stats) {
+        for (int e = 0; e < 4; e++) {
+            st.m_vis += hstat[e][ST_MVIS];
+            st.bfs_started += hstat[e][ST_STARTED];
+            st.bfs_exact += hstat[e][ST_EXACT];
+            st.bfs_cut += hstat[e][ST_CUT];
+            st.skipped += hstat[e][ST_SKIPPED];
+            st.deferred += hstat[e][ST_DEFERRED];
+            st.max_level = (int32_t)std::max<int64_t>(st.max_level, hstat[e][ST_MAXLEVEL]);
+        }
+        st.batch_width = c->tune.batch_width;
+        st.variant_used = variant;
+        st.mode_used = mode;
+        st.nb_rounds = rounds;
+        st.ms_reach = t1 - t0;
+        st.ms_bounds = t2 - t1;
+        st.ms_traverse = t3 - t2;
+        st.ms_total = t4 - t0;
+        int best = 0;
+        for (int e = 1; e < 3; e++)
+            if (ms_eng[e] > ms_eng[best]) best = e;
+        st.main_kernel = best;
+        st.ms_kernel_main = ms_eng[best];
+        st.main_launches = nl_eng[best];
+        st.bytes_main = best == 0 ? hstat[0][ST_BYTES]
+                                  : (best == 1 ? hstat[1][ST_BYTES] + hstat[3][ST_BYTES] : hstat[2][ST_BYTES]);
+        *stats = st;
+    }
+    return TKC_OK;
+}
+
+// AUTO variant: one full search from the highest-degree vertex measures its
+// eccentricity; a deep graph (road-like) gets NB + level-based updates,
+// a shallow one NB + BFSCut.
+int32_t tkc_auto_variant(tkc_ctx* c, tkc_graph* g) {
+    if (g->auto_variant) return g->auto_variant;
+    std::vector<int32_t> deg(g->n);
+    if (hipMemcpy(deg.data(), g->deg, 4 * (size_t)g->n, hipMemcpyDeviceToHost) != hipSuccess)
+        return TKC_NB_CUT;
+    int32_t src = (int32_t)(std::max_element(deg.begin(), deg.end()) - deg.begin());
+    int64_t S = 0, r = 0;
+    tkc_stats st;
+    int rc = tkc_sums_impl(c, g, &src, 1, &S, &r, &st);
+    int32_t v = TKC_NB_CUT;
+    if (rc == TKC_OK) {
+        double lg = std::log2((double)std::max<int32_t>(g->n, 2));
+        if (st.max_level > 64 && st.max_level > 4 * lg) v = TKC_NB_BOUND;
+    }
+    g->auto_variant = v;
+    return v;
+}
+
+// ------------------------------------------------------------ inspection
+extern "C" int tkc_graph_reach(tkc_graph* g, int64_t* alpha, int64_t* omega, int32_t* scc) {
+    if (!g || !alpha || !omega) return tkc_fail(TKC_EINVAL, "NULL argument");
+    tkc_ctx* c = g->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    int rc = tkc_ws_reserve(c, c->ws, tkc_shape_for(c, g, 1, false));
+    if (rc) return rc;
+    rc = tkc_step_reach(c, g, c->ws);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(alpha, c->ws.alpha, 8 * (size_t)g->n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(omega, c->ws.omega, 8 * (size_t)g->n, hipMemcpyDeviceToHost, c->stream));
+    if (scc && g->directed)
+        HIPCHK(hipMemcpyAsync(scc, c->ws.scc, 4 * (size_t)g->n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return TKC_OK;
+}
+
+extern "C" int tkc_graph_bounds(tkc_graph* g, int32_t variant, int64_t* num, int64_t* den, int32_t* order) {
+    if (!g || !num || !den) return tkc_fail(TKC_EINVAL, "NULL argument");
+    if (variant < TKC_DEG_CUT || variant > TKC_NB_BOUND) return tkc_fail(TKC_EINVAL, "bad variant");
+    tkc_ctx* c = g->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    int rc = tkc_ws_reserve(c, c->ws, tkc_shape_for(c, g, 1, false));
+    if (rc) return rc;
+    rc = tkc_step_reach(c, g, c->ws);
+    if (rc) return rc;
+    bool nb = (variant == TKC_NB_CUT || variant == TKC_NB_BOUND);
+    rc = tkc_step_bounds(c, g, c->ws, nb, nullptr);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(num, c->ws.lnum, 8 * (size_t)g->n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(den, c->ws.lden, 8 * (size_t)g->n, hipMemcpyDeviceToHost, c->stream));
+    if (order) HIPCHK(hipMemcpyAsync(order, c->ws.ord, 4 * (size_t)g->n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return TKC_OK;
+}
+
+int tkc_sums_impl(tkc_ctx* c, tkc_graph* g, const int32_t* sources, int32_t count, int64_t* S, int64_t* R,
+                  tkc_stats* stout) {
+    Workspace& ws = c->ws;
+    hipStream_t s = c->stream;
+    int rc = tkc_ws_reserve(c, ws, tkc_shape_for(c, g, std::max(1, ws.shape.kcap), ws.shape.lb));
+    if (rc) return rc;
+    rc = tkc_step_reach(c, g, ws);
+    if (rc) return rc;
+    int32_t* dsrc = ws.s_deferred;
+    HIPCHK(hipMemcpyAsync(dsrc, sources, 4 * (size_t)count, hipMemcpyHostToDevice, s));
+    DevTopk tk = topk_view(ws);
+    if (tkc_launch_topk_init(tk, 1, s)) return tkc_fail(TKC_EDEVICE, "top-k init failed");
+    HIPCHK(hipMemsetAsync(ws.stats, 0, 8 * ST_COUNT, s));
+    DevReach rcv{ws.alpha, ws.omega, g->directed ? ws.scc : nullptr};
+    OrderView ov{ws.ord, ws.key, 0, false};
+    BoundsView bv{ws.lnum, ws.lden};
+    int grid = 0;
+    std::lock_guard<std::mutex> lk(tkc_coop_mutex());
+    if (tkc_launch_batch(g->view(), rcv, ov, bv, tk, batch_view(ws), ws.stats, dsrc, count, 0, 0, false, true,
+                         ws.b_outS, ws.b_outR, c->tune, s, &grid))
+        return tkc_fail(TKC_EDEVICE, "batched engine launch failed");
+    HIPCHK(hipMemcpyAsync(S, ws.b_outS, 8 * (size_t)count, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(R, ws.b_outR, 8 * (size_t)count, hipMemcpyDeviceToHost, s));
+    int64_t hs[ST_COUNT];
+    HIPCHK(hipMemcpyAsync(hs, ws.stats, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (stout) {
+        memset(stout, 0, sizeof(*stout));
+        stout->m_vis = hs[ST_MVIS];
+        stout->max_level = (int32_t)hs[ST_MAXLEVEL];
+        stout->bfs_started = hs[ST_STARTED];
+        stout->bfs_exact = hs[ST_EXACT];
+    }
+    return TKC_OK;
+}
+
+extern "C" int tkc_graph_sums(tkc_graph* g, const int32_t* sources, int32_t count, int64_t* S, int64_t* R) {
+    if (!g || !sources || !S || !R || count < 0) return tkc_fail(TKC_EINVAL, "bad argument");
+    for (int32_t i = 0; i < count; i++)
+        if (sources[i] < 0 || sources[i] >= g->n) return tkc_fail(TKC_EINVAL, "source %d out of range", sources[i]);
+    HIPCHK(hipSetDevice(g->ctx->device));
+    // the source list shares n-sized buffers: chunks of at most n
+    for (int32_t off = 0; off < count; off += g->n) {
+        int32_t c = std::min(count - off, g->n);
+        int rc = tkc_sums_impl(g->ctx, g, sources + off, c, S + off, R + off, nullptr);
+        if (rc) return rc;
+    }
+    return TKC_OK;
+}
+
+extern "C" int tkc_graph_lb_update(tkc_graph* g, const int32_t* sources, int32_t count, int64_t* num,
+                                   int64_t* den) {
+    if (!g || !sources || !num || !den || count < 0) return tkc_fail(TKC_EINVAL, "bad argument");
+    for (int32_t i = 0; i < count; i++)
+        if (sources[i] < 0 || sources[i] >= g->n) return tkc_fail(TKC_EINVAL, "source %d out of range", sources[i]);
+    tkc_ctx* c = g->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    Workspace& ws = c->ws;
+    int rc = tkc_ws_reserve(c, ws, tkc_shape_for(c, g, 1, true));
+    if (rc) return rc;
+    rc = tkc_step_reach(c, g, ws);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(ws.lnum, num, 8 * (size_t)g->n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ws.lden, den, 8 * (size_t)g->n, hipMemcpyHostToDevice, s));
+    DevTopk tk = topk_view(ws);
+    if (tkc_launch_topk_init(tk, 1, s)) return tkc_fail(TKC_EDEVICE, "top-k init failed");
+    HIPCHK(hipMemsetAsync(ws.stats, 0, 8 * ST_COUNT, s));
+    DevReach rcv{ws.alpha, ws.omega, g->directed ? ws.scc : nullptr};
+    OrderView ov{ws.ord, ws.key, 0, false};
+    BoundsView bv{ws.lnum, ws.lden};
+    int grid = 0;
+    for (int32_t off = 0; off < count; off += g->n) {
+        int32_t cnt = std::min(count - off, g->n);
+        HIPCHK(hipMemcpyAsync(ws.s_deferred, sources + off, 4 * (size_t)cnt, hipMemcpyHostToDevice, s));
+        std::lock_guard<std::mutex> lk(tkc_coop_mutex());
+        if (tkc_launch_batch(g->view(), rcv, ov, bv, tk, batch_view(ws), ws.stats, ws.s_deferred, cnt, 0, 0,
+                             true, true, ws.b_outS, ws.b_outR, c->tune, s, &grid))
+            return tkc_fail(TKC_EDEVICE, "batched engine launch failed");
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    HIPCHK(hipMemcpyAsync(num, ws.lnum, 8 * (size_t)g->n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(den, ws.lden, 8 * (size_t)g->n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return TKC_OK;
+}
+
+// ------------------------------------------- cached preprocessing (serving)
+static size_t prep_bytes(int32_t n) { return (size_t)n * 44 + 8 * 256; }
+
+bool tkc_prep_cached(tkc_ctx* c, tkc_graph* g, bool nb, int32_t* rounds) {
+    tkc_graph::Prep* p;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        p = &g->prep[nb ? 1 : 0];
+        if (!g->cache_prep || !p->ready) return false;
+    }
+    size_t n = (size_t)g->n;
+    char* b = (char*)p->base;
+    Workspace& ws = c->ws;
+    hipStream_t s = c->stream;
+    bool ok = hipMemcpyAsync(ws.alpha, b, 8 * n, hipMemcpyDeviceToDevice, s) == hipSuccess &&
+              hipMemcpyAsync(ws.omega, b + 8 * n, 8 * n, hipMemcpyDeviceToDevice, s) == hipSuccess &&
+              hipMemcpyAsync(ws.lnum, b + 16 * n, 8 * n, hipMemcpyDeviceToDevice, s) == hipSuccess &&
+              hipMemcpyAsync(ws.lden, b + 24 * n, 8 * n, hipMemcpyDeviceToDevice, s) == hipSuccess &&
+              hipMemcpyAsync(ws.ord, b + 32 * n, 4 * n, hipMemcpyDeviceToDevice, s) == hipSuccess &&
+              hipMemcpyAsync(ws.key, b + 36 * n, 4 * n, hipMemcpyDeviceToDevice, s) == hipSuccess &&
+              (!g->directed || hipMemcpyAsync(ws.scc, b + 40 * n, 4 * n, hipMemcpyDeviceToDevice, s) == hipSuccess);
+    if (!ok) return false;
+    *rounds = p->rounds;
+    return true;
+}
+
+int tkc_prep_store(tkc_ctx* c, tkc_graph* g, bool nb, int32_t rounds) {
+    std::lock_guard<std::mutex> lk(g->mu);
+    tkc_graph::Prep& p = g->prep[nb ? 1 : 0];
+    if (p.ready) return TKC_OK;
+    size_t n = (size_t)g->n;
+    if (!p.base && hipMalloc(&p.base, prep_bytes(g->n)) != hipSuccess) {
+        hipGetLastError();
+        p.base = nullptr;
+        return TKC_OK;   // no cache: queries recompute
+    }
+    char* b = (char*)p.base;
+    Workspace& ws = c->ws;
+    hipStream_t s = c->stream;
+    HIPCHK(hipMemcpyAsync(b, ws.alpha, 8 * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(b + 8 * n, ws.omega, 8 * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(b + 16 * n, ws.lnum, 8 * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(b + 24 * n, ws.lden, 8 * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(b + 32 * n, ws.ord, 4 * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(b + 36 * n, ws.key, 4 * n, hipMemcpyDeviceToDevice, s));
+    if (g->directed) HIPCHK(hipMemcpyAsync(b + 40 * n, ws.scc, 4 * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    p.rounds = rounds;
+    p.ready = true;
+    return TKC_OK;
+}
+
+extern "C" const char* tkc_last_error(void) { return g_err.c_str(); }
+extern "C" const char* tkc_version(void) { return "tkc 0.1 gfx950"; }

@@ -1,0 +1,230 @@
+// Device-side helpers shared by the HIP kernels of the top-k closeness path.
+// gfx950 (CDNA4): 64-lane wavefronts, per-XCD L2, agent-scope atomics for
+// anything another workgroup may read before the kernel ends.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define TKC_DEV __device__ __forceinline__
+
+typedef unsigned __int128 tkc_u128;
+
+// ---------------------------------------------------------------- atomics
+template <typename T>
+TKC_DEV T ld_acq(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+TKC_DEV T ld_rlx(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+TKC_DEV void st_rel(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+TKC_DEV void st_rlx(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+TKC_DEV T fadd_rlx(T* p, T v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+TKC_DEV T for_rlx(T* p, T v) {
+    return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// or into a word only this workgroup touches
+template <typename T>
+TKC_DEV T for_wg(T* p, T v) {
+    return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// ------------------------------------------------------------ wave helpers
+TKC_DEV int lane_id() { return (int)__lane_id(); }
+
+TKC_DEV int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+TKC_DEV int32_t wave_sum_i32(int32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+TKC_DEV uint64_t wave_or_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+    return v;
+}
+// exclusive prefix of a 0/1 predicate within the wave, plus the wave total
+TKC_DEV int wave_rank(bool pred, int* total) {
+    uint64_t m = __ballot(pred);
+    *total = __popcll(m);
+    uint64_t below = (lane_id() == 0) ? 0ull : (m & (~0ull >> (64 - lane_id())));
+    return __popcll(below);
+}
+
+// --------------------------------------------------- exact farness algebra
+// A farness value in units of (n-1): num / den with den = (r-1)^2 > 0, or
+// +inf encoded as den == 0.  Comparisons are exact (128-bit products: num
+// stays below 2^40 and den below 2^62 on every supported graph).
+TKC_DEV int rat_cmp(int64_t na, int64_t da, int64_t nb, int64_t db) {
+    bool ia = (da == 0), ib = (db == 0);
+    if (ia || ib) return (int)ia - (int)ib;
+    tkc_u128 x = (tkc_u128)(uint64_t)na * (uint64_t)db;
+    tkc_u128 y = (tkc_u128)(uint64_t)nb * (uint64_t)da;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+// signed numerators (the raw Lemma 6.1 form can go negative)
+TKC_DEV int rat_cmp_signed(int64_t na, int64_t da, int64_t nb, int64_t db) {
+    __int128 x = (__int128)na * (__int128)db;
+    __int128 y = (__int128)nb * (__int128)da;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+TKC_DEV int64_t sq64(int64_t a) { return a * a; }
+
+// exact (farness, id) order: true when (na/da, ia) comes strictly after (nb/db, ib)
+TKC_DEV bool lex_after(int64_t na, int64_t da, int32_t ia, int64_t nb, int64_t db, int32_t ib) {
+    int c = rat_cmp(na, da, nb, db);
+    return c > 0 || (c == 0 && ia > ib);
+}
+
+// -------------------------------------------------------------- k-th value
+// The current k-th best result x = (S, r, id).  Published through a ring of
+// records and a sequence counter so readers never mix two records: a reader
+// takes seq, the record, then seq again, and retries unless fewer than RING
+// newer records were published meanwhile.  seq < 0 means "fewer than k
+// results so far" (x = +inf).
+#define TKC_XRING 256
+struct XRec {
+    int64_t S;
+    int64_t r;
+    int64_t id;
+};
+struct TopkState {
+    int32_t lock;
+    int32_t cnt;
+    int64_t seq;      // number of published records - 1
+    int32_t k;
+    int32_t pad;
+    int64_t n_inserts;
+};
+struct XVal {
+    int64_t num;      // S
+    int64_t den;      // (r-1)^2, 0 = +inf
+    int32_t id;
+};
+
+TKC_DEV XVal read_x(TopkState* st, const XRec* ring) {
+    XVal x;
+    for (;;) {
+        int64_t s1 = ld_acq(&st->seq);
+        if (s1 < 0) { x.num = 0; x.den = 0; x.id = 0x7fffffff; return x; }
+        const XRec* rc = ring + (s1 % TKC_XRING);
+        int64_t S = ld_rlx(&rc->S), r = ld_rlx(&rc->r), id = ld_rlx(&rc->id);
+        int64_t s2 = ld_acq(&st->seq);
+        if (s2 - s1 < TKC_XRING - 1) {
+            x.num = S;
+            x.den = r <= 1 ? 0 : sq64(r - 1);
+            x.id = (int32_t)id;
+            return x;
+        }
+    }
+}
+
+// Insert an exact result; the caller is one thread.  topk arrays hold the
+// min(k, inserted) best (S, r, id) in exact order.  Spins on st->lock.
+TKC_DEV void topk_insert(TopkState* st, XRec* ring, int64_t* tS, int64_t* tR, int32_t* tI,
+                         int64_t S, int64_t r, int32_t id) {
+    while (__hip_atomic_exchange(&st->lock, 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0)
+        __builtin_amdgcn_s_sleep(2);
+    int32_t k = ld_rlx(&st->k);
+    int32_t cnt = ld_rlx(&st->cnt);
+    int64_t den = r <= 1 ? 0 : sq64(r - 1);
+    // position = number of entries that precede (S, r, id)
+    int32_t p = cnt;
+    while (p > 0) {
+        int64_t pr = ld_rlx(&tR[p - 1]);
+        int64_t pd = pr <= 1 ? 0 : sq64(pr - 1);
+        if (lex_after(ld_rlx(&tS[p - 1]), pd, ld_rlx(&tI[p - 1]), S, den, id)) p--;
+        else break;
+    }
+    if (p < k) {
+        int32_t last = cnt < k ? cnt : k - 1;
+        for (int32_t q = last; q > p; q--) {
+            st_rlx(&tS[q], ld_rlx(&tS[q - 1]));
+            st_rlx(&tR[q], ld_rlx(&tR[q - 1]));
+            st_rlx(&tI[q], ld_rlx(&tI[q - 1]));
+        }
+        st_rlx(&tS[p], S); st_rlx(&tR[p], r); st_rlx(&tI[p], id);
+        if (cnt < k) { cnt++; st_rlx(&st->cnt, cnt); }
+        if (cnt == k) {
+            int64_t s = ld_rlx(&st->seq) + 1;
+            XRec* rc = ring + (s % TKC_XRING);
+            st_rlx(&rc->S, ld_rlx(&tS[k - 1]));
+            st_rlx(&rc->r, ld_rlx(&tR[k - 1]));
+            st_rlx(&rc->id, (int64_t)ld_rlx(&tI[k - 1]));
+            st_rel(&st->seq, s);
+        }
+    }
+    fadd_rlx(&st->n_inserts, (int64_t)1);
+    __hip_atomic_store(&st->lock, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ----------------------------------------------------- BFSCut bound (Sect. 6)
+// After levels 0..D are fully known (nD vertices, distance sum SD) and U
+// bounds the size of level D+1, the least S(v) consistent with r(v) = r is
+//   S_D + (D+1) rem + max(0, rem - U),   rem = r - nD
+// (Lemma 6.1 tightened: every unseen vertex sits at distance >= D+1 and at
+// most U of them at D+1).  With only alpha <= r <= omega known (Sect. 8.2)
+// the farness bound is minimised over r in [a', o'] with a' = max(alpha, nD),
+// o' = max(omega, a'); as a function of r the bound is convex piecewise
+// linear with one kink at r = nD + U, so the ends and the clamped kink are
+// the only candidates (Lemma 8.1).  Returns the bound as num/den.
+TKC_DEV void cut_bound(int64_t SD, int64_t nD, int64_t U, int64_t D, int64_t alpha, int64_t omega,
+                       int64_t* bnum, int64_t* bden) {
+    int64_t a1 = alpha > nD ? alpha : nD;
+    int64_t o1 = omega > a1 ? omega : a1;
+    int64_t kink = nD + U;
+    kink = kink < a1 ? a1 : (kink > o1 ? o1 : kink);
+    int64_t cand[3] = {a1, o1, kink};
+    int64_t bn = 0, bd = 0;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        int64_t r = cand[c];
+        if (r <= 1) continue;
+        int64_t rem = r - nD;
+        int64_t extra = rem - U;
+        int64_t s = SD + (D + 1) * rem + (extra > 0 ? extra : 0);
+        int64_t d = sq64(r - 1);
+        if (bd == 0 || rat_cmp(s, d, bn, bd) < 0) { bn = s; bd = d; }
+    }
+    *bnum = bn;
+    *bden = bd;
+}
+
+// key of a lower bound for the processing order: the top 32 bits of the
+// IEEE double num/den (monotone in the value; +inf sorts last).  Its value
+// read back never exceeds the true bound by more than the double rounding.
+TKC_DEV uint32_t order_key(int64_t num, int64_t den) {
+    if (den == 0) return 0xffffffffu;
+    double d = (double)num / (double)den;
+    uint64_t b = (uint64_t)__double_as_longlong(d);
+    return (uint32_t)(b >> 32);
+}
+TKC_DEV double key_value(uint32_t key) {
+    if (key == 0xffffffffu) return __builtin_inf();
+    return __longlong_as_double((long long)((uint64_t)key << 32));
+}
+// Stop test of Alg. 1 on a key: every vertex at or after this key position
+// has a bound strictly above x (1e-9 relative margin covers the two double
+// roundings of the key and of x).
+TKC_DEV bool key_stops(uint32_t key, XVal x) {
+    if (x.den == 0) return false;
+    double kv = key_value(key);
+    if (kv == __builtin_inf()) return true;
+    double xv = (double)x.num / (double)x.den;
+    return kv > xv * (1.0 + 1e-9);
+}

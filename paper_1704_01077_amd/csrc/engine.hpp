@@ -1,0 +1,135 @@
+// Host-side view of the device data used by the kernels, and the launch
+// entry points each .hip file provides to the driver.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+struct TopkState;
+struct XRec;
+
+struct DevGraph {
+    int32_t n;
+    int64_t m;            // arcs
+    bool directed;
+    const int32_t* rp;    // out-arcs CSR
+    const int32_t* ci;
+    const int32_t* rrp;   // in-arcs CSR (== rp/ci when undirected)
+    const int32_t* rci;
+    int32_t* deg;         // out-degree
+};
+
+// reachability and bounds of one query
+struct DevReach {
+    const int64_t* alpha;   // alpha = omega = r when known
+    const int64_t* omega;
+    const int32_t* scc;     // directed only (same-SCC rule of the LB update)
+};
+
+struct DevTopk {
+    TopkState* st;
+    XRec* ring;
+    int64_t* S;
+    int64_t* R;
+    int32_t* I;
+};
+
+// counters the engines add to (device, int64 each)
+enum {
+    ST_MVIS = 0, ST_STARTED, ST_EXACT, ST_CUT, ST_SKIPPED, ST_DEFERRED, ST_MAXLEVEL, ST_CURSOR,
+    ST_STOP, ST_BYTES, ST_COUNT
+};
+
+struct OrderView {
+    const int32_t* ord;      // vertex per position
+    const uint32_t* key;     // sorted key per position
+    int32_t count;           // positions available
+    bool key_is_bound;       // NB keys bound the farness; Deg keys only order
+};
+
+struct BoundsView {
+    int64_t* num;            // current lower bound num/den (den 0 = +inf)
+    int64_t* den;
+};
+
+struct EngineTuning {
+    int32_t td_bu_alpha = 14;    // push -> pull when frontier arcs > unexplored arcs / alpha
+    int32_t bu_td_beta = 24;     // pull -> push when frontier vertices < n / beta
+    int32_t batch_width = 64;
+    int32_t swarm_qcap = 16384;
+    int32_t block = 256;
+};
+
+// k_prep.hip
+int tkc_launch_degrees(const DevGraph& g, int32_t* heavy, int32_t* nheavy, hipStream_t s);
+int tkc_launch_cc(const DevGraph& g, const int32_t* heavy, int32_t nheavy, int32_t* parent,
+                  int64_t* size, int64_t* alpha, int64_t* omega, hipStream_t s);
+int tkc_launch_nb(const DevGraph& g, const int32_t* heavy, int32_t nheavy, const int64_t* alpha,
+                  const int64_t* omega, int64_t* gbuf, int64_t* sum, int64_t* vis, uint8_t* flags,
+                  int64_t* num, int64_t* den, int32_t* nfin_dev, int32_t* nfin_host, hipStream_t s);
+int tkc_launch_deg_bounds(const DevGraph& g, const int64_t* omega, int64_t* num, int64_t* den,
+                          uint32_t* key, int32_t* val, hipStream_t s);
+int tkc_launch_nb_keys(int32_t n, const int64_t* num, const int64_t* den, uint32_t* key,
+                       int32_t* val, hipStream_t s);
+
+// k_sort.hip: stable ascending sort of (key, val) pairs; the result ends in
+// keys/vals.  tmp_* hold n items, hist holds sort_hist_words(n) int32.
+int64_t tkc_sort_hist_words(int32_t n);
+int tkc_sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* tmp_keys, int32_t* tmp_vals,
+                   int32_t n, int32_t* hist, uint32_t* mask_dev, uint32_t* mask_host,
+                   hipStream_t s);
+
+// k_topk.hip
+int tkc_launch_topk_init(DevTopk t, int32_t k, hipStream_t s);
+
+// k_plain.hip: one source at a time on the whole GPU (cooperative kernel).
+struct PlainWork {
+    uint32_t* vis;       // n bits
+    uint32_t* fb;        // 3 x n bits (frontier bitmaps of pull steps)
+    int32_t* ql;         // queue of light vertices (n)
+    int32_t* qh;         // queue of heavy vertices (n)
+    int64_t* ctr;        // 3 x 4 level counters + tails
+    int32_t* lvl;        // distance from the source (level-based updates)
+    int64_t* levcnt;     // vertices per level (n + 2)
+    int64_t* levtab;     // Lev(i) table (n + 2)
+};
+int tkc_launch_plain(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv, DevTopk tk,
+                     PlainWork w, int64_t* stats, const int32_t* list, int32_t list_count,
+                     bool lb_mode, const EngineTuning& tune, hipStream_t s, int* grid_out);
+
+// k_batch.hip: W sources per launch, one bit lane each (cooperative kernel).
+struct BatchWork {
+    uint64_t* vis;       // n * nw words
+    uint64_t* frt0;      // n * nw
+    uint64_t* frt1;      // n * nw
+    uint64_t* nxt;       // n * nw
+    int32_t* list;       // frontier lists, 2 * n
+    int32_t* touched;    // every vertex touched in the batch (for clearing), cap n
+    int64_t* ctr;        // per-lane level counters, 3 * 2 * 256 + misc
+    int64_t* lanes;      // per-lane state
+    uint16_t* lvl;       // n * W levels (level-based updates), may be null
+    int64_t* hist;       // LCAP * W vertices per level per lane
+    int64_t* levtab;     // LCAP * W Lev tables
+    int32_t lcap;
+    int32_t* cand;       // selected candidates of a batch (W)
+};
+int tkc_launch_batch(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv, DevTopk tk,
+                     BatchWork w, int64_t* stats, const int32_t* list, int32_t list_count,
+                     int32_t start_pos, int32_t max_batches, bool lb_mode, bool no_cut,
+                     int64_t* out_S, int64_t* out_r, const EngineTuning& tune, hipStream_t s,
+                     int* grid_out);
+
+// k_swarm.hip: one search per workgroup for short cut searches.
+struct SwarmWork {
+    uint32_t* vis;       // nblocks * words_per_block
+    int32_t* queue;      // nblocks * qcap
+    int32_t* deferred;   // n
+    int32_t* ndeferred;  // 1
+    int32_t* cursor;     // 1
+    int32_t* stop;       // 1
+    int32_t nblocks;
+    int32_t qcap;
+};
+int tkc_launch_swarm(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv, DevTopk tk,
+                     SwarmWork w, int64_t* stats, int32_t start_pos, const EngineTuning& tune,
+                     hipStream_t s);
+int tkc_swarm_max_blocks(int block);

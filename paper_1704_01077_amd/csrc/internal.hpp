@@ -1,0 +1,116 @@
+// Library-private host structures: context, device graph, query workspace.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <vector>
+
+#include "../../include/tkc.h"
+#include "engine.hpp"
+
+struct WsShape {
+    int32_t n = 0, W = 64, nw = 1, kcap = 1, lcap = 0, qcap = 0, swarm_blocks = 0;
+    bool lb = false;
+    bool covers(const WsShape& o) const {
+        return n >= o.n && nw >= o.nw && W >= o.W && kcap >= o.kcap && lcap >= o.lcap && qcap >= o.qcap &&
+               swarm_blocks >= o.swarm_blocks && (lb || !o.lb);
+    }
+};
+
+// Every device buffer one query may touch; one allocation, grown on demand.
+struct Workspace {
+    char* base = nullptr;
+    size_t bytes = 0;
+    WsShape shape;
+    int64_t *alpha, *omega;
+    int32_t* scc;
+    int64_t *lnum, *lden;
+    uint32_t *key, *tkey;
+    int32_t *ord, *tval;
+    int32_t* hist;
+    void* mask;
+    int32_t* parent;
+    int64_t* csize;
+    int64_t *gbuf, *nbsum, *nbvis;
+    uint8_t* nbflags;
+    void* small;
+    void* tstate;
+    void* ring;
+    int64_t *tS, *tR;
+    int32_t* tI;
+    int64_t* stats;
+    // plain engine
+    uint32_t *p_vis, *p_fb;
+    int32_t *p_ql, *p_qh, *p_lvl;
+    int64_t *p_ctr, *p_levcnt, *p_levtab;
+    // batched engine
+    uint64_t *b_vis, *b_frt0, *b_frt1, *b_nxt;
+    int32_t *b_list, *b_mark, *b_cand;
+    int64_t *b_ctr, *b_hist, *b_levtab, *b_outS, *b_outR;
+    uint16_t* b_lvl;
+    // per-workgroup engine
+    uint32_t* s_vis;
+    int32_t *s_queue, *s_deferred;
+};
+
+struct tkc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    EngineTuning tune;
+    Workspace ws;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    void* pinned = nullptr;   // 4 KiB of pinned host memory for small readbacks
+};
+
+struct tkc_graph {
+    tkc_ctx* ctx = nullptr;
+    int32_t n = 0;
+    int64_t m = 0;
+    bool directed = false;
+    void* dbase = nullptr;
+    int32_t *rp = nullptr, *ci = nullptr, *rrp = nullptr, *rci = nullptr;
+    int32_t* deg = nullptr;
+    int32_t* heavy = nullptr;
+    int32_t nheavy = 0;
+    int32_t server_refs = 0;
+    int32_t auto_variant = 0;
+    // directed graphs keep a host copy for the reachability bounds
+    std::vector<int32_t> h_rp, h_ci;
+    std::vector<int64_t> h_alpha, h_omega;
+    std::vector<int32_t> h_scc;
+    std::mutex mu;
+    // cached preprocessing (serving): [0] Deg, [1] NB
+    struct Prep {
+        void* base = nullptr;
+        int32_t rounds = 0;
+        bool ready = false;
+    } prep[2];
+    bool cache_prep = false;
+    DevGraph view() const {
+        DevGraph g;
+        g.n = n; g.m = m; g.directed = directed;
+        g.rp = rp; g.ci = ci; g.rrp = rrp; g.rci = rci; g.deg = deg;
+        return g;
+    }
+};
+
+int tkc_fail(int code, const char* fmt, ...);
+int tkc_ws_reserve(tkc_ctx* ctx, Workspace& ws, const WsShape& sh);
+int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t mode, int32_t* ids,
+                  int64_t* sum_dist, int64_t* reach, double* farness, int32_t* n_out, tkc_stats* stats);
+int tkc_sums_impl(tkc_ctx* c, tkc_graph* g, const int32_t* sources, int32_t count, int64_t* S, int64_t* R,
+                  tkc_stats* st);
+int32_t tkc_auto_variant(tkc_ctx* c, tkc_graph* g);
+int tkc_step_reach(tkc_ctx* c, tkc_graph* g, Workspace& ws);
+int tkc_step_bounds(tkc_ctx* c, tkc_graph* g, Workspace& ws, bool nb, int32_t* rounds);
+// copy a graph's cached reachability/bounds/order into c's workspace; false
+// when the graph has no cache for this bound kind
+bool tkc_prep_cached(tkc_ctx* c, tkc_graph* g, bool nb, int32_t* rounds);
+// build that cache from c's workspace after a query computed it
+int tkc_prep_store(tkc_ctx* c, tkc_graph* g, bool nb, int32_t rounds);
+WsShape tkc_shape_for(tkc_ctx* c, tkc_graph* g, int32_t k, bool lb);
+size_t tkc_ws_bytes(const WsShape& sh);
+// one cooperative kernel at a time on the device
+std::mutex& tkc_coop_mutex();

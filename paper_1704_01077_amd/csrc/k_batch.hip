@@ -1,0 +1,658 @@
+// Batched engine: W candidates of Alg. 1 searched together, one bit lane
+// per source in W-bit words per vertex (visited, frontier, next).  A push
+// step reads each frontier vertex's adjacency once for all its lanes and
+// ORs the lanes into its neighbours' next words; a pull step lets every
+// vertex with unreached lanes scan its in-arcs for frontier lanes.  Each
+// lane keeps its own BFSCut state (Sect. 6): after every level the exact
+// per-lane counts give the bound, and a lane whose bound passes the k-th
+// farness x retires (its bits are masked out of later steps).  Bound
+// variants run every lane to the end and then apply the level-based update
+// (Sect. 7) of all lanes at once.
+//
+// One cooperative launch processes batch after batch; block 0's first wave
+// selects the next candidates from the order (stop and skip rules of
+// Alg. 1) and every workgroup replicates the per-lane control so all take
+// the same path through the grid barriers.
+#include <hip/hip_cooperative_groups.h>
+
+#include "dev_common.hpp"
+#include "engine.hpp"
+
+namespace cg = cooperative_groups;
+
+#define HEAVY_DEG 64
+#define BB 256
+#define MAXW 256
+
+// ctr layout (int64)
+#define C_CNT(p, l) ((p) * 2 * MAXW + (l))
+#define C_DEG(p, l) ((p) * 2 * MAXW + MAXW + (l))
+#define C_BASE (3 * 2 * MAXW)
+#define C_UCNT(p) (C_BASE + (p) * 4 + 0)
+#define C_UDEG(p) (C_BASE + (p) * 4 + 1)
+#define C_TL(p) (C_BASE + (p) * 4 + 2)      // next light list tail
+#define C_TH(p) (C_BASE + (p) * 4 + 3)      // next heavy list tail
+#define C_NSEL (C_BASE + 12)
+#define C_POS (C_BASE + 13)
+#define C_STOP (C_BASE + 14)
+#define C_LBOK (C_BASE + 15)
+#define C_TOTAL (C_BASE + 16)
+
+struct BatchArgs {
+    DevGraph g;
+    DevReach rc;
+    OrderView ov;
+    BoundsView bv;
+    DevTopk tk;
+    BatchWork w;
+    int64_t* stats;
+    const int32_t* list;
+    int32_t list_count;
+    int32_t start_pos;
+    int32_t max_batches;
+    int32_t lb_mode;
+    int32_t no_cut;        // full searches, results to out_S / out_r only
+    int32_t until_x;       // stop after the batch in which x becomes finite
+    int32_t W;
+    int32_t alpha_td;
+    int32_t beta_bu;
+    int64_t* out_S;
+    int64_t* out_r;
+    int32_t* mark;         // per-vertex level stamp (NW > 1)
+};
+
+TKC_DEV int64_t shfl64b(int64_t v, int src) {
+    int32_t lo = __shfl((int32_t)(v & 0xffffffff), src, 64);
+    int32_t hi = __shfl((int32_t)(v >> 32), src, 64);
+    return ((int64_t)hi << 32) | (uint32_t)lo;
+}
+TKC_DEV uint64_t below_mask() {
+    int l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+template <int NW>
+struct Mask {
+    uint64_t w[NW];
+    TKC_DEV bool any() const {
+        uint64_t o = 0;
+#pragma unroll
+        for (int j = 0; j < NW; j++) o |= w[j];
+        return o != 0;
+    }
+};
+
+TKC_DEV void list_append(bool isnew, int32_t w, int32_t dw, int32_t* ll, int32_t* lh, int64_t* tl,
+                         int64_t* th) {
+    bool hv = isnew && dw > HEAVY_DEG;
+    bool lt = isnew && !hv;
+    uint64_t ml = __ballot(lt), mh = __ballot(hv);
+    if ((ml | mh) == 0) return;
+    int leader = __ffsll((long long)__ballot(1)) - 1;
+    int64_t bl = 0, bh = 0;
+    if (lane_id() == leader) {
+        if (ml) bl = fadd_rlx(tl, (int64_t)__popcll(ml));
+        if (mh) bh = fadd_rlx(th, (int64_t)__popcll(mh));
+    }
+    bl = shfl64b(bl, leader);
+    bh = shfl64b(bh, leader);
+    uint64_t b = below_mask();
+    if (lt) ll[bl + __popcll(ml & b)] = w;
+    if (hv) lh[bh + __popcll(mh & b)] = w;
+}
+
+// OR the lanes nb into w's next word(s); true for exactly one caller per
+// vertex and level (the one that makes it appear in the next list)
+template <int NW>
+TKC_DEV bool push_lanes(uint64_t* nxt, int32_t* mark, int32_t w, const Mask<NW>& nb, int32_t stamp) {
+    if (NW == 1) {
+        uint64_t old = for_rlx(&nxt[w], nb.w[0]);
+        return old == 0;
+    } else {
+#pragma unroll
+        for (int j = 0; j < NW; j++)
+            if (nb.w[j]) for_rlx(&nxt[(int64_t)w * NW + j], nb.w[j]);
+        int32_t old = __hip_atomic_fetch_max(&mark[w], stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return old < stamp;
+    }
+}
+
+template <int NW>
+__global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
+    cg::grid_group grid = cg::this_grid();
+    const int32_t n = a.g.n;
+    const bool dir = a.g.directed;
+    const int W = a.W;
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nwaves = nthreads / 64;
+    const int64_t gwave = gtid / 64;
+    const int lane = lane_id();
+    const int tid = threadIdx.x;
+    const bool boss = (blockIdx.x == 0 && tid == 0);
+    const int32_t* __restrict__ rp = a.g.rp;
+    const int32_t* __restrict__ ci = a.g.ci;
+    const int32_t* __restrict__ deg = a.g.deg;
+    int64_t* ctr = a.w.ctr;
+    uint64_t* vis = a.w.vis;
+    int64_t* stats = a.stats;
+    const bool order_mode = (a.list == nullptr);
+    const int32_t count = order_mode ? a.ov.count : a.list_count;
+
+    // replicated per-lane control state
+    __shared__ int32_t s_v[MAXW];
+    __shared__ int64_t s_a[MAXW], s_o[MAXW], s_nD[MAXW], s_SD[MAXW], s_U[MAXW], s_nf[MAXW], s_mf[MAXW];
+    __shared__ int32_t s_st[MAXW];      // 0 unused, 1 active, 2 exact, 3 cut
+    __shared__ int32_t s_maxD[MAXW];
+    __shared__ uint64_t s_act[NW];
+    __shared__ int32_t s_red_cnt[MAXW];
+    __shared__ int64_t s_red_deg[MAXW];
+    __shared__ int64_t s_scal[8];
+
+    int32_t pos = a.start_pos;
+    int32_t batches = 0;
+    while (batches < a.max_batches) {
+        // ---------------------------------------------- candidate selection
+        if (blockIdx.x == 0 && tid < 64) {
+            XVal x = read_x(a.tk.st, a.tk.ring);
+            int32_t nsel = 0;
+            int32_t stop = 0;
+            int64_t skipped = 0, r1 = 0;
+            while (nsel < W && pos < count && !stop) {
+                int32_t i = pos + lane;
+                bool valid = i < count;
+                int32_t v = valid ? (order_mode ? a.ov.ord[i] : a.list[i]) : -1;
+                bool st = false, sk = false, one = false;
+                if (valid && !a.no_cut) {
+                    if (order_mode) {
+                        uint32_t key = a.ov.key[i];
+                        st = a.ov.key_is_bound ? key_stops(key, x) : (key == 0xffffffffu && x.den != 0);
+                    }
+                    if (!st) sk = lex_after(a.bv.num[v], a.bv.den[v], v, x.num, x.den, x.id);
+                }
+                // in list mode without cuts every position gets a lane, sinks included
+                if (valid && !st && !sk && !a.no_cut) one = a.rc.omega[v] <= 1;
+                uint64_t mst = __ballot(valid && st);
+                int lim = mst ? (__ffsll((long long)mst) - 1) : 64;
+                bool inwin = valid && lane < lim;
+                bool elig = inwin && !st && !sk && !one;
+                uint64_t me = __ballot(elig);
+                int room = W - nsel;
+                // lanes beyond the room-th eligible one are left for the next batch
+                int cut_lane = 64;
+                if (__popcll(me) > room) {
+                    uint64_t m = me;
+                    for (int q = 0; q < room; q++) m &= m - 1;
+                    cut_lane = __ffsll((long long)m) - 1;
+                }
+                bool take = inwin && lane < cut_lane;
+                int rank = __popcll(me & below_mask());
+                if (take && elig) a.w.cand[nsel + rank] = v;
+                uint64_t mone = __ballot(take && one);
+                uint64_t msk = __ballot(take && sk);
+                // vertices that reach nothing are exact at once: (S, r) = (0, 1)
+                if (lane == 0) {
+                    uint64_t m = mone;
+                    while (m) {
+                        int l = __ffsll((long long)m) - 1;
+                        m &= m - 1;
+                        int32_t vv = order_mode ? a.ov.ord[pos + l] : a.list[pos + l];
+                        topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, 0, 1, vv);
+                    }
+                }
+                r1 += __popcll(mone);
+                skipped += __popcll(msk);
+                int took = __popcll(me & ((cut_lane >= 64) ? ~0ull : ((1ull << cut_lane) - 1)));
+                int consumed = lim < cut_lane ? lim : cut_lane;
+                if (consumed > count - pos) consumed = count - pos;
+                nsel += took;
+                pos += consumed;
+                if (mst && lim < cut_lane) stop = 1;
+                if (r1) x = read_x(a.tk.st, a.tk.ring);
+            }
+            if (lane == 0) {
+                ctr[C_NSEL] = nsel;
+                ctr[C_POS] = pos;
+                ctr[C_STOP] = stop;
+                stats[ST_SKIPPED] += skipped;
+                stats[ST_STARTED] += r1;
+                stats[ST_EXACT] += r1;
+                if (stop) stats[ST_STOP] = 1;
+            }
+        }
+        grid.sync();
+        const int32_t nsel = (int32_t)ld_rlx(&ctr[C_NSEL]);
+        pos = (int32_t)ld_rlx(&ctr[C_POS]);
+        const bool stop_now = ld_rlx(&ctr[C_STOP]) != 0;
+        if (nsel == 0) break;
+
+        // ------------------------------------------------------ lane init
+        const XVal x = read_x(a.tk.st, a.tk.ring);
+        if (tid < MAXW) {
+            int l = tid;
+            if (l < nsel) {
+                int32_t v = a.w.cand[l];
+                s_v[l] = v;
+                s_a[l] = a.rc.alpha[v];
+                s_o[l] = a.rc.omega[v];
+                s_nD[l] = 1; s_SD[l] = 0;
+                s_U[l] = deg[v]; s_nf[l] = 1; s_mf[l] = deg[v];
+                s_st[l] = 1;
+                s_maxD[l] = 0;
+            } else {
+                s_st[l] = 0;
+            }
+        }
+        if (blockIdx.x == 0 && tid < nsel) {
+            int l = tid;
+            int32_t v = a.w.cand[l];
+            // a source list may name one vertex twice: atomic ORs
+            for_rlx(&vis[(int64_t)v * NW + (l >> 6)], (uint64_t)1 << (l & 63));
+            for_rlx(&a.w.frt0[(int64_t)v * NW + (l >> 6)], (uint64_t)1 << (l & 63));
+            if (a.lb_mode) { a.w.lvl[(int64_t)v * W + l] = 0; a.w.hist[l] = 1; }
+        }
+        if (boss) {
+            // level-0 frontier lists: sources split by degree
+            int64_t nl = 0, nh = 0;
+            for (int l = 0; l < nsel; l++) {
+                int32_t v = a.w.cand[l];
+                if (deg[v] > HEAVY_DEG) a.w.list[2 * (int64_t)n + nh++] = v;
+                else a.w.list[nl++] = v;
+            }
+            for (int p = 0; p < 3; p++) {
+                ctr[C_UCNT(p)] = 0; ctr[C_UDEG(p)] = 0; ctr[C_TL(p)] = 0; ctr[C_TH(p)] = 0;
+            }
+            ctr[C_TL(2)] = nl;     // "previous level" lists of level 0
+            ctr[C_TH(2)] = nh;
+            for (int p = 0; p < 3; p++)
+                for (int l = 0; l < MAXW; l++) { ctr[C_CNT(p, l)] = 0; ctr[C_DEG(p, l)] = 0; }
+        }
+        grid.sync();
+
+        int64_t D = 0;
+        int64_t fl_len = ld_rlx(&ctr[C_TL(2)]), fh_len = ld_rlx(&ctr[C_TH(2)]);
+        int64_t ucnt = nsel, udeg = 0;
+        for (int l = 0; l < nsel; l++) udeg += s_mf[l];
+        int64_t udisc = udeg;
+        bool bu = false;
+        int64_t mvis = 0, bytes = 0;
+        for (;;) {
+            // ------------------------------------ per-lane control (replicated)
+            if (tid < MAXW) {
+                int l = tid;
+                if (s_st[l] == 1) {
+                    if (s_nf[l] == 0) {
+                        s_st[l] = 2;
+                        s_maxD[l] = (int32_t)(D - 1);
+                    } else if (!a.lb_mode && !a.no_cut) {
+                        int64_t bn, bd;
+                        cut_bound(s_SD[l], s_nD[l], s_U[l], D, s_a[l], s_o[l], &bn, &bd);
+                        if (lex_after(bn, bd, s_v[l], x.num, x.den, x.id)) {
+                            s_st[l] = 3;
+                            s_maxD[l] = (int32_t)D;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (tid < 64 * NW) {
+                int l = tid;
+                uint64_t m = __ballot(s_st[l] == 1);
+                if (lane == 0) s_act[l >> 6] = m;
+            }
+            if (tid == 0) {
+                int64_t mv = 0;
+                for (int l = 0; l < nsel; l++) if (s_st[l] == 1) mv += s_mf[l];
+                s_scal[0] = mv;
+            }
+            __syncthreads();
+            Mask<NW> act;
+            bool any = false;
+#pragma unroll
+            for (int j = 0; j < NW; j++) { act.w[j] = s_act[j]; any |= act.w[j] != 0; }
+            if (!any) break;
+            mvis += s_scal[0];
+            // direction on the union frontier (Beamer's rule)
+            bool want_bu = bu ? (ucnt >= (int64_t)n / a.beta_bu)
+                              : (udeg > (a.g.m - udisc) / a.alpha_td && ucnt > 256);
+            bu = want_bu;
+            const int p = (int)(D % 3);
+            const int32_t* fl = a.w.list + (int64_t)(D & 1) * n;
+            const int32_t* fh = a.w.list + 2 * (int64_t)n + (int64_t)(D & 1) * n;
+            int32_t* nl = a.w.list + (int64_t)((D + 1) & 1) * n;
+            int32_t* nh = a.w.list + 2 * (int64_t)n + (int64_t)((D + 1) & 1) * n;
+            const uint64_t* fcur = (D & 1) ? a.w.frt1 : a.w.frt0;
+            uint64_t* fnxt = (D & 1) ? a.w.frt0 : a.w.frt1;
+            const int32_t stamp = (int32_t)(D + 1);
+            bytes += bu ? (int64_t)n * (8 * NW) : (fl_len + fh_len) * (8 + 8 * NW);
+            if (!bu) {
+                // push, light frontier vertices: one per lane
+                for (int64_t base = gwave * 64; base < fl_len; base += nwaves * 64) {
+                    int64_t i = base + lane;
+                    int32_t e = 0, end = 0;
+                    Mask<NW> f;
+#pragma unroll
+                    for (int j = 0; j < NW; j++) f.w[j] = 0;
+                    if (i < fl_len) {
+                        int32_t u = fl[i];
+#pragma unroll
+                        for (int j = 0; j < NW; j++) f.w[j] = fcur[(int64_t)u * NW + j] & act.w[j];
+                        if (f.any()) { e = rp[u]; end = rp[u + 1]; }
+                    }
+                    while (__any(e < end)) {
+                        bool isnew = false;
+                        int32_t w = 0, dw = 0;
+                        if (e < end) {
+                            w = ci[e]; e++;
+                            Mask<NW> nb;
+#pragma unroll
+                            for (int j = 0; j < NW; j++) nb.w[j] = f.w[j] & ~ld_rlx(&vis[(int64_t)w * NW + j]);
+                            if (nb.any() && push_lanes<NW>(a.w.nxt, a.mark, w, nb, stamp)) {
+                                isnew = true;
+                                dw = deg[w];
+                            }
+                        }
+                        list_append(isnew, w, dw, nl, nh, &ctr[C_TL(p)], &ctr[C_TH(p)]);
+                    }
+                }
+                // push, heavy frontier vertices: one per wave
+                for (int64_t hi = gwave; hi < fh_len; hi += nwaves) {
+                    int32_t u = fh[hi];
+                    Mask<NW> f;
+#pragma unroll
+                    for (int j = 0; j < NW; j++) f.w[j] = fcur[(int64_t)u * NW + j] & act.w[j];
+                    if (!f.any()) continue;
+                    int32_t b = rp[u], end = rp[u + 1];
+                    for (int32_t e0 = b; e0 < end; e0 += 64) {
+                        int32_t e = e0 + lane;
+                        bool isnew = false;
+                        int32_t w = 0, dw = 0;
+                        if (e < end) {
+                            w = ci[e];
+                            Mask<NW> nb;
+#pragma unroll
+                            for (int j = 0; j < NW; j++) nb.w[j] = f.w[j] & ~ld_rlx(&vis[(int64_t)w * NW + j]);
+                            if (nb.any() && push_lanes<NW>(a.w.nxt, a.mark, w, nb, stamp)) {
+                                isnew = true;
+                                dw = deg[w];
+                            }
+                        }
+                        list_append(isnew, w, dw, nl, nh, &ctr[C_TL(p)], &ctr[C_TH(p)]);
+                    }
+                }
+            } else {
+                // pull: vertices with unreached active lanes scan their in-arcs
+                for (int64_t base = gwave * 64; base < n; base += nwaves * 64) {
+                    int32_t w = (int32_t)(base + lane);
+                    bool isnew = false;
+                    int32_t dw = 0;
+                    if (w < n) {
+                        Mask<NW> miss, acc;
+                        bool need = false;
+#pragma unroll
+                        for (int j = 0; j < NW; j++) {
+                            miss.w[j] = act.w[j] & ~vis[(int64_t)w * NW + j];
+                            acc.w[j] = 0;
+                            need |= miss.w[j] != 0;
+                        }
+                        if (need) {
+                            for (int32_t e = a.g.rrp[w]; e < a.g.rrp[w + 1]; e++) {
+                                int32_t u = a.g.rci[e];
+                                bool full = true;
+#pragma unroll
+                                for (int j = 0; j < NW; j++) {
+                                    acc.w[j] |= fcur[(int64_t)u * NW + j] & miss.w[j];
+                                    full &= acc.w[j] == miss.w[j];
+                                }
+                                if (full) break;
+                            }
+                            if (acc.any()) {
+#pragma unroll
+                                for (int j = 0; j < NW; j++) a.w.nxt[(int64_t)w * NW + j] = acc.w[j];
+                                isnew = true;
+                                dw = deg[w];
+                            }
+                        }
+                    }
+                    list_append(isnew, w, dw, nl, nh, &ctr[C_TL(p)], &ctr[C_TH(p)]);
+                }
+            }
+            grid.sync();
+            // ------------------------------------------------------ epilogue
+            const int64_t nl_len = ld_rlx(&ctr[C_TL(p)]), nh_len = ld_rlx(&ctr[C_TH(p)]);
+            if (tid < MAXW) { s_red_cnt[tid] = 0; s_red_deg[tid] = 0; }
+            __syncthreads();
+            // old frontier words are cleared (the next level uses the other array)
+            uint64_t* fcur_w = (uint64_t*)fcur;
+            for (int64_t i = gtid; i < fl_len + fh_len; i += nthreads) {
+                int32_t u = i < fl_len ? fl[i] : fh[i - fl_len];
+#pragma unroll
+                for (int j = 0; j < NW; j++) fcur_w[(int64_t)u * NW + j] = 0;
+            }
+            int64_t my_u = 0, my_ud = 0;
+            for (int64_t base = gwave * 64; base < nl_len + nh_len; base += nwaves * 64) {
+                int64_t i = base + lane;
+                Mask<NW> nb;
+#pragma unroll
+                for (int j = 0; j < NW; j++) nb.w[j] = 0;
+                int32_t dw = 0;
+                if (i < nl_len + nh_len) {
+                    int32_t w = i < nl_len ? nl[i] : nh[i - nl_len];
+                    dw = deg[w];
+#pragma unroll
+                    for (int j = 0; j < NW; j++) {
+                        uint64_t b = a.w.nxt[(int64_t)w * NW + j];
+                        nb.w[j] = b;
+                        a.w.nxt[(int64_t)w * NW + j] = 0;
+                        vis[(int64_t)w * NW + j] |= b;
+                        fnxt[(int64_t)w * NW + j] = b;
+                    }
+                    if (a.lb_mode && D + 1 < a.w.lcap) {
+#pragma unroll
+                        for (int j = 0; j < NW; j++) {
+                            uint64_t m = nb.w[j];
+                            while (m) {
+                                int l = __ffsll((long long)m) - 1;
+                                m &= m - 1;
+                                a.w.lvl[(int64_t)w * W + j * 64 + l] = (uint16_t)(D + 1);
+                            }
+                        }
+                    }
+                    my_u += 1;
+                    my_ud += dw;
+                }
+                // per-lane counts: transpose the wave's bit matrix lane by lane
+#pragma unroll
+                for (int j = 0; j < NW; j++) {
+                    uint64_t lanes_here = wave_or_u64(nb.w[j]);
+                    while (lanes_here) {
+                        int l = __ffsll((long long)lanes_here) - 1;
+                        lanes_here &= lanes_here - 1;
+                        bool has = (nb.w[j] >> l) & 1ull;
+                        int c = __popcll(__ballot(has));
+                        int64_t d = wave_sum_i64(has ? (int64_t)dw : 0);
+                        if (lane == 0) {
+                            atomicAdd(&s_red_cnt[j * 64 + l], c);
+                            atomicAdd((unsigned long long*)&s_red_deg[j * 64 + l], (unsigned long long)d);
+                        }
+                    }
+                }
+            }
+            my_u = wave_sum_i64(my_u);
+            my_ud = wave_sum_i64(my_ud);
+            if (lane == 0 && my_u) {
+                fadd_rlx(&ctr[C_UCNT(p)], my_u);
+                fadd_rlx(&ctr[C_UDEG(p)], my_ud);
+            }
+            __syncthreads();
+            if (tid < W && s_red_cnt[tid]) {
+                fadd_rlx(&ctr[C_CNT(p, tid)], (int64_t)s_red_cnt[tid]);
+                fadd_rlx(&ctr[C_DEG(p, tid)], s_red_deg[tid]);
+            }
+            grid.sync();
+            // --------------------------------------------- advance lane state
+            if (tid < MAXW) {
+                int l = tid;
+                if (s_st[l] == 1) {
+                    int64_t c = ld_rlx(&ctr[C_CNT(p, l)]);
+                    int64_t d = ld_rlx(&ctr[C_DEG(p, l)]);
+                    s_nD[l] += c;
+                    s_SD[l] += (D + 1) * c;
+                    s_U[l] = dir ? d : d - c;
+                    s_nf[l] = c;
+                    s_mf[l] = d;
+                    if (a.lb_mode && blockIdx.x == 0) {
+                        if (D + 1 < a.w.lcap) a.w.hist[(D + 1) * W + l] = c;
+                    }
+                }
+            }
+            ucnt = ld_rlx(&ctr[C_UCNT(p)]);
+            udeg = ld_rlx(&ctr[C_UDEG(p)]);
+            udisc += udeg;
+            bytes += ucnt * 8 * (3 * NW) + (int64_t)nl_len * 4;
+            if (boss) {
+                int q = (int)((D + 2) % 3);
+                for (int l = 0; l < W; l++) { ctr[C_CNT(q, l)] = 0; ctr[C_DEG(q, l)] = 0; }
+                ctr[C_UCNT(q)] = 0; ctr[C_UDEG(q)] = 0; ctr[C_TL(q)] = 0; ctr[C_TH(q)] = 0;
+            }
+            fl_len = nl_len;
+            fh_len = nh_len;
+            D++;
+            __syncthreads();
+        }
+        // ----------------------------------------------------- batch results
+        if (boss) {
+            int64_t ex = 0, cu = 0, md = stats[ST_MAXLEVEL];
+            for (int l = 0; l < nsel; l++) {
+                if (s_maxD[l] > md) md = s_maxD[l];
+                if (s_st[l] == 2) {
+                    ex++;
+                    if (!a.no_cut)
+                        topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, s_SD[l], s_nD[l], s_v[l]);
+                } else if (s_st[l] == 3) cu++;
+            }
+            stats[ST_STARTED] += nsel;
+            stats[ST_EXACT] += ex;
+            stats[ST_CUT] += cu;
+            stats[ST_MVIS] += mvis;
+            stats[ST_BYTES] += bytes;
+            stats[ST_MAXLEVEL] = md;
+        }
+        if (a.no_cut && blockIdx.x == 0 && tid < nsel) {
+            a.out_S[pos - nsel + tid] = s_SD[tid];
+            a.out_r[pos - nsel + tid] = s_nD[tid];
+        }
+        if (a.lb_mode) {
+            // Lev tables per exact lane (thread per lane), then every vertex
+            // takes the best level bound over the lanes that reached it
+            // every level's counts and levels fit the tables (same value in
+            // every workgroup: D is replicated)
+            const bool lbok = D < a.w.lcap;
+            if (lbok) {
+                if (blockIdx.x == 0 && tid < nsel && s_st[tid] == 2) {
+                    int l = tid;
+                    int64_t maxD = s_maxD[l];
+                    int64_t r = s_nD[l];
+                    int64_t* lev = a.w.levtab;
+                    const int64_t* gam = a.w.hist;
+                    int64_t L = -2;
+                    for (int64_t j = 0; j <= maxD; j++) {
+                        int64_t t = j > 1 ? j - 1 : 1 - j;
+                        L += (t <= 1 ? 2 : t) * gam[j * W + l];
+                    }
+                    lev[1 * W + l] = L;
+                    int64_t pre = 0, low = 0;
+                    for (int64_t j = 0; j <= 2 && j <= maxD; j++) pre += gam[j * W + l];
+                    for (int64_t i = 2; i <= maxD; i++) {
+                        if (i + 1 <= maxD) pre += gam[(i + 1) * W + l];
+                        if (i - 3 >= 0) low += gam[(i - 3) * W + l];
+                        lev[i * W + l] = lev[(i - 1) * W + l] + (dir ? 0 : low) - (r - pre);
+                    }
+                }
+                grid.sync();
+                for (int64_t w = gtid; w < n; w += nthreads) {
+                    int64_t best = -1;
+                    int64_t bden = 0;
+#pragma unroll
+                    for (int j = 0; j < NW; j++) {
+                        uint64_t m = vis[w * NW + j];
+                        while (m) {
+                            int l = j * 64 + __ffsll((long long)m) - 1;
+                            m &= m - 1;
+                            if (l >= nsel || s_st[l] != 2 || s_v[l] == w) continue;
+                            if (dir && a.rc.scc[w] != a.rc.scc[s_v[l]]) continue;
+                            int64_t lv = a.w.lvl[w * W + l];
+                            int64_t b = a.w.levtab[lv * W + l];
+                            if (b > best) { best = b; bden = sq64(s_nD[l] - 1); }
+                        }
+                    }
+                    if (best >= 0) {
+                        int64_t b = best - deg[w];
+                        if (b < 0) b = 0;
+                        int64_t on = a.bv.num[w], od = a.bv.den[w];
+                        if (od != 0 && rat_cmp(b, bden, on, od) > 0) { a.bv.num[w] = b; a.bv.den[w] = bden; }
+                    }
+                }
+            }
+        }
+        grid.sync();
+        // clear the batch's words for the next batch
+        {
+            int64_t tot = (int64_t)n * NW;
+            for (int64_t q = gtid; q < tot; q += nthreads) {
+                vis[q] = 0;
+                a.w.frt0[q] = 0;
+                a.w.frt1[q] = 0;
+            }
+            if (NW > 1)
+                for (int64_t q = gtid; q < n; q += nthreads) a.mark[q] = 0;
+        }
+        grid.sync();
+        batches++;
+        if (stop_now) break;
+        if (a.until_x && ld_acq(&a.tk.st->seq) >= 0) break;
+    }
+    if (boss) stats[ST_CURSOR] = pos;
+}
+
+int tkc_launch_batch(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv, DevTopk tk,
+                     BatchWork w, int64_t* stats, const int32_t* list, int32_t list_count,
+                     int32_t start_pos, int32_t max_batches, bool lb_mode, bool no_cut,
+                     int64_t* out_S, int64_t* out_r, const EngineTuning& tune, hipStream_t s,
+                     int* grid_out) {
+    int W = tune.batch_width;
+    if (W != 32 && W != 64 && W != 128 && W != 256) return -2;
+    int NW = W <= 64 ? 1 : W / 64;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return -1;
+    const void* fn = NW == 1 ? (const void*)k_batch<1> : (NW == 2 ? (const void*)k_batch<2> : (const void*)k_batch<4>);
+    int occ = 0;
+    hipError_t e;
+    if (NW == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch<1>, BB, 0);
+    else if (NW == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch<2>, BB, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch<4>, BB, 0);
+    if (e != hipSuccess || occ < 1) return -1;
+    int per = occ < 2 ? occ : 2;
+    int grid = prop.multiProcessorCount * per;
+    if (grid_out) *grid_out = grid;
+    BatchArgs a;
+    a.g = g; a.rc = rc; a.ov = ov; a.bv = bv; a.tk = tk; a.w = w;
+    a.stats = stats; a.list = list; a.list_count = list_count;
+    a.start_pos = start_pos;
+    a.max_batches = max_batches > 0 ? max_batches : 0x7fffffff;
+    a.lb_mode = lb_mode ? 1 : 0;
+    a.no_cut = no_cut ? 1 : 0;
+    a.until_x = (max_batches == -1) ? 1 : 0;
+    if (max_batches == -1) a.max_batches = 0x7fffffff;
+    a.W = W;
+    a.alpha_td = tune.td_bu_alpha > 0 ? tune.td_bu_alpha : 14;
+    a.beta_bu = tune.bu_td_beta > 0 ? tune.bu_td_beta : 24;
+    a.out_S = out_S;
+    a.out_r = out_r;
+    a.mark = (int32_t*)w.touched;
+    void* args[] = {&a};
+    e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(BB), args, 0, s);
+    return e == hipSuccess ? 0 : -1;
+}

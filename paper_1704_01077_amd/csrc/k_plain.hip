@@ -1,0 +1,359 @@
+// Plain engine: the candidates of Alg. 1 are searched one at a time, each
+// search spread over the whole GPU.  One cooperative (persistent) launch
+// walks the candidate order; every level of a search is one grid-wide phase
+// followed by a grid barrier, so there is no host round trip per level.
+//
+// Per search (updateBoundsBFSCut, Sect. 6, or updateBoundsLB, Sect. 7):
+//   - level-synchronous BFS; push steps expand the frontier queue (light
+//     vertices one per lane, heavy vertices one per wave), pull steps scan
+//     the unvisited vertices' in-arcs against a frontier bitmap (Beamer's
+//     direction switch);
+//   - after each level the exact counts n_D, S_D and the out-degree sum U of
+//     the level give the BFSCut bound, checked against the current k-th
+//     farness x in the exact (farness, id) order;
+//   - Bound variants search to the end and then raise the bounds of every
+//     reached vertex with the level-based bound (Eq. 4 / Eq. 5).
+// Control decisions are computed redundantly by every thread from values
+// read after a barrier, so all workgroups take the same path.
+#include <hip/hip_cooperative_groups.h>
+
+#include "dev_common.hpp"
+#include "engine.hpp"
+
+namespace cg = cooperative_groups;
+
+#define HEAVY_DEG 64
+#define PB 256
+
+struct PlainArgs {
+    DevGraph g;
+    DevReach rc;
+    OrderView ov;
+    BoundsView bv;
+    DevTopk tk;
+    PlainWork w;
+    int64_t* stats;
+    const int32_t* list;
+    int32_t list_count;
+    int32_t lb_mode;
+    int32_t alpha_td;
+    int32_t beta_bu;
+};
+
+TKC_DEV int64_t shfl64(int64_t v, int src) {
+    int32_t lo = __shfl((int32_t)(v & 0xffffffff), src, 64);
+    int32_t hi = __shfl((int32_t)(v >> 32), src, 64);
+    return ((int64_t)hi << 32) | (uint32_t)lo;
+}
+TKC_DEV uint64_t lanes_below() {
+    int l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// wave-aggregated append of newly found vertices to the light/heavy queues;
+// the level's appends count from zero in its own counters (cnts[0] light,
+// cnts[1] heavy) on top of the segment ends lbase / hbase, so the queue ends
+// every workgroup reads after the barrier never move under it
+TKC_DEV void q_append(bool isnew, int32_t w, int32_t dw, int32_t* ql, int32_t* qh, int64_t* cnts,
+                      int64_t lbase, int64_t hbase) {
+    bool hv = isnew && dw > HEAVY_DEG;
+    bool lt = isnew && !hv;
+    uint64_t ml = __ballot(lt), mh = __ballot(hv);
+    if ((ml | mh) == 0) return;
+    int leader = __ffsll((long long)__ballot(1)) - 1;
+    int64_t bl = 0, bh = 0;
+    if (lane_id() == leader) {
+        if (ml) bl = fadd_rlx(&cnts[0], (int64_t)__popcll(ml));
+        if (mh) bh = fadd_rlx(&cnts[1], (int64_t)__popcll(mh));
+    }
+    bl = shfl64(bl, leader) + lbase;
+    bh = shfl64(bh, leader) + hbase;
+    uint64_t below = lanes_below();
+    if (lt) ql[bl + __popcll(ml & below)] = w;
+    if (hv) qh[bh + __popcll(mh & below)] = w;
+}
+
+// test-and-set of a visited bit; true for the single caller that sets it
+TKC_DEV bool visit(uint32_t* vis, int32_t w) {
+    uint32_t bit = 1u << (w & 31);
+    if (ld_rlx(&vis[w >> 5]) & bit) return false;
+    uint32_t old = for_rlx(&vis[w >> 5], bit);
+    return !(old & bit);
+}
+
+// level table of the level-based bound from per-level counts gamma_0..maxD
+// (gamma_0 = 1 counts the source): Lev(1) from the definition, then the
+// recurrence of Lemma 7.2 (undirected) or its one-sided form for Eq. 5.
+TKC_DEV void lev_table(const int64_t* gam, int64_t maxD, int64_t r, bool directed, int64_t* lev) {
+    int64_t L = -2;
+    for (int64_t j = 0; j <= maxD; j++) {
+        int64_t t = j > 1 ? j - 1 : 1 - j;
+        L += (t <= 1 ? 2 : t) * gam[j];
+    }
+    lev[1] = L;
+    int64_t pre = 0;   // sum of gamma_j for j <= i+1, maintained incrementally
+    for (int64_t j = 0; j <= 2 && j <= maxD; j++) pre += gam[j];
+    int64_t low = 0;   // sum of gamma_j for j < i-2
+    for (int64_t i = 2; i <= maxD; i++) {
+        if (i + 1 <= maxD) pre += gam[i + 1];
+        if (i - 3 >= 0) low += gam[i - 3];
+        int64_t high = r - pre;   // sum_{j > i+1} gamma_j
+        lev[i] = lev[i - 1] + (directed ? 0 : low) - high;
+    }
+}
+
+__global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
+    cg::grid_group grid = cg::this_grid();
+    const int32_t n = a.g.n;
+    const bool dir = a.g.directed;
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nwaves = nthreads / 64;
+    const int64_t gwave = gtid / 64;
+    const int lane = lane_id();
+    const bool boss = (blockIdx.x == 0 && threadIdx.x == 0);
+    const int32_t* __restrict__ rp = a.g.rp;
+    const int32_t* __restrict__ ci = a.g.ci;
+    const int32_t* __restrict__ deg = a.g.deg;
+    // ctr[p*4 + 0..3], p = level % 3: vertices found, their degree sum,
+    // light and heavy queue appends of that level
+    int64_t* ctr = a.w.ctr;
+    uint32_t* vis = a.w.vis;
+    const int64_t words = ((int64_t)n + 31) / 32;
+    const int32_t count = a.list ? a.list_count : a.ov.count;
+    int64_t* stats = a.stats;
+
+    int32_t pos;
+    for (pos = 0; pos < count; pos++) {
+        const int32_t v = a.list ? a.list[pos] : a.ov.ord[pos];
+        const XVal x = read_x(a.tk.st, a.tk.ring);
+        if (!a.list) {
+            uint32_t key = a.ov.key[pos];
+            bool stop = a.ov.key_is_bound ? key_stops(key, x) : (key == 0xffffffffu && x.den != 0);
+            if (stop) {
+                if (boss) stats[ST_STOP] = 1;
+                break;
+            }
+        }
+        if (lex_after(a.bv.num[v], a.bv.den[v], v, x.num, x.den, x.id)) {
+            if (boss) stats[ST_SKIPPED]++;
+            continue;
+        }
+        const int64_t av = a.rc.alpha[v], ov = a.rc.omega[v];
+        if (ov <= 1) {   // reaches nothing: S = 0, r = 1, farness +inf
+            if (boss) {
+                stats[ST_STARTED]++;
+                stats[ST_EXACT]++;
+                topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, 0, 1, v);
+            }
+            grid.sync();
+            continue;
+        }
+        const int64_t dv = deg[v];
+        if (boss) {
+            for (int q = 0; q < 12; q++) ctr[q] = 0;
+            for_rlx(&vis[v >> 5], 1u << (v & 31));
+            if (dv > HEAVY_DEG) a.w.qh[0] = v;
+            else a.w.ql[0] = v;
+            if (a.lb_mode) { a.w.lvl[v] = 0; a.w.levcnt[0] = 1; }
+        }
+        grid.sync();
+
+        int64_t D = 0, nD = 1, SD = 0;
+        int64_t U = dv, mf = dv, nf = 1, mdisc = dv;
+        int64_t ls = 0, le = dv > HEAVY_DEG ? 0 : 1, hs = 0, he = dv > HEAVY_DEG ? 1 : 0;
+        bool bu = false, used_bu = false;
+        int status = 0;   // 1 exact, 2 cut
+        int64_t mvis = 0, bytes = 0;
+        for (;;) {
+            if (nf == 0) { status = 1; break; }
+            if (!a.lb_mode) {
+                int64_t bn, bd;
+                cut_bound(SD, nD, U, D, av, ov, &bn, &bd);
+                if (lex_after(bn, bd, v, x.num, x.den, x.id)) { status = 2; break; }
+            }
+            // direction (Beamer): pull when the frontier's arcs outweigh the
+            // unexplored ones, push again once the frontier is small
+            bool want_bu = bu ? (nf >= (int64_t)n / a.beta_bu)
+                              : (mf > (a.g.m - mdisc) / a.alpha_td && nf > 64);
+            if (want_bu && !bu) {
+                // frontier bitmap of level D from the queue segments
+                for (int64_t q = gtid; q < 3 * words; q += nthreads) a.w.fb[q] = 0;
+                grid.sync();
+                uint32_t* fcur = a.w.fb + (D % 3) * words;
+                for (int64_t i = gtid; i < le - ls; i += nthreads) {
+                    int32_t u = a.w.ql[ls + i];
+                    for_rlx(&fcur[u >> 5], 1u << (u & 31));
+                }
+                for (int64_t i = gtid; i < he - hs; i += nthreads) {
+                    int32_t u = a.w.qh[hs + i];
+                    for_rlx(&fcur[u >> 5], 1u << (u & 31));
+                }
+                grid.sync();
+                used_bu = true;
+            }
+            bu = want_bu;
+            mvis += mf;
+            bytes += 8 * mf + 12 * nf;
+            const int p = (int)(D % 3);
+            int64_t my_cnt = 0, my_deg = 0;
+            if (!bu) {
+                // push: light frontier vertices, one per lane
+                for (int64_t base = gwave * 64; base < le - ls; base += nwaves * 64) {
+                    int64_t i = base + lane;
+                    int32_t e = 0, end = 0;
+                    if (i < le - ls) {
+                        int32_t u = a.w.ql[ls + i];
+                        e = rp[u]; end = rp[u + 1];
+                    }
+                    while (__any(e < end)) {
+                        bool isnew = false;
+                        int32_t w = 0, dw = 0;
+                        if (e < end) {
+                            w = ci[e]; e++;
+                            if (visit(vis, w)) { isnew = true; dw = deg[w]; }
+                        }
+                        if (isnew) {
+                            my_cnt++; my_deg += dw;
+                            if (a.lb_mode) a.w.lvl[w] = (int32_t)(D + 1);
+                        }
+                        q_append(isnew, w, dw, a.w.ql, a.w.qh, &ctr[p * 4 + 2], le, he);
+                    }
+                }
+                // push: heavy frontier vertices, one per wave
+                for (int64_t hi = gwave; hi < he - hs; hi += nwaves) {
+                    int32_t u = a.w.qh[hs + hi];
+                    int32_t b = rp[u], end = rp[u + 1];
+                    for (int32_t e0 = b; e0 < end; e0 += 64) {
+                        int32_t e = e0 + lane;
+                        bool isnew = false;
+                        int32_t w = 0, dw = 0;
+                        if (e < end) {
+                            w = ci[e];
+                            if (visit(vis, w)) { isnew = true; dw = deg[w]; }
+                        }
+                        if (isnew) {
+                            my_cnt++; my_deg += dw;
+                            if (a.lb_mode) a.w.lvl[w] = (int32_t)(D + 1);
+                        }
+                        q_append(isnew, w, dw, a.w.ql, a.w.qh, &ctr[p * 4 + 2], le, he);
+                    }
+                }
+            } else {
+                // pull: every unvisited vertex looks for an in-neighbour in the frontier
+                const uint32_t* fcur = a.w.fb + (D % 3) * words;
+                uint32_t* fnxt = a.w.fb + ((D + 1) % 3) * words;
+                uint32_t* fold = a.w.fb + ((D + 2) % 3) * words;
+                for (int64_t q = gtid; q < words; q += nthreads) fold[q] = 0;
+                for (int64_t base = gwave * 64; base < n; base += nwaves * 64) {
+                    int32_t w = (int32_t)(base + lane);
+                    bool isnew = false;
+                    int32_t dw = 0;
+                    if (w < n && !(ld_rlx(&vis[w >> 5]) & (1u << (w & 31)))) {
+                        for (int32_t e = a.g.rrp[w]; e < a.g.rrp[w + 1]; e++) {
+                            int32_t u = a.g.rci[e];
+                            if (fcur[u >> 5] & (1u << (u & 31))) { isnew = true; break; }
+                        }
+                        if (isnew) {
+                            for_rlx(&vis[w >> 5], 1u << (w & 31));
+                            for_rlx(&fnxt[w >> 5], 1u << (w & 31));
+                            dw = deg[w];
+                            my_cnt++; my_deg += dw;
+                            if (a.lb_mode) a.w.lvl[w] = (int32_t)(D + 1);
+                        }
+                    }
+                    q_append(isnew, w, dw, a.w.ql, a.w.qh, &ctr[p * 4 + 2], le, he);
+                }
+            }
+            my_cnt = wave_sum_i64(my_cnt);
+            my_deg = wave_sum_i64(my_deg);
+            if (lane == 0 && (my_cnt | my_deg)) {
+                fadd_rlx(&ctr[p * 4 + 0], my_cnt);
+                fadd_rlx(&ctr[p * 4 + 1], my_deg);
+            }
+            grid.sync();
+            const int64_t cnt = ld_rlx(&ctr[p * 4 + 0]);
+            const int64_t dsum = ld_rlx(&ctr[p * 4 + 1]);
+            const int64_t tl = le + ld_rlx(&ctr[p * 4 + 2]), th = he + ld_rlx(&ctr[p * 4 + 3]);
+            if (boss) {
+                int q = (int)((D + 2) % 3);
+                for (int j = 0; j < 4; j++) ctr[q * 4 + j] = 0;
+            }
+            D++;
+            nD += cnt;
+            SD += D * cnt;
+            U = dir ? dsum : dsum - cnt;
+            mf = dsum;
+            nf = cnt;
+            mdisc += dsum;
+            bytes += 16 * cnt;
+            ls = le; le = tl; hs = he; he = th;
+            if (a.lb_mode && boss) a.w.levcnt[D] = cnt;
+        }
+        const int64_t maxD = D - (status == 1 ? 1 : 0);
+        if (a.lb_mode && status == 1) {
+            // level-based update of every reached vertex (Sect. 7)
+            if (boss) {
+                a.w.levcnt[D] = 0;
+                lev_table(a.w.levcnt, maxD, nD, dir, a.w.levtab);
+            }
+            grid.sync();
+            const int64_t den = sq64(nD - 1);
+            const int32_t sc = dir ? a.rc.scc[v] : 0;
+            for (int64_t i = gtid; i < le + he; i += nthreads) {
+                int32_t w = i < le ? a.w.ql[i] : a.w.qh[i - le];
+                if (w == v) continue;
+                if (dir && a.rc.scc[w] != sc) continue;
+                int64_t b = a.w.levtab[a.w.lvl[w]] - deg[w];
+                if (b < 0) b = 0;
+                int64_t on = a.bv.num[w], od = a.bv.den[w];
+                if (od != 0 && rat_cmp(b, den, on, od) > 0) { a.bv.num[w] = b; a.bv.den[w] = den; }
+            }
+        }
+        // clear the visited bits of every reached vertex
+        for (int64_t i = gtid; i < le + he; i += nthreads) {
+            int32_t w = i < le ? a.w.ql[i] : a.w.qh[i - le];
+            vis[w >> 5] = 0;
+        }
+        if (used_bu)
+            for (int64_t q = gtid; q < 3 * words; q += nthreads) a.w.fb[q] = 0;
+        if (boss) {
+            stats[ST_STARTED]++;
+            stats[ST_MVIS] += mvis;
+            stats[ST_BYTES] += bytes;
+            if (maxD > stats[ST_MAXLEVEL]) stats[ST_MAXLEVEL] = maxD;
+            if (status == 1) {
+                stats[ST_EXACT]++;
+                topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, SD, nD, v);
+            } else {
+                stats[ST_CUT]++;
+            }
+        }
+        grid.sync();
+    }
+    if (boss) stats[ST_CURSOR] = pos;
+}
+
+int tkc_launch_plain(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv, DevTopk tk,
+                     PlainWork w, int64_t* stats, const int32_t* list, int32_t list_count,
+                     bool lb_mode, const EngineTuning& tune, hipStream_t s, int* grid_out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return -1;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_plain, PB, 0) != hipSuccess) return -1;
+    if (occ < 1) return -1;
+    int per = occ < 2 ? occ : 2;
+    int grid = prop.multiProcessorCount * per;
+    if (grid_out) *grid_out = grid;
+    PlainArgs a;
+    a.g = g; a.rc = rc; a.ov = ov; a.bv = bv; a.tk = tk; a.w = w;
+    a.stats = stats; a.list = list; a.list_count = list_count;
+    a.lb_mode = lb_mode ? 1 : 0;
+    a.alpha_td = tune.td_bu_alpha > 0 ? tune.td_bu_alpha : 14;
+    a.beta_bu = tune.bu_td_beta > 0 ? tune.bu_td_beta : 24;
+    void* args[] = {&a};
+    hipError_t e = hipLaunchCooperativeKernel((const void*)k_plain, dim3(grid), dim3(PB), args, 0, s);
+    return e == hipSuccess ? 0 : -1;
+}

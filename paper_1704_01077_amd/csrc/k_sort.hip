@@ -1,0 +1,195 @@
+// Stable LSD radix sort of (uint32 key, int32 value) pairs, 4-bit digits.
+// Used once per query to lay out the processing order of Alg. 1 (values
+// start as vertex ids, so equal keys keep ascending ids).  Digits on which
+// all keys agree are skipped.
+#include "dev_common.hpp"
+#include "engine.hpp"
+
+#define RS_THREADS 256
+#define RS_ITEMS 8
+#define RS_TILE (RS_THREADS * RS_ITEMS)
+#define RS_DIG 16
+
+static inline int rs_tiles(int32_t n) { return (n + RS_TILE - 1) / RS_TILE; }
+
+__global__ void k_rs_mask(const uint32_t* __restrict__ keys, int32_t n, uint32_t* mask) {
+    // mask[0] = OR of keys, mask[1] = AND of keys
+    uint32_t o = 0, a = 0xffffffffu;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        uint32_t k = keys[i];
+        o |= k; a &= k;
+    }
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) {
+        o |= __shfl_xor(o, s, 64);
+        a &= __shfl_xor(a, s, 64);
+    }
+    if (lane_id() == 0) {
+        __hip_atomic_fetch_or(&mask[0], o, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_and(&mask[1], a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// per-tile digit counts, stored digit-major: cnt[d * tiles + tile]
+__global__ void __launch_bounds__(RS_THREADS) k_rs_count(const uint32_t* __restrict__ keys, int32_t n,
+                                                          int shift, int32_t* cnt, int32_t tiles) {
+    __shared__ int32_t part[RS_THREADS / 64][RS_DIG];
+    int32_t base = blockIdx.x * RS_TILE + threadIdx.x * RS_ITEMS;
+    int32_t c[RS_DIG];
+#pragma unroll
+    for (int d = 0; d < RS_DIG; d++) c[d] = 0;
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; j++) {
+        int32_t i = base + j;
+        if (i < n) {
+            uint32_t dg = (keys[i] >> shift) & 15u;
+#pragma unroll
+            for (int d = 0; d < RS_DIG; d++) c[d] += (dg == (uint32_t)d);
+        }
+    }
+    int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 0; d < RS_DIG; d++) {
+        int32_t s = wave_sum_i32(c[d]);
+        if (lane_id() == 0) part[wv][d] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < RS_DIG) {
+        int32_t s = 0;
+        for (int w = 0; w < RS_THREADS / 64; w++) s += part[w][threadIdx.x];
+        cnt[threadIdx.x * tiles + blockIdx.x] = s;
+    }
+}
+
+// exclusive scan of `len` int32 in place, one workgroup of 1024 threads
+__global__ void __launch_bounds__(1024) k_rs_scan(int32_t* a, int32_t len) {
+    __shared__ int32_t wsum[16];
+    int32_t per = (len + 1023) / 1024;
+    int32_t lo = threadIdx.x * per;
+    int32_t hi = lo + per < len ? lo + per : len;
+    int32_t s = 0;
+    for (int32_t i = lo; i < hi; i++) s += a[i];
+    // block exclusive scan of s
+    int32_t x = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int32_t y = __shfl_up(x, o, 64);
+        if (lane_id() >= o) x += y;
+    }
+    int wv = threadIdx.x >> 6;
+    if (lane_id() == 63) wsum[wv] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int w = 0; w < 16; w++) { int32_t t = wsum[w]; wsum[w] = run; run += t; }
+    }
+    __syncthreads();
+    int32_t run = wsum[wv] + x - s;
+    for (int32_t i = lo; i < hi; i++) { int32_t t = a[i]; a[i] = run; run += t; }
+}
+
+__global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint32_t* __restrict__ keys,
+                                                            const int32_t* __restrict__ vals, int32_t n,
+                                                            int shift, const int32_t* __restrict__ off,
+                                                            int32_t tiles, uint32_t* __restrict__ okeys,
+                                                            int32_t* __restrict__ ovals) {
+    __shared__ int32_t cs[RS_DIG * RS_THREADS];   // [digit][thread]
+    __shared__ int32_t wtot[RS_THREADS / 64];
+    __shared__ int32_t dstart[RS_DIG];
+    int32_t base = blockIdx.x * RS_TILE + threadIdx.x * RS_ITEMS;
+    uint32_t k[RS_ITEMS];
+    int32_t v[RS_ITEMS];
+    uint32_t dg[RS_ITEMS];
+    int32_t c[RS_DIG];
+#pragma unroll
+    for (int d = 0; d < RS_DIG; d++) c[d] = 0;
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; j++) {
+        int32_t i = base + j;
+        if (i < n) {
+            k[j] = keys[i]; v[j] = vals[i];
+            dg[j] = (k[j] >> shift) & 15u;
+        } else {
+            dg[j] = RS_DIG;
+        }
+#pragma unroll
+        for (int d = 0; d < RS_DIG; d++) c[d] += (dg[j] == (uint32_t)d);
+    }
+#pragma unroll
+    for (int d = 0; d < RS_DIG; d++) cs[d * RS_THREADS + threadIdx.x] = c[d];
+    __syncthreads();
+    // exclusive scan over the 4096 entries in digit-major order: thread t
+    // owns 16 consecutive entries
+    int32_t loc[16];
+    int32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < 16; q++) { loc[q] = cs[threadIdx.x * 16 + q]; s += loc[q]; }
+    int32_t x = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int32_t y = __shfl_up(x, o, 64);
+        if (lane_id() >= o) x += y;
+    }
+    int wv = threadIdx.x >> 6;
+    if (lane_id() == 63) wtot[wv] = x;
+    __syncthreads();
+    int32_t run = x - s;
+    for (int w = 0; w < wv; w++) run += wtot[w];
+#pragma unroll
+    for (int q = 0; q < 16; q++) { int32_t t = loc[q]; cs[threadIdx.x * 16 + q] = run; run += t; }
+    __syncthreads();
+    if (threadIdx.x < RS_DIG) dstart[threadIdx.x] = cs[threadIdx.x * RS_THREADS];
+    __syncthreads();
+    int32_t seen[RS_DIG];
+#pragma unroll
+    for (int d = 0; d < RS_DIG; d++) seen[d] = 0;
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; j++) {
+        uint32_t d = dg[j];
+        if (d < RS_DIG) {
+            int32_t rank = 0, pre = 0, st = 0;
+#pragma unroll
+            for (int e = 0; e < RS_DIG; e++) {
+                if ((uint32_t)e == d) { rank = seen[e]; seen[e]++; }
+            }
+            pre = cs[d * RS_THREADS + threadIdx.x];
+            st = dstart[d];
+            int32_t pos = off[d * tiles + blockIdx.x] + (pre - st) + rank;
+            okeys[pos] = k[j];
+            ovals[pos] = v[j];
+        }
+    }
+}
+
+int64_t tkc_sort_hist_words(int32_t n) { return (int64_t)RS_DIG * rs_tiles(n > 0 ? n : 1) + 16; }
+
+int tkc_sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* tmp_keys, int32_t* tmp_vals, int32_t n,
+                   int32_t* hist, uint32_t* mask_dev, uint32_t* mask_host, hipStream_t s) {
+    if (n <= 1) return 0;
+    uint32_t init[2] = {0u, 0xffffffffu};
+    if (hipMemcpyAsync(mask_dev, init, sizeof(init), hipMemcpyHostToDevice, s) != hipSuccess) return -1;
+    int gb = rs_tiles(n);
+    if (gb > 1024) gb = 1024;
+    hipLaunchKernelGGL(k_rs_mask, dim3(gb), dim3(256), 0, s, keys, n, mask_dev);
+    if (hipMemcpyAsync(mask_host, mask_dev, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return -1;
+    if (hipStreamSynchronize(s) != hipSuccess) return -1;
+    uint32_t vary = mask_host[0] ^ mask_host[1];
+    int tiles = rs_tiles(n);
+    uint32_t* ka = keys; int32_t* va = vals;
+    uint32_t* kb = tmp_keys; int32_t* vb = tmp_vals;
+    for (int shift = 0; shift < 32; shift += 4) {
+        if (((vary >> shift) & 15u) == 0) continue;
+        hipLaunchKernelGGL(k_rs_count, dim3(tiles), dim3(RS_THREADS), 0, s, ka, n, shift, hist, tiles);
+        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, s, hist, RS_DIG * tiles);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(tiles), dim3(RS_THREADS), 0, s, ka, va, n, shift, hist,
+                           tiles, kb, vb);
+        uint32_t* tk = ka; ka = kb; kb = tk;
+        int32_t* tv = va; va = vb; vb = tv;
+    }
+    if (ka != keys) {
+        hipMemcpyAsync(keys, ka, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, s);
+        hipMemcpyAsync(vals, va, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}

@@ -1,0 +1,266 @@
+// Serving loop: graphs stay resident on the device and top-k requests are
+// admitted as they arrive.  The server owns `max_inflight` slots; each slot
+// is a worker thread with its own HIP stream and query workspace, so the
+// device work of requests in different slots overlaps (continuous batching:
+// a request that arrives while others run starts as soon as a slot and
+// memory are free, it does not wait for the running ones to finish).
+//   - Admission: a request needs its slot's workspace grown to the request's
+//     shape; the sum of all slot workspaces must stay within the HBM budget.
+//     A request that could never fit is refused at submission (TKC_EBUSY).
+//   - Per-graph preprocessing (reachability, initial bounds, order) is
+//     computed by the first request on a graph and reused by later ones.
+//   - Cooperative (grid-barrier) kernels of different slots never overlap:
+//     they take a process-wide lock, while ordinary kernels run freely.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "../../include/tkc.h"
+#include "internal.hpp"
+
+namespace {
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+    uint64_t ticket = 0;
+    int32_t graph_id = 0;
+    int32_t k = 1;
+    int32_t variant = TKC_AUTO;
+    double t_submit = 0, t_done = 0;
+    int state = 0;          // 0 queued, 1 running, 2 done
+    bool cancelled = false;
+    int status = TKC_OK;
+    std::string err;
+    std::vector<int32_t> ids;
+    std::vector<int64_t> S, R;
+    std::vector<double> F;
+    size_t need = 0;        // workspace bytes this request needs
+};
+
+}  // namespace
+
+struct tkc_server {
+    tkc_ctx* ctx = nullptr;
+    size_t budget = 0;
+    int32_t slots_n = 0;
+    std::vector<tkc_graph*> graphs;
+    std::vector<tkc_ctx*> slot_ctx;
+    std::vector<size_t> slot_bytes;
+    std::vector<std::thread> workers;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::shared_ptr<Request>> queue;
+    std::map<uint64_t, std::shared_ptr<Request>> all;
+    uint64_t next_ticket = 1;
+    bool stopping = false;
+
+    size_t committed_except(int slot) {
+        size_t t = 0;
+        for (int i = 0; i < slots_n; i++)
+            if (i != slot) t += slot_bytes[i];
+        return t;
+    }
+
+    void worker(int slot) {
+        tkc_ctx* c = slot_ctx[slot];
+        hipSetDevice(c->device);
+        for (;;) {
+            std::shared_ptr<Request> rq;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                for (;;) {
+                    if (stopping) return;
+                    // first queued request whose workspace fits next to the others
+                    for (auto it = queue.begin(); it != queue.end(); ++it) {
+                        size_t need = std::max((*it)->need, slot_bytes[slot]);
+                        if (committed_except(slot) + need <= budget) {
+                            rq = *it;
+                            queue.erase(it);
+                            slot_bytes[slot] = need;
+                            break;
+                        }
+                    }
+                    if (rq) break;
+                    if (!queue.empty() && slot_bytes[slot] > 0) {
+                        // nothing fits next to the other slots: give this idle
+                        // slot's workspace back so a waiting request can run
+                        if (c->ws.base) {
+                            hipStreamSynchronize(c->stream);
+                            hipFree(c->ws.base);
+                            c->ws.base = nullptr;
+                            c->ws.bytes = 0;
+                            c->ws.shape = WsShape();
+                        }
+                        slot_bytes[slot] = 0;
+                        cv_work.notify_all();
+                        continue;
+                    }
+                    cv_work.wait(lk);
+                }
+                rq->state = 1;
+            }
+            tkc_graph* g = graphs[rq->graph_id];
+            int32_t k = std::min(rq->k, g->n);
+            rq->ids.resize(k);
+            rq->S.resize(k);
+            rq->R.resize(k);
+            rq->F.resize(k);
+            int32_t got = 0;
+            int st = TKC_OK;
+            if (!rq->cancelled)
+                st = tkc_run_query(c, g, k, rq->variant, TKC_HYBRID, rq->ids.data(), rq->S.data(), rq->R.data(),
+                                   rq->F.data(), &got, nullptr);
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                rq->status = rq->cancelled ? TKC_ECANCELED : st;
+                if (st != TKC_OK) rq->err = tkc_last_error();
+                rq->t_done = now_ms();
+                rq->state = 2;
+                slot_bytes[slot] = c->ws.bytes;
+            }
+            cv_done.notify_all();
+            cv_work.notify_all();
+        }
+    }
+};
+
+extern "C" int tkc_server_create(tkc_ctx* ctx, size_t hbm_budget_bytes, int32_t max_inflight, tkc_server** out) {
+    if (!ctx || !out) return tkc_fail(TKC_EINVAL, "NULL argument");
+    if (max_inflight < 1 || max_inflight > 64) return tkc_fail(TKC_EINVAL, "max_inflight must be in [1, 64]");
+    if (hbm_budget_bytes == 0) return tkc_fail(TKC_EINVAL, "hbm budget must be > 0");
+    tkc_server* s = new tkc_server();
+    s->ctx = ctx;
+    s->budget = hbm_budget_bytes;
+    s->slots_n = max_inflight;
+    for (int i = 0; i < max_inflight; i++) {
+        tkc_ctx* c = nullptr;
+        int rc = tkc_ctx_create(ctx->device, nullptr, &c);
+        if (rc) {
+            for (auto* cc : s->slot_ctx) tkc_ctx_destroy(cc);
+            delete s;
+            return rc;
+        }
+        c->tune = ctx->tune;
+        s->slot_ctx.push_back(c);
+        s->slot_bytes.push_back(0);
+    }
+    for (int i = 0; i < max_inflight; i++) s->workers.emplace_back(&tkc_server::worker, s, i);
+    *out = s;
+    return TKC_OK;
+}
+
+extern "C" int tkc_server_add_graph(tkc_server* s, tkc_graph* g, int32_t* graph_id) {
+    if (!s || !g || !graph_id) return tkc_fail(TKC_EINVAL, "NULL argument");
+    if (g->ctx->device != s->ctx->device) return tkc_fail(TKC_EINVAL, "graph lives on another device");
+    std::lock_guard<std::mutex> lk(s->mu);
+    {
+        std::lock_guard<std::mutex> gl(g->mu);
+        g->server_refs++;
+        g->cache_prep = true;
+    }
+    s->graphs.push_back(g);
+    *graph_id = (int32_t)s->graphs.size() - 1;
+    return TKC_OK;
+}
+
+extern "C" int tkc_server_submit(tkc_server* s, int32_t graph_id, int32_t k, int32_t variant, uint64_t* ticket) {
+    if (!s || !ticket) return tkc_fail(TKC_EINVAL, "NULL argument");
+    if (k < 1) return tkc_fail(TKC_EINVAL, "k must be >= 1");
+    if (variant < TKC_AUTO || variant > TKC_NB_BOUND) return tkc_fail(TKC_EINVAL, "unknown variant");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (graph_id < 0 || graph_id >= (int32_t)s->graphs.size()) return tkc_fail(TKC_EINVAL, "unknown graph id");
+    tkc_graph* g = s->graphs[graph_id];
+    auto rq = std::make_shared<Request>();
+    rq->ticket = s->next_ticket++;
+    rq->graph_id = graph_id;
+    rq->k = k;
+    rq->variant = variant;
+    rq->t_submit = now_ms();
+    bool lb = (variant == TKC_DEG_BOUND || variant == TKC_NB_BOUND || variant == TKC_AUTO);
+    rq->need = tkc_ws_bytes(tkc_shape_for(s->ctx, g, std::min(k, g->n), lb));
+    if (rq->need > s->budget) return tkc_fail(TKC_EBUSY, "request needs %zu bytes, budget is %zu", rq->need, s->budget);
+    s->queue.push_back(rq);
+    s->all[rq->ticket] = rq;
+    *ticket = rq->ticket;
+    s->cv_work.notify_all();
+    return TKC_OK;
+}
+
+extern "C" int tkc_server_poll(tkc_server* s, uint64_t ticket, int32_t* done) {
+    if (!s || !done) return tkc_fail(TKC_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return tkc_fail(TKC_EINVAL, "unknown ticket");
+    *done = it->second->state == 2 ? 1 : 0;
+    return TKC_OK;
+}
+
+extern "C" int tkc_server_result(tkc_server* s, uint64_t ticket, int32_t* ids, int64_t* sum_dist, int64_t* reach,
+                                 double* farness, int32_t* n_out, double* latency_ms) {
+    if (!s || !ids || !n_out) return tkc_fail(TKC_EINVAL, "NULL argument");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return tkc_fail(TKC_EINVAL, "unknown ticket");
+    std::shared_ptr<Request> rq = it->second;
+    s->cv_done.wait(lk, [&] { return rq->state == 2; });
+    s->all.erase(it);
+    if (rq->status != TKC_OK) {
+        if (rq->status == TKC_ECANCELED) return tkc_fail(TKC_ECANCELED, "request cancelled");
+        return tkc_fail(rq->status, "%s", rq->err.c_str());
+    }
+    int32_t c = (int32_t)rq->ids.size();
+    memcpy(ids, rq->ids.data(), 4 * (size_t)c);
+    if (sum_dist) memcpy(sum_dist, rq->S.data(), 8 * (size_t)c);
+    if (reach) memcpy(reach, rq->R.data(), 8 * (size_t)c);
+    if (farness) memcpy(farness, rq->F.data(), 8 * (size_t)c);
+    *n_out = c;
+    if (latency_ms) *latency_ms = rq->t_done - rq->t_submit;
+    return TKC_OK;
+}
+
+extern "C" int tkc_server_cancel(tkc_server* s, uint64_t ticket) {
+    if (!s) return tkc_fail(TKC_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return tkc_fail(TKC_EINVAL, "unknown ticket");
+    std::shared_ptr<Request> rq = it->second;
+    rq->cancelled = true;
+    if (rq->state == 0) {
+        for (auto q = s->queue.begin(); q != s->queue.end(); ++q)
+            if (*q == rq) { s->queue.erase(q); break; }
+        rq->state = 2;
+        rq->status = TKC_ECANCELED;
+        rq->t_done = now_ms();
+        s->cv_done.notify_all();
+    }
+    return TKC_OK;
+}
+
+extern "C" int tkc_server_destroy(tkc_server* s) {
+    if (!s) return TKC_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+    }
+    s->cv_work.notify_all();
+    for (auto& t : s->workers) t.join();
+    for (auto* c : s->slot_ctx) tkc_ctx_destroy(c);
+    for (auto* g : s->graphs) {
+        std::lock_guard<std::mutex> gl(g->mu);
+        g->server_refs--;
+    }
+    delete s;
+    return TKC_OK;
+}

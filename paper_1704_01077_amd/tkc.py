@@ -1,0 +1,312 @@
+"""Python binding of libtkc.so (argument marshalling only).
+
+Every entry point of ``include/tkc.h`` is exposed under the same name; the
+helpers ``Graph`` / ``topk_closeness`` wrap them for numpy arrays and torch
+tensors.  Nothing here computes any part of the method: all of it runs in
+the HIP library, and importing this module fails loudly when the library is
+missing or cannot be loaded.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtkc.so")
+
+TKC_OK = 0
+TKC_EINVAL = -1
+TKC_ENOMEM = -2
+TKC_EDEVICE = -3
+TKC_ENOTSUP = -4
+TKC_EBUSY = -5
+TKC_ECANCELED = -6
+
+TKC_AUTO, TKC_DEG_CUT, TKC_NB_CUT, TKC_DEG_BOUND, TKC_NB_BOUND = 0, 1, 2, 3, 4
+TKC_PLAIN, TKC_BATCHED, TKC_HYBRID = 0, 1, 2
+TKC_DIRECTED, TKC_VALIDATE, TKC_DEVICE_PTRS = 1, 2, 4
+
+VARIANTS = {"auto": TKC_AUTO, "degcut": TKC_DEG_CUT, "nbcut": TKC_NB_CUT,
+            "degbound": TKC_DEG_BOUND, "nbbound": TKC_NB_BOUND}
+MODES = {"plain": TKC_PLAIN, "batched": TKC_BATCHED, "hybrid": TKC_HYBRID}
+
+EXPORTS = [
+    "tkc_ctx_create", "tkc_ctx_destroy", "tkc_ctx_set_tuning", "tkc_graph_upload", "tkc_graph_free",
+    "tkc_topk_closeness", "tkc_graph_reach", "tkc_graph_bounds", "tkc_graph_lb_update",
+    "tkc_graph_sums", "tkc_server_create", "tkc_server_add_graph", "tkc_server_submit",
+    "tkc_server_poll", "tkc_server_result", "tkc_server_cancel", "tkc_server_destroy",
+    "tkc_last_error", "tkc_version",
+]
+
+
+class tkc_stats(ctypes.Structure):
+    _fields_ = [
+        ("m_vis", ctypes.c_int64), ("bfs_started", ctypes.c_int64), ("bfs_exact", ctypes.c_int64),
+        ("bfs_cut", ctypes.c_int64), ("skipped", ctypes.c_int64), ("deferred", ctypes.c_int64),
+        ("max_level", ctypes.c_int32), ("batch_width", ctypes.c_int32), ("variant_used", ctypes.c_int32),
+        ("mode_used", ctypes.c_int32), ("nb_rounds", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("ms_reach", ctypes.c_double), ("ms_bounds", ctypes.c_double), ("ms_traverse", ctypes.c_double),
+        ("ms_total", ctypes.c_double), ("ms_kernel_main", ctypes.c_double),
+        ("main_launches", ctypes.c_int32), ("main_kernel", ctypes.c_int32), ("bytes_main", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
+
+
+class TkcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("tkc error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libtkc.so is not built (run __graft_entry__.build() or "
+                          "python -m paper_1704_01077_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    c = ctypes
+    vp, i32, i64, u32, u64 = c.c_void_p, c.c_int32, c.c_int64, c.c_uint32, c.c_uint64
+    P = c.POINTER
+    sig = {
+        "tkc_ctx_create": [c.c_int, vp, P(vp)],
+        "tkc_ctx_destroy": [vp],
+        "tkc_ctx_set_tuning": [vp, i32, i32, i32, i32, i32],
+        "tkc_graph_upload": [vp, i32, i64, vp, vp, vp, vp, u32, P(vp)],
+        "tkc_graph_free": [vp],
+        "tkc_topk_closeness": [vp, i32, i32, i32, vp, vp, vp, vp, P(i32), P(tkc_stats)],
+        "tkc_graph_reach": [vp, vp, vp, vp],
+        "tkc_graph_bounds": [vp, i32, vp, vp, vp],
+        "tkc_graph_lb_update": [vp, vp, i32, vp, vp],
+        "tkc_graph_sums": [vp, vp, i32, vp, vp],
+        "tkc_server_create": [vp, c.c_size_t, i32, P(vp)],
+        "tkc_server_add_graph": [vp, vp, P(i32)],
+        "tkc_server_submit": [vp, i32, i32, i32, P(u64)],
+        "tkc_server_poll": [vp, u64, P(i32)],
+        "tkc_server_result": [vp, u64, vp, vp, vp, vp, P(i32), P(c.c_double)],
+        "tkc_server_cancel": [vp, u64],
+        "tkc_server_destroy": [vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = c.c_int
+    lib.tkc_last_error.restype = c.c_char_p
+    lib.tkc_last_error.argtypes = []
+    lib.tkc_version.restype = c.c_char_p
+    lib.tkc_version.argtypes = []
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc):
+    if rc != TKC_OK:
+        raise TkcError(rc, lib.tkc_last_error().decode())
+    return rc
+
+
+def _ptr(a):
+    """Device or host pointer of a numpy array / torch tensor (or None)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(ctypes.c_void_p)
+    return ctypes.c_void_p(a.data_ptr())   # torch tensor
+
+
+# ---------------------------------------------------------- raw entry points
+def tkc_ctx_create(device: int = 0, hip_stream: int | None = None):
+    h = ctypes.c_void_p()
+    _check(lib.tkc_ctx_create(device, ctypes.c_void_p(hip_stream) if hip_stream else None, ctypes.byref(h)))
+    return h
+
+
+def tkc_ctx_destroy(ctx):
+    _check(lib.tkc_ctx_destroy(ctx))
+
+
+def tkc_ctx_set_tuning(ctx, batch_width=0, td_bu_alpha=0, bu_td_beta=0, swarm_qcap=0, block_size=0):
+    _check(lib.tkc_ctx_set_tuning(ctx, batch_width, td_bu_alpha, bu_td_beta, swarm_qcap, block_size))
+
+
+def tkc_graph_upload(ctx, n, m_arcs, row_ptr, col_idx, rrow_ptr=None, rcol_idx=None, flags=0):
+    h = ctypes.c_void_p()
+    _check(lib.tkc_graph_upload(ctx, n, m_arcs, _ptr(row_ptr), _ptr(col_idx), _ptr(rrow_ptr),
+                                _ptr(rcol_idx), flags, ctypes.byref(h)))
+    return h
+
+
+def tkc_graph_free(g):
+    _check(lib.tkc_graph_free(g))
+
+
+def tkc_topk_closeness(g, k, variant, mode, ids, sum_dist=None, reach=None, farness=None):
+    n_out = ctypes.c_int32(0)
+    st = tkc_stats()
+    _check(lib.tkc_topk_closeness(g, k, variant, mode, _ptr(ids), _ptr(sum_dist), _ptr(reach),
+                                  _ptr(farness), ctypes.byref(n_out), ctypes.byref(st)))
+    return n_out.value, st
+
+
+def tkc_graph_reach(g, alpha, omega, scc=None):
+    _check(lib.tkc_graph_reach(g, _ptr(alpha), _ptr(omega), _ptr(scc)))
+
+
+def tkc_graph_bounds(g, variant, num, den, order=None):
+    _check(lib.tkc_graph_bounds(g, variant, _ptr(num), _ptr(den), _ptr(order)))
+
+
+def tkc_graph_lb_update(g, sources, num, den):
+    _check(lib.tkc_graph_lb_update(g, _ptr(sources), len(sources), _ptr(num), _ptr(den)))
+
+
+def tkc_graph_sums(g, sources, S, R):
+    _check(lib.tkc_graph_sums(g, _ptr(sources), len(sources), _ptr(S), _ptr(R)))
+
+
+def tkc_server_create(ctx, hbm_budget_bytes, max_inflight):
+    h = ctypes.c_void_p()
+    _check(lib.tkc_server_create(ctx, hbm_budget_bytes, max_inflight, ctypes.byref(h)))
+    return h
+
+
+def tkc_server_add_graph(s, g):
+    gid = ctypes.c_int32(0)
+    _check(lib.tkc_server_add_graph(s, g, ctypes.byref(gid)))
+    return gid.value
+
+
+def tkc_server_submit(s, graph_id, k, variant=TKC_AUTO):
+    t = ctypes.c_uint64(0)
+    _check(lib.tkc_server_submit(s, graph_id, k, variant, ctypes.byref(t)))
+    return t.value
+
+
+def tkc_server_poll(s, ticket):
+    d = ctypes.c_int32(0)
+    _check(lib.tkc_server_poll(s, ticket, ctypes.byref(d)))
+    return bool(d.value)
+
+
+def tkc_server_result(s, ticket, ids, sum_dist=None, reach=None, farness=None):
+    n_out = ctypes.c_int32(0)
+    lat = ctypes.c_double(0)
+    _check(lib.tkc_server_result(s, ticket, _ptr(ids), _ptr(sum_dist), _ptr(reach), _ptr(farness),
+                                 ctypes.byref(n_out), ctypes.byref(lat)))
+    return n_out.value, lat.value
+
+
+def tkc_server_cancel(s, ticket):
+    _check(lib.tkc_server_cancel(s, ticket))
+
+
+def tkc_server_destroy(s):
+    _check(lib.tkc_server_destroy(s))
+
+
+def tkc_last_error() -> str:
+    return lib.tkc_last_error().decode()
+
+
+def tkc_version() -> str:
+    return lib.tkc_version().decode()
+
+
+# ------------------------------------------------------------ convenience
+class Context:
+    def __init__(self, device=0, stream=None):
+        if stream is None:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    stream = torch.cuda.current_stream(device).cuda_stream
+            except Exception:
+                stream = None
+        self.h = tkc_ctx_create(device, stream)
+
+    def tune(self, **kw):
+        tkc_ctx_set_tuning(self.h, **kw)
+
+    def close(self):
+        if self.h:
+            tkc_ctx_destroy(self.h)
+            self.h = None
+
+
+class Graph:
+    """A graph resident on the device (CSR copied at construction)."""
+
+    def __init__(self, ctx: Context, n, row_ptr, col_idx, rrow_ptr=None, rcol_idx=None,
+                 validate=False, device_ptrs=False):
+        row_ptr = _as_i32(row_ptr)
+        col_idx = _as_i32(col_idx)
+        flags = (TKC_DIRECTED if rrow_ptr is not None else 0) | (TKC_VALIDATE if validate else 0)
+        if device_ptrs:
+            flags |= TKC_DEVICE_PTRS
+        if rrow_ptr is not None:
+            rrow_ptr, rcol_idx = _as_i32(rrow_ptr), _as_i32(rcol_idx)
+        self.n = int(n)
+        self.m = int(col_idx.shape[0])
+        self.directed = rrow_ptr is not None
+        self._keep = (row_ptr, col_idx, rrow_ptr, rcol_idx)
+        self.h = tkc_graph_upload(ctx.h, self.n, self.m, row_ptr, col_idx, rrow_ptr, rcol_idx, flags)
+
+    @classmethod
+    def from_graphgen(cls, ctx, g, validate=False):
+        return cls(ctx, g.n, g.row_ptr, g.col_idx, g.rrow_ptr, g.rcol_idx, validate=validate)
+
+    def free(self):
+        if self.h:
+            tkc_graph_free(self.h)
+            self.h = None
+
+    def reach(self):
+        a = np.zeros(self.n, np.int64)
+        o = np.zeros(self.n, np.int64)
+        s = np.zeros(self.n, np.int32)
+        tkc_graph_reach(self.h, a, o, s)
+        return a, o, (s if self.directed else None)
+
+    def bounds(self, variant):
+        num = np.zeros(self.n, np.int64)
+        den = np.zeros(self.n, np.int64)
+        order = np.zeros(self.n, np.int32)
+        tkc_graph_bounds(self.h, VARIANTS.get(variant, variant), num, den, order)
+        return num, den, order
+
+    def lb_update(self, sources, num, den):
+        num = np.ascontiguousarray(num, dtype=np.int64).copy()
+        den = np.ascontiguousarray(den, dtype=np.int64).copy()
+        tkc_graph_lb_update(self.h, np.ascontiguousarray(sources, dtype=np.int32), num, den)
+        return num, den
+
+    def sums(self, sources):
+        src = np.ascontiguousarray(sources, dtype=np.int32)
+        S = np.zeros(max(1, src.size), np.int64)
+        R = np.zeros(max(1, src.size), np.int64)
+        if src.size:
+            tkc_graph_sums(self.h, src, S, R)
+        return S[: src.size], R[: src.size]
+
+
+def _as_i32(a):
+    if isinstance(a, np.ndarray):
+        return np.ascontiguousarray(a, dtype=np.int32)
+    return a   # torch tensor (host or device), int32 and contiguous
+
+
+def topk_closeness(g: Graph, k: int, variant="auto", mode="hybrid"):
+    """(ids int32, S int64, r int64, farness float64, stats) of the top min(k, n)."""
+    kk = min(int(k), g.n) if k > 0 else k
+    cap = max(1, kk)
+    ids = np.zeros(cap, np.int32)
+    S = np.zeros(cap, np.int64)
+    R = np.zeros(cap, np.int64)
+    F = np.zeros(cap, np.float64)
+    n_out, st = tkc_topk_closeness(g.h, int(k), VARIANTS.get(variant, variant), MODES.get(mode, mode),
+                                   ids, S, R, F)
+    return ids[:n_out], S[:n_out], R[:n_out], F[:n_out], st.as_dict()

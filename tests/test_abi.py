@@ -1,0 +1,70 @@
+"""The C-ABI library builds, loads and exports every symbol include/tkc.h
+declares.  No compute call runs here (no GPU in the CPU suite)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+from conftest import ROOT, hip_available
+
+HEADER = os.path.join(ROOT, "include", "tkc.h")
+
+
+def declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(tkc_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ["tkc_ctx_create", "tkc_graph_upload", "tkc_topk_closeness", "tkc_graph_free",
+                 "tkc_server_create", "tkc_server_submit", "tkc_server_result", "tkc_last_error"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1704_01077_amd import tkc
+    out = subprocess.run(["nm", "-D", "--defined-only", tkc.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r" T (tkc_\w+)", out))
+    missing = [n for n in declared() if n not in exported]
+    assert not missing, missing
+    assert set(tkc.EXPORTS) == set(declared())
+
+
+def test_binding_names_match_abi():
+    from paper_1704_01077_amd import tkc
+    for n in declared():
+        assert hasattr(tkc, n), n
+    assert tkc.tkc_version().startswith("tkc")
+
+
+def test_header_compiles_as_c():
+    src = '#include "tkc.h"\nint main(void){ tkc_stats s; (void)s; return TKC_OK; }\n'
+    r = subprocess.run(["gcc", "-x", "c", "-std=c99", "-Wall", "-Werror", "-I", os.path.dirname(HEADER),
+                        "-fsyntax-only", "-"], input=src, text=True, capture_output=True)
+    assert r.returncode == 0, r.stderr
+
+
+@pytest.mark.skipif(hip_available(), reason="checks the no-device error path")
+def test_no_device_is_a_clean_error():
+    from paper_1704_01077_amd import tkc
+    with pytest.raises(tkc.TkcError) as e:
+        tkc.tkc_ctx_create(0, None)
+    assert e.value.code == tkc.TKC_EDEVICE
+
+
+def test_stats_struct_layout_matches_header():
+    """sizeof(tkc_stats) seen by C equals the ctypes mirror."""
+    from paper_1704_01077_amd import tkc
+    import ctypes
+    src = ('#include <stdio.h>\n#include "tkc.h"\n'
+           'int main(void){ printf("%zu", sizeof(tkc_stats)); return 0; }\n')
+    exe = "/tmp/tkc_sizeof_%d" % os.getpid()
+    subprocess.run(["gcc", "-x", "c", "-I", os.path.dirname(HEADER), "-o", exe, "-"], input=src, text=True,
+                   check=True)
+    size = int(subprocess.run([exe], capture_output=True, text=True, check=True).stdout)
+    os.unlink(exe)
+    assert size == ctypes.sizeof(tkc.tkc_stats)
