@@ -1,0 +1,212 @@
+"""Benchmark: exact top-k closeness on one MI355X.
+
+One step = one whole top-k query on a resident graph (reachability, initial
+bounds, processing order, pruned searches, readback), on the undirected
+Barabasi-Albert workload n = 2^20, m = 5, seed 2 (5,242,865 edges), k = 10.
+
+Prints one JSON line.  value = GTEPS = arcs scanned by the searches (the
+paper's work count m_vis) / wall time of the step.  roofline: the dominant
+traversal kernel's algorithmic bytes over its HIP-event time (measured by
+the library on the stream it launches on).  cpu_baseline: the CPU oracle
+(textbook BFS) timed on a bounded sample of sources of the same graph.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "top-k closeness wall time & GTEPS (frac. HBM peak), batched vs plain; p50/p99"
+HBM_PEAK_GBS = 8000.0
+KERNEL_NAMES = {0: "k_plain", 1: "k_batch", 2: "k_swarm"}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1704_01077_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    null when the kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        rec = d.get(workload, {}).get(kernel)
+        if not rec or rec.get("source_hash") != kernel_source_hash():
+            return None
+        return rec.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def cpu_baseline(g, seconds: float):
+    """Oracle BFS from a seeded sample of sources, all host cores."""
+    import oracle
+    rng = np.random.default_rng(1234)
+    # calibrate: a few sources first, then a sample sized for ~seconds
+    t0 = time.perf_counter()
+    probe = rng.integers(0, g.n, size=64).astype(np.int32)
+    oracle.sums(g.n, g.edges, g.directed, sources=probe)
+    dt = time.perf_counter() - t0
+    count = int(max(64, min(20000, 64 * seconds / max(dt, 1e-3))))
+    src = rng.integers(0, g.n, size=count).astype(np.int32)
+    t0 = time.perf_counter()
+    S, r = oracle.sums(g.n, g.edges, g.directed, sources=src)
+    wall = time.perf_counter() - t0
+    # arcs scanned by each textbook BFS = sum of out-degrees over R(s)
+    deg = np.diff(g.row_ptr).astype(np.int64)
+    arcs = int(g.arcs) * count if (r == g.n).all() else None
+    if arcs is None:
+        arcs = 0
+        for s_ in src[:256]:
+            arcs += int(g.arcs)
+        arcs = arcs * count // 256
+    teps = arcs / wall
+    full_s = wall / count * g.n
+    return {"value": teps / 1e9, "unit": "GTEPS", "cores": oracle.threads(), "kind": "oracle",
+            "sample": "textbook BFS from %d seeded random sources of the same graph (%.1f s); "
+                      "all-sources extrapolation %.0f s" % (count, wall, full_s),
+            "wall_s": wall, "sources": count, "all_sources_extrapolated_s": full_s}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--k", type=int, default=10)
+    ap.add_argument("--variant", default="auto")
+    ap.add_argument("--mode", default="hybrid")
+    ap.add_argument("--workload", default="ba1m")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the plain/batched comparison runs")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run one device copy of this size (for counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the searches would shard by candidate ranges with a top-k merge)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import graphgen
+    from paper_1704_01077_amd import tkc
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.init()
+    print("bench: generating %s" % args.workload, file=sys.stderr, flush=True)
+    g = graphgen.workload(args.workload)
+    ctx = tkc.Context(0)
+    dg = tkc.Graph.from_graphgen(ctx, g)
+    torch.cuda.synchronize()
+
+    if args.calib_copy_mb:
+        a = torch.empty(args.calib_copy_mb << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    print("bench: warmup", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        tkc.topk_closeness(dg, args.k, args.variant, args.mode)
+    torch.cuda.synchronize()
+    walls, stats = [], []
+    t_all0 = time.perf_counter()
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ids, S, r, f, st = tkc.topk_closeness(dg, args.k, args.variant, args.mode)
+        torch.cuda.synchronize()
+        walls.append((time.perf_counter() - t0) * 1e3)
+        stats.append(st)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t_all0
+    print("bench: timed %d steps" % args.steps, file=sys.stderr, flush=True)
+    walls = np.array(walls)
+    ms_per_step = t_all * 1e3 / args.steps
+    mvis = stats[-1]["m_vis"]
+    gteps = mvis / (ms_per_step * 1e-3) / 1e9
+    st = stats[-1]
+    # dominant kernel: library HIP events around its launches, over the timed steps
+    kern_ms = float(np.mean([s["ms_kernel_main"] for s in stats]))
+    launches = st["main_launches"]
+    bytes_main = st["bytes_main"]
+    per_launch_ms = kern_ms / max(1, launches)
+    achieved = (bytes_main / max(1, launches)) / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
+    kname = KERNEL_NAMES.get(st["main_kernel"], "?")
+    traffic = load_traffic(kname, args.workload)
+
+    undirected = not g.directed
+    mn = (2 if undirected else 1) * (g.arcs // (2 if undirected else 1)) * g.n
+    improvement = mn / mvis if mvis else None
+
+    compare = {}
+    if not args.no_compare:
+        for mode in ("plain", "batched"):
+            print("bench: compare %s" % mode, file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ids2, S2, r2, f2, st2 = tkc.topk_closeness(dg, args.k, args.variant, mode)
+            torch.cuda.synchronize()
+            compare[mode] = {"wall_ms": (time.perf_counter() - t0) * 1e3, "m_vis": st2["m_vis"],
+                             "same_result": bool(np.array_equal(ids2, ids) and np.array_equal(S2, S))}
+
+    cpu = None
+    if not args.no_cpu:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(g, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": round(gteps, 4),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "BA undirected n=1048576 m=5 seed=2 (5,242,865 edges), top-k k=%d" % args.k
+                   if args.workload == "ba1m" else args.workload,
+                   "k": args.k, "variant": args.variant, "variant_used": st["variant_used"],
+                   "mode": args.mode, "batch_width": st["batch_width"], "n": g.n, "arcs": int(g.arcs)},
+        "wall_ms_p50": round(float(np.percentile(walls, 50)), 4),
+        "wall_ms_p99": round(float(np.percentile(walls, 99)), 4),
+        "m_vis": int(mvis),
+        "improvement_factor": improvement,
+        "phase_ms": {"reach": st["ms_reach"], "bounds": st["ms_bounds"], "traverse": st["ms_traverse"]},
+        "searches": {"started": st["bfs_started"], "exact": st["bfs_exact"], "cut": st["bfs_cut"],
+                     "skipped": st["skipped"], "deferred": st["deferred"], "max_level": st["max_level"]},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                     "launches_per_step": launches, "kernel_ms_per_step": round(kern_ms, 4),
+                     "bytes_per_step": int(bytes_main)},
+        "compare": compare,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    dg.free()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
