@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -73,9 +74,10 @@ static size_t ws_items(Workspace& ws, const WsShape& sh, std::vector<WsItem>& it
         {(void**)&ws.tval, 4 * n, false},
         {(void**)&ws.hist, 4 * (size_t)tkc_sort_hist_words(sh.n), false},
         {(void**)&ws.mask, 64, false}, {(void**)&ws.parent, 4 * n, false},
-        {(void**)&ws.csize, 8 * n, false}, {(void**)&ws.gbuf, 24 * n, false},
+        {(void**)&ws.csize, 8 * n + 8, false}, {(void**)&ws.gbuf, 24 * n, false},
         {(void**)&ws.nbsum, 8 * n, false}, {(void**)&ws.nbvis, 8 * n, false},
         {(void**)&ws.nbflags, n, false}, {(void**)&ws.small, 4096, false},
+        {(void**)&ws.nbpart, 8 * (size_t)sh.nchunks + 8, false},
         {(void**)&ws.tstate, 4096, false}, {(void**)&ws.ring, sizeof(XRec) * TKC_XRING, false},
         {(void**)&ws.tS, 8 * (size_t)sh.kcap, false}, {(void**)&ws.tR, 8 * (size_t)sh.kcap, false},
         {(void**)&ws.tI, 4 * (size_t)sh.kcap, false},
@@ -83,12 +85,12 @@ static size_t ws_items(Workspace& ws, const WsShape& sh, std::vector<WsItem>& it
         // plain engine
         {(void**)&ws.p_vis, 4 * words, true}, {(void**)&ws.p_fb, 12 * words, true},
         {(void**)&ws.p_ql, 4 * n, false}, {(void**)&ws.p_qh, 4 * n, false},
-        {(void**)&ws.p_ctr, 8 * 16, true}, {(void**)&ws.p_lvl, 4 * n, false},
+        {(void**)&ws.p_qg, 4 * n, false}, {(void**)&ws.p_ctr, 8 * 32, true}, {(void**)&ws.p_lvl, 4 * n, false},
         {(void**)&ws.p_levcnt, 8 * (n + 2), false}, {(void**)&ws.p_levtab, 8 * (n + 2), false},
         // batched engine
         {(void**)&ws.b_vis, 8 * n * nw, true}, {(void**)&ws.b_frt0, 8 * n * nw, true},
         {(void**)&ws.b_frt1, 8 * n * nw, true}, {(void**)&ws.b_nxt, 8 * n * nw, true},
-        {(void**)&ws.b_list, 16 * n, false}, {(void**)&ws.b_mark, 4 * n, true},
+        {(void**)&ws.b_list, 24 * n, false}, {(void**)&ws.b_mark, 4 * n, true},
         {(void**)&ws.b_ctr, 8 * 2048, true}, {(void**)&ws.b_cand, 4 * 256, false},
         {(void**)&ws.b_hist, sh.lb ? 8 * lcap * W : 8, false},
         {(void**)&ws.b_levtab, sh.lb ? 8 * lcap * W : 8, false},
@@ -139,6 +141,9 @@ int tkc_ws_reserve(tkc_ctx* ctx, Workspace& ws, const WsShape& sh) {
         if (it.zero) HIPCHK(hipMemsetAsync(ws.base + off, 0, it.bytes, ctx->stream));
         off += align_up(it.bytes);
     }
+    if (getenv("TKC_TRACE") && !ws.trace) {
+        if (hipMalloc((void**)&ws.trace, 8 * (8 + 8 * 4096)) != hipSuccess) ws.trace = nullptr;
+    }
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return TKC_OK;
 }
@@ -175,6 +180,7 @@ extern "C" int tkc_ctx_destroy(tkc_ctx* c) {
     hipSetDevice(c->device);
     hipStreamSynchronize(c->stream);
     if (c->ws.base) hipFree(c->ws.base);
+    if (c->ws.trace) hipFree(c->ws.trace);
     if (c->pinned) hipHostFree(c->pinned);
     hipEventDestroy(c->ev0);
     hipEventDestroy(c->ev1);
@@ -281,7 +287,22 @@ extern "C" int tkc_graph_upload(tkc_ctx* c, int32_t n, int64_t m, const int32_t*
     g->n = n;
     g->m = m;
     g->directed = directed;
-    size_t bytes = 4 * (size_t)(n + 1) + 4 * (size_t)(m ? m : 1) + 4 * (size_t)n + 4 * (size_t)(n + 1);
+    // heavy vertices and their arc chunks (ascending ids: deterministic)
+    std::vector<int32_t> hv, hcb(1, 0), cb, ce;
+    for (int32_t u = 0; u < n; u++) {
+        int32_t d = hrp[u + 1] - hrp[u];
+        if (d <= HEAVY_DEG) continue;
+        hv.push_back(u);
+        for (int32_t b = hrp[u]; b < hrp[u + 1]; b += CHUNK_ARCS) {
+            cb.push_back(b);
+            ce.push_back(std::min(b + CHUNK_ARCS, hrp[u + 1]));
+        }
+        hcb.push_back((int32_t)cb.size());
+    }
+    g->nheavy = (int32_t)hv.size();
+    g->nchunks = (int32_t)cb.size();
+    size_t bytes = 4 * (size_t)(n + 1) + 4 * (size_t)(m ? m : 1) + 4 * (size_t)n + 4 * (hv.size() + 1) +
+                   4 * hcb.size() + 8 * (cb.size() + 1) + 8 * 256;
     if (directed) bytes += 4 * (size_t)(n + 1) + 4 * (size_t)(m ? m : 1);
     if (hipMalloc(&g->dbase, bytes + 1024) != hipSuccess) {
         hipGetLastError();
@@ -293,7 +314,10 @@ extern "C" int tkc_graph_upload(tkc_ctx* c, int32_t n, int64_t m, const int32_t*
     g->rp = (int32_t*)take(4 * (size_t)(n + 1));
     g->ci = (int32_t*)take(4 * (size_t)(m ? m : 1));
     g->deg = (int32_t*)take(4 * (size_t)n);
-    g->heavy = (int32_t*)take(4 * (size_t)(n + 1));
+    g->heavy = (int32_t*)take(4 * (hv.size() + 1));
+    g->hcb = (int32_t*)take(4 * hcb.size());
+    g->ch_beg = (int32_t*)take(4 * (cb.size() + 1));
+    g->ch_end = (int32_t*)take(4 * (cb.size() + 1));
     if (directed) {
         g->rrp = (int32_t*)take(4 * (size_t)(n + 1));
         g->rci = (int32_t*)take(4 * (size_t)(m ? m : 1));
@@ -310,16 +334,15 @@ extern "C" int tkc_graph_upload(tkc_ctx* c, int32_t n, int64_t m, const int32_t*
         (hipMemcpyAsync(g->rrp, hrrp.data(), 4 * (size_t)(n + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
          (m && hipMemcpyAsync(g->rci, hrci.data(), 4 * (size_t)m, hipMemcpyHostToDevice, s) != hipSuccess)))
         rc = tkc_fail(TKC_EDEVICE, "reverse graph copy failed");
+    if (!rc && ((hv.size() && hipMemcpyAsync(g->heavy, hv.data(), 4 * hv.size(), hipMemcpyHostToDevice, s)) ||
+                hipMemcpyAsync(g->hcb, hcb.data(), 4 * hcb.size(), hipMemcpyHostToDevice, s) ||
+                (cb.size() && (hipMemcpyAsync(g->ch_beg, cb.data(), 4 * cb.size(), hipMemcpyHostToDevice, s) ||
+                               hipMemcpyAsync(g->ch_end, ce.data(), 4 * ce.size(), hipMemcpyHostToDevice, s)))))
+        rc = tkc_fail(TKC_EDEVICE, "heavy-vertex table copy failed");
     if (!rc) {
         DevGraph dg = g->view();
-        int32_t* nh = (int32_t*)c->pinned;
-        int32_t* nh_dev = g->heavy + n;   // last slot holds the count
-        if (tkc_launch_degrees(dg, g->heavy, nh_dev, s) ||
-            hipMemcpyAsync(nh, nh_dev, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
+        if (tkc_launch_degrees(dg, s) || hipStreamSynchronize(s) != hipSuccess)
             rc = tkc_fail(TKC_EDEVICE, "degree kernel failed");
-        else
-            g->nheavy = *nh;
     }
     if (rc) {
         hipStreamSynchronize(s);
@@ -356,6 +379,7 @@ WsShape tkc_shape_for(tkc_ctx* c, tkc_graph* g, int32_t k, bool lb) {
     sh.kcap = std::max(k, 1);
     sh.lb = lb;
     sh.lcap = (int32_t)std::min<int64_t>((int64_t)g->n + 2, 65000);
+    sh.nchunks = g->nchunks;
     sh.qcap = std::max(64, std::min(c->tune.swarm_qcap, g->n));
     sh.swarm_blocks = std::max(1, tkc_swarm_max_blocks(256));
     // the private bitmaps of the per-workgroup engine cost blocks * n/8 bytes;
@@ -370,7 +394,7 @@ int tkc_step_reach(tkc_ctx* c, tkc_graph* g, Workspace& ws) {
     hipStream_t s = c->stream;
     DevGraph dg = g->view();
     if (!g->directed) {
-        if (tkc_launch_cc(dg, g->heavy, g->nheavy, ws.parent, ws.csize, ws.alpha, ws.omega, s))
+        if (tkc_launch_cc(dg, ws.parent, ws.csize, ws.alpha, ws.omega, ws.nbflags, (int32_t*)c->pinned, s))
             return tkc_fail(TKC_EDEVICE, "components kernel failed");
         return TKC_OK;
     }
@@ -393,8 +417,8 @@ int tkc_step_bounds(tkc_ctx* c, tkc_graph* g, Workspace& ws, bool nb, int32_t* r
     if (rounds) *rounds = 0;
     if (nb) {
         int32_t* nfin_dev = (int32_t*)ws.small;
-        int r = tkc_launch_nb(dg, g->heavy, g->nheavy, ws.alpha, ws.omega, ws.gbuf, ws.nbsum, ws.nbvis,
-                              ws.nbflags, ws.lnum, ws.lden, nfin_dev, (int32_t*)c->pinned, s);
+        int r = tkc_launch_nb(dg, ws.alpha, ws.omega, ws.gbuf, ws.nbsum, ws.nbvis, ws.nbflags, ws.lnum, ws.lden,
+                              ws.nbpart, nfin_dev, (int32_t*)c->pinned, s);
         if (r < 0) return tkc_fail(TKC_EDEVICE, "NB bound kernels failed");
         if (rounds) *rounds = r;
         if (tkc_launch_nb_keys(n, ws.lnum, ws.lden, ws.key, ws.ord, s))
@@ -421,7 +445,7 @@ static DevTopk topk_view(Workspace& ws) {
 
 static PlainWork plain_view(Workspace& ws) {
     PlainWork w;
-    w.vis = ws.p_vis; w.fb = ws.p_fb; w.ql = ws.p_ql; w.qh = ws.p_qh; w.ctr = ws.p_ctr;
+    w.vis = ws.p_vis; w.fb = ws.p_fb; w.ql = ws.p_ql; w.qh = ws.p_qh; w.qg = ws.p_qg; w.ctr = ws.p_ctr;
     w.lvl = ws.p_lvl; w.levcnt = ws.p_levcnt; w.levtab = ws.p_levtab;
     return w;
 }
@@ -431,7 +455,32 @@ static BatchWork batch_view(Workspace& ws) {
     w.list = ws.b_list; w.touched = ws.b_mark; w.ctr = ws.b_ctr; w.lanes = nullptr;
     w.lvl = ws.b_lvl; w.hist = ws.b_hist; w.levtab = ws.b_levtab; w.lcap = ws.shape.lcap;
     w.cand = ws.b_cand;
+    w.trace = ws.trace;
+    w.trace_cap = ws.trace ? 4096 : 0;
     return w;
+}
+
+// optional per-level trace of the batched engine (environment TKC_TRACE=1):
+// one line per level on stderr, timestamps from the device wall clock
+static void trace_reset(tkc_ctx* c) {
+    if (c->ws.trace) hipMemsetAsync(c->ws.trace, 0, 8 * 8, c->stream);
+}
+static void trace_dump(tkc_ctx* c, const char* tag) {
+    if (!c->ws.trace) return;
+    std::vector<int64_t> h(8 + 8 * 4096);
+    hipMemcpyAsync(h.data(), c->ws.trace, 8 * h.size(), hipMemcpyDeviceToHost, c->stream);
+    hipStreamSynchronize(c->stream);
+    int64_t cnt = std::min<int64_t>(h[0], 4096);
+    int rate = 0;
+    hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, c->device);
+    double khz = rate > 0 ? rate : 100000.0;
+    for (int64_t i = 0; i < cnt; i++) {
+        const int64_t* r = h.data() + 8 + 8 * i;
+        double dt = i + 1 < cnt ? (h[8 + 8 * (i + 1) + 5] - r[5]) / khz * 1e3 : 0.0;
+        fprintf(stderr, "trace %s batch %lld level %lld %s frontier %lld arcs %lld lanes %lld/%lld  %.1f us\n", tag,
+                (long long)r[0], (long long)r[1], r[2] ? "pull" : "push", (long long)r[3], (long long)r[4],
+                (long long)r[7], (long long)r[6], dt);
+    }
 }
 
 // time one engine launch with events on the context stream
@@ -528,15 +577,18 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
             return tkc_fail(TKC_EDEVICE, "plain engine launch failed: %s", hipGetErrorString(hipGetLastError()));
         tm.done();
     } else if (mode == TKC_BATCHED) {
+        trace_reset(c);
         EngineTimer tm(c, &ms_eng[1], &nl_eng[1]);
         int e = tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_batch, nullptr, 0, 0, 0, lb, false,
                                  nullptr, nullptr, c->tune, s, &grid);
         if (e) return tkc_fail(TKC_EDEVICE, "batched engine launch failed: %s", hipGetErrorString(hipGetLastError()));
         tm.done();
+        trace_dump(c, "batched");
     } else {
         // hybrid: batched seed until x is known, then one search per workgroup,
         // then the deferred (large) searches batched
         int64_t hs[ST_COUNT];
+        trace_reset(c);
         {
             EngineTimer tm(c, &ms_eng[1], &nl_eng[1]);
             if (tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_batch, nullptr, 0, 0, -1, false,
@@ -544,6 +596,7 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
                 return tkc_fail(TKC_EDEVICE, "batched seed launch failed: %s", hipGetErrorString(hipGetLastError()));
             tm.done();
         }
+        trace_dump(c, "seed");
         rc = read_stats(c, st_batch, hs);
         if (rc) return rc;
         int32_t cursor = (int32_t)hs[ST_CURSOR];
@@ -571,11 +624,13 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
             HIPCHK(hipStreamSynchronize(s));
             int32_t ndef = pin[0];
             if (ndef > 0) {
+                trace_reset(c);
                 EngineTimer tm(c, &ms_eng[1], &nl_eng[1]);
                 if (tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_tail, ws.s_deferred, ndef, 0, 0,
                                      false, false, nullptr, nullptr, c->tune, s, &grid))
                     return tkc_fail(TKC_EDEVICE, "batched tail launch failed");
                 tm.done();
+                trace_dump(c, "tail");
             }
         }
     }

@@ -16,7 +16,18 @@ struct DevGraph {
     const int32_t* rrp;   // in-arcs CSR (== rp/ci when undirected)
     const int32_t* rci;
     int32_t* deg;         // out-degree
+    // vertices with more than HEAVY_DEG out-arcs, ascending, and their arcs cut
+    // into chunks of CHUNK_ARCS: heavy vertex i owns chunks [hcb[i], hcb[i+1])
+    const int32_t* heavy;
+    int32_t nheavy;
+    const int32_t* hcb;
+    const int32_t* ch_beg;
+    const int32_t* ch_end;
+    int32_t nchunks;
 };
+#define HEAVY_DEG 64
+#define GIANT_DEG 1024
+#define CHUNK_ARCS 512
 
 // reachability and bounds of one query
 struct DevReach {
@@ -60,12 +71,14 @@ struct EngineTuning {
 };
 
 // k_prep.hip
-int tkc_launch_degrees(const DevGraph& g, int32_t* heavy, int32_t* nheavy, hipStream_t s);
-int tkc_launch_cc(const DevGraph& g, const int32_t* heavy, int32_t nheavy, int32_t* parent,
-                  int64_t* size, int64_t* alpha, int64_t* omega, hipStream_t s);
-int tkc_launch_nb(const DevGraph& g, const int32_t* heavy, int32_t nheavy, const int64_t* alpha,
-                  const int64_t* omega, int64_t* gbuf, int64_t* sum, int64_t* vis, uint8_t* flags,
-                  int64_t* num, int64_t* den, int32_t* nfin_dev, int32_t* nfin_host, hipStream_t s);
+int tkc_launch_degrees(const DevGraph& g, hipStream_t s);
+// size holds n+1 int64; in_giant n bytes; sample_host 1024 pinned int32
+int tkc_launch_cc(const DevGraph& g, int32_t* parent, int64_t* size, int64_t* alpha, int64_t* omega,
+                  uint8_t* in_giant, int32_t* sample_host, hipStream_t s);
+// partial holds nchunks uint64
+int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega, int64_t* gbuf, int64_t* sum,
+                  int64_t* vis, uint8_t* flags, int64_t* num, int64_t* den, uint64_t* partial,
+                  int32_t* nfin_dev, int32_t* nfin_host, hipStream_t s);
 int tkc_launch_deg_bounds(const DevGraph& g, const int64_t* omega, int64_t* num, int64_t* den,
                           uint32_t* key, int32_t* val, hipStream_t s);
 int tkc_launch_nb_keys(int32_t n, const int64_t* num, const int64_t* den, uint32_t* key,
@@ -87,7 +100,8 @@ struct PlainWork {
     uint32_t* fb;        // 3 x n bits (frontier bitmaps of pull steps)
     int32_t* ql;         // queue of light vertices (n)
     int32_t* qh;         // queue of heavy vertices (n)
-    int64_t* ctr;        // 3 x 4 level counters + tails
+    int32_t* qg;         // queue of giant vertices (n)
+    int64_t* ctr;        // 3 x 8 level counters
     int32_t* lvl;        // distance from the source (level-based updates)
     int64_t* levcnt;     // vertices per level (n + 2)
     int64_t* levtab;     // Lev(i) table (n + 2)
@@ -111,6 +125,8 @@ struct BatchWork {
     int64_t* levtab;     // LCAP * W Lev tables
     int32_t lcap;
     int32_t* cand;       // selected candidates of a batch (W)
+    int64_t* trace;      // optional per-level records (8 int64 each), [0] = count
+    int64_t trace_cap;
 };
 int tkc_launch_batch(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv, DevTopk tk,
                      BatchWork w, int64_t* stats, const int32_t* list, int32_t list_count,

@@ -10,11 +10,11 @@
 #include "engine.hpp"
 
 struct WsShape {
-    int32_t n = 0, W = 64, nw = 1, kcap = 1, lcap = 0, qcap = 0, swarm_blocks = 0;
+    int32_t n = 0, W = 64, nw = 1, kcap = 1, lcap = 0, qcap = 0, swarm_blocks = 0, nchunks = 0;
     bool lb = false;
     bool covers(const WsShape& o) const {
         return n >= o.n && nw >= o.nw && W >= o.W && kcap >= o.kcap && lcap >= o.lcap && qcap >= o.qcap &&
-               swarm_blocks >= o.swarm_blocks && (lb || !o.lb);
+               swarm_blocks >= o.swarm_blocks && nchunks >= o.nchunks && (lb || !o.lb);
     }
 };
 
@@ -33,6 +33,7 @@ struct Workspace {
     int32_t* parent;
     int64_t* csize;
     int64_t *gbuf, *nbsum, *nbvis;
+    uint64_t* nbpart;
     uint8_t* nbflags;
     void* small;
     void* tstate;
@@ -42,7 +43,7 @@ struct Workspace {
     int64_t* stats;
     // plain engine
     uint32_t *p_vis, *p_fb;
-    int32_t *p_ql, *p_qh, *p_lvl;
+    int32_t *p_ql, *p_qh, *p_qg, *p_lvl;
     int64_t *p_ctr, *p_levcnt, *p_levtab;
     // batched engine
     uint64_t *b_vis, *b_frt0, *b_frt1, *b_nxt;
@@ -52,6 +53,7 @@ struct Workspace {
     // per-workgroup engine
     uint32_t* s_vis;
     int32_t *s_queue, *s_deferred;
+    int64_t* trace = nullptr;   // optional level trace (separate allocation)
 };
 
 struct tkc_ctx {
@@ -74,6 +76,8 @@ struct tkc_graph {
     int32_t* deg = nullptr;
     int32_t* heavy = nullptr;
     int32_t nheavy = 0;
+    int32_t *hcb = nullptr, *ch_beg = nullptr, *ch_end = nullptr;
+    int32_t nchunks = 0;
     int32_t server_refs = 0;
     int32_t auto_variant = 0;
     // directed graphs keep a host copy for the reachability bounds
@@ -92,6 +96,8 @@ struct tkc_graph {
         DevGraph g;
         g.n = n; g.m = m; g.directed = directed;
         g.rp = rp; g.ci = ci; g.rrp = rrp; g.rci = rci; g.deg = deg;
+        g.heavy = heavy; g.nheavy = nheavy; g.hcb = hcb; g.ch_beg = ch_beg; g.ch_end = ch_end;
+        g.nchunks = nchunks;
         return g;
     }
 };

@@ -20,7 +20,6 @@
 
 namespace cg = cooperative_groups;
 
-#define HEAVY_DEG 64
 #define BB 256
 #define MAXW 256
 
@@ -28,15 +27,13 @@ namespace cg = cooperative_groups;
 #define C_CNT(p, l) ((p) * 2 * MAXW + (l))
 #define C_DEG(p, l) ((p) * 2 * MAXW + MAXW + (l))
 #define C_BASE (3 * 2 * MAXW)
-#define C_UCNT(p) (C_BASE + (p) * 4 + 0)
-#define C_UDEG(p) (C_BASE + (p) * 4 + 1)
-#define C_TL(p) (C_BASE + (p) * 4 + 2)      // next light list tail
-#define C_TH(p) (C_BASE + (p) * 4 + 3)      // next heavy list tail
-#define C_NSEL (C_BASE + 12)
-#define C_POS (C_BASE + 13)
-#define C_STOP (C_BASE + 14)
-#define C_LBOK (C_BASE + 15)
-#define C_TOTAL (C_BASE + 16)
+#define C_UCNT(p) (C_BASE + (p) * 8 + 0)
+#define C_UDEG(p) (C_BASE + (p) * 8 + 1)
+#define C_T(p, c) (C_BASE + (p) * 8 + 2 + (c))   // next list tails: light, heavy, giant
+#define C_NSEL (C_BASE + 24)
+#define C_POS (C_BASE + 25)
+#define C_STOP (C_BASE + 26)
+#define C_TOTAL (C_BASE + 32)
 
 struct BatchArgs {
     DevGraph g;
@@ -82,23 +79,26 @@ struct Mask {
     }
 };
 
-TKC_DEV void list_append(bool isnew, int32_t w, int32_t dw, int32_t* ll, int32_t* lh, int64_t* tl,
-                         int64_t* th) {
-    bool hv = isnew && dw > HEAVY_DEG;
-    bool lt = isnew && !hv;
-    uint64_t ml = __ballot(lt), mh = __ballot(hv);
-    if ((ml | mh) == 0) return;
+// wave-aggregated append to the next level's light / heavy / giant lists
+TKC_DEV void list_append(bool isnew, int32_t w, int32_t dw, int32_t* const* lists, int64_t* tails) {
+    int cls = dw > GIANT_DEG ? 2 : (dw > HEAVY_DEG ? 1 : 0);
+    uint64_t m[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) m[c] = __ballot(isnew && cls == c);
+    if ((m[0] | m[1] | m[2]) == 0) return;
     int leader = __ffsll((long long)__ballot(1)) - 1;
-    int64_t bl = 0, bh = 0;
+    int64_t b[3] = {0, 0, 0};
     if (lane_id() == leader) {
-        if (ml) bl = fadd_rlx(tl, (int64_t)__popcll(ml));
-        if (mh) bh = fadd_rlx(th, (int64_t)__popcll(mh));
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+            if (m[c]) b[c] = fadd_rlx(&tails[c], (int64_t)__popcll(m[c]));
     }
-    bl = shfl64b(bl, leader);
-    bh = shfl64b(bh, leader);
-    uint64_t b = below_mask();
-    if (lt) ll[bl + __popcll(ml & b)] = w;
-    if (hv) lh[bh + __popcll(mh & b)] = w;
+    uint64_t bm = below_mask();
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        int64_t bc = shfl64b(b[c], leader);
+        if (isnew && cls == c) lists[c][bc + __popcll(m[c] & bm)] = w;
+    }
 }
 
 // OR the lanes nb into w's next word(s); true for exactly one caller per
@@ -252,25 +252,26 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             if (a.lb_mode) { a.w.lvl[(int64_t)v * W + l] = 0; a.w.hist[l] = 1; }
         }
         if (boss) {
-            // level-0 frontier lists: sources split by degree
-            int64_t nl = 0, nh = 0;
+            // level-0 frontier lists (parity 0): sources split by degree class
+            int64_t cnt3[3] = {0, 0, 0};
             for (int l = 0; l < nsel; l++) {
                 int32_t v = a.w.cand[l];
-                if (deg[v] > HEAVY_DEG) a.w.list[2 * (int64_t)n + nh++] = v;
-                else a.w.list[nl++] = v;
+                int c = deg[v] > GIANT_DEG ? 2 : (deg[v] > HEAVY_DEG ? 1 : 0);
+                a.w.list[(int64_t)(2 * c) * n + cnt3[c]++] = v;
             }
             for (int p = 0; p < 3; p++) {
-                ctr[C_UCNT(p)] = 0; ctr[C_UDEG(p)] = 0; ctr[C_TL(p)] = 0; ctr[C_TH(p)] = 0;
+                ctr[C_UCNT(p)] = 0; ctr[C_UDEG(p)] = 0;
+                for (int c = 0; c < 3; c++) ctr[C_T(p, c)] = 0;
             }
-            ctr[C_TL(2)] = nl;     // "previous level" lists of level 0
-            ctr[C_TH(2)] = nh;
+            for (int c = 0; c < 3; c++) ctr[C_T(2, c)] = cnt3[c];   // "previous level" lists of level 0
             for (int p = 0; p < 3; p++)
                 for (int l = 0; l < MAXW; l++) { ctr[C_CNT(p, l)] = 0; ctr[C_DEG(p, l)] = 0; }
         }
         grid.sync();
 
         int64_t D = 0;
-        int64_t fl_len = ld_rlx(&ctr[C_TL(2)]), fh_len = ld_rlx(&ctr[C_TH(2)]);
+        int64_t flen[3];
+        for (int c = 0; c < 3; c++) flen[c] = ld_rlx(&ctr[C_T(2, c)]);
         int64_t ucnt = nsel, udeg = 0;
         for (int l = 0; l < nsel; l++) udeg += s_mf[l];
         int64_t udisc = udeg;
@@ -316,15 +317,28 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             bool want_bu = bu ? (ucnt >= (int64_t)n / a.beta_bu)
                               : (udeg > (a.g.m - udisc) / a.alpha_td && ucnt > 256);
             bu = want_bu;
+            if (boss && a.w.trace) {
+                int64_t t = fadd_rlx(&a.w.trace[0], (int64_t)1);
+                if (t < a.w.trace_cap) {
+                    int64_t* r = a.w.trace + 8 + 8 * t;
+                    r[0] = batches; r[1] = D; r[2] = bu; r[3] = ucnt; r[4] = udeg;
+                    r[5] = (int64_t)wall_clock64(); r[6] = nsel; r[7] = 0;
+                    for (int j = 0; j < NW; j++) r[7] += __popcll(act.w[j]);
+                }
+            }
             const int p = (int)(D % 3);
-            const int32_t* fl = a.w.list + (int64_t)(D & 1) * n;
-            const int32_t* fh = a.w.list + 2 * (int64_t)n + (int64_t)(D & 1) * n;
-            int32_t* nl = a.w.list + (int64_t)((D + 1) & 1) * n;
-            int32_t* nh = a.w.list + 2 * (int64_t)n + (int64_t)((D + 1) & 1) * n;
+            // lists of class c at parity q live at list + (2c + q) n
+            const int32_t* fl = a.w.list + (int64_t)(0 + (D & 1)) * n;
+            const int32_t* fh = a.w.list + (int64_t)(2 + (D & 1)) * n;
+            const int32_t* fg = a.w.list + (int64_t)(4 + (D & 1)) * n;
+            int32_t* const nls[3] = {a.w.list + (int64_t)(0 + ((D + 1) & 1)) * n,
+                                     a.w.list + (int64_t)(2 + ((D + 1) & 1)) * n,
+                                     a.w.list + (int64_t)(4 + ((D + 1) & 1)) * n};
+            const int64_t fl_len = flen[0], fh_len = flen[1], fg_len = flen[2];
             const uint64_t* fcur = (D & 1) ? a.w.frt1 : a.w.frt0;
             uint64_t* fnxt = (D & 1) ? a.w.frt0 : a.w.frt1;
             const int32_t stamp = (int32_t)(D + 1);
-            bytes += bu ? (int64_t)n * (8 * NW) : (fl_len + fh_len) * (8 + 8 * NW);
+            bytes += bu ? (int64_t)n * (8 * NW) : (fl_len + fh_len + fg_len) * (8 + 8 * NW);
             if (!bu) {
                 // push, light frontier vertices: one per lane
                 for (int64_t base = gwave * 64; base < fl_len; base += nwaves * 64) {
@@ -352,7 +366,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                                 dw = deg[w];
                             }
                         }
-                        list_append(isnew, w, dw, nl, nh, &ctr[C_TL(p)], &ctr[C_TH(p)]);
+                        list_append(isnew, w, dw, nls, &ctr[C_T(p, 0)]);
                     }
                 }
                 // push, heavy frontier vertices: one per wave
@@ -377,7 +391,32 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                                 dw = deg[w];
                             }
                         }
-                        list_append(isnew, w, dw, nl, nh, &ctr[C_TL(p)], &ctr[C_TH(p)]);
+                        list_append(isnew, w, dw, nls, &ctr[C_T(p, 0)]);
+                    }
+                }
+                // push, giant frontier vertices: the whole grid on each in turn
+                for (int64_t gi = 0; gi < fg_len; gi++) {
+                    int32_t u = fg[gi];
+                    Mask<NW> f;
+#pragma unroll
+                    for (int j = 0; j < NW; j++) f.w[j] = fcur[(int64_t)u * NW + j] & act.w[j];
+                    if (!f.any()) continue;
+                    int64_t b = rp[u], end = rp[u + 1];
+                    for (int64_t e0 = b + gwave * 64; e0 < end; e0 += nwaves * 64) {
+                        int64_t e = e0 + lane;
+                        bool isnew = false;
+                        int32_t w = 0, dw = 0;
+                        if (e < end) {
+                            w = ci[e];
+                            Mask<NW> nb;
+#pragma unroll
+                            for (int j = 0; j < NW; j++) nb.w[j] = f.w[j] & ~ld_rlx(&vis[(int64_t)w * NW + j]);
+                            if (nb.any() && push_lanes<NW>(a.w.nxt, a.mark, w, nb, stamp)) {
+                                isnew = true;
+                                dw = deg[w];
+                            }
+                        }
+                        list_append(isnew, w, dw, nls, &ctr[C_T(p, 0)]);
                     }
                 }
             } else {
@@ -414,30 +453,33 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                             }
                         }
                     }
-                    list_append(isnew, w, dw, nl, nh, &ctr[C_TL(p)], &ctr[C_TH(p)]);
+                    list_append(isnew, w, dw, nls, &ctr[C_T(p, 0)]);
                 }
             }
             grid.sync();
             // ------------------------------------------------------ epilogue
-            const int64_t nl_len = ld_rlx(&ctr[C_TL(p)]), nh_len = ld_rlx(&ctr[C_TH(p)]);
+            int64_t nlen[3];
+            for (int c = 0; c < 3; c++) nlen[c] = ld_rlx(&ctr[C_T(p, c)]);
+            const int64_t nall = nlen[0] + nlen[1] + nlen[2];
             if (tid < MAXW) { s_red_cnt[tid] = 0; s_red_deg[tid] = 0; }
             __syncthreads();
             // old frontier words are cleared (the next level uses the other array)
             uint64_t* fcur_w = (uint64_t*)fcur;
-            for (int64_t i = gtid; i < fl_len + fh_len; i += nthreads) {
-                int32_t u = i < fl_len ? fl[i] : fh[i - fl_len];
+            for (int64_t i = gtid; i < fl_len + fh_len + fg_len; i += nthreads) {
+                int32_t u = i < fl_len ? fl[i] : (i < fl_len + fh_len ? fh[i - fl_len] : fg[i - fl_len - fh_len]);
 #pragma unroll
                 for (int j = 0; j < NW; j++) fcur_w[(int64_t)u * NW + j] = 0;
             }
             int64_t my_u = 0, my_ud = 0;
-            for (int64_t base = gwave * 64; base < nl_len + nh_len; base += nwaves * 64) {
+            for (int64_t base = gwave * 64; base < nall; base += nwaves * 64) {
                 int64_t i = base + lane;
                 Mask<NW> nb;
 #pragma unroll
                 for (int j = 0; j < NW; j++) nb.w[j] = 0;
                 int32_t dw = 0;
-                if (i < nl_len + nh_len) {
-                    int32_t w = i < nl_len ? nl[i] : nh[i - nl_len];
+                if (i < nall) {
+                    int32_t w = i < nlen[0] ? nls[0][i]
+                                            : (i < nlen[0] + nlen[1] ? nls[1][i - nlen[0]] : nls[2][i - nlen[0] - nlen[1]]);
                     dw = deg[w];
 #pragma unroll
                     for (int j = 0; j < NW; j++) {
@@ -509,14 +551,14 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             ucnt = ld_rlx(&ctr[C_UCNT(p)]);
             udeg = ld_rlx(&ctr[C_UDEG(p)]);
             udisc += udeg;
-            bytes += ucnt * 8 * (3 * NW) + (int64_t)nl_len * 4;
+            bytes += ucnt * 8 * (3 * NW) + nall * 4;
             if (boss) {
                 int q = (int)((D + 2) % 3);
                 for (int l = 0; l < W; l++) { ctr[C_CNT(q, l)] = 0; ctr[C_DEG(q, l)] = 0; }
-                ctr[C_UCNT(q)] = 0; ctr[C_UDEG(q)] = 0; ctr[C_TL(q)] = 0; ctr[C_TH(q)] = 0;
+                ctr[C_UCNT(q)] = 0; ctr[C_UDEG(q)] = 0;
+                for (int c = 0; c < 3; c++) ctr[C_T(q, c)] = 0;
             }
-            fl_len = nl_len;
-            fh_len = nh_len;
+            for (int c = 0; c < 3; c++) flen[c] = nlen[c];
             D++;
             __syncthreads();
         }

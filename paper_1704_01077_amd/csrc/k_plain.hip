@@ -22,8 +22,8 @@
 
 namespace cg = cooperative_groups;
 
-#define HEAVY_DEG 64
 #define PB 256
+#define CS 8   // counters per level parity: found, degree sum, light/heavy/giant appends
 
 struct PlainArgs {
     DevGraph g;
@@ -50,27 +50,30 @@ TKC_DEV uint64_t lanes_below() {
     return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
-// wave-aggregated append of newly found vertices to the light/heavy queues;
-// the level's appends count from zero in its own counters (cnts[0] light,
-// cnts[1] heavy) on top of the segment ends lbase / hbase, so the queue ends
-// every workgroup reads after the barrier never move under it
-TKC_DEV void q_append(bool isnew, int32_t w, int32_t dw, int32_t* ql, int32_t* qh, int64_t* cnts,
-                      int64_t lbase, int64_t hbase) {
-    bool hv = isnew && dw > HEAVY_DEG;
-    bool lt = isnew && !hv;
-    uint64_t ml = __ballot(lt), mh = __ballot(hv);
-    if ((ml | mh) == 0) return;
+// wave-aggregated append of newly found vertices to the light, heavy and
+// giant queues (by out-degree); the level's appends count from zero in its
+// own counters cnts[0..2] on top of the segment ends base[0..2], so the queue
+// ends every workgroup reads after the barrier never move under it
+TKC_DEV void q_append(bool isnew, int32_t w, int32_t dw, int32_t* const* q, int64_t* cnts,
+                      const int64_t* base) {
+    int cls = dw > GIANT_DEG ? 2 : (dw > HEAVY_DEG ? 1 : 0);
+    uint64_t m[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) m[c] = __ballot(isnew && cls == c);
+    if ((m[0] | m[1] | m[2]) == 0) return;
     int leader = __ffsll((long long)__ballot(1)) - 1;
-    int64_t bl = 0, bh = 0;
+    int64_t b[3] = {0, 0, 0};
     if (lane_id() == leader) {
-        if (ml) bl = fadd_rlx(&cnts[0], (int64_t)__popcll(ml));
-        if (mh) bh = fadd_rlx(&cnts[1], (int64_t)__popcll(mh));
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+            if (m[c]) b[c] = fadd_rlx(&cnts[c], (int64_t)__popcll(m[c]));
     }
-    bl = shfl64(bl, leader) + lbase;
-    bh = shfl64(bh, leader) + hbase;
     uint64_t below = lanes_below();
-    if (lt) ql[bl + __popcll(ml & below)] = w;
-    if (hv) qh[bh + __popcll(mh & below)] = w;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        int64_t bc = shfl64(b[c], leader) + base[c];
+        if (isnew && cls == c) q[c][bc + __popcll(m[c] & below)] = w;
+    }
 }
 
 // test-and-set of a visited bit; true for the single caller that sets it
@@ -115,9 +118,10 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
     const int32_t* __restrict__ rp = a.g.rp;
     const int32_t* __restrict__ ci = a.g.ci;
     const int32_t* __restrict__ deg = a.g.deg;
-    // ctr[p*4 + 0..3], p = level % 3: vertices found, their degree sum,
-    // light and heavy queue appends of that level
+    // ctr[p*CS + 0..4], p = level % 3: vertices found, their degree sum,
+    // light, heavy and giant queue appends of that level
     int64_t* ctr = a.w.ctr;
+    int32_t* const qs[3] = {a.w.ql, a.w.qh, a.w.qg};
     uint32_t* vis = a.w.vis;
     const int64_t words = ((int64_t)n + 31) / 32;
     const int32_t count = a.list ? a.list_count : a.ov.count;
@@ -151,17 +155,18 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
         }
         const int64_t dv = deg[v];
         if (boss) {
-            for (int q = 0; q < 12; q++) ctr[q] = 0;
+            for (int q = 0; q < 3 * CS; q++) ctr[q] = 0;
             for_rlx(&vis[v >> 5], 1u << (v & 31));
-            if (dv > HEAVY_DEG) a.w.qh[0] = v;
-            else a.w.ql[0] = v;
+            qs[dv > GIANT_DEG ? 2 : (dv > HEAVY_DEG ? 1 : 0)][0] = v;
             if (a.lb_mode) { a.w.lvl[v] = 0; a.w.levcnt[0] = 1; }
         }
         grid.sync();
 
         int64_t D = 0, nD = 1, SD = 0;
         int64_t U = dv, mf = dv, nf = 1, mdisc = dv;
-        int64_t ls = 0, le = dv > HEAVY_DEG ? 0 : 1, hs = 0, he = dv > HEAVY_DEG ? 1 : 0;
+        // frontier segments [st[c], en[c]) of the three queues
+        int64_t st[3] = {0, 0, 0}, en[3] = {0, 0, 0};
+        en[dv > GIANT_DEG ? 2 : (dv > HEAVY_DEG ? 1 : 0)] = 1;
         bool bu = false, used_bu = false;
         int status = 0;   // 1 exact, 2 cut
         int64_t mvis = 0, bytes = 0;
@@ -181,14 +186,11 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
                 for (int64_t q = gtid; q < 3 * words; q += nthreads) a.w.fb[q] = 0;
                 grid.sync();
                 uint32_t* fcur = a.w.fb + (D % 3) * words;
-                for (int64_t i = gtid; i < le - ls; i += nthreads) {
-                    int32_t u = a.w.ql[ls + i];
-                    for_rlx(&fcur[u >> 5], 1u << (u & 31));
-                }
-                for (int64_t i = gtid; i < he - hs; i += nthreads) {
-                    int32_t u = a.w.qh[hs + i];
-                    for_rlx(&fcur[u >> 5], 1u << (u & 31));
-                }
+                for (int c = 0; c < 3; c++)
+                    for (int64_t i = gtid; i < en[c] - st[c]; i += nthreads) {
+                        int32_t u = qs[c][st[c] + i];
+                        for_rlx(&fcur[u >> 5], 1u << (u & 31));
+                    }
                 grid.sync();
                 used_bu = true;
             }
@@ -199,11 +201,11 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
             int64_t my_cnt = 0, my_deg = 0;
             if (!bu) {
                 // push: light frontier vertices, one per lane
-                for (int64_t base = gwave * 64; base < le - ls; base += nwaves * 64) {
+                for (int64_t base = gwave * 64; base < en[0] - st[0]; base += nwaves * 64) {
                     int64_t i = base + lane;
                     int32_t e = 0, end = 0;
-                    if (i < le - ls) {
-                        int32_t u = a.w.ql[ls + i];
+                    if (i < en[0] - st[0]) {
+                        int32_t u = a.w.ql[st[0] + i];
                         e = rp[u]; end = rp[u + 1];
                     }
                     while (__any(e < end)) {
@@ -217,12 +219,12 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
                             my_cnt++; my_deg += dw;
                             if (a.lb_mode) a.w.lvl[w] = (int32_t)(D + 1);
                         }
-                        q_append(isnew, w, dw, a.w.ql, a.w.qh, &ctr[p * 4 + 2], le, he);
+                        q_append(isnew, w, dw, qs, &ctr[p * CS + 2], en);
                     }
                 }
                 // push: heavy frontier vertices, one per wave
-                for (int64_t hi = gwave; hi < he - hs; hi += nwaves) {
-                    int32_t u = a.w.qh[hs + hi];
+                for (int64_t hi = gwave; hi < en[1] - st[1]; hi += nwaves) {
+                    int32_t u = a.w.qh[st[1] + hi];
                     int32_t b = rp[u], end = rp[u + 1];
                     for (int32_t e0 = b; e0 < end; e0 += 64) {
                         int32_t e = e0 + lane;
@@ -236,7 +238,26 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
                             my_cnt++; my_deg += dw;
                             if (a.lb_mode) a.w.lvl[w] = (int32_t)(D + 1);
                         }
-                        q_append(isnew, w, dw, a.w.ql, a.w.qh, &ctr[p * 4 + 2], le, he);
+                        q_append(isnew, w, dw, qs, &ctr[p * CS + 2], en);
+                    }
+                }
+                // push: giant frontier vertices, the whole grid on each in turn
+                for (int64_t gi = 0; gi < en[2] - st[2]; gi++) {
+                    int32_t u = a.w.qg[st[2] + gi];
+                    int64_t b = rp[u], end = rp[u + 1];
+                    for (int64_t e0 = b + gwave * 64; e0 < end; e0 += nwaves * 64) {
+                        int64_t e = e0 + lane;
+                        bool isnew = false;
+                        int32_t w = 0, dw = 0;
+                        if (e < end) {
+                            w = ci[e];
+                            if (visit(vis, w)) { isnew = true; dw = deg[w]; }
+                        }
+                        if (isnew) {
+                            my_cnt++; my_deg += dw;
+                            if (a.lb_mode) a.w.lvl[w] = (int32_t)(D + 1);
+                        }
+                        q_append(isnew, w, dw, qs, &ctr[p * CS + 2], en);
                     }
                 }
             } else {
@@ -262,22 +283,23 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
                             if (a.lb_mode) a.w.lvl[w] = (int32_t)(D + 1);
                         }
                     }
-                    q_append(isnew, w, dw, a.w.ql, a.w.qh, &ctr[p * 4 + 2], le, he);
+                    q_append(isnew, w, dw, qs, &ctr[p * CS + 2], en);
                 }
             }
             my_cnt = wave_sum_i64(my_cnt);
             my_deg = wave_sum_i64(my_deg);
             if (lane == 0 && (my_cnt | my_deg)) {
-                fadd_rlx(&ctr[p * 4 + 0], my_cnt);
-                fadd_rlx(&ctr[p * 4 + 1], my_deg);
+                fadd_rlx(&ctr[p * CS + 0], my_cnt);
+                fadd_rlx(&ctr[p * CS + 1], my_deg);
             }
             grid.sync();
-            const int64_t cnt = ld_rlx(&ctr[p * 4 + 0]);
-            const int64_t dsum = ld_rlx(&ctr[p * 4 + 1]);
-            const int64_t tl = le + ld_rlx(&ctr[p * 4 + 2]), th = he + ld_rlx(&ctr[p * 4 + 3]);
+            const int64_t cnt = ld_rlx(&ctr[p * CS + 0]);
+            const int64_t dsum = ld_rlx(&ctr[p * CS + 1]);
+            int64_t tails[3];
+            for (int c = 0; c < 3; c++) tails[c] = en[c] + ld_rlx(&ctr[p * CS + 2 + c]);
             if (boss) {
                 int q = (int)((D + 2) % 3);
-                for (int j = 0; j < 4; j++) ctr[q * 4 + j] = 0;
+                for (int j = 0; j < CS; j++) ctr[q * CS + j] = 0;
             }
             D++;
             nD += cnt;
@@ -287,7 +309,7 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
             nf = cnt;
             mdisc += dsum;
             bytes += 16 * cnt;
-            ls = le; le = tl; hs = he; he = th;
+            for (int c = 0; c < 3; c++) { st[c] = en[c]; en[c] = tails[c]; }
             if (a.lb_mode && boss) a.w.levcnt[D] = cnt;
         }
         const int64_t maxD = D - (status == 1 ? 1 : 0);
@@ -300,8 +322,8 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
             grid.sync();
             const int64_t den = sq64(nD - 1);
             const int32_t sc = dir ? a.rc.scc[v] : 0;
-            for (int64_t i = gtid; i < le + he; i += nthreads) {
-                int32_t w = i < le ? a.w.ql[i] : a.w.qh[i - le];
+            for (int64_t i = gtid; i < en[0] + en[1] + en[2]; i += nthreads) {
+                int32_t w = i < en[0] ? a.w.ql[i] : (i < en[0] + en[1] ? a.w.qh[i - en[0]] : a.w.qg[i - en[0] - en[1]]);
                 if (w == v) continue;
                 if (dir && a.rc.scc[w] != sc) continue;
                 int64_t b = a.w.levtab[a.w.lvl[w]] - deg[w];
@@ -311,8 +333,8 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
             }
         }
         // clear the visited bits of every reached vertex
-        for (int64_t i = gtid; i < le + he; i += nthreads) {
-            int32_t w = i < le ? a.w.ql[i] : a.w.qh[i - le];
+        for (int64_t i = gtid; i < en[0] + en[1] + en[2]; i += nthreads) {
+            int32_t w = i < en[0] ? a.w.ql[i] : (i < en[0] + en[1] ? a.w.qh[i - en[0]] : a.w.qg[i - en[0] - en[1]]);
             vis[w >> 5] = 0;
         }
         if (used_bu)

@@ -1,11 +1,12 @@
 // Preprocessing kernels: out-degrees, connected components (r(v) of an
 // undirected graph), the neighbourhood-based lower bound of Sect. 5 and the
 // keys of the processing order (Sect. 4, computeBounds).
+#include <algorithm>
+
 #include "dev_common.hpp"
 #include "engine.hpp"
 
 #define NB_INF ((int64_t)1 << 62)
-#define HEAVY_DEG 64
 
 // --------------------------------------------------------------- degrees
 __global__ void k_degrees(int32_t n, const int32_t* __restrict__ rp, int32_t* __restrict__ deg) {
@@ -13,82 +14,111 @@ __global__ void k_degrees(int32_t n, const int32_t* __restrict__ rp, int32_t* __
     if (v < n) deg[v] = rp[v + 1] - rp[v];
 }
 
-// list of vertices with more than HEAVY_DEG arcs (wave-per-vertex work)
-__global__ void k_heavy_list(int32_t n, const int32_t* __restrict__ deg, int32_t* heavy,
-                             int32_t* nheavy) {
-    int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    bool h = v < n && deg[v] > HEAVY_DEG;
-    int tot;
-    int rank = wave_rank(h, &tot);
-    int leader = __ffsll((long long)__ballot(1)) - 1;
-    int base = 0;
-    if (lane_id() == leader && tot) base = fadd_rlx(nheavy, tot);
-    base = __shfl(base, leader, 64);
-    if (h) heavy[base + rank] = v;
-}
 
 // ----------------------------------------------- connected components
-// Lock-free union-find: roots only ever point to smaller ids, so every
-// component ends rooted at its smallest vertex and every chain of parents
-// strictly decreases (no cycles even under races).  Parent reads go
-// through agent-scope atomics so a retry never sees a stale cached line.
-TKC_DEV int32_t uf_find(int32_t* parent, int32_t x) {
+// r(v) of an undirected graph is the size of v's component (Sect. 4).
+// Lock-free union-find in the style of Afforest (Sutton, Ben-Nun, Barak,
+// 2018): every vertex first links to its first two neighbours, the
+// dominant component G is read off a sample of roots, and only vertices
+// outside G then link their remaining neighbours (an edge from G to a
+// vertex outside it is seen from the outside end, so nothing is missed).
+// Roots only ever point to smaller ids: every component ends rooted at its
+// smallest vertex and parent chains strictly decrease, so a find that reads
+// a stale parent still terminates; the compare-and-swap that links a root
+// is the only authority, and a failed swap retries with coherent reads.
+TKC_DEV int32_t uf_find_plain(const int32_t* parent, int32_t x) {
+    int32_t p = parent[x];
+    while (p != x) { x = p; p = parent[x]; }
+    return x;
+}
+TKC_DEV int32_t uf_find_coherent(int32_t* parent, int32_t x) {
     for (;;) {
         int32_t p = ld_rlx(&parent[x]);
         if (p == x) return x;
-        int32_t gp = ld_rlx(&parent[p]);
-        if (gp != p) st_rlx(&parent[x], gp);   // path halving (gp is still an ancestor)
-        x = gp;
+        x = p;
     }
 }
 TKC_DEV void uf_union(int32_t* parent, int32_t a, int32_t b) {
+    int32_t ra = uf_find_plain(parent, a), rb = uf_find_plain(parent, b);
     for (;;) {
-        int32_t ra = uf_find(parent, a), rb = uf_find(parent, b);
         if (ra == rb) return;
         int32_t hi = ra > rb ? ra : rb, lo = ra > rb ? rb : ra;
         int32_t exp = hi;
         if (__hip_atomic_compare_exchange_strong(&parent[hi], &exp, lo, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             return;
+        ra = uf_find_coherent(parent, a);
+        rb = uf_find_coherent(parent, b);
     }
 }
-__global__ void k_cc_init(int32_t n, int32_t* parent, int64_t* size) {
+__global__ void k_cc_init(int32_t n, int32_t* parent) {
     int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n) { parent[v] = v; size[v] = 0; }
+    if (v < n) parent[v] = v;
 }
-// light vertices: one thread each; heavy vertices: one wave each
-__global__ void k_cc_hook(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                          const int32_t* __restrict__ deg, const int32_t* __restrict__ heavy,
-                          int32_t nheavy, int32_t nlight_blocks, int32_t* parent) {
+// phase 1: link every vertex to its neighbour number `which` (one per
+// round, so in a round a thread mostly swaps only its own root entry)
+__global__ void k_cc_link_one(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                              int32_t which, int32_t* parent) {
+    int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    int32_t q = rp[u] + which;
+    if (q < rp[u + 1]) uf_union(parent, u, ci[q]);
+}
+// full path compression; snapshot of membership in the component rooted at giant
+__global__ void k_cc_compress(int32_t n, int32_t* parent, int32_t giant, uint8_t* in_giant) {
+    int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int32_t r = uf_find_coherent(parent, v);
+    parent[v] = r;
+    if (in_giant) in_giant[v] = (r == giant);
+}
+__global__ void k_cc_sample(int32_t n, int32_t ns, const int32_t* parent, int32_t* out) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ns) out[i] = parent[(int64_t)i * n / ns];
+}
+// phase 2: vertices outside the dominant component link their other
+// neighbours (light: one thread each; heavy: one wave each)
+__global__ void k_cc_link_rest(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                               const int32_t* __restrict__ deg, const int32_t* __restrict__ heavy,
+                               int32_t nheavy, int32_t nlight_blocks, int32_t first,
+                               const uint8_t* __restrict__ in_giant, int32_t* parent) {
     if ((int32_t)blockIdx.x < nlight_blocks) {
         int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-        if (u >= n || deg[u] > HEAVY_DEG) return;
-        for (int32_t e = rp[u]; e < rp[u + 1]; e++) {
-            int32_t w = ci[e];
-            if (w > u) uf_union(parent, u, w);
-        }
+        if (u >= n || deg[u] > HEAVY_DEG || in_giant[u]) return;
+        for (int32_t q = rp[u] + first; q < rp[u + 1]; q++) uf_union(parent, u, ci[q]);
     } else {
         int32_t wv = ((blockIdx.x - nlight_blocks) * blockDim.x + threadIdx.x) >> 6;
         if (wv >= nheavy) return;
         int32_t u = heavy[wv];
-        for (int32_t e = rp[u] + lane_id(); e < rp[u + 1]; e += 64) {
-            int32_t w = ci[e];
-            if (w > u) uf_union(parent, u, w);
-        }
+        if (in_giant[u]) return;
+        for (int32_t q = rp[u] + first + lane_id(); q < rp[u + 1]; q += 64) uf_union(parent, u, ci[q]);
     }
 }
-__global__ void k_cc_finish(int32_t n, int32_t* parent, int64_t* size) {
+// sizes: vertices outside the dominant component count into their root,
+// the dominant component's size is n minus all of those
+__global__ void k_cc_count(int32_t n, const int32_t* __restrict__ parent, int32_t giant, int64_t* size,
+                           int64_t* outside) {
+    __shared__ int64_t part[4];
     int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    int32_t root = uf_find(parent, v);
-    parent[v] = root;
-    fadd_rlx(&size[root], (int64_t)1);
+    int64_t mine = 0;
+    if (v < n) {
+        int32_t r = parent[v];
+        if (r != giant) { fadd_rlx(&size[r], (int64_t)1); mine = 1; }
+    }
+    int64_t s = wave_sum_i64(mine);
+    if (lane_id() == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = part[0] + part[1] + part[2] + part[3];
+        if (t) fadd_rlx(outside, t);
+    }
 }
-__global__ void k_cc_assign(int32_t n, const int32_t* parent, const int64_t* size, int64_t* alpha,
-                            int64_t* omega) {
+__global__ void k_cc_assign(int32_t n, const int32_t* parent, const int64_t* size, int32_t giant,
+                            const int64_t* outside, int64_t* alpha, int64_t* omega) {
     int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
-    int64_t s = size[parent[v]];
+    int32_t r = parent[v];
+    int64_t s = (r == giant) ? (int64_t)n - *outside : size[r];
     alpha[v] = s;
     omega[v] = s;
 }
@@ -187,13 +217,14 @@ TKC_DEV void nb_finish_vertex(int32_t s, uint64_t acc, int64_t k, int32_t d, con
 
 template <bool DIRECTED>
 __global__ void k_nb_round(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                           const int32_t* __restrict__ deg, const int32_t* __restrict__ heavy,
-                           int32_t nheavy, int32_t nlight_blocks, int64_t k,
-                           const int64_t* __restrict__ g1, const int64_t* __restrict__ g2,
+                           const int32_t* __restrict__ deg, const int32_t* __restrict__ ch_beg,
+                           const int32_t* __restrict__ ch_end, int32_t nchunks, int32_t nlight_blocks,
+                           int64_t k, const int64_t* __restrict__ g1, const int64_t* __restrict__ g2,
                            int64_t* __restrict__ gk, const int64_t* __restrict__ alpha,
-                           const int64_t* __restrict__ omega, NBState st, int32_t* nfin) {
-    bool fin = false;
+                           const int64_t* __restrict__ omega, NBState st, uint64_t* partial, int32_t* nfin) {
     if ((int32_t)blockIdx.x < nlight_blocks) {
+        // light vertices: one thread each, finished in place
+        bool fin = false;
         int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
         if (s < n && deg[s] <= HEAVY_DEG) {
             uint64_t acc = 0;
@@ -213,11 +244,11 @@ __global__ void k_nb_round(int32_t n, const int32_t* __restrict__ rp, const int3
         wave_rank(fin, &tot);
         if (lane_id() == 0 && tot) fadd_rlx(nfin, tot);
     } else {
-        int32_t wv = ((blockIdx.x - nlight_blocks) * blockDim.x + threadIdx.x) >> 6;
-        if (wv >= nheavy) return;   // wave-uniform
-        int32_t s = heavy[wv];
+        // arcs of heavy vertices: one wave per chunk, saturating partial sum
+        int32_t c = ((blockIdx.x - nlight_blocks) * blockDim.x + threadIdx.x) >> 6;
+        if (c >= nchunks) return;   // wave-uniform
         uint64_t acc = 0;
-        for (int32_t e = rp[s] + lane_id(); e < rp[s + 1]; e += 64) {
+        for (int32_t e = ch_beg[c] + lane_id(); e < ch_end[c]; e += 64) {
             acc += (uint64_t)g1[ci[e]];
             if (acc > (uint64_t)NB_INF) acc = NB_INF;
         }
@@ -226,11 +257,30 @@ __global__ void k_nb_round(int32_t n, const int32_t* __restrict__ rp, const int3
             acc += __shfl_xor(acc, o, 64);
             if (acc > (uint64_t)NB_INF) acc = NB_INF;
         }
-        if (lane_id() == 0) {
-            nb_finish_vertex<DIRECTED>(s, acc, k, deg[s], g2, gk, alpha, omega, st, &fin);
-            if (fin) fadd_rlx(nfin, 1);
-        }
+        if (lane_id() == 0) partial[c] = acc;
     }
+}
+// heavy vertices: sum their chunks' partials and finish (one thread each)
+template <bool DIRECTED>
+__global__ void k_nb_heavy(int32_t nheavy, const int32_t* __restrict__ heavy, const int32_t* __restrict__ hcb,
+                           const uint64_t* __restrict__ partial, const int32_t* __restrict__ deg, int64_t k,
+                           const int64_t* __restrict__ g2, int64_t* __restrict__ gk,
+                           const int64_t* __restrict__ alpha, const int64_t* __restrict__ omega, NBState st,
+                           int32_t* nfin) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool fin = false;
+    if (i < nheavy) {
+        uint64_t acc = 0;
+        for (int32_t c = hcb[i]; c < hcb[i + 1]; c++) {
+            acc += partial[c];
+            if (acc > (uint64_t)NB_INF) acc = NB_INF;
+        }
+        int32_t s = heavy[i];
+        nb_finish_vertex<DIRECTED>(s, acc, k, deg[s], g2, gk, alpha, omega, st, &fin);
+    }
+    int tot;
+    wave_rank(fin, &tot);
+    if (lane_id() == 0 && tot) fadd_rlx(nfin, tot);
 }
 
 // ------------------------------------------------------ order keys (Sect. 4)
@@ -258,34 +308,66 @@ __global__ void k_nb_keys(int32_t n, const int64_t* __restrict__ num, const int6
 // ------------------------------------------------------------ host side
 static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
-int tkc_launch_degrees(const DevGraph& g, int32_t* heavy, int32_t* nheavy, hipStream_t s) {
+int tkc_launch_degrees(const DevGraph& g, hipStream_t s) {
     int32_t n = g.n;
     hipLaunchKernelGGL(k_degrees, dim3(nblk(n, 256)), dim3(256), 0, s, n, g.rp, g.deg);
-    hipMemsetAsync(nheavy, 0, sizeof(int32_t), s);
-    hipLaunchKernelGGL(k_heavy_list, dim3(nblk(n, 256)), dim3(256), 0, s, n, g.deg, heavy, nheavy);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int tkc_launch_cc(const DevGraph& g, const int32_t* heavy, int32_t nheavy, int32_t* parent,
-                  int64_t* size, int64_t* alpha, int64_t* omega, hipStream_t s) {
+int tkc_launch_cc(const DevGraph& g, int32_t* parent, int64_t* size, int64_t* alpha, int64_t* omega,
+                  uint8_t* in_giant, int32_t* sample_host, hipStream_t s) {
     int32_t n = g.n;
+    const int32_t* heavy = g.heavy;
+    const int32_t nheavy = g.nheavy;
     int nl = nblk(n, 256);
-    hipLaunchKernelGGL(k_cc_init, dim3(nl), dim3(256), 0, s, n, parent, size);
+    const int32_t first = 2;
+    hipLaunchKernelGGL(k_cc_init, dim3(nl), dim3(256), 0, s, n, parent);
+    for (int32_t which = 0; which < first; which++) {
+        hipLaunchKernelGGL(k_cc_link_one, dim3(nl), dim3(256), 0, s, n, g.rp, g.ci, which, parent);
+        hipLaunchKernelGGL(k_cc_compress, dim3(nl), dim3(256), 0, s, n, parent, -1, (uint8_t*)nullptr);
+    }
+    // dominant component: most frequent root among evenly spaced samples
+    const int NS = 1024;
+    int ns = n < NS ? n : NS;
+    int32_t* sample_dev = (int32_t*)size;   // free until the counting below
+    hipLaunchKernelGGL(k_cc_sample, dim3(nblk(ns, 256)), dim3(256), 0, s, n, ns, parent, sample_dev);
+    if (hipMemcpyAsync(sample_host, sample_dev, 4 * (size_t)ns, hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
+    if (hipStreamSynchronize(s) != hipSuccess) return -1;
+    // mode of the sample (ties: smallest root)
+    int32_t giant = sample_host[0];
+    {
+        std::sort(sample_host, sample_host + ns);
+        int best = 0;
+        for (int i = 0; i < ns;) {
+            int j = i;
+            while (j < ns && sample_host[j] == sample_host[i]) j++;
+            if (j - i > best) { best = j - i; giant = sample_host[i]; }
+            i = j;
+        }
+    }
+    hipLaunchKernelGGL(k_cc_compress, dim3(nl), dim3(256), 0, s, n, parent, giant, in_giant);
     int nh = nblk((int64_t)nheavy * 64, 256);
-    hipLaunchKernelGGL(k_cc_hook, dim3(nl + nh), dim3(256), 0, s, n, g.rp, g.ci, g.deg, heavy,
-                       nheavy, nl, parent);
-    hipLaunchKernelGGL(k_cc_finish, dim3(nl), dim3(256), 0, s, n, parent, size);
-    hipLaunchKernelGGL(k_cc_assign, dim3(nl), dim3(256), 0, s, n, parent, size, alpha, omega);
+    hipLaunchKernelGGL(k_cc_link_rest, dim3(nl + nh), dim3(256), 0, s, n, g.rp, g.ci, g.deg, heavy, nheavy,
+                       nl, first, in_giant, parent);
+    hipLaunchKernelGGL(k_cc_compress, dim3(nl), dim3(256), 0, s, n, parent, -1, (uint8_t*)nullptr);
+    // the dominant component may have been linked under a smaller root
+    if (hipMemcpyAsync(sample_host, parent + giant, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
+    if (hipStreamSynchronize(s) != hipSuccess) return -1;
+    giant = sample_host[0];
+    if (hipMemsetAsync(size, 0, sizeof(int64_t) * ((size_t)n + 1), s) != hipSuccess) return -1;
+    hipLaunchKernelGGL(k_cc_count, dim3(nl), dim3(256), 0, s, n, parent, giant, size, size + n);
+    hipLaunchKernelGGL(k_cc_assign, dim3(nl), dim3(256), 0, s, n, parent, size, giant, size + n, alpha, omega);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 // NB bound: returns the number of rounds, -1 on error.  gbuf holds 3*n int64.
-int tkc_launch_nb(const DevGraph& g, const int32_t* heavy, int32_t nheavy, const int64_t* alpha,
-                  const int64_t* omega, int64_t* gbuf, int64_t* sum, int64_t* vis, uint8_t* flags,
-                  int64_t* num, int64_t* den, int32_t* nfin_dev, int32_t* nfin_host, hipStream_t s) {
+int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega, int64_t* gbuf, int64_t* sum,
+                  int64_t* vis, uint8_t* flags, int64_t* num, int64_t* den, uint64_t* partial,
+                  int32_t* nfin_dev, int32_t* nfin_host, hipStream_t s) {
     int32_t n = g.n;
     int nl = nblk(n, 256);
-    int nh = nblk((int64_t)nheavy * 64, 256);
+    int nc = nblk((int64_t)g.nchunks * 64, 256);
+    int nhb = nblk(g.nheavy, 256);
     NBState st{sum, vis, flags, num, den};
     int64_t* buf[3] = {gbuf, gbuf + n, gbuf + 2 * (int64_t)n};
     hipMemsetAsync(nfin_dev, 0, sizeof(int32_t), s);
@@ -307,12 +389,21 @@ int tkc_launch_nb(const DevGraph& g, const int32_t* heavy, int32_t nheavy, const
             int64_t* g1 = buf[(k - 1) % 3];
             int64_t* g2 = buf[(k - 2) % 3];
             int64_t* gk = buf[k % 3];
-            if (g.directed)
-                hipLaunchKernelGGL(k_nb_round<true>, dim3(nl + nh), dim3(256), 0, s, n, g.rp, g.ci,
-                                   g.deg, heavy, nheavy, nl, k, g1, g2, gk, alpha, omega, st, nfin_dev);
-            else
-                hipLaunchKernelGGL(k_nb_round<false>, dim3(nl + nh), dim3(256), 0, s, n, g.rp, g.ci,
-                                   g.deg, heavy, nheavy, nl, k, g1, g2, gk, alpha, omega, st, nfin_dev);
+            if (g.directed) {
+                hipLaunchKernelGGL(k_nb_round<true>, dim3(nl + nc), dim3(256), 0, s, n, g.rp, g.ci, g.deg,
+                                   g.ch_beg, g.ch_end, g.nchunks, nl, k, g1, g2, gk, alpha, omega, st, partial,
+                                   nfin_dev);
+                if (g.nheavy)
+                    hipLaunchKernelGGL(k_nb_heavy<true>, dim3(nhb), dim3(256), 0, s, g.nheavy, g.heavy, g.hcb,
+                                       partial, g.deg, k, g2, gk, alpha, omega, st, nfin_dev);
+            } else {
+                hipLaunchKernelGGL(k_nb_round<false>, dim3(nl + nc), dim3(256), 0, s, n, g.rp, g.ci, g.deg,
+                                   g.ch_beg, g.ch_end, g.nchunks, nl, k, g1, g2, gk, alpha, omega, st, partial,
+                                   nfin_dev);
+                if (g.nheavy)
+                    hipLaunchKernelGGL(k_nb_heavy<false>, dim3(nhb), dim3(256), 0, s, g.nheavy, g.heavy, g.hcb,
+                                       partial, g.deg, k, g2, gk, alpha, omega, st, nfin_dev);
+            }
         }
         if (hipGetLastError() != hipSuccess) return -1;
     }

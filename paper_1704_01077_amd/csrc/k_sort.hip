@@ -24,7 +24,11 @@ __global__ void k_rs_mask(const uint32_t* __restrict__ keys, int32_t n, uint32_t
         o |= __shfl_xor(o, s, 64);
         a &= __shfl_xor(a, s, 64);
     }
-    if (lane_id() == 0) {
+    __shared__ uint32_t so[4], sa[4];
+    if (lane_id() == 0) { so[threadIdx.x >> 6] = o; sa[threadIdx.x >> 6] = a; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); w++) { o |= so[w]; a &= sa[w]; }
         __hip_atomic_fetch_or(&mask[0], o, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_and(&mask[1], a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -169,7 +173,7 @@ int tkc_sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* tmp_keys, int32_t* t
     uint32_t init[2] = {0u, 0xffffffffu};
     if (hipMemcpyAsync(mask_dev, init, sizeof(init), hipMemcpyHostToDevice, s) != hipSuccess) return -1;
     int gb = rs_tiles(n);
-    if (gb > 1024) gb = 1024;
+    if (gb > 256) gb = 256;
     hipLaunchKernelGGL(k_rs_mask, dim3(gb), dim3(256), 0, s, keys, n, mask_dev);
     if (hipMemcpyAsync(mask_host, mask_dev, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
         return -1;
