@@ -110,10 +110,15 @@ int tkc_ctx_destroy(tkc_ctx *ctx);
 
 /* Tuning knobs (0 keeps the current value).  batch_width in {32, 64, 128,
  * 256}; td_bu_alpha / bu_td_beta are the push->pull and pull->push switch
- * thresholds (Beamer's alpha and beta); swarm_qcap is the queue capacity of
- * one per-workgroup search before it is handed to the batched engine. */
+ * thresholds (Beamer's alpha and beta) of one-source searches; batch_alpha
+ * is the push->pull threshold of batched searches (a pull over several lanes
+ * rarely stops early, so it pays later); swarm_qcap is the queue capacity
+ * of one per-workgroup search before it is handed to the batched engine;
+ * seed_lanes caps the lanes of the first (seed) batch of the hybrid mode
+ * (0: the batch width).  Errors: TKC_EINVAL. */
 int tkc_ctx_set_tuning(tkc_ctx *ctx, int32_t batch_width, int32_t td_bu_alpha,
-                       int32_t bu_td_beta, int32_t swarm_qcap, int32_t block_size);
+                       int32_t bu_td_beta, int32_t batch_alpha, int32_t swarm_qcap,
+                       int32_t seed_lanes);
 
 /* Copy a graph to device memory.  row_ptr[n+1], col_idx[m_arcs] give the
  * out-arcs; rrow_ptr/rcol_idx give the in-arcs and are required iff

@@ -82,15 +82,16 @@ static size_t ws_items(Workspace& ws, const WsShape& sh, std::vector<WsItem>& it
         {(void**)&ws.tS, 8 * (size_t)sh.kcap, false}, {(void**)&ws.tR, 8 * (size_t)sh.kcap, false},
         {(void**)&ws.tI, 4 * (size_t)sh.kcap, false},
         {(void**)&ws.stats, 8 * 4 * ST_COUNT, false},
+        {(void**)&ws.bar, 4 * tkc_bar_words(4096), true},
         // plain engine
         {(void**)&ws.p_vis, 4 * words, true}, {(void**)&ws.p_fb, 12 * words, true},
         {(void**)&ws.p_ql, 4 * n, false}, {(void**)&ws.p_qh, 4 * n, false},
-        {(void**)&ws.p_qg, 4 * n, false}, {(void**)&ws.p_ctr, 8 * 32, true}, {(void**)&ws.p_lvl, 4 * n, false},
+        {(void**)&ws.p_qg, 8 * ((size_t)sh.nchunks + 64), false}, {(void**)&ws.p_ctr, 8 * 32, true}, {(void**)&ws.p_lvl, 4 * n, false},
         {(void**)&ws.p_levcnt, 8 * (n + 2), false}, {(void**)&ws.p_levtab, 8 * (n + 2), false},
         // batched engine
         {(void**)&ws.b_vis, 8 * n * nw, true}, {(void**)&ws.b_frt0, 8 * n * nw, true},
         {(void**)&ws.b_frt1, 8 * n * nw, true}, {(void**)&ws.b_nxt, 8 * n * nw, true},
-        {(void**)&ws.b_list, 24 * n, false}, {(void**)&ws.b_mark, 4 * n, true},
+        {(void**)&ws.b_list, 16 * n + 16 * ((size_t)sh.nchunks + 64), false}, {(void**)&ws.b_mark, 4 * n, true},
         {(void**)&ws.b_ctr, 8 * 2048, true}, {(void**)&ws.b_cand, 4 * 256, false},
         {(void**)&ws.b_hist, sh.lb ? 8 * lcap * W : 8, false},
         {(void**)&ws.b_levtab, sh.lb ? 8 * lcap * W : 8, false},
@@ -190,17 +191,18 @@ extern "C" int tkc_ctx_destroy(tkc_ctx* c) {
 }
 
 extern "C" int tkc_ctx_set_tuning(tkc_ctx* c, int32_t batch_width, int32_t td_bu_alpha, int32_t bu_td_beta,
-                                  int32_t swarm_qcap, int32_t block_size) {
+                                  int32_t batch_alpha, int32_t swarm_qcap, int32_t seed_lanes) {
     if (!c) return tkc_fail(TKC_EINVAL, "ctx is NULL");
     if (batch_width && batch_width != 32 && batch_width != 64 && batch_width != 128 && batch_width != 256)
         return tkc_fail(TKC_EINVAL, "batch_width must be 32, 64, 128 or 256");
-    if (td_bu_alpha < 0 || bu_td_beta < 0 || swarm_qcap < 0 || block_size < 0)
+    if (td_bu_alpha < 0 || bu_td_beta < 0 || batch_alpha < 0 || swarm_qcap < 0 || seed_lanes < 0)
         return tkc_fail(TKC_EINVAL, "negative tuning value");
     if (batch_width) c->tune.batch_width = batch_width;
     if (td_bu_alpha) c->tune.td_bu_alpha = td_bu_alpha;
     if (bu_td_beta) c->tune.bu_td_beta = bu_td_beta;
+    if (batch_alpha) c->tune.batch_alpha = batch_alpha;
     if (swarm_qcap) c->tune.swarm_qcap = swarm_qcap;
-    if (block_size) c->tune.block = block_size;
+    if (seed_lanes) c->tune.seed_lanes = seed_lanes;
     return TKC_OK;
 }
 
@@ -287,8 +289,9 @@ extern "C" int tkc_graph_upload(tkc_ctx* c, int32_t n, int64_t m, const int32_t*
     g->n = n;
     g->m = m;
     g->directed = directed;
-    // heavy vertices and their arc chunks (ascending ids: deterministic)
-    std::vector<int32_t> hv, hcb(1, 0), cb, ce;
+    // heavy vertices and their arc chunks (ascending ids: deterministic), for
+    // the out-arcs and (directed) the in-arcs
+    std::vector<int32_t> hv, hcb(1, 0), cb, ce, cv, rcb, rce, rcv;
     for (int32_t u = 0; u < n; u++) {
         int32_t d = hrp[u + 1] - hrp[u];
         if (d <= HEAVY_DEG) continue;
@@ -296,13 +299,25 @@ extern "C" int tkc_graph_upload(tkc_ctx* c, int32_t n, int64_t m, const int32_t*
         for (int32_t b = hrp[u]; b < hrp[u + 1]; b += CHUNK_ARCS) {
             cb.push_back(b);
             ce.push_back(std::min(b + CHUNK_ARCS, hrp[u + 1]));
+            cv.push_back(u);
         }
         hcb.push_back((int32_t)cb.size());
     }
+    if (directed) {
+        for (int32_t u = 0; u < n; u++) {
+            if (hrrp[u + 1] - hrrp[u] <= HEAVY_DEG) continue;
+            for (int32_t b = hrrp[u]; b < hrrp[u + 1]; b += CHUNK_ARCS) {
+                rcb.push_back(b);
+                rce.push_back(std::min(b + CHUNK_ARCS, hrrp[u + 1]));
+                rcv.push_back(u);
+            }
+        }
+    }
     g->nheavy = (int32_t)hv.size();
     g->nchunks = (int32_t)cb.size();
+    g->rnchunks = directed ? (int32_t)rcb.size() : g->nchunks;
     size_t bytes = 4 * (size_t)(n + 1) + 4 * (size_t)(m ? m : 1) + 4 * (size_t)n + 4 * (hv.size() + 1) +
-                   4 * hcb.size() + 8 * (cb.size() + 1) + 8 * 256;
+                   4 * hcb.size() + 12 * (cb.size() + 1) + 12 * (rcb.size() + 1) + 16 * 256;
     if (directed) bytes += 4 * (size_t)(n + 1) + 4 * (size_t)(m ? m : 1);
     if (hipMalloc(&g->dbase, bytes + 1024) != hipSuccess) {
         hipGetLastError();
@@ -318,6 +333,16 @@ extern "C" int tkc_graph_upload(tkc_ctx* c, int32_t n, int64_t m, const int32_t*
     g->hcb = (int32_t*)take(4 * hcb.size());
     g->ch_beg = (int32_t*)take(4 * (cb.size() + 1));
     g->ch_end = (int32_t*)take(4 * (cb.size() + 1));
+    g->ch_vtx = (int32_t*)take(4 * (cb.size() + 1));
+    if (directed) {
+        g->rch_beg = (int32_t*)take(4 * (rcb.size() + 1));
+        g->rch_end = (int32_t*)take(4 * (rcb.size() + 1));
+        g->rch_vtx = (int32_t*)take(4 * (rcb.size() + 1));
+    } else {
+        g->rch_beg = g->ch_beg;
+        g->rch_end = g->ch_end;
+        g->rch_vtx = g->ch_vtx;
+    }
     if (directed) {
         g->rrp = (int32_t*)take(4 * (size_t)(n + 1));
         g->rci = (int32_t*)take(4 * (size_t)(m ? m : 1));
@@ -337,7 +362,11 @@ extern "C" int tkc_graph_upload(tkc_ctx* c, int32_t n, int64_t m, const int32_t*
     if (!rc && ((hv.size() && hipMemcpyAsync(g->heavy, hv.data(), 4 * hv.size(), hipMemcpyHostToDevice, s)) ||
                 hipMemcpyAsync(g->hcb, hcb.data(), 4 * hcb.size(), hipMemcpyHostToDevice, s) ||
                 (cb.size() && (hipMemcpyAsync(g->ch_beg, cb.data(), 4 * cb.size(), hipMemcpyHostToDevice, s) ||
-                               hipMemcpyAsync(g->ch_end, ce.data(), 4 * ce.size(), hipMemcpyHostToDevice, s)))))
+                               hipMemcpyAsync(g->ch_end, ce.data(), 4 * ce.size(), hipMemcpyHostToDevice, s) ||
+                               hipMemcpyAsync(g->ch_vtx, cv.data(), 4 * cv.size(), hipMemcpyHostToDevice, s))) ||
+                (rcb.size() && (hipMemcpyAsync(g->rch_beg, rcb.data(), 4 * rcb.size(), hipMemcpyHostToDevice, s) ||
+                                hipMemcpyAsync(g->rch_end, rce.data(), 4 * rce.size(), hipMemcpyHostToDevice, s) ||
+                                hipMemcpyAsync(g->rch_vtx, rcv.data(), 4 * rcv.size(), hipMemcpyHostToDevice, s)))))
         rc = tkc_fail(TKC_EDEVICE, "heavy-vertex table copy failed");
     if (!rc) {
         DevGraph dg = g->view();
@@ -379,7 +408,7 @@ WsShape tkc_shape_for(tkc_ctx* c, tkc_graph* g, int32_t k, bool lb) {
     sh.kcap = std::max(k, 1);
     sh.lb = lb;
     sh.lcap = (int32_t)std::min<int64_t>((int64_t)g->n + 2, 65000);
-    sh.nchunks = g->nchunks;
+    sh.nchunks = std::max(g->nchunks, g->rnchunks);
     sh.qcap = std::max(64, std::min(c->tune.swarm_qcap, g->n));
     sh.swarm_blocks = std::max(1, tkc_swarm_max_blocks(256));
     // the private bitmaps of the per-workgroup engine cost blocks * n/8 bytes;
@@ -444,19 +473,23 @@ static DevTopk topk_view(Workspace& ws) {
 }
 
 static PlainWork plain_view(Workspace& ws) {
-    PlainWork w;
+    PlainWork w{};
     w.vis = ws.p_vis; w.fb = ws.p_fb; w.ql = ws.p_ql; w.qh = ws.p_qh; w.qg = ws.p_qg; w.ctr = ws.p_ctr;
+    w.ccap = (int64_t)ws.shape.nchunks + 64;
     w.lvl = ws.p_lvl; w.levcnt = ws.p_levcnt; w.levtab = ws.p_levtab;
+    w.bar = ws.bar;
     return w;
 }
 static BatchWork batch_view(Workspace& ws) {
-    BatchWork w;
+    BatchWork w{};
     w.vis = ws.b_vis; w.frt0 = ws.b_frt0; w.frt1 = ws.b_frt1; w.nxt = ws.b_nxt;
     w.list = ws.b_list; w.touched = ws.b_mark; w.ctr = ws.b_ctr; w.lanes = nullptr;
+    w.ccap = (int64_t)ws.shape.nchunks + 64;
     w.lvl = ws.b_lvl; w.hist = ws.b_hist; w.levtab = ws.b_levtab; w.lcap = ws.shape.lcap;
     w.cand = ws.b_cand;
     w.trace = ws.trace;
     w.trace_cap = ws.trace ? 4096 : 0;
+    w.bar = ws.bar;
     return w;
 }
 
@@ -591,8 +624,10 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
         trace_reset(c);
         {
             EngineTimer tm(c, &ms_eng[1], &nl_eng[1]);
+            EngineTuning seed = c->tune;
+            seed.lanes_cap = seed.seed_lanes;
             if (tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_batch, nullptr, 0, 0, -1, false,
-                                 false, nullptr, nullptr, c->tune, s, &grid))
+                                 false, nullptr, nullptr, seed, s, &grid))
                 return tkc_fail(TKC_EDEVICE, "batched seed launch failed: %s", hipGetErrorString(hipGetLastError()));
             tm.done();
         }
@@ -602,7 +637,7 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
         int32_t cursor = (int32_t)hs[ST_CURSOR];
         bool stopped = hs[ST_STOP] != 0;
         if (!stopped && cursor < n) {
-            SwarmWork sw;
+            SwarmWork sw{};
             sw.vis = ws.s_vis;
             sw.queue = ws.s_queue;
             sw.deferred = ws.s_deferred;

@@ -40,6 +40,58 @@ TKC_DEV T for_wg(T* p, T v) {
     return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// ------------------------------------------------------------ grid barrier
+// Barrier of a cooperative (all workgroups resident) launch.  Same-address
+// atomics serialize at the memory side (~75 ns each on MI355X), so a flat
+// counter costs ~75 ns per workgroup; here arrivals go up a tree of
+// counters with fan-in 16, each counter on its own 128-byte line, and only
+// the last arriver of a group climbs.  The overall last arriver bumps the
+// generation word that everyone else polls.  Counters return to zero after
+// every use (the last arriver of a group resets it before climbing; nobody
+// re-arrives before the generation changes).  Layout of `bar`: word 0 is
+// the generation, counter slot s lives at word (s + 1) * TKC_BAR_PAD.
+// Every wave publishes its own stores with an agent-scope release fence
+// before the workgroup barrier: a workgroup barrier alone does not wait for
+// a wave's outstanding global stores, and a fence only covers the stores of
+// the wave that executes it.  Every wave then takes an agent-scope acquire
+// fence after the release, before it reads what other workgroups wrote.
+#define TKC_BAR_FAN 16
+#define TKC_BAR_PAD 32
+TKC_DEV void grid_barrier(uint32_t* bar, uint32_t nblocks) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t* gen = bar;
+        uint32_t g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t idx = blockIdx.x, width = nblocks, base = 0;
+        for (;;) {
+            uint32_t grp = idx / TKC_BAR_FAN;
+            uint32_t ngroups = (width + TKC_BAR_FAN - 1) / TKC_BAR_FAN;
+            uint32_t gsize = width - grp * TKC_BAR_FAN;
+            if (gsize > TKC_BAR_FAN) gsize = TKC_BAR_FAN;
+            uint32_t* c = bar + (size_t)(base + grp + 1) * TKC_BAR_PAD;
+            uint32_t old = __hip_atomic_fetch_add(c, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (old + 1 != gsize) {
+                while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
+                    __builtin_amdgcn_s_sleep(1);
+                break;
+            }
+            __hip_atomic_store(c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (ngroups == 1) {
+                __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            base += ngroups;
+            idx = grp;
+            width = ngroups;
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+// words of barrier state for up to `nblocks` workgroups
+static inline size_t tkc_bar_words(uint32_t nblocks) { return (size_t)(nblocks + 2) * TKC_BAR_PAD; }
+
 // ------------------------------------------------------------ wave helpers
 TKC_DEV int lane_id() { return (int)__lane_id(); }
 

@@ -24,9 +24,14 @@ struct DevGraph {
     const int32_t* ch_beg;
     const int32_t* ch_end;
     int32_t nchunks;
+    // in-arc chunks of the vertices with more than HEAVY_DEG in-arcs (pull
+    // steps; the same table as above for undirected graphs)
+    const int32_t* rch_vtx;
+    const int32_t* rch_beg;
+    const int32_t* rch_end;
+    int32_t rnchunks;
 };
 #define HEAVY_DEG 64
-#define GIANT_DEG 1024
 #define CHUNK_ARCS 512
 
 // reachability and bounds of one query
@@ -65,9 +70,11 @@ struct BoundsView {
 struct EngineTuning {
     int32_t td_bu_alpha = 14;    // push -> pull when frontier arcs > unexplored arcs / alpha
     int32_t bu_td_beta = 24;     // pull -> push when frontier vertices < n / beta
+    int32_t batch_alpha = 14;    // the same push -> pull rule for batched searches
     int32_t batch_width = 64;
-    int32_t swarm_qcap = 16384;
-    int32_t block = 256;
+    int32_t swarm_qcap = 65536;
+    int32_t seed_lanes = 0;      // lanes of the hybrid mode's seed batch (0: batch_width)
+    int32_t lanes_cap = 0;       // lanes used per batch in one launch (0: batch_width)
 };
 
 // k_prep.hip
@@ -100,11 +107,13 @@ struct PlainWork {
     uint32_t* fb;        // 3 x n bits (frontier bitmaps of pull steps)
     int32_t* ql;         // queue of light vertices (n)
     int32_t* qh;         // queue of heavy vertices (n)
-    int32_t* qg;         // queue of giant vertices (n)
+    int32_t* qg;         // chunk queue: owners [0, ccap), first arcs [ccap, 2 ccap)
+    int64_t ccap;
     int64_t* ctr;        // 3 x 8 level counters
     int32_t* lvl;        // distance from the source (level-based updates)
     int64_t* levcnt;     // vertices per level (n + 2)
     int64_t* levtab;     // Lev(i) table (n + 2)
+    uint32_t* bar;       // grid barrier state (zeroed once)
 };
 int tkc_launch_plain(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv, DevTopk tk,
                      PlainWork w, int64_t* stats, const int32_t* list, int32_t list_count,
@@ -116,7 +125,8 @@ struct BatchWork {
     uint64_t* frt0;      // n * nw
     uint64_t* frt1;      // n * nw
     uint64_t* nxt;       // n * nw
-    int32_t* list;       // frontier lists, 2 * n
+    int32_t* list;       // frontier lists: 4 n vertex entries + 4 ccap chunk entries
+    int64_t ccap;        // chunk entries per list
     int32_t* touched;    // every vertex touched in the batch (for clearing), cap n
     int64_t* ctr;        // per-lane level counters, 3 * 2 * 256 + misc
     int64_t* lanes;      // per-lane state
@@ -127,6 +137,7 @@ struct BatchWork {
     int32_t* cand;       // selected candidates of a batch (W)
     int64_t* trace;      // optional per-level records (8 int64 each), [0] = count
     int64_t trace_cap;
+    uint32_t* bar;       // grid barrier state (zeroed once)
 };
 int tkc_launch_batch(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv, DevTopk tk,
                      BatchWork w, int64_t* stats, const int32_t* list, int32_t list_count,

@@ -41,6 +41,7 @@ struct Workspace {
     int64_t *tS, *tR;
     int32_t* tI;
     int64_t* stats;
+    uint32_t* bar;
     // plain engine
     uint32_t *p_vis, *p_fb;
     int32_t *p_ql, *p_qh, *p_qg, *p_lvl;
@@ -76,8 +77,9 @@ struct tkc_graph {
     int32_t* deg = nullptr;
     int32_t* heavy = nullptr;
     int32_t nheavy = 0;
-    int32_t *hcb = nullptr, *ch_beg = nullptr, *ch_end = nullptr;
-    int32_t nchunks = 0;
+    int32_t *hcb = nullptr, *ch_beg = nullptr, *ch_end = nullptr, *ch_vtx = nullptr;
+    int32_t *rch_beg = nullptr, *rch_end = nullptr, *rch_vtx = nullptr;
+    int32_t nchunks = 0, rnchunks = 0;
     int32_t server_refs = 0;
     int32_t auto_variant = 0;
     // directed graphs keep a host copy for the reachability bounds
@@ -98,6 +100,7 @@ struct tkc_graph {
         g.rp = rp; g.ci = ci; g.rrp = rrp; g.rci = rci; g.deg = deg;
         g.heavy = heavy; g.nheavy = nheavy; g.hcb = hcb; g.ch_beg = ch_beg; g.ch_end = ch_end;
         g.nchunks = nchunks;
+        g.rch_vtx = rch_vtx; g.rch_beg = rch_beg; g.rch_end = rch_end; g.rnchunks = rnchunks;
         return g;
     }
 };

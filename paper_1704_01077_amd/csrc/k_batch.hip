@@ -13,12 +13,8 @@
 // selects the next candidates from the order (stop and skip rules of
 // Alg. 1) and every workgroup replicates the per-lane control so all take
 // the same path through the grid barriers.
-#include <hip/hip_cooperative_groups.h>
-
 #include "dev_common.hpp"
 #include "engine.hpp"
-
-namespace cg = cooperative_groups;
 
 #define BB 256
 #define MAXW 256
@@ -30,10 +26,11 @@ namespace cg = cooperative_groups;
 #define C_UCNT(p) (C_BASE + (p) * 8 + 0)
 #define C_UDEG(p) (C_BASE + (p) * 8 + 1)
 #define C_T(p, c) (C_BASE + (p) * 8 + 2 + (c))   // next list tails: light, heavy, giant
+#define C_L0 (C_BASE + 28)                    // level-0 list lengths (3)
 #define C_NSEL (C_BASE + 24)
 #define C_POS (C_BASE + 25)
 #define C_STOP (C_BASE + 26)
-#define C_TOTAL (C_BASE + 32)
+#define C_TOTAL (C_BASE + 32)   // C_L0 + 2 < C_TOTAL
 
 struct BatchArgs {
     DevGraph g;
@@ -51,11 +48,13 @@ struct BatchArgs {
     int32_t no_cut;        // full searches, results to out_S / out_r only
     int32_t until_x;       // stop after the batch in which x becomes finite
     int32_t W;
+    int32_t Wsel;          // lanes filled per batch (<= W)
     int32_t alpha_td;
     int32_t beta_bu;
     int64_t* out_S;
     int64_t* out_r;
     int32_t* mark;         // per-vertex level stamp (NW > 1)
+    uint32_t* bar;         // grid barrier state
 };
 
 TKC_DEV int64_t shfl64b(int64_t v, int src) {
@@ -79,23 +78,23 @@ struct Mask {
     }
 };
 
-// wave-aggregated append to the next level's light / heavy / giant lists
+// wave-aggregated append to the next level's light / heavy vertex lists
 TKC_DEV void list_append(bool isnew, int32_t w, int32_t dw, int32_t* const* lists, int64_t* tails) {
-    int cls = dw > GIANT_DEG ? 2 : (dw > HEAVY_DEG ? 1 : 0);
-    uint64_t m[3];
+    int cls = dw > HEAVY_DEG ? 1 : 0;
+    uint64_t m[2];
 #pragma unroll
-    for (int c = 0; c < 3; c++) m[c] = __ballot(isnew && cls == c);
-    if ((m[0] | m[1] | m[2]) == 0) return;
+    for (int c = 0; c < 2; c++) m[c] = __ballot(isnew && cls == c);
+    if ((m[0] | m[1]) == 0) return;
     int leader = __ffsll((long long)__ballot(1)) - 1;
-    int64_t b[3] = {0, 0, 0};
+    int64_t b[2] = {0, 0};
     if (lane_id() == leader) {
 #pragma unroll
-        for (int c = 0; c < 3; c++)
+        for (int c = 0; c < 2; c++)
             if (m[c]) b[c] = fadd_rlx(&tails[c], (int64_t)__popcll(m[c]));
     }
     uint64_t bm = below_mask();
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
+    for (int c = 0; c < 2; c++) {
         int64_t bc = shfl64b(b[c], leader);
         if (isnew && cls == c) lists[c][bc + __popcll(m[c] & bm)] = w;
     }
@@ -103,9 +102,15 @@ TKC_DEV void list_append(bool isnew, int32_t w, int32_t dw, int32_t* const* list
 
 // OR the lanes nb into w's next word(s); true for exactly one caller per
 // vertex and level (the one that makes it appear in the next list)
+// (the visited words are read with plain loads: they only change in the
+// epilogue, which barriers separate from the expansion; a plain read of the
+// next word that already holds every lane in nb proves another caller has
+// set it first, since the word only gains bits during the expansion)
 template <int NW>
 TKC_DEV bool push_lanes(uint64_t* nxt, int32_t* mark, int32_t w, const Mask<NW>& nb, int32_t stamp) {
     if (NW == 1) {
+        uint64_t seen = nxt[w];
+        if ((seen & nb.w[0]) == nb.w[0]) return false;
         uint64_t old = for_rlx(&nxt[w], nb.w[0]);
         return old == 0;
     } else {
@@ -117,9 +122,14 @@ TKC_DEV bool push_lanes(uint64_t* nxt, int32_t* mark, int32_t w, const Mask<NW>&
     }
 }
 
+// vertex list of class c (0 light, 1 heavy) at parity q, and the chunk
+// lists (owner vertex, first arc) at parity q
+#define VL(c, q) (a.w.list + (int64_t)(2 * (c) + (q)) * n)
+#define CU(q) (a.w.list + 4 * (int64_t)n + (int64_t)(2 * (q)) * a.w.ccap)
+#define CB(q) (a.w.list + 4 * (int64_t)n + (int64_t)(2 * (q) + 1) * a.w.ccap)
+
 template <int NW>
 __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
-    cg::grid_group grid = cg::this_grid();
     const int32_t n = a.g.n;
     const bool dir = a.g.directed;
     const int W = a.W;
@@ -158,7 +168,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             int32_t nsel = 0;
             int32_t stop = 0;
             int64_t skipped = 0, r1 = 0;
-            while (nsel < W && pos < count && !stop) {
+            while (nsel < a.Wsel && pos < count && !stop) {
                 int32_t i = pos + lane;
                 bool valid = i < count;
                 int32_t v = valid ? (order_mode ? a.ov.ord[i] : a.list[i]) : -1;
@@ -177,7 +187,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 bool inwin = valid && lane < lim;
                 bool elig = inwin && !st && !sk && !one;
                 uint64_t me = __ballot(elig);
-                int room = W - nsel;
+                int room = a.Wsel - nsel;
                 // lanes beyond the room-th eligible one are left for the next batch
                 int cut_lane = 64;
                 if (__popcll(me) > room) {
@@ -220,7 +230,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 if (stop) stats[ST_STOP] = 1;
             }
         }
-        grid.sync();
+        grid_barrier(a.bar, gridDim.x);
         const int32_t nsel = (int32_t)ld_rlx(&ctr[C_NSEL]);
         pos = (int32_t)ld_rlx(&ctr[C_POS]);
         const bool stop_now = ld_rlx(&ctr[C_STOP]) != 0;
@@ -252,27 +262,39 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             if (a.lb_mode) { a.w.lvl[(int64_t)v * W + l] = 0; a.w.hist[l] = 1; }
         }
         if (boss) {
-            // level-0 frontier lists (parity 0): sources split by degree class
-            int64_t cnt3[3] = {0, 0, 0};
+            // level-0 frontier (parity 0): light sources, heavy sources and
+            // the heavy sources' arc chunks
+            int64_t nl0 = 0, nh0 = 0, nc0 = 0;
             for (int l = 0; l < nsel; l++) {
                 int32_t v = a.w.cand[l];
-                int c = deg[v] > GIANT_DEG ? 2 : (deg[v] > HEAVY_DEG ? 1 : 0);
-                a.w.list[(int64_t)(2 * c) * n + cnt3[c]++] = v;
+                bool dup = false;
+                for (int q = 0; q < l; q++) dup |= a.w.cand[q] == v;
+                if (dup) continue;
+                if (deg[v] > HEAVY_DEG) {
+                    VL(1, 0)[nh0++] = v;
+                    for (int32_t b = rp[v]; b < rp[v + 1]; b += CHUNK_ARCS) {
+                        CU(0)[nc0] = v;
+                        CB(0)[nc0] = b;
+                        nc0++;
+                    }
+                } else {
+                    VL(0, 0)[nl0++] = v;
+                }
             }
             for (int p = 0; p < 3; p++) {
                 ctr[C_UCNT(p)] = 0; ctr[C_UDEG(p)] = 0;
                 for (int c = 0; c < 3; c++) ctr[C_T(p, c)] = 0;
             }
-            for (int c = 0; c < 3; c++) ctr[C_T(2, c)] = cnt3[c];   // "previous level" lists of level 0
+            ctr[C_L0 + 0] = nl0; ctr[C_L0 + 1] = nh0; ctr[C_L0 + 2] = nc0;
             for (int p = 0; p < 3; p++)
                 for (int l = 0; l < MAXW; l++) { ctr[C_CNT(p, l)] = 0; ctr[C_DEG(p, l)] = 0; }
         }
-        grid.sync();
+        grid_barrier(a.bar, gridDim.x);
 
         int64_t D = 0;
-        int64_t flen[3];
-        for (int c = 0; c < 3; c++) flen[c] = ld_rlx(&ctr[C_T(2, c)]);
-        int64_t ucnt = nsel, udeg = 0;
+        // current frontier: light / heavy vertex lists and the heavy chunk list
+        int64_t fl_len = ld_rlx(&ctr[C_L0 + 0]), fh_len = ld_rlx(&ctr[C_L0 + 1]), fc_len = ld_rlx(&ctr[C_L0 + 2]);
+        int64_t ucnt = fl_len + fh_len, udeg = 0;
         for (int l = 0; l < nsel; l++) udeg += s_mf[l];
         int64_t udisc = udeg;
         bool bu = false;
@@ -313,7 +335,9 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             for (int j = 0; j < NW; j++) { act.w[j] = s_act[j]; any |= act.w[j] != 0; }
             if (!any) break;
             mvis += s_scal[0];
-            // direction on the union frontier (Beamer's rule)
+            // direction on the union frontier.  With several lanes a pull
+            // rarely stops early (every missing lane must be found), so it
+            // pays only once the frontier's arcs rival the unexplored ones.
             bool want_bu = bu ? (ucnt >= (int64_t)n / a.beta_bu)
                               : (udeg > (a.g.m - udisc) / a.alpha_td && ucnt > 256);
             bu = want_bu;
@@ -327,18 +351,16 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 }
             }
             const int p = (int)(D % 3);
-            // lists of class c at parity q live at list + (2c + q) n
-            const int32_t* fl = a.w.list + (int64_t)(0 + (D & 1)) * n;
-            const int32_t* fh = a.w.list + (int64_t)(2 + (D & 1)) * n;
-            const int32_t* fg = a.w.list + (int64_t)(4 + (D & 1)) * n;
-            int32_t* const nls[3] = {a.w.list + (int64_t)(0 + ((D + 1) & 1)) * n,
-                                     a.w.list + (int64_t)(2 + ((D + 1) & 1)) * n,
-                                     a.w.list + (int64_t)(4 + ((D + 1) & 1)) * n};
-            const int64_t fl_len = flen[0], fh_len = flen[1], fg_len = flen[2];
-            const uint64_t* fcur = (D & 1) ? a.w.frt1 : a.w.frt0;
-            uint64_t* fnxt = (D & 1) ? a.w.frt0 : a.w.frt1;
+            const int q = (int)(D & 1);
+            const int32_t* fl = VL(0, q);
+            const int32_t* fh = VL(1, q);
+            const int32_t* fcu = CU(q);
+            const int32_t* fcb = CB(q);
+            int32_t* const nls[2] = {VL(0, q ^ 1), VL(1, q ^ 1)};
+            const uint64_t* fcur = q ? a.w.frt1 : a.w.frt0;
+            uint64_t* fnxt = q ? a.w.frt0 : a.w.frt1;
             const int32_t stamp = (int32_t)(D + 1);
-            bytes += bu ? (int64_t)n * (8 * NW) : (fl_len + fh_len + fg_len) * (8 + 8 * NW);
+            bytes += bu ? (int64_t)n * (8 * NW) : (fl_len + fh_len) * (8 + 8 * NW);
             if (!bu) {
                 // push, light frontier vertices: one per lane
                 for (int64_t base = gwave * 64; base < fl_len; base += nwaves * 64) {
@@ -360,7 +382,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                             w = ci[e]; e++;
                             Mask<NW> nb;
 #pragma unroll
-                            for (int j = 0; j < NW; j++) nb.w[j] = f.w[j] & ~ld_rlx(&vis[(int64_t)w * NW + j]);
+                            for (int j = 0; j < NW; j++) nb.w[j] = f.w[j] & ~vis[(int64_t)w * NW + j];
                             if (nb.any() && push_lanes<NW>(a.w.nxt, a.mark, w, nb, stamp)) {
                                 isnew = true;
                                 dw = deg[w];
@@ -369,14 +391,15 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                         list_append(isnew, w, dw, nls, &ctr[C_T(p, 0)]);
                     }
                 }
-                // push, heavy frontier vertices: one per wave
-                for (int64_t hi = gwave; hi < fh_len; hi += nwaves) {
-                    int32_t u = fh[hi];
+                // push, heavy frontier vertices: one wave per chunk of arcs
+                for (int64_t c = gwave; c < fc_len; c += nwaves) {
+                    int32_t u = fcu[c];
                     Mask<NW> f;
 #pragma unroll
                     for (int j = 0; j < NW; j++) f.w[j] = fcur[(int64_t)u * NW + j] & act.w[j];
                     if (!f.any()) continue;
-                    int32_t b = rp[u], end = rp[u + 1];
+                    int32_t b = fcb[c];
+                    int32_t end = b + CHUNK_ARCS < rp[u + 1] ? b + CHUNK_ARCS : rp[u + 1];
                     for (int32_t e0 = b; e0 < end; e0 += 64) {
                         int32_t e = e0 + lane;
                         bool isnew = false;
@@ -385,32 +408,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                             w = ci[e];
                             Mask<NW> nb;
 #pragma unroll
-                            for (int j = 0; j < NW; j++) nb.w[j] = f.w[j] & ~ld_rlx(&vis[(int64_t)w * NW + j]);
-                            if (nb.any() && push_lanes<NW>(a.w.nxt, a.mark, w, nb, stamp)) {
-                                isnew = true;
-                                dw = deg[w];
-                            }
-                        }
-                        list_append(isnew, w, dw, nls, &ctr[C_T(p, 0)]);
-                    }
-                }
-                // push, giant frontier vertices: the whole grid on each in turn
-                for (int64_t gi = 0; gi < fg_len; gi++) {
-                    int32_t u = fg[gi];
-                    Mask<NW> f;
-#pragma unroll
-                    for (int j = 0; j < NW; j++) f.w[j] = fcur[(int64_t)u * NW + j] & act.w[j];
-                    if (!f.any()) continue;
-                    int64_t b = rp[u], end = rp[u + 1];
-                    for (int64_t e0 = b + gwave * 64; e0 < end; e0 += nwaves * 64) {
-                        int64_t e = e0 + lane;
-                        bool isnew = false;
-                        int32_t w = 0, dw = 0;
-                        if (e < end) {
-                            w = ci[e];
-                            Mask<NW> nb;
-#pragma unroll
-                            for (int j = 0; j < NW; j++) nb.w[j] = f.w[j] & ~ld_rlx(&vis[(int64_t)w * NW + j]);
+                            for (int j = 0; j < NW; j++) nb.w[j] = f.w[j] & ~vis[(int64_t)w * NW + j];
                             if (nb.any() && push_lanes<NW>(a.w.nxt, a.mark, w, nb, stamp)) {
                                 isnew = true;
                                 dw = deg[w];
@@ -420,22 +418,24 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                     }
                 }
             } else {
-                // pull: vertices with unreached active lanes scan their in-arcs
+                // pull, light vertices (few in-arcs): one per lane, scanning
+                // in-arcs until every missing active lane is found
                 for (int64_t base = gwave * 64; base < n; base += nwaves * 64) {
                     int32_t w = (int32_t)(base + lane);
                     bool isnew = false;
                     int32_t dw = 0;
                     if (w < n) {
+                        int32_t eb = a.g.rrp[w], ee = a.g.rrp[w + 1];
                         Mask<NW> miss, acc;
-                        bool need = false;
+                        bool need = ee - eb <= HEAVY_DEG;
 #pragma unroll
                         for (int j = 0; j < NW; j++) {
                             miss.w[j] = act.w[j] & ~vis[(int64_t)w * NW + j];
                             acc.w[j] = 0;
-                            need |= miss.w[j] != 0;
                         }
+                        need = need && miss.any();
                         if (need) {
-                            for (int32_t e = a.g.rrp[w]; e < a.g.rrp[w + 1]; e++) {
+                            for (int32_t e = eb; e < ee; e++) {
                                 int32_t u = a.g.rci[e];
                                 bool full = true;
 #pragma unroll
@@ -455,18 +455,54 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                     }
                     list_append(isnew, w, dw, nls, &ctr[C_T(p, 0)]);
                 }
+                // pull, heavy vertices: one wave per chunk of their in-arcs
+                for (int64_t c = gwave; c < a.g.rnchunks; c += nwaves) {
+                    int32_t w = a.g.rch_vtx[c];
+                    Mask<NW> miss, acc;
+#pragma unroll
+                    for (int j = 0; j < NW; j++) {
+                        miss.w[j] = __shfl(act.w[j] & ~vis[(int64_t)w * NW + j], 0, 64);
+                        acc.w[j] = 0;
+                    }
+                    if (!miss.any()) continue;   // wave-uniform
+                    int32_t eb = a.g.rch_beg[c], ee = a.g.rch_end[c];
+                    for (int32_t e0 = eb; e0 < ee; e0 += 64) {
+                        int32_t e = e0 + lane;
+                        if (e < ee) {
+                            int32_t u = a.g.rci[e];
+#pragma unroll
+                            for (int j = 0; j < NW; j++) acc.w[j] |= fcur[(int64_t)u * NW + j] & miss.w[j];
+                        }
+                        bool full = true;
+#pragma unroll
+                        for (int j = 0; j < NW; j++) {
+                            acc.w[j] = wave_or_u64(acc.w[j]);
+                            full &= acc.w[j] == miss.w[j];
+                        }
+                        if (full) break;
+                    }
+                    bool isnew = false;
+                    int32_t dw = 0;
+                    if (lane == 0 && acc.any() && push_lanes<NW>(a.w.nxt, a.mark, w, acc, stamp)) {
+                        isnew = true;
+                        dw = deg[w];
+                    }
+                    list_append(isnew, w, dw, nls, &ctr[C_T(p, 0)]);
+                }
             }
-            grid.sync();
+            grid_barrier(a.bar, gridDim.x);
             // ------------------------------------------------------ epilogue
-            int64_t nlen[3];
-            for (int c = 0; c < 3; c++) nlen[c] = ld_rlx(&ctr[C_T(p, c)]);
-            const int64_t nall = nlen[0] + nlen[1] + nlen[2];
+            const int64_t nl_len = ld_rlx(&ctr[C_T(p, 0)]), nh_len = ld_rlx(&ctr[C_T(p, 1)]);
+            const int64_t nall = nl_len + nh_len;
+            int64_t* ctail = &ctr[C_T((D + 1) % 3, 2)];   // chunk list of the next level
+            int32_t* ncu = CU(q ^ 1);
+            int32_t* ncb = CB(q ^ 1);
             if (tid < MAXW) { s_red_cnt[tid] = 0; s_red_deg[tid] = 0; }
             __syncthreads();
             // old frontier words are cleared (the next level uses the other array)
             uint64_t* fcur_w = (uint64_t*)fcur;
-            for (int64_t i = gtid; i < fl_len + fh_len + fg_len; i += nthreads) {
-                int32_t u = i < fl_len ? fl[i] : (i < fl_len + fh_len ? fh[i - fl_len] : fg[i - fl_len - fh_len]);
+            for (int64_t i = gtid; i < fl_len + fh_len; i += nthreads) {
+                int32_t u = i < fl_len ? fl[i] : fh[i - fl_len];
 #pragma unroll
                 for (int j = 0; j < NW; j++) fcur_w[(int64_t)u * NW + j] = 0;
             }
@@ -476,10 +512,9 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 Mask<NW> nb;
 #pragma unroll
                 for (int j = 0; j < NW; j++) nb.w[j] = 0;
-                int32_t dw = 0;
+                int32_t dw = 0, w = 0;
                 if (i < nall) {
-                    int32_t w = i < nlen[0] ? nls[0][i]
-                                            : (i < nlen[0] + nlen[1] ? nls[1][i - nlen[0]] : nls[2][i - nlen[0] - nlen[1]]);
+                    w = i < nl_len ? nls[0][i] : nls[1][i - nl_len];
                     dw = deg[w];
 #pragma unroll
                     for (int j = 0; j < NW; j++) {
@@ -502,6 +537,26 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                     }
                     my_u += 1;
                     my_ud += dw;
+                }
+                // heavy vertices of the next frontier: their arc chunks
+                int32_t nck = (i < nall && dw > HEAVY_DEG) ? (dw + CHUNK_ARCS - 1) / CHUNK_ARCS : 0;
+                int32_t pre = nck;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    int32_t y = __shfl_up(pre, o, 64);
+                    if (lane >= o) pre += y;
+                }
+                int32_t tot = __shfl(pre, 63, 64);
+                pre -= nck;
+                if (tot) {
+                    int64_t cbase = 0;
+                    if (lane == 0) cbase = fadd_rlx(ctail, (int64_t)tot);
+                    cbase = shfl64b(cbase, 0);
+                    int32_t b0 = nck ? rp[w] : 0;
+                    for (int32_t j = 0; j < nck; j++) {
+                        ncu[cbase + pre + j] = w;
+                        ncb[cbase + pre + j] = b0 + j * CHUNK_ARCS;
+                    }
                 }
                 // per-lane counts: transpose the wave's bit matrix lane by lane
 #pragma unroll
@@ -531,7 +586,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 fadd_rlx(&ctr[C_CNT(p, tid)], (int64_t)s_red_cnt[tid]);
                 fadd_rlx(&ctr[C_DEG(p, tid)], s_red_deg[tid]);
             }
-            grid.sync();
+            grid_barrier(a.bar, gridDim.x);
             // --------------------------------------------- advance lane state
             if (tid < MAXW) {
                 int l = tid;
@@ -552,13 +607,15 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             udeg = ld_rlx(&ctr[C_UDEG(p)]);
             udisc += udeg;
             bytes += ucnt * 8 * (3 * NW) + nall * 4;
+            fc_len = ld_rlx(ctail);
             if (boss) {
-                int q = (int)((D + 2) % 3);
-                for (int l = 0; l < W; l++) { ctr[C_CNT(q, l)] = 0; ctr[C_DEG(q, l)] = 0; }
-                ctr[C_UCNT(q)] = 0; ctr[C_UDEG(q)] = 0;
-                for (int c = 0; c < 3; c++) ctr[C_T(q, c)] = 0;
+                int q3 = (int)((D + 2) % 3);
+                for (int l = 0; l < W; l++) { ctr[C_CNT(q3, l)] = 0; ctr[C_DEG(q3, l)] = 0; }
+                ctr[C_UCNT(q3)] = 0; ctr[C_UDEG(q3)] = 0;
+                for (int c = 0; c < 3; c++) ctr[C_T(q3, c)] = 0;
             }
-            for (int c = 0; c < 3; c++) flen[c] = nlen[c];
+            fl_len = nl_len;
+            fh_len = nh_len;
             D++;
             __syncthreads();
         }
@@ -611,7 +668,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                         lev[i * W + l] = lev[(i - 1) * W + l] + (dir ? 0 : low) - (r - pre);
                     }
                 }
-                grid.sync();
+                grid_barrier(a.bar, gridDim.x);
                 for (int64_t w = gtid; w < n; w += nthreads) {
                     int64_t best = -1;
                     int64_t bden = 0;
@@ -637,7 +694,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 }
             }
         }
-        grid.sync();
+        grid_barrier(a.bar, gridDim.x);
         // clear the batch's words for the next batch
         {
             int64_t tot = (int64_t)n * NW;
@@ -649,7 +706,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             if (NW > 1)
                 for (int64_t q = gtid; q < n; q += nthreads) a.mark[q] = 0;
         }
-        grid.sync();
+        grid_barrier(a.bar, gridDim.x);
         batches++;
         if (stop_now) break;
         if (a.until_x && ld_acq(&a.tk.st->seq) >= 0) break;
@@ -664,6 +721,8 @@ int tkc_launch_batch(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv
                      int* grid_out) {
     int W = tune.batch_width;
     if (W != 32 && W != 64 && W != 128 && W != 256) return -2;
+    if (!w.bar || !w.vis || !w.frt0 || !w.frt1 || !w.nxt || !w.list || !w.ctr || !w.cand || !stats) return -2;
+    if (lb_mode && (!w.lvl || !w.hist || !w.levtab)) return -2;
     int NW = W <= 64 ? 1 : W / 64;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return -1;
@@ -679,7 +738,7 @@ int tkc_launch_batch(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv
     int per = occ < 2 ? occ : 2;
     int grid = prop.multiProcessorCount * per;
     if (grid_out) *grid_out = grid;
-    BatchArgs a;
+    BatchArgs a{};
     a.g = g; a.rc = rc; a.ov = ov; a.bv = bv; a.tk = tk; a.w = w;
     a.stats = stats; a.list = list; a.list_count = list_count;
     a.start_pos = start_pos;
@@ -689,11 +748,13 @@ int tkc_launch_batch(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv
     a.until_x = (max_batches == -1) ? 1 : 0;
     if (max_batches == -1) a.max_batches = 0x7fffffff;
     a.W = W;
-    a.alpha_td = tune.td_bu_alpha > 0 ? tune.td_bu_alpha : 14;
+    a.Wsel = (tune.lanes_cap > 0 && tune.lanes_cap < W) ? tune.lanes_cap : W;
+    a.alpha_td = tune.batch_alpha > 0 ? tune.batch_alpha : 14;
     a.beta_bu = tune.bu_td_beta > 0 ? tune.bu_td_beta : 24;
     a.out_S = out_S;
     a.out_r = out_r;
     a.mark = (int32_t*)w.touched;
+    a.bar = w.bar;
     void* args[] = {&a};
     e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(BB), args, 0, s);
     return e == hipSuccess ? 0 : -1;

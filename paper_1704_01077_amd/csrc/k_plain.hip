@@ -15,15 +15,11 @@
 //     reached vertex with the level-based bound (Eq. 4 / Eq. 5).
 // Control decisions are computed redundantly by every thread from values
 // read after a barrier, so all workgroups take the same path.
-#include <hip/hip_cooperative_groups.h>
-
 #include "dev_common.hpp"
 #include "engine.hpp"
 
-namespace cg = cooperative_groups;
-
 #define PB 256
-#define CS 8   // counters per level parity: found, degree sum, light/heavy/giant appends
+#define CS 8   // counters per level parity: found, degree sum, light/heavy/chunk appends
 
 struct PlainArgs {
     DevGraph g;
@@ -38,6 +34,7 @@ struct PlainArgs {
     int32_t lb_mode;
     int32_t alpha_td;
     int32_t beta_bu;
+    uint32_t* bar;
 };
 
 TKC_DEV int64_t shfl64(int64_t v, int src) {
@@ -50,36 +47,56 @@ TKC_DEV uint64_t lanes_below() {
     return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
-// wave-aggregated append of newly found vertices to the light, heavy and
-// giant queues (by out-degree); the level's appends count from zero in its
-// own counters cnts[0..2] on top of the segment ends base[0..2], so the queue
-// ends every workgroup reads after the barrier never move under it
-TKC_DEV void q_append(bool isnew, int32_t w, int32_t dw, int32_t* const* q, int64_t* cnts,
-                      const int64_t* base) {
-    int cls = dw > GIANT_DEG ? 2 : (dw > HEAVY_DEG ? 1 : 0);
-    uint64_t m[3];
+// wave-aggregated append of newly found vertices: light ones to ql, heavy
+// ones to qh and their arc chunks (owner, first arc) to qcu/qcb.  The
+// level's appends count from zero in its own counters cnts[0..2] on top of
+// the segment ends base[0..2], so the queue ends every workgroup reads after
+// the barrier never move under it.
+TKC_DEV void q_append(bool isnew, int32_t w, int32_t dw, int32_t* ql, int32_t* qh, int32_t* qcu,
+                      int32_t* qcb, const int32_t* rp, int64_t* cnts, const int64_t* base) {
+    bool hv = isnew && dw > HEAVY_DEG;
+    bool lt = isnew && !hv;
+    uint64_t ml = __ballot(lt), mh = __ballot(hv);
+    if ((ml | mh) == 0) return;
+    int32_t nck = hv ? (dw + CHUNK_ARCS - 1) / CHUNK_ARCS : 0;
+    int32_t pre = nck;
 #pragma unroll
-    for (int c = 0; c < 3; c++) m[c] = __ballot(isnew && cls == c);
-    if ((m[0] | m[1] | m[2]) == 0) return;
+    for (int o = 1; o < 64; o <<= 1) {
+        int32_t y = __shfl_up(pre, o, 64);
+        if (lane_id() >= o) pre += y;
+    }
     int leader = __ffsll((long long)__ballot(1)) - 1;
-    int64_t b[3] = {0, 0, 0};
+    int32_t tot = __shfl(pre, 63, 64);
+    pre -= nck;
+    int64_t bl = 0, bh = 0, bc = 0;
     if (lane_id() == leader) {
-#pragma unroll
-        for (int c = 0; c < 3; c++)
-            if (m[c]) b[c] = fadd_rlx(&cnts[c], (int64_t)__popcll(m[c]));
+        if (ml) bl = fadd_rlx(&cnts[0], (int64_t)__popcll(ml));
+        if (mh) {
+            bh = fadd_rlx(&cnts[1], (int64_t)__popcll(mh));
+            bc = fadd_rlx(&cnts[2], (int64_t)tot);
+        }
     }
     uint64_t below = lanes_below();
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-        int64_t bc = shfl64(b[c], leader) + base[c];
-        if (isnew && cls == c) q[c][bc + __popcll(m[c] & below)] = w;
+    bl = shfl64(bl, leader) + base[0];
+    bh = shfl64(bh, leader) + base[1];
+    bc = shfl64(bc, leader) + base[2];
+    if (lt) ql[bl + __popcll(ml & below)] = w;
+    if (hv) {
+        qh[bh + __popcll(mh & below)] = w;
+        int32_t b0 = rp[w];
+        for (int32_t j = 0; j < nck; j++) {
+            qcu[bc + pre + j] = w;
+            qcb[bc + pre + j] = b0 + j * CHUNK_ARCS;
+        }
     }
 }
 
 // test-and-set of a visited bit; true for the single caller that sets it
+// (the plain pre-read may be stale, but bits only turn on during a search,
+// so a set bit seen there is really set)
 TKC_DEV bool visit(uint32_t* vis, int32_t w) {
     uint32_t bit = 1u << (w & 31);
-    if (ld_rlx(&vis[w >> 5]) & bit) return false;
+    if (vis[w >> 5] & bit) return false;
     uint32_t old = for_rlx(&vis[w >> 5], bit);
     return !(old & bit);
 }
@@ -106,7 +123,6 @@ TKC_DEV void lev_table(const int64_t* gam, int64_t maxD, int64_t r, bool directe
 }
 
 __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
-    cg::grid_group grid = cg::this_grid();
     const int32_t n = a.g.n;
     const bool dir = a.g.directed;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
@@ -119,9 +135,10 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
     const int32_t* __restrict__ ci = a.g.ci;
     const int32_t* __restrict__ deg = a.g.deg;
     // ctr[p*CS + 0..4], p = level % 3: vertices found, their degree sum,
-    // light, heavy and giant queue appends of that level
+    // light, heavy and chunk queue appends of that level
     int64_t* ctr = a.w.ctr;
-    int32_t* const qs[3] = {a.w.ql, a.w.qh, a.w.qg};
+    int32_t* const qcu = a.w.qg;
+    int32_t* const qcb = a.w.qg + a.w.ccap;
     uint32_t* vis = a.w.vis;
     const int64_t words = ((int64_t)n + 31) / 32;
     const int32_t count = a.list ? a.list_count : a.ov.count;
@@ -150,23 +167,30 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
                 stats[ST_EXACT]++;
                 topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, 0, 1, v);
             }
-            grid.sync();
+            grid_barrier(a.bar, gridDim.x);
             continue;
         }
         const int64_t dv = deg[v];
         if (boss) {
             for (int q = 0; q < 3 * CS; q++) ctr[q] = 0;
             for_rlx(&vis[v >> 5], 1u << (v & 31));
-            qs[dv > GIANT_DEG ? 2 : (dv > HEAVY_DEG ? 1 : 0)][0] = v;
+            if (dv > HEAVY_DEG) {
+                a.w.qh[0] = v;
+                int32_t j = 0;
+                for (int32_t b = rp[v]; b < rp[v + 1]; b += CHUNK_ARCS, j++) { qcu[j] = v; qcb[j] = b; }
+            } else {
+                a.w.ql[0] = v;
+            }
             if (a.lb_mode) { a.w.lvl[v] = 0; a.w.levcnt[0] = 1; }
         }
-        grid.sync();
+        grid_barrier(a.bar, gridDim.x);
 
         int64_t D = 0, nD = 1, SD = 0;
         int64_t U = dv, mf = dv, nf = 1, mdisc = dv;
-        // frontier segments [st[c], en[c]) of the three queues
+        // frontier segments [st[c], en[c]) of the light, heavy and chunk queues
         int64_t st[3] = {0, 0, 0}, en[3] = {0, 0, 0};
-        en[dv > GIANT_DEG ? 2 : (dv > HEAVY_DEG ? 1 : 0)] = 1;
+        if (dv > HEAVY_DEG) { en[1] = 1; en[2] = (dv + CHUNK_ARCS - 1) / CHUNK_ARCS; }
+        else en[0] = 1;
         bool bu = false, used_bu = false;
         int status = 0;   // 1 exact, 2 cut
         int64_t mvis = 0, bytes = 0;
@@ -184,14 +208,17 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
             if (want_bu && !bu) {
                 // frontier bitmap of level D from the queue segments
                 for (int64_t q = gtid; q < 3 * words; q += nthreads) a.w.fb[q] = 0;
-                grid.sync();
+                grid_barrier(a.bar, gridDim.x);
                 uint32_t* fcur = a.w.fb + (D % 3) * words;
-                for (int c = 0; c < 3; c++)
-                    for (int64_t i = gtid; i < en[c] - st[c]; i += nthreads) {
-                        int32_t u = qs[c][st[c] + i];
-                        for_rlx(&fcur[u >> 5], 1u << (u & 31));
-                    }
-                grid.sync();
+                for (int64_t i = gtid; i < en[0] - st[0]; i += nthreads) {
+                    int32_t u = a.w.ql[st[0] + i];
+                    for_rlx(&fcur[u >> 5], 1u << (u & 31));
+                }
+                for (int64_t i = gtid; i < en[1] - st[1]; i += nthreads) {
+                    int32_t u = a.w.qh[st[1] + i];
+                    for_rlx(&fcur[u >> 5], 1u << (u & 31));
+                }
+                grid_barrier(a.bar, gridDim.x);
                 used_bu = true;
             }
             bu = want_bu;
@@ -219,13 +246,14 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
                             my_cnt++; my_deg += dw;
                             if (a.lb_mode) a.w.lvl[w] = (int32_t)(D + 1);
                         }
-                        q_append(isnew, w, dw, qs, &ctr[p * CS + 2], en);
+                        q_append(isnew, w, dw, a.w.ql, a.w.qh, qcu, qcb, rp, &ctr[p * CS + 2], en);
                     }
                 }
-                // push: heavy frontier vertices, one per wave
-                for (int64_t hi = gwave; hi < en[1] - st[1]; hi += nwaves) {
-                    int32_t u = a.w.qh[st[1] + hi];
-                    int32_t b = rp[u], end = rp[u + 1];
+                // push: heavy frontier vertices, one wave per chunk of arcs
+                for (int64_t c = gwave; c < en[2] - st[2]; c += nwaves) {
+                    int32_t u = qcu[st[2] + c];
+                    int32_t b = qcb[st[2] + c];
+                    int32_t end = b + CHUNK_ARCS < rp[u + 1] ? b + CHUNK_ARCS : rp[u + 1];
                     for (int32_t e0 = b; e0 < end; e0 += 64) {
                         int32_t e = e0 + lane;
                         bool isnew = false;
@@ -238,26 +266,7 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
                             my_cnt++; my_deg += dw;
                             if (a.lb_mode) a.w.lvl[w] = (int32_t)(D + 1);
                         }
-                        q_append(isnew, w, dw, qs, &ctr[p * CS + 2], en);
-                    }
-                }
-                // push: giant frontier vertices, the whole grid on each in turn
-                for (int64_t gi = 0; gi < en[2] - st[2]; gi++) {
-                    int32_t u = a.w.qg[st[2] + gi];
-                    int64_t b = rp[u], end = rp[u + 1];
-                    for (int64_t e0 = b + gwave * 64; e0 < end; e0 += nwaves * 64) {
-                        int64_t e = e0 + lane;
-                        bool isnew = false;
-                        int32_t w = 0, dw = 0;
-                        if (e < end) {
-                            w = ci[e];
-                            if (visit(vis, w)) { isnew = true; dw = deg[w]; }
-                        }
-                        if (isnew) {
-                            my_cnt++; my_deg += dw;
-                            if (a.lb_mode) a.w.lvl[w] = (int32_t)(D + 1);
-                        }
-                        q_append(isnew, w, dw, qs, &ctr[p * CS + 2], en);
+                        q_append(isnew, w, dw, a.w.ql, a.w.qh, qcu, qcb, rp, &ctr[p * CS + 2], en);
                     }
                 }
             } else {
@@ -266,11 +275,13 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
                 uint32_t* fnxt = a.w.fb + ((D + 1) % 3) * words;
                 uint32_t* fold = a.w.fb + ((D + 2) % 3) * words;
                 for (int64_t q = gtid; q < words; q += nthreads) fold[q] = 0;
+                // light vertices (few in-arcs): one per lane
                 for (int64_t base = gwave * 64; base < n; base += nwaves * 64) {
                     int32_t w = (int32_t)(base + lane);
                     bool isnew = false;
                     int32_t dw = 0;
-                    if (w < n && !(ld_rlx(&vis[w >> 5]) & (1u << (w & 31)))) {
+                    if (w < n && a.g.rrp[w + 1] - a.g.rrp[w] <= HEAVY_DEG &&
+                        !(ld_rlx(&vis[w >> 5]) & (1u << (w & 31)))) {
                         for (int32_t e = a.g.rrp[w]; e < a.g.rrp[w + 1]; e++) {
                             int32_t u = a.g.rci[e];
                             if (fcur[u >> 5] & (1u << (u & 31))) { isnew = true; break; }
@@ -283,7 +294,35 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
                             if (a.lb_mode) a.w.lvl[w] = (int32_t)(D + 1);
                         }
                     }
-                    q_append(isnew, w, dw, qs, &ctr[p * CS + 2], en);
+                    q_append(isnew, w, dw, a.w.ql, a.w.qh, qcu, qcb, rp, &ctr[p * CS + 2], en);
+                }
+                // heavy vertices: one wave per chunk of their in-arcs; the
+                // visited bit decides which chunk's wave reports the vertex
+                for (int64_t c = gwave; c < a.g.rnchunks; c += nwaves) {
+                    int32_t w = a.g.rch_vtx[c];
+                    int vw = (int)(ld_rlx(&vis[w >> 5]) >> (w & 31)) & 1;
+                    if (__shfl(vw, 0, 64)) continue;   // wave-uniform
+                    int32_t eb = a.g.rch_beg[c], ee = a.g.rch_end[c];
+                    bool found = false;
+                    for (int32_t e0 = eb; e0 < ee && !found; e0 += 64) {
+                        int32_t e = e0 + lane;
+                        bool hit = false;
+                        if (e < ee) {
+                            int32_t u = a.g.rci[e];
+                            hit = (fcur[u >> 5] & (1u << (u & 31))) != 0;
+                        }
+                        found = __any(hit);
+                    }
+                    bool isnew = false;
+                    int32_t dw = 0;
+                    if (found && lane == 0 && visit(vis, w)) {
+                        for_rlx(&fnxt[w >> 5], 1u << (w & 31));
+                        isnew = true;
+                        dw = deg[w];
+                        my_cnt++; my_deg += dw;
+                        if (a.lb_mode) a.w.lvl[w] = (int32_t)(D + 1);
+                    }
+                    q_append(isnew, w, dw, a.w.ql, a.w.qh, qcu, qcb, rp, &ctr[p * CS + 2], en);
                 }
             }
             my_cnt = wave_sum_i64(my_cnt);
@@ -292,7 +331,7 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
                 fadd_rlx(&ctr[p * CS + 0], my_cnt);
                 fadd_rlx(&ctr[p * CS + 1], my_deg);
             }
-            grid.sync();
+            grid_barrier(a.bar, gridDim.x);
             const int64_t cnt = ld_rlx(&ctr[p * CS + 0]);
             const int64_t dsum = ld_rlx(&ctr[p * CS + 1]);
             int64_t tails[3];
@@ -319,11 +358,11 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
                 a.w.levcnt[D] = 0;
                 lev_table(a.w.levcnt, maxD, nD, dir, a.w.levtab);
             }
-            grid.sync();
+            grid_barrier(a.bar, gridDim.x);
             const int64_t den = sq64(nD - 1);
             const int32_t sc = dir ? a.rc.scc[v] : 0;
-            for (int64_t i = gtid; i < en[0] + en[1] + en[2]; i += nthreads) {
-                int32_t w = i < en[0] ? a.w.ql[i] : (i < en[0] + en[1] ? a.w.qh[i - en[0]] : a.w.qg[i - en[0] - en[1]]);
+            for (int64_t i = gtid; i < en[0] + en[1]; i += nthreads) {
+                int32_t w = i < en[0] ? a.w.ql[i] : a.w.qh[i - en[0]];
                 if (w == v) continue;
                 if (dir && a.rc.scc[w] != sc) continue;
                 int64_t b = a.w.levtab[a.w.lvl[w]] - deg[w];
@@ -333,8 +372,8 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
             }
         }
         // clear the visited bits of every reached vertex
-        for (int64_t i = gtid; i < en[0] + en[1] + en[2]; i += nthreads) {
-            int32_t w = i < en[0] ? a.w.ql[i] : (i < en[0] + en[1] ? a.w.qh[i - en[0]] : a.w.qg[i - en[0] - en[1]]);
+        for (int64_t i = gtid; i < en[0] + en[1]; i += nthreads) {
+            int32_t w = i < en[0] ? a.w.ql[i] : a.w.qh[i - en[0]];
             vis[w >> 5] = 0;
         }
         if (used_bu)
@@ -351,7 +390,7 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
                 stats[ST_CUT]++;
             }
         }
-        grid.sync();
+        grid_barrier(a.bar, gridDim.x);
     }
     if (boss) stats[ST_CURSOR] = pos;
 }
@@ -359,6 +398,7 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
 int tkc_launch_plain(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv, DevTopk tk,
                      PlainWork w, int64_t* stats, const int32_t* list, int32_t list_count,
                      bool lb_mode, const EngineTuning& tune, hipStream_t s, int* grid_out) {
+    if (!w.bar || !w.vis || !w.fb || !w.ql || !w.qh || !w.qg || !w.ctr || !stats) return -2;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return -1;
     hipDeviceProp_t prop;
@@ -369,12 +409,13 @@ int tkc_launch_plain(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv
     int per = occ < 2 ? occ : 2;
     int grid = prop.multiProcessorCount * per;
     if (grid_out) *grid_out = grid;
-    PlainArgs a;
+    PlainArgs a{};
     a.g = g; a.rc = rc; a.ov = ov; a.bv = bv; a.tk = tk; a.w = w;
     a.stats = stats; a.list = list; a.list_count = list_count;
     a.lb_mode = lb_mode ? 1 : 0;
     a.alpha_td = tune.td_bu_alpha > 0 ? tune.td_bu_alpha : 14;
     a.beta_bu = tune.bu_td_beta > 0 ? tune.bu_td_beta : 24;
+    a.bar = w.bar;
     void* args[] = {&a};
     hipError_t e = hipLaunchCooperativeKernel((const void*)k_plain, dim3(grid), dim3(PB), args, 0, s);
     return e == hipSuccess ? 0 : -1;

@@ -241,7 +241,7 @@ int tkc_launch_swarm(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv
                      SwarmWork w, int64_t* stats, int32_t start_pos, const EngineTuning& tune,
                      hipStream_t s) {
     (void)tune;
-    SwarmArgs a;
+    SwarmArgs a{};
     a.g = g; a.rc = rc; a.ov = ov; a.bv = bv; a.tk = tk; a.w = w;
     a.stats = stats;
     a.start_pos = start_pos;

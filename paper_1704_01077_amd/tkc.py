@@ -73,7 +73,7 @@ def _load():
     sig = {
         "tkc_ctx_create": [c.c_int, vp, P(vp)],
         "tkc_ctx_destroy": [vp],
-        "tkc_ctx_set_tuning": [vp, i32, i32, i32, i32, i32],
+        "tkc_ctx_set_tuning": [vp, i32, i32, i32, i32, i32, i32],
         "tkc_graph_upload": [vp, i32, i64, vp, vp, vp, vp, u32, P(vp)],
         "tkc_graph_free": [vp],
         "tkc_topk_closeness": [vp, i32, i32, i32, vp, vp, vp, vp, P(i32), P(tkc_stats)],
@@ -129,8 +129,10 @@ def tkc_ctx_destroy(ctx):
     _check(lib.tkc_ctx_destroy(ctx))
 
 
-def tkc_ctx_set_tuning(ctx, batch_width=0, td_bu_alpha=0, bu_td_beta=0, swarm_qcap=0, block_size=0):
-    _check(lib.tkc_ctx_set_tuning(ctx, batch_width, td_bu_alpha, bu_td_beta, swarm_qcap, block_size))
+def tkc_ctx_set_tuning(ctx, batch_width=0, td_bu_alpha=0, bu_td_beta=0, batch_alpha=0, swarm_qcap=0,
+                       seed_lanes=0):
+    _check(lib.tkc_ctx_set_tuning(ctx, batch_width, td_bu_alpha, bu_td_beta, batch_alpha, swarm_qcap,
+                                  seed_lanes))
 
 
 def tkc_graph_upload(ctx, n, m_arcs, row_ptr, col_idx, rrow_ptr=None, rcol_idx=None, flags=0):
