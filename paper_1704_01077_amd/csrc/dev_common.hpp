@@ -50,19 +50,25 @@ TKC_DEV T for_wg(T* p, T v) {
 // every use (the last arriver of a group resets it before climbing; nobody
 // re-arrives before the generation changes).  Layout of `bar`: word 0 is
 // the generation, counter slot s lives at word (s + 1) * TKC_BAR_PAD.
-// Every wave publishes its own stores with an agent-scope release fence
-// before the workgroup barrier: a workgroup barrier alone does not wait for
-// a wave's outstanding global stores, and a fence only covers the stores of
-// the wave that executes it.  Every wave then takes an agent-scope acquire
-// fence after the release, before it reads what other workgroups wrote.
+// Publication: a workgroup barrier does not wait for a wave's outstanding
+// global stores, so every wave first waits for its own (vmcnt(0)); once all
+// of them sit in the XCD's L2, one agent-scope release fence by thread 0
+// (an L2 write-back) publishes the whole workgroup's stores before its
+// relaxed arrival.  The last arriver of a group takes an acquire-release
+// fence before it climbs, and thread 0 of every workgroup takes an
+// agent-scope acquire fence (L1/L2 invalidate, shared by the workgroup's
+// waves on one CU) before the closing workgroup barrier.  Per-wave fences
+// instead of thread-0 fences cost about three times as much (43 us against
+// 13 us per barrier at 512 workgroups).
 #define TKC_BAR_FAN 16
 #define TKC_BAR_PAD 32
 TKC_DEV void grid_barrier(uint32_t* bar, uint32_t nblocks) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's stores done
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t* gen = bar;
         uint32_t g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         uint32_t idx = blockIdx.x, width = nblocks, base = 0;
         for (;;) {
             uint32_t grp = idx / TKC_BAR_FAN;
@@ -70,24 +76,25 @@ TKC_DEV void grid_barrier(uint32_t* bar, uint32_t nblocks) {
             uint32_t gsize = width - grp * TKC_BAR_FAN;
             if (gsize > TKC_BAR_FAN) gsize = TKC_BAR_FAN;
             uint32_t* c = bar + (size_t)(base + grp + 1) * TKC_BAR_PAD;
-            uint32_t old = __hip_atomic_fetch_add(c, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t old = __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (old + 1 != gsize) {
                 while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
                     __builtin_amdgcn_s_sleep(1);
                 break;
             }
             __hip_atomic_store(c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
             if (ngroups == 1) {
-                __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
             base += ngroups;
             idx = grp;
             width = ngroups;
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 // words of barrier state for up to `nblocks` workgroups
 static inline size_t tkc_bar_words(uint32_t nblocks) { return (size_t)(nblocks + 2) * TKC_BAR_PAD; }
