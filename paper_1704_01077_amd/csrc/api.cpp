@@ -143,7 +143,7 @@ int tkc_ws_reserve(tkc_ctx* ctx, Workspace& ws, const WsShape& sh) {
         off += align_up(it.bytes);
     }
     if (getenv("TKC_TRACE") && !ws.trace) {
-        if (hipMalloc((void**)&ws.trace, 8 * (8 + 8 * 4096)) != hipSuccess) ws.trace = nullptr;
+        if (hipMalloc((void**)&ws.trace, 8 * (8 + 16 * 4096)) != hipSuccess) ws.trace = nullptr;
     }
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return TKC_OK;
@@ -500,7 +500,7 @@ static void trace_reset(tkc_ctx* c) {
 }
 static void trace_dump(tkc_ctx* c, const char* tag) {
     if (!c->ws.trace) return;
-    std::vector<int64_t> h(8 + 8 * 4096);
+    std::vector<int64_t> h(8 + 16 * 4096);
     hipMemcpyAsync(h.data(), c->ws.trace, 8 * h.size(), hipMemcpyDeviceToHost, c->stream);
     hipStreamSynchronize(c->stream);
     int64_t cnt = std::min<int64_t>(h[0], 4096);
@@ -508,11 +508,15 @@ static void trace_dump(tkc_ctx* c, const char* tag) {
     hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, c->device);
     double khz = rate > 0 ? rate : 100000.0;
     for (int64_t i = 0; i < cnt; i++) {
-        const int64_t* r = h.data() + 8 + 8 * i;
-        double dt = i + 1 < cnt ? (h[8 + 8 * (i + 1) + 5] - r[5]) / khz * 1e3 : 0.0;
-        fprintf(stderr, "trace %s batch %lld level %lld %s frontier %lld arcs %lld lanes %lld/%lld  %.1f us\n", tag,
-                (long long)r[0], (long long)r[1], r[2] ? "pull" : "push", (long long)r[3], (long long)r[4],
-                (long long)r[7], (long long)r[6], dt);
+        const int64_t* r = h.data() + 8 + 16 * i;
+        double dt = i + 1 < cnt ? (h[8 + 16 * (i + 1) + 5] - r[5]) / khz * 1e3 : 0.0;
+        double te = r[8] ? (r[8] - r[5]) / khz * 1e3 : 0.0;
+        double tp = r[9] ? (r[9] - r[8]) / khz * 1e3 : 0.0;
+        fprintf(stderr,
+                "trace %s batch %lld level %lld %s frontier %lld arcs %lld lanes %lld/%lld  %.1f us"
+                " (expand %.1f, epilogue %.1f)\n",
+                tag, (long long)r[0], (long long)r[1], r[2] ? "pull" : "push", (long long)r[3], (long long)r[4],
+                (long long)r[7], (long long)r[6], dt, te, tp);
     }
 }
 
@@ -619,7 +623,9 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
         trace_dump(c, "batched");
     } else {
         // hybrid: batched seed until x is known, then one search per workgroup,
-        // then the deferred (large) searches batched
+        // then the deferred (large) searches batched; if the per-workgroup
+        // engine closed itself (too many deferrals), the rest of the order
+        // continues batched from its cursor
         int64_t hs[ST_COUNT];
         trace_reset(c);
         {
@@ -647,6 +653,7 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
             sw.stop = small + 6;
             sw.nblocks = ws.shape.swarm_blocks;
             sw.qcap = ws.shape.qcap;
+            sw.defer_cap = c->tune.batch_width;
             HIPCHK(hipMemsetAsync(small + 4, 0, 3 * sizeof(int32_t), s));
             {
                 EngineTimer tm(c, &ms_eng[2], &nl_eng[2]);
@@ -655,9 +662,9 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
                 tm.done();
             }
             int32_t* pin = (int32_t*)c->pinned;
-            HIPCHK(hipMemcpyAsync(pin, small + 4, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(pin, small + 4, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
-            int32_t ndef = pin[0];
+            const int32_t ndef = pin[0], fetched = pin[1], sw_stop = pin[2];
             if (ndef > 0) {
                 trace_reset(c);
                 EngineTimer tm(c, &ms_eng[1], &nl_eng[1]);
@@ -666,6 +673,18 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
                     return tkc_fail(TKC_EDEVICE, "batched tail launch failed");
                 tm.done();
                 trace_dump(c, "tail");
+            }
+            // every position the cursor handed out was searched, skipped or
+            // deferred; without a stop rule firing, the order resumes there
+            const int32_t resume = cursor + std::min(fetched, n - cursor);
+            if (!(sw_stop & 1) && (sw_stop & 2) && resume < n) {
+                trace_reset(c);
+                EngineTimer tm(c, &ms_eng[1], &nl_eng[1]);
+                if (tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_batch, nullptr, 0, resume, 0, false,
+                                     false, nullptr, nullptr, c->tune, s, &grid))
+                    return tkc_fail(TKC_EDEVICE, "batched continuation launch failed");
+                tm.done();
+                trace_dump(c, "rest");
             }
         }
     }

@@ -135,7 +135,7 @@ struct BatchWork {
     int64_t* levtab;     // LCAP * W Lev tables
     int32_t lcap;
     int32_t* cand;       // selected candidates of a batch (W)
-    int64_t* trace;      // optional per-level records (8 int64 each), [0] = count
+    int64_t* trace;      // optional per-level records (16 int64 from word 8), [0] = count
     int64_t trace_cap;
     uint32_t* bar;       // grid barrier state (zeroed once)
 };
@@ -152,9 +152,10 @@ struct SwarmWork {
     int32_t* deferred;   // n
     int32_t* ndeferred;  // 1
     int32_t* cursor;     // 1
-    int32_t* stop;       // 1
+    int32_t* stop;       // 1: bit 0 stop rule fired, bit 1 engine closed
     int32_t nblocks;
     int32_t qcap;
+    int32_t defer_cap;   // deferrals after which the engine closes itself
 };
 int tkc_launch_swarm(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv, DevTopk tk,
                      SwarmWork w, int64_t* stats, int32_t start_pos, const EngineTuning& tune,

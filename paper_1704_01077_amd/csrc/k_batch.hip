@@ -26,6 +26,7 @@
 #define C_UCNT(p) (C_BASE + (p) * 8 + 0)
 #define C_UDEG(p) (C_BASE + (p) * 8 + 1)
 #define C_T(p, c) (C_BASE + (p) * 8 + 2 + (c))   // next list tails: light, heavy, giant
+#define C_DDONE(p) (C_BASE + (p) * 8 + 5)       // out-degrees of vertices now seen by every active lane
 #define C_L0 (C_BASE + 28)                    // level-0 list lengths (3)
 #define C_NSEL (C_BASE + 24)
 #define C_POS (C_BASE + 25)
@@ -78,25 +79,43 @@ struct Mask {
     }
 };
 
-// wave-aggregated append to the next level's light / heavy vertex lists
-TKC_DEV void list_append(bool isnew, int32_t w, int32_t dw, int32_t* const* lists, int64_t* tails) {
-    int cls = dw > HEAVY_DEG ? 1 : 0;
-    uint64_t m[2];
-#pragma unroll
-    for (int c = 0; c < 2; c++) m[c] = __ballot(isnew && cls == c);
-    if ((m[0] | m[1]) == 0) return;
-    int leader = __ffsll((long long)__ballot(1)) - 1;
-    int64_t b[2] = {0, 0};
-    if (lane_id() == leader) {
-#pragma unroll
-        for (int c = 0; c < 2; c++)
-            if (m[c]) b[c] = fadd_rlx(&tails[c], (int64_t)__popcll(m[c]));
+// Appends to the next level's vertex lists.  One tail counter per list
+// takes every append, and a large level makes tens of thousands of them, so
+// light vertices (the vast majority) are first staged in a per-wave LDS
+// buffer and reserved in the list once per STAGE entries; heavy vertices
+// (rare) are appended directly.
+#define STAGE 1024
+struct Stage {
+    int32_t* buf;   // this wave's LDS slots
+    int32_t n;      // filled slots (wave-uniform)
+};
+TKC_DEV void stage_flush(Stage& st, int32_t* list, int64_t* tail) {
+    if (st.n == 0) return;
+    int64_t b = 0;
+    if (lane_id() == 0) b = fadd_rlx(tail, (int64_t)st.n);
+    b = shfl64b(b, 0);
+    __builtin_amdgcn_wave_barrier();
+    for (int32_t i = lane_id(); i < st.n; i += 64) list[b + i] = st.buf[i];
+    __builtin_amdgcn_wave_barrier();
+    st.n = 0;
+}
+// called by all 64 lanes of a wave
+TKC_DEV void list_append(bool isnew, int32_t w, int32_t dw, int32_t* const* lists, int64_t* tails, Stage& st) {
+    const bool heavy = dw > HEAVY_DEG;
+    const uint64_t ml = __ballot(isnew && !heavy);
+    const uint64_t mh = __ballot(isnew && heavy);
+    const uint64_t bm = below_mask();
+    if (mh) {
+        int64_t b = 0;
+        if (lane_id() == 0) b = fadd_rlx(&tails[1], (int64_t)__popcll(mh));
+        b = shfl64b(b, 0);
+        if (isnew && heavy) lists[1][b + __popcll(mh & bm)] = w;
     }
-    uint64_t bm = below_mask();
-#pragma unroll
-    for (int c = 0; c < 2; c++) {
-        int64_t bc = shfl64b(b[c], leader);
-        if (isnew && cls == c) lists[c][bc + __popcll(m[c] & bm)] = w;
+    if (ml) {
+        const int32_t c = __popcll(ml);
+        if (st.n + c > STAGE) stage_flush(st, lists[0], &tails[0]);
+        if (isnew && !heavy) st.buf[st.n + __popcll(ml & bm)] = w;
+        st.n += c;
     }
 }
 
@@ -158,6 +177,8 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
     __shared__ int32_t s_red_cnt[MAXW];
     __shared__ int64_t s_red_deg[MAXW];
     __shared__ int64_t s_scal[8];
+    __shared__ int32_t s_stage[BB / 64][STAGE];
+    __shared__ int64_t s_blk[3];
 
     int32_t pos = a.start_pos;
     int32_t batches = 0;
@@ -282,7 +303,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 }
             }
             for (int p = 0; p < 3; p++) {
-                ctr[C_UCNT(p)] = 0; ctr[C_UDEG(p)] = 0;
+                ctr[C_UCNT(p)] = 0; ctr[C_UDEG(p)] = 0; ctr[C_DDONE(p)] = 0;
                 for (int c = 0; c < 3; c++) ctr[C_T(p, c)] = 0;
             }
             ctr[C_L0 + 0] = nl0; ctr[C_L0 + 1] = nh0; ctr[C_L0 + 2] = nc0;
@@ -296,8 +317,11 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
         int64_t fl_len = ld_rlx(&ctr[C_L0 + 0]), fh_len = ld_rlx(&ctr[C_L0 + 1]), fc_len = ld_rlx(&ctr[C_L0 + 2]);
         int64_t ucnt = fl_len + fh_len, udeg = 0;
         for (int l = 0; l < nsel; l++) udeg += s_mf[l];
-        int64_t udisc = udeg;
+        // out-arcs of vertices that every active lane has reached: a pull
+        // step never scans their in-arcs again
+        int64_t ddone = 0;
         bool bu = false;
+        int64_t tslot = -1;
         int64_t mvis = 0, bytes = 0;
         for (;;) {
             // ------------------------------------ per-lane control (replicated)
@@ -337,14 +361,19 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             mvis += s_scal[0];
             // direction on the union frontier.  With several lanes a pull
             // rarely stops early (every missing lane must be found), so it
-            // pays only once the frontier's arcs rival the unexplored ones.
-            bool want_bu = bu ? (ucnt >= (int64_t)n / a.beta_bu)
-                              : (udeg > (a.g.m - udisc) / a.alpha_td && ucnt > 256);
+            // pays only once the frontier's arcs rival the arcs still to be
+            // scanned.  A pull also needs a frontier of at least n / beta
+            // vertices, the size below which a pull returns to push, so the
+            // choice cannot flip back and forth between small levels.
+            const bool big = ucnt >= (int64_t)n / a.beta_bu;
+            bool want_bu = bu ? big : (big && udeg > (a.g.m - ddone) / a.alpha_td);
             bu = want_bu;
+            tslot = -1;
             if (boss && a.w.trace) {
                 int64_t t = fadd_rlx(&a.w.trace[0], (int64_t)1);
                 if (t < a.w.trace_cap) {
-                    int64_t* r = a.w.trace + 8 + 8 * t;
+                    tslot = t;
+                    int64_t* r = a.w.trace + 8 + 16 * t;
                     r[0] = batches; r[1] = D; r[2] = bu; r[3] = ucnt; r[4] = udeg;
                     r[5] = (int64_t)wall_clock64(); r[6] = nsel; r[7] = 0;
                     for (int j = 0; j < NW; j++) r[7] += __popcll(act.w[j]);
@@ -361,6 +390,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             uint64_t* fnxt = q ? a.w.frt0 : a.w.frt1;
             const int32_t stamp = (int32_t)(D + 1);
             bytes += bu ? (int64_t)n * (8 * NW) : (fl_len + fh_len) * (8 + 8 * NW);
+            Stage stg{&s_stage[tid >> 6][0], 0};
             if (!bu) {
                 // push, light frontier vertices: one per lane
                 for (int64_t base = gwave * 64; base < fl_len; base += nwaves * 64) {
@@ -388,7 +418,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                                 dw = deg[w];
                             }
                         }
-                        list_append(isnew, w, dw, nls, &ctr[C_T(p, 0)]);
+                        list_append(isnew, w, dw, nls, &ctr[C_T(p, 0)], stg);
                     }
                 }
                 // push, heavy frontier vertices: one wave per chunk of arcs
@@ -414,7 +444,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                                 dw = deg[w];
                             }
                         }
-                        list_append(isnew, w, dw, nls, &ctr[C_T(p, 0)]);
+                        list_append(isnew, w, dw, nls, &ctr[C_T(p, 0)], stg);
                     }
                 }
             } else {
@@ -435,12 +465,20 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                         }
                         need = need && miss.any();
                         if (need) {
-                            for (int32_t e = eb; e < ee; e++) {
-                                int32_t u = a.g.rci[e];
+                            // in-arcs in groups of four: four independent index
+                            // loads, then four independent frontier loads
+                            for (int32_t e = eb; e < ee; e += 4) {
+                                int32_t u[4];
+#pragma unroll
+                                for (int t = 0; t < 4; t++) u[t] = e + t < ee ? a.g.rci[e + t] : -1;
                                 bool full = true;
 #pragma unroll
                                 for (int j = 0; j < NW; j++) {
-                                    acc.w[j] |= fcur[(int64_t)u * NW + j] & miss.w[j];
+                                    uint64_t f = 0;
+#pragma unroll
+                                    for (int t = 0; t < 4; t++)
+                                        if (u[t] >= 0) f |= fcur[(int64_t)u[t] * NW + j];
+                                    acc.w[j] |= f & miss.w[j];
                                     full &= acc.w[j] == miss.w[j];
                                 }
                                 if (full) break;
@@ -453,7 +491,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                             }
                         }
                     }
-                    list_append(isnew, w, dw, nls, &ctr[C_T(p, 0)]);
+                    list_append(isnew, w, dw, nls, &ctr[C_T(p, 0)], stg);
                 }
                 // pull, heavy vertices: one wave per chunk of their in-arcs
                 for (int64_t c = gwave; c < a.g.rnchunks; c += nwaves) {
@@ -487,10 +525,12 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                         isnew = true;
                         dw = deg[w];
                     }
-                    list_append(isnew, w, dw, nls, &ctr[C_T(p, 0)]);
+                    list_append(isnew, w, dw, nls, &ctr[C_T(p, 0)], stg);
                 }
             }
+            stage_flush(stg, nls[0], &ctr[C_T(p, 0)]);
             grid_barrier(a.bar, gridDim.x);
+            if (boss && tslot >= 0) a.w.trace[8 + 16 * tslot + 8] = (int64_t)wall_clock64();
             // ------------------------------------------------------ epilogue
             const int64_t nl_len = ld_rlx(&ctr[C_T(p, 0)]), nh_len = ld_rlx(&ctr[C_T(p, 1)]);
             const int64_t nall = nl_len + nh_len;
@@ -498,6 +538,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             int32_t* ncu = CU(q ^ 1);
             int32_t* ncb = CB(q ^ 1);
             if (tid < MAXW) { s_red_cnt[tid] = 0; s_red_deg[tid] = 0; }
+            if (tid < 3) s_blk[tid] = 0;
             __syncthreads();
             // old frontier words are cleared (the next level uses the other array)
             uint64_t* fcur_w = (uint64_t*)fcur;
@@ -506,7 +547,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
 #pragma unroll
                 for (int j = 0; j < NW; j++) fcur_w[(int64_t)u * NW + j] = 0;
             }
-            int64_t my_u = 0, my_ud = 0;
+            int64_t my_u = 0, my_ud = 0, my_dd = 0;
             for (int64_t base = gwave * 64; base < nall; base += nwaves * 64) {
                 int64_t i = base + lane;
                 Mask<NW> nb;
@@ -516,14 +557,18 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 if (i < nall) {
                     w = i < nl_len ? nls[0][i] : nls[1][i - nl_len];
                     dw = deg[w];
+                    bool done = true;
 #pragma unroll
                     for (int j = 0; j < NW; j++) {
                         uint64_t b = a.w.nxt[(int64_t)w * NW + j];
                         nb.w[j] = b;
                         a.w.nxt[(int64_t)w * NW + j] = 0;
-                        vis[(int64_t)w * NW + j] |= b;
+                        uint64_t vn = vis[(int64_t)w * NW + j] | b;
+                        vis[(int64_t)w * NW + j] = vn;
                         fnxt[(int64_t)w * NW + j] = b;
+                        done &= (act.w[j] & ~vn) == 0;
                     }
+                    if (done) my_dd += dw;
                     if (a.lb_mode && D + 1 < a.w.lcap) {
 #pragma unroll
                         for (int j = 0; j < NW; j++) {
@@ -577,16 +622,24 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             }
             my_u = wave_sum_i64(my_u);
             my_ud = wave_sum_i64(my_ud);
+            my_dd = wave_sum_i64(my_dd);
             if (lane == 0 && my_u) {
-                fadd_rlx(&ctr[C_UCNT(p)], my_u);
-                fadd_rlx(&ctr[C_UDEG(p)], my_ud);
+                atomicAdd((unsigned long long*)&s_blk[0], (unsigned long long)my_u);
+                atomicAdd((unsigned long long*)&s_blk[1], (unsigned long long)my_ud);
+                atomicAdd((unsigned long long*)&s_blk[2], (unsigned long long)my_dd);
             }
             __syncthreads();
+            if (tid == 0 && s_blk[0]) {
+                fadd_rlx(&ctr[C_UCNT(p)], s_blk[0]);
+                fadd_rlx(&ctr[C_UDEG(p)], s_blk[1]);
+                if (s_blk[2]) fadd_rlx(&ctr[C_DDONE(p)], s_blk[2]);
+            }
             if (tid < W && s_red_cnt[tid]) {
                 fadd_rlx(&ctr[C_CNT(p, tid)], (int64_t)s_red_cnt[tid]);
                 fadd_rlx(&ctr[C_DEG(p, tid)], s_red_deg[tid]);
             }
             grid_barrier(a.bar, gridDim.x);
+            if (boss && tslot >= 0) a.w.trace[8 + 16 * tslot + 9] = (int64_t)wall_clock64();
             // --------------------------------------------- advance lane state
             if (tid < MAXW) {
                 int l = tid;
@@ -605,13 +658,13 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             }
             ucnt = ld_rlx(&ctr[C_UCNT(p)]);
             udeg = ld_rlx(&ctr[C_UDEG(p)]);
-            udisc += udeg;
+            ddone += ld_rlx(&ctr[C_DDONE(p)]);
             bytes += ucnt * 8 * (3 * NW) + nall * 4;
             fc_len = ld_rlx(ctail);
             if (boss) {
                 int q3 = (int)((D + 2) % 3);
                 for (int l = 0; l < W; l++) { ctr[C_CNT(q3, l)] = 0; ctr[C_DEG(q3, l)] = 0; }
-                ctr[C_UCNT(q3)] = 0; ctr[C_UDEG(q3)] = 0;
+                ctr[C_UCNT(q3)] = 0; ctr[C_UDEG(q3)] = 0; ctr[C_DDONE(q3)] = 0;
                 for (int c = 0; c < 3; c++) ctr[C_T(q3, c)] = 0;
             }
             fl_len = nl_len;

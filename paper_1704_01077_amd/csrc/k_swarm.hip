@@ -9,6 +9,15 @@
 // engine, which is better at large searches.  The stop rule of Alg. 1 is
 // applied when a candidate is taken: once one candidate's key proves that
 // every later bound exceeds x, the cursor is closed for all workgroups.
+//
+// Deferred searches do not lower x, so on a graph where most candidates
+// reach a large part of the graph quickly the workgroups would walk the
+// whole order deferring everything.  After `defer_cap` deferrals the engine
+// therefore closes itself: the cursor stops, searches in flight are
+// deferred at their next level boundary, and the host hands the deferred
+// list and the rest of the order to the batched engine.
+//
+// stop word bits: 1 = the stop rule fired, 2 = the engine closed itself.
 #include "dev_common.hpp"
 #include "engine.hpp"
 
@@ -24,6 +33,7 @@ struct SwarmArgs {
     int64_t* stats;
     int32_t start_pos;
     int32_t words;
+    int32_t defer_cap;
 };
 
 // exclusive scan of one int per thread over the workgroup; returns the total
@@ -58,6 +68,7 @@ __global__ void __launch_bounds__(SB) k_swarm(SwarmArgs a) {
     __shared__ int64_t s_cnt, s_deg;
     __shared__ int64_t s_x[3];
     __shared__ int32_t s_dec;
+    __shared__ int32_t s_closed;
 
     const int tid = threadIdx.x;
     const int32_t* __restrict__ rp = a.g.rp;
@@ -83,7 +94,7 @@ __global__ void __launch_bounds__(SB) k_swarm(SwarmArgs a) {
                 int32_t v = a.ov.ord[p];
                 uint32_t key = a.ov.key[p];
                 bool stop = a.ov.key_is_bound ? key_stops(key, x) : (key == 0xffffffffu && x.den != 0);
-                if (stop) { st_rlx(a.w.stop, 1); s_dec = 1; }
+                if (stop) { for_rlx(a.w.stop, 1); s_dec = 1; }
                 else if (lex_after(a.bv.num[v], a.bv.den[v], v, x.num, x.den, x.id)) { s_dec = 2; st_skip++; }
                 else if (a.rc.omega[v] <= 1) {
                     s_dec = 3;
@@ -121,6 +132,7 @@ __global__ void __launch_bounds__(SB) k_swarm(SwarmArgs a) {
                 XVal x = read_x(a.tk.st, a.tk.ring);
                 s_x[0] = x.num; s_x[1] = x.den; s_x[2] = x.id;
                 s_cnt = 0; s_deg = 0;
+                s_closed = (ld_rlx(a.w.stop) & 2) != 0;
             }
             __syncthreads();
             {
@@ -128,6 +140,7 @@ __global__ void __launch_bounds__(SB) k_swarm(SwarmArgs a) {
                 cut_bound(SD, nD, U, D, av, ov, &bn, &bd);
                 if (lex_after(bn, bd, v, s_x[0], s_x[1], (int32_t)s_x[2])) { status = 2; break; }
             }
+            if (s_closed) { status = 3; break; }
             // expand level D: frontier q[ls, le), edge-balanced in chunks of SB vertices
             int64_t my_cnt = 0, my_deg = 0;
             for (int32_t c = ls; c < le; c += SB) {
@@ -185,8 +198,9 @@ __global__ void __launch_bounds__(SB) k_swarm(SwarmArgs a) {
             le = s_tail;
             __syncthreads();
         }
-        // clear the private bitmap
-        if (status == 3) {
+        // clear the private bitmap: by the queue, unless it overflowed (then
+        // some marked vertices are not in it)
+        if (status == 3 && s_over) {
             for (int32_t qw = tid; qw < a.words; qw += SB) vis[qw] = 0;
         } else {
             int32_t tail = s_tail;
@@ -206,8 +220,10 @@ __global__ void __launch_bounds__(SB) k_swarm(SwarmArgs a) {
             } else {
                 st_def++;
                 st_started--;
+                // every candidate is taken once, so slot < n
                 int32_t slot = fadd_rlx(a.w.ndeferred, 1);
                 a.w.deferred[slot] = v;
+                if (slot + 1 >= a.defer_cap) for_rlx(a.w.stop, 2);
             }
         }
         __syncthreads();
@@ -246,6 +262,7 @@ int tkc_launch_swarm(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv
     a.stats = stats;
     a.start_pos = start_pos;
     a.words = (int32_t)(((int64_t)g.n + 31) / 32);
+    a.defer_cap = w.defer_cap > 0 ? w.defer_cap : 0x7fffffff;
     hipLaunchKernelGGL(k_swarm, dim3(w.nblocks), dim3(SB), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
