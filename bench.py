@@ -27,6 +27,13 @@ sys.path.insert(0, ROOT)
 METRIC = "top-k closeness wall time & GTEPS (frac. HBM peak), batched vs plain; p50/p99"
 HBM_PEAK_GBS = 8000.0
 KERNEL_NAMES = {0: "k_plain", 1: "k_batch", 2: "k_swarm"}
+MODE_NAMES = {0: "plain", 1: "batched", 2: "hybrid"}
+WORKLOADS = {
+    "ba2k": "BA undirected n=2000 m=5 seed=1",
+    "ba1m": "BA undirected n=1048576 m=5 seed=2 (5,242,865 edges)",
+    "rmat20": "R-MAT directed scale 20 edge factor 16 (a,b,c,d)=(.57,.19,.19,.05) seed=3",
+    "grid2000": "2000x2000 4-neighbour grid, 5% edges deleted, 1000 shortcuts, largest component, seed=4",
+}
 
 
 def kernel_source_hash() -> str:
@@ -91,11 +98,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--variant", default="auto")
-    ap.add_argument("--mode", default="hybrid")
+    ap.add_argument("--mode", default="auto",
+                    help="plain | batched | hybrid | auto (the autotuned setting of this graph and query)")
+    ap.add_argument("--autotune-ms", type=float, default=8000.0,
+                    help="time budget of the autotuner that runs before the warm-up when --mode auto")
     ap.add_argument("--workload", default="ba1m")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-compare", action="store_true", help="skip the plain/batched comparison runs")
+    ap.add_argument("--compare", default="plain,batched,hybrid",
+                    help="modes timed once each (default knobs) beside the main run")
+    ap.add_argument("--no-compare", action="store_true", help="skip the comparison runs")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -122,6 +134,11 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
 
+    tuning = None
+    if args.mode == "auto" and args.autotune_ms > 0:
+        print("bench: autotune (budget %.0f ms)" % args.autotune_ms, file=sys.stderr, flush=True)
+        tuning, tuned_ms = dg.autotune(args.k, args.variant, args.autotune_ms)
+        print("bench: autotuned %s (%.3f ms)" % (tuning, tuned_ms), file=sys.stderr, flush=True)
     print("bench: warmup", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         tkc.topk_closeness(dg, args.k, args.variant, args.mode)
@@ -158,7 +175,7 @@ def main():
 
     compare = {}
     if not args.no_compare:
-        for mode in ("plain", "batched"):
+        for mode in [m for m in args.compare.split(",") if m]:
             print("bench: compare %s" % mode, file=sys.stderr, flush=True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -185,10 +202,10 @@ def main():
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": "BA undirected n=1048576 m=5 seed=2 (5,242,865 edges), top-k k=%d" % args.k
-                   if args.workload == "ba1m" else args.workload,
+        "config": {"workload": "%s, top-k k=%d" % (WORKLOADS.get(args.workload, args.workload), args.k),
                    "k": args.k, "variant": args.variant, "variant_used": st["variant_used"],
-                   "mode": args.mode, "batch_width": st["batch_width"], "n": g.n, "arcs": int(g.arcs)},
+                   "mode": args.mode, "mode_used": MODE_NAMES.get(st["mode_used"], st["mode_used"]),
+                   "batch_width": st["batch_width"], "tuning": tuning, "n": g.n, "arcs": int(g.arcs)},
         "wall_ms_p50": round(float(np.percentile(walls, 50)), 4),
         "wall_ms_p99": round(float(np.percentile(walls, 99)), 4),
         "m_vis": int(mvis),

@@ -66,6 +66,9 @@ extern "C" {
 #define TKC_BATCHED 1       /* W sources per launch, one bit lane each    */
 #define TKC_HYBRID 2        /* batched seed, then one search per workgroup
                                for short cut searches, batched tail        */
+#define TKC_MODE_AUTO 3     /* the graph's autotuned mode and knobs when
+                               tkc_autotune has run on it, else the
+                               context's preferred mode and knobs          */
 
 /* graph flags */
 #define TKC_DIRECTED 1u     /* arcs are directed; reverse CSR required    */
@@ -108,17 +111,38 @@ typedef struct {
 int tkc_ctx_create(int device, void *hip_stream, tkc_ctx **out);
 int tkc_ctx_destroy(tkc_ctx *ctx);
 
-/* Tuning knobs (0 keeps the current value).  batch_width in {32, 64, 128,
- * 256}; td_bu_alpha / bu_td_beta are the push->pull and pull->push switch
- * thresholds (Beamer's alpha and beta) of one-source searches; batch_alpha
- * is the push->pull threshold of batched searches (a pull over several lanes
- * rarely stops early, so it pays later); swarm_qcap is the queue capacity
- * of one per-workgroup search before it is handed to the batched engine;
- * seed_lanes caps the lanes of the first (seed) batch of the hybrid mode
- * (0: the batch width).  Errors: TKC_EINVAL. */
-int tkc_ctx_set_tuning(tkc_ctx *ctx, int32_t batch_width, int32_t td_bu_alpha,
-                       int32_t bu_td_beta, int32_t batch_alpha, int32_t swarm_qcap,
-                       int32_t seed_lanes);
+/* Execution knobs of a context (performance only: results never depend on
+ * them).
+ *   batch_width    lanes (sources) per batch: 32, 64, 128 or 256
+ *   td_bu_alpha    one-source searches go push -> pull when the frontier's
+ *                  arcs exceed the unexplored arcs / alpha (Beamer's alpha)
+ *   bu_td_beta     ... and pull -> push when the frontier holds fewer than
+ *                  n / beta vertices (Beamer's beta; batches use it too)
+ *   batch_alpha    the push -> pull rule for batched searches (a pull over
+ *                  several lanes rarely stops early, so it pays later)
+ *   swarm_qcap     queue capacity of one per-workgroup search (>= 64) before
+ *                  it is handed to the batched engine
+ *   seed_lanes     lanes of the hybrid mode's first (seed) batch, 0 meaning
+ *                  batch_width
+ *   blocks_per_cu  workgroups per compute unit of the persistent kernels,
+ *                  1..8 (capped at what fits; more hides more latency, fewer
+ *                  make grid barriers cheaper)
+ *   mode           TKC_PLAIN, TKC_BATCHED or TKC_HYBRID: what TKC_MODE_AUTO
+ *                  runs on a graph that has not been autotuned */
+typedef struct {
+    int32_t batch_width;
+    int32_t td_bu_alpha;
+    int32_t bu_td_beta;
+    int32_t batch_alpha;
+    int32_t swarm_qcap;
+    int32_t seed_lanes;
+    int32_t blocks_per_cu;
+    int32_t mode;
+} tkc_tuning;
+
+int tkc_ctx_get_tuning(tkc_ctx *ctx, tkc_tuning *out);
+/* Every field is checked; TKC_EINVAL leaves the context unchanged. */
+int tkc_ctx_set_tuning(tkc_ctx *ctx, const tkc_tuning *t);
 
 /* Copy a graph to device memory.  row_ptr[n+1], col_idx[m_arcs] give the
  * out-arcs; rrow_ptr/rcol_idx give the in-arcs and are required iff
@@ -142,6 +166,17 @@ int tkc_graph_free(tkc_graph *g);
 int tkc_topk_closeness(tkc_graph *g, int32_t k, int32_t variant, int32_t mode,
                        int32_t *ids, int64_t *sum_dist, int64_t *reach, double *farness,
                        int32_t *n_out, tkc_stats *stats);
+
+/* Autotuner: times the query (k, variant) on g under candidate knob
+ * settings, one knob at a time (batch width, mode, workgroups per CU, batch
+ * alpha), keeping each improvement, until the settings are exhausted or the
+ * measured time passes budget_ms (at least the context's own settings run).
+ * Every trial's ids must agree (TKC_EDEVICE otherwise: an internal error).
+ * The fastest setting is stored on the graph, where TKC_MODE_AUTO queries
+ * (and the server) use it, and copied to best / best_ms (either may be
+ * NULL).  The context's own settings are left as they were. */
+int tkc_autotune(tkc_graph *g, int32_t k, int32_t variant, double budget_ms, tkc_tuning *best,
+                 double *best_ms);
 
 /* ---- inspection of the individual steps (host output arrays of n items) */
 /* Reachability (Sect. 4 and Sect. 8.4, Alg. 6): undirected graphs get

@@ -190,20 +190,49 @@ extern "C" int tkc_ctx_destroy(tkc_ctx* c) {
     return TKC_OK;
 }
 
-extern "C" int tkc_ctx_set_tuning(tkc_ctx* c, int32_t batch_width, int32_t td_bu_alpha, int32_t bu_td_beta,
-                                  int32_t batch_alpha, int32_t swarm_qcap, int32_t seed_lanes) {
-    if (!c) return tkc_fail(TKC_EINVAL, "ctx is NULL");
-    if (batch_width && batch_width != 32 && batch_width != 64 && batch_width != 128 && batch_width != 256)
+static void tuning_out(const EngineTuning& e, tkc_tuning* t) {
+    t->batch_width = e.batch_width;
+    t->td_bu_alpha = e.td_bu_alpha;
+    t->bu_td_beta = e.bu_td_beta;
+    t->batch_alpha = e.batch_alpha;
+    t->swarm_qcap = e.swarm_qcap;
+    t->seed_lanes = e.seed_lanes;
+    t->blocks_per_cu = e.blocks_per_cu;
+    t->mode = e.mode;
+}
+
+static int tuning_in(const tkc_tuning* t, EngineTuning* e) {
+    const int32_t bw = t->batch_width;
+    if (bw != 32 && bw != 64 && bw != 128 && bw != 256)
         return tkc_fail(TKC_EINVAL, "batch_width must be 32, 64, 128 or 256");
-    if (td_bu_alpha < 0 || bu_td_beta < 0 || batch_alpha < 0 || swarm_qcap < 0 || seed_lanes < 0)
-        return tkc_fail(TKC_EINVAL, "negative tuning value");
-    if (batch_width) c->tune.batch_width = batch_width;
-    if (td_bu_alpha) c->tune.td_bu_alpha = td_bu_alpha;
-    if (bu_td_beta) c->tune.bu_td_beta = bu_td_beta;
-    if (batch_alpha) c->tune.batch_alpha = batch_alpha;
-    if (swarm_qcap) c->tune.swarm_qcap = swarm_qcap;
-    if (seed_lanes) c->tune.seed_lanes = seed_lanes;
+    if (t->td_bu_alpha < 1 || t->bu_td_beta < 1 || t->batch_alpha < 1)
+        return tkc_fail(TKC_EINVAL, "direction thresholds must be >= 1");
+    if (t->swarm_qcap < 64) return tkc_fail(TKC_EINVAL, "swarm_qcap must be >= 64");
+    if (t->seed_lanes < 0 || t->seed_lanes > bw) return tkc_fail(TKC_EINVAL, "seed_lanes must be in [0, batch_width]");
+    if (t->blocks_per_cu < 1 || t->blocks_per_cu > 8) return tkc_fail(TKC_EINVAL, "blocks_per_cu must be in [1, 8]");
+    if (t->mode < TKC_PLAIN || t->mode > TKC_HYBRID) return tkc_fail(TKC_EINVAL, "mode must be plain, batched or hybrid");
+    EngineTuning x = *e;
+    x.batch_width = bw;
+    x.td_bu_alpha = t->td_bu_alpha;
+    x.bu_td_beta = t->bu_td_beta;
+    x.batch_alpha = t->batch_alpha;
+    x.swarm_qcap = t->swarm_qcap;
+    x.seed_lanes = t->seed_lanes;
+    x.blocks_per_cu = t->blocks_per_cu;
+    x.mode = t->mode;
+    *e = x;
     return TKC_OK;
+}
+
+extern "C" int tkc_ctx_get_tuning(tkc_ctx* c, tkc_tuning* out) {
+    if (!c || !out) return tkc_fail(TKC_EINVAL, "NULL argument");
+    tuning_out(c->tune, out);
+    return TKC_OK;
+}
+
+extern "C" int tkc_ctx_set_tuning(tkc_ctx* c, const tkc_tuning* t) {
+    if (!c || !t) return tkc_fail(TKC_EINVAL, "NULL argument");
+    return tuning_in(t, &c->tune);
 }
 
 // ------------------------------------------------------------------ graphs
@@ -400,16 +429,21 @@ extern "C" int tkc_graph_free(tkc_graph* g) {
 }
 
 // ------------------------------------------------------------ query steps
-WsShape tkc_shape_for(tkc_ctx* c, tkc_graph* g, int32_t k, bool lb) {
+EngineTuning tkc_effective_tuning(const EngineTuning& ctx_tune, tkc_graph* g) {
+    std::lock_guard<std::mutex> lk(g->mu);
+    return g->tuned ? g->tune : ctx_tune;
+}
+
+WsShape tkc_shape_for(const EngineTuning& t, tkc_graph* g, int32_t k, bool lb) {
     WsShape sh;
     sh.n = g->n;
-    sh.W = c->tune.batch_width;
+    sh.W = t.batch_width;
     sh.nw = sh.W <= 64 ? 1 : sh.W / 64;
     sh.kcap = std::max(k, 1);
     sh.lb = lb;
     sh.lcap = (int32_t)std::min<int64_t>((int64_t)g->n + 2, 65000);
     sh.nchunks = std::max(g->nchunks, g->rnchunks);
-    sh.qcap = std::max(64, std::min(c->tune.swarm_qcap, g->n));
+    sh.qcap = std::max(64, std::min(t.swarm_qcap, g->n));
     sh.swarm_blocks = std::max(1, tkc_swarm_max_blocks(256));
     // the private bitmaps of the per-workgroup engine cost blocks * n/8 bytes;
     // keep them under 2 GiB
@@ -551,10 +585,88 @@ extern "C" int tkc_topk_closeness(tkc_graph* g, int32_t k, int32_t variant, int3
     if (!g || !ids || !n_out) return tkc_fail(TKC_EINVAL, "NULL argument");
     if (k < 1) return tkc_fail(TKC_EINVAL, "k must be >= 1");
     if (variant < TKC_AUTO || variant > TKC_NB_BOUND) return tkc_fail(TKC_EINVAL, "unknown variant %d", variant);
-    if (mode < TKC_PLAIN || mode > TKC_HYBRID) return tkc_fail(TKC_EINVAL, "unknown mode %d", mode);
+    if (mode < TKC_PLAIN || mode > TKC_MODE_AUTO) return tkc_fail(TKC_EINVAL, "unknown mode %d", mode);
     tkc_ctx* c = g->ctx;
     HIPCHK(hipSetDevice(c->device));
     return tkc_run_query(c, g, k, variant, mode, ids, sum_dist, reach, farness, n_out, stats);
+}
+
+// Runs one query under knobs t (on the graph's context, whose own knobs are
+// restored afterwards) and returns its wall time.
+static int autotune_trial(tkc_graph* g, int32_t k, int32_t variant, const EngineTuning& t,
+                          std::vector<int32_t>& ids, double* ms) {
+    tkc_ctx* c = g->ctx;
+    const EngineTuning keep = c->tune;
+    c->tune = t;
+    int32_t nout = 0;
+    double best = 1e300;
+    int rc = TKC_OK;
+    // short queries are repeated (best of three) so that noise does not pick
+    for (int rep = 0; rep < 3 && rc == TKC_OK; rep++) {
+        double t0 = now_ms();
+        rc = tkc_run_query(c, g, k, variant, t.mode, ids.data(), nullptr, nullptr, nullptr, &nout, nullptr);
+        double dt = now_ms() - t0;
+        best = std::min(best, dt);
+        if (dt > 20.0) break;
+    }
+    c->tune = keep;
+    *ms = best;
+    return rc;
+}
+
+extern "C" int tkc_autotune(tkc_graph* g, int32_t k, int32_t variant, double budget_ms, tkc_tuning* best,
+                            double* best_ms) {
+    if (!g) return tkc_fail(TKC_EINVAL, "graph is NULL");
+    if (k < 1) return tkc_fail(TKC_EINVAL, "k must be >= 1");
+    if (variant < TKC_AUTO || variant > TKC_NB_BOUND) return tkc_fail(TKC_EINVAL, "unknown variant %d", variant);
+    tkc_ctx* c = g->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    if (variant == TKC_AUTO) variant = tkc_auto_variant(c, g);
+    const bool lb = (variant == TKC_DEG_BOUND || variant == TKC_NB_BOUND);
+    const int32_t kk = std::min(k, g->n);
+    std::vector<int32_t> ref(kk), ids(kk);
+    EngineTuning cur = c->tune;
+    if (cur.mode == TKC_PLAIN) cur.mode = TKC_BATCHED;
+    double cur_ms = 0, spent = 0;
+    // the first trial also warms up (workspace, preprocessing)
+    int rc = autotune_trial(g, k, variant, cur, ref, &cur_ms);
+    if (rc) return rc;
+    rc = autotune_trial(g, k, variant, cur, ref, &cur_ms);
+    if (rc) return rc;
+    spent += cur_ms;
+    // one knob at a time, most influential first
+    struct Axis {
+        int32_t EngineTuning::*field;
+        std::vector<int32_t> values;
+    };
+    std::vector<Axis> axes = {
+        {&EngineTuning::batch_width, {64, 128, 256, 32}},
+        {&EngineTuning::mode, lb ? std::vector<int32_t>{TKC_BATCHED} : std::vector<int32_t>{TKC_BATCHED, TKC_HYBRID}},
+        {&EngineTuning::blocks_per_cu, {1, 2, 3, 4}},
+        {&EngineTuning::batch_alpha, {4, 14, 40}},
+    };
+    for (const Axis& ax : axes) {
+        for (int32_t v : ax.values) {
+            if (spent >= budget_ms) break;
+            if (cur.*(ax.field) == v) continue;
+            EngineTuning t = cur;
+            t.*(ax.field) = v;
+            double ms = 0;
+            rc = autotune_trial(g, k, variant, t, ids, &ms);
+            if (rc) return rc;
+            spent += ms;
+            if (ids != ref) return tkc_fail(TKC_EDEVICE, "internal error: autotune trials disagree");
+            if (ms < cur_ms) { cur = t; cur_ms = ms; }
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        g->tune = cur;
+        g->tuned = true;
+    }
+    if (best) tuning_out(cur, best);
+    if (best_ms) *best_ms = cur_ms;
+    return TKC_OK;
 }
 
 int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t mode, int32_t* ids,
@@ -567,11 +679,20 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
     tkc_stats st;
     memset(&st, 0, sizeof(st));
     int rc;
+    // AUTO mode: the graph's autotuned knobs for this query, else the
+    // context's preferred mode
+    if (mode == TKC_MODE_AUTO) {
+        const EngineTuning keep = c->tune;
+        c->tune = tkc_effective_tuning(keep, g);
+        rc = tkc_run_query(c, g, k, variant, c->tune.mode, ids, sum_dist, reach, farness, n_out, stats);
+        c->tune = keep;
+        return rc;
+    }
     // AUTO: high-diameter graphs favour level-based updates (Sect. 9.1)
     if (variant == TKC_AUTO) variant = tkc_auto_variant(c, g);
     const bool lb = (variant == TKC_DEG_BOUND || variant == TKC_NB_BOUND);
     const bool nb = (variant == TKC_NB_CUT || variant == TKC_NB_BOUND);
-    rc = tkc_ws_reserve(c, ws, tkc_shape_for(c, g, k, lb));
+    rc = tkc_ws_reserve(c, ws, tkc_shape_for(c->tune, g, k, lb));
     if (rc) return rc;
     int32_t rounds = 0;
     double t1;
@@ -771,7 +892,7 @@ extern "C" int tkc_graph_reach(tkc_graph* g, int64_t* alpha, int64_t* omega, int
     if (!g || !alpha || !omega) return tkc_fail(TKC_EINVAL, "NULL argument");
     tkc_ctx* c = g->ctx;
     HIPCHK(hipSetDevice(c->device));
-    int rc = tkc_ws_reserve(c, c->ws, tkc_shape_for(c, g, 1, false));
+    int rc = tkc_ws_reserve(c, c->ws, tkc_shape_for(c->tune, g, 1, false));
     if (rc) return rc;
     rc = tkc_step_reach(c, g, c->ws);
     if (rc) return rc;
@@ -788,7 +909,7 @@ extern "C" int tkc_graph_bounds(tkc_graph* g, int32_t variant, int64_t* num, int
     if (variant < TKC_DEG_CUT || variant > TKC_NB_BOUND) return tkc_fail(TKC_EINVAL, "bad variant");
     tkc_ctx* c = g->ctx;
     HIPCHK(hipSetDevice(c->device));
-    int rc = tkc_ws_reserve(c, c->ws, tkc_shape_for(c, g, 1, false));
+    int rc = tkc_ws_reserve(c, c->ws, tkc_shape_for(c->tune, g, 1, false));
     if (rc) return rc;
     rc = tkc_step_reach(c, g, c->ws);
     if (rc) return rc;
@@ -806,7 +927,7 @@ int tkc_sums_impl(tkc_ctx* c, tkc_graph* g, const int32_t* sources, int32_t coun
                   tkc_stats* stout) {
     Workspace& ws = c->ws;
     hipStream_t s = c->stream;
-    int rc = tkc_ws_reserve(c, ws, tkc_shape_for(c, g, std::max(1, ws.shape.kcap), ws.shape.lb));
+    int rc = tkc_ws_reserve(c, ws, tkc_shape_for(c->tune, g, std::max(1, ws.shape.kcap), ws.shape.lb));
     if (rc) return rc;
     rc = tkc_step_reach(c, g, ws);
     if (rc) return rc;
@@ -861,7 +982,7 @@ extern "C" int tkc_graph_lb_update(tkc_graph* g, const int32_t* sources, int32_t
     HIPCHK(hipSetDevice(c->device));
     hipStream_t s = c->stream;
     Workspace& ws = c->ws;
-    int rc = tkc_ws_reserve(c, ws, tkc_shape_for(c, g, 1, true));
+    int rc = tkc_ws_reserve(c, ws, tkc_shape_for(c->tune, g, 1, true));
     if (rc) return rc;
     rc = tkc_step_reach(c, g, ws);
     if (rc) return rc;

@@ -75,6 +75,8 @@ struct EngineTuning {
     int32_t swarm_qcap = 65536;
     int32_t seed_lanes = 0;      // lanes of the hybrid mode's seed batch (0: batch_width)
     int32_t lanes_cap = 0;       // lanes used per batch in one launch (0: batch_width)
+    int32_t blocks_per_cu = 2;   // workgroups per CU of the persistent kernels
+    int32_t mode = 1;            // preferred mode (TKC_BATCHED) for TKC_MODE_AUTO
 };
 
 // k_prep.hip

@@ -94,6 +94,9 @@ struct tkc_graph {
         bool ready = false;
     } prep[2];
     bool cache_prep = false;
+    // autotuned knobs (TKC_MODE_AUTO)
+    bool tuned = false;
+    EngineTuning tune;
     DevGraph view() const {
         DevGraph g;
         g.n = n; g.m = m; g.directed = directed;
@@ -119,7 +122,9 @@ int tkc_step_bounds(tkc_ctx* c, tkc_graph* g, Workspace& ws, bool nb, int32_t* r
 bool tkc_prep_cached(tkc_ctx* c, tkc_graph* g, bool nb, int32_t* rounds);
 // build that cache from c's workspace after a query computed it
 int tkc_prep_store(tkc_ctx* c, tkc_graph* g, bool nb, int32_t rounds);
-WsShape tkc_shape_for(tkc_ctx* c, tkc_graph* g, int32_t k, bool lb);
+WsShape tkc_shape_for(const EngineTuning& t, tkc_graph* g, int32_t k, bool lb);
+// the knobs a TKC_MODE_AUTO query on g runs with, given the context's own
+EngineTuning tkc_effective_tuning(const EngineTuning& ctx_tune, tkc_graph* g);
 size_t tkc_ws_bytes(const WsShape& sh);
 // one cooperative kernel at a time on the device
 std::mutex& tkc_coop_mutex();

@@ -788,7 +788,8 @@ int tkc_launch_batch(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv
     else if (NW == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch<2>, BB, 0);
     else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch<4>, BB, 0);
     if (e != hipSuccess || occ < 1) return -1;
-    int per = occ < 2 ? occ : 2;
+    const int want = tune.blocks_per_cu > 0 ? tune.blocks_per_cu : 2;
+    int per = occ < want ? occ : want;
     int grid = prop.multiProcessorCount * per;
     if (grid_out) *grid_out = grid;
     BatchArgs a{};

@@ -406,7 +406,8 @@ int tkc_launch_plain(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_plain, PB, 0) != hipSuccess) return -1;
     if (occ < 1) return -1;
-    int per = occ < 2 ? occ : 2;
+    const int want = tune.blocks_per_cu > 0 ? tune.blocks_per_cu : 2;
+    int per = occ < want ? occ : want;
     int grid = prop.multiProcessorCount * per;
     if (grid_out) *grid_out = grid;
     PlainArgs a{};

@@ -120,7 +120,7 @@ struct tkc_server {
             int32_t got = 0;
             int st = TKC_OK;
             if (!rq->cancelled)
-                st = tkc_run_query(c, g, k, rq->variant, TKC_HYBRID, rq->ids.data(), rq->S.data(), rq->R.data(),
+                st = tkc_run_query(c, g, k, rq->variant, TKC_MODE_AUTO, rq->ids.data(), rq->S.data(), rq->R.data(),
                                    rq->F.data(), &got, nullptr);
             {
                 std::lock_guard<std::mutex> lk(mu);
@@ -189,7 +189,7 @@ extern "C" int tkc_server_submit(tkc_server* s, int32_t graph_id, int32_t k, int
     rq->variant = variant;
     rq->t_submit = now_ms();
     bool lb = (variant == TKC_DEG_BOUND || variant == TKC_NB_BOUND || variant == TKC_AUTO);
-    rq->need = tkc_ws_bytes(tkc_shape_for(s->ctx, g, std::min(k, g->n), lb));
+    rq->need = tkc_ws_bytes(tkc_shape_for(tkc_effective_tuning(s->ctx->tune, g), g, std::min(k, g->n), lb));
     if (rq->need > s->budget) return tkc_fail(TKC_EBUSY, "request needs %zu bytes, budget is %zu", rq->need, s->budget);
     s->queue.push_back(rq);
     s->all[rq->ticket] = rq;

@@ -25,16 +25,16 @@ TKC_EBUSY = -5
 TKC_ECANCELED = -6
 
 TKC_AUTO, TKC_DEG_CUT, TKC_NB_CUT, TKC_DEG_BOUND, TKC_NB_BOUND = 0, 1, 2, 3, 4
-TKC_PLAIN, TKC_BATCHED, TKC_HYBRID = 0, 1, 2
+TKC_PLAIN, TKC_BATCHED, TKC_HYBRID, TKC_MODE_AUTO = 0, 1, 2, 3
 TKC_DIRECTED, TKC_VALIDATE, TKC_DEVICE_PTRS = 1, 2, 4
 
 VARIANTS = {"auto": TKC_AUTO, "degcut": TKC_DEG_CUT, "nbcut": TKC_NB_CUT,
             "degbound": TKC_DEG_BOUND, "nbbound": TKC_NB_BOUND}
-MODES = {"plain": TKC_PLAIN, "batched": TKC_BATCHED, "hybrid": TKC_HYBRID}
+MODES = {"plain": TKC_PLAIN, "batched": TKC_BATCHED, "hybrid": TKC_HYBRID, "auto": TKC_MODE_AUTO}
 
 EXPORTS = [
-    "tkc_ctx_create", "tkc_ctx_destroy", "tkc_ctx_set_tuning", "tkc_graph_upload", "tkc_graph_free",
-    "tkc_topk_closeness", "tkc_graph_reach", "tkc_graph_bounds", "tkc_graph_lb_update",
+    "tkc_ctx_create", "tkc_ctx_destroy", "tkc_ctx_get_tuning", "tkc_ctx_set_tuning", "tkc_graph_upload",
+    "tkc_graph_free", "tkc_topk_closeness", "tkc_autotune", "tkc_graph_reach", "tkc_graph_bounds", "tkc_graph_lb_update",
     "tkc_graph_sums", "tkc_server_create", "tkc_server_add_graph", "tkc_server_submit",
     "tkc_server_poll", "tkc_server_result", "tkc_server_cancel", "tkc_server_destroy",
     "tkc_last_error", "tkc_version",
@@ -56,6 +56,14 @@ class tkc_stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
 
 
+class tkc_tuning(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32) for f in ("batch_width", "td_bu_alpha", "bu_td_beta", "batch_alpha",
+                                              "swarm_qcap", "seed_lanes", "blocks_per_cu", "mode")]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class TkcError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("tkc error %d: %s" % (code, msg))
@@ -73,7 +81,9 @@ def _load():
     sig = {
         "tkc_ctx_create": [c.c_int, vp, P(vp)],
         "tkc_ctx_destroy": [vp],
-        "tkc_ctx_set_tuning": [vp, i32, i32, i32, i32, i32, i32],
+        "tkc_ctx_get_tuning": [vp, P(tkc_tuning)],
+        "tkc_ctx_set_tuning": [vp, P(tkc_tuning)],
+        "tkc_autotune": [vp, i32, i32, c.c_double, P(tkc_tuning), P(c.c_double)],
         "tkc_graph_upload": [vp, i32, i64, vp, vp, vp, vp, u32, P(vp)],
         "tkc_graph_free": [vp],
         "tkc_topk_closeness": [vp, i32, i32, i32, vp, vp, vp, vp, P(i32), P(tkc_stats)],
@@ -129,10 +139,32 @@ def tkc_ctx_destroy(ctx):
     _check(lib.tkc_ctx_destroy(ctx))
 
 
-def tkc_ctx_set_tuning(ctx, batch_width=0, td_bu_alpha=0, bu_td_beta=0, batch_alpha=0, swarm_qcap=0,
-                       seed_lanes=0):
-    _check(lib.tkc_ctx_set_tuning(ctx, batch_width, td_bu_alpha, bu_td_beta, batch_alpha, swarm_qcap,
-                                  seed_lanes))
+def tkc_ctx_get_tuning(ctx) -> dict:
+    t = tkc_tuning()
+    _check(lib.tkc_ctx_get_tuning(ctx, ctypes.byref(t)))
+    return t.as_dict()
+
+
+def tkc_ctx_set_tuning(ctx, **kw):
+    """Set the named knobs; the others keep their current values."""
+    t = tkc_tuning()
+    _check(lib.tkc_ctx_get_tuning(ctx, ctypes.byref(t)))
+    for k, v in kw.items():
+        if k == "mode":
+            v = MODES.get(v, v)
+        if k not in t.as_dict():
+            raise TypeError("unknown tuning knob %r" % k)
+        setattr(t, k, int(v))
+    _check(lib.tkc_ctx_set_tuning(ctx, ctypes.byref(t)))
+
+
+def tkc_autotune(g, k, variant=TKC_AUTO, budget_ms=10000.0):
+    """Returns (best knob dict, best query ms); the graph keeps the setting."""
+    t = tkc_tuning()
+    ms = ctypes.c_double()
+    _check(lib.tkc_autotune(g, int(k), VARIANTS.get(variant, variant), float(budget_ms), ctypes.byref(t),
+                            ctypes.byref(ms)))
+    return t.as_dict(), ms.value
 
 
 def tkc_graph_upload(ctx, n, m_arcs, row_ptr, col_idx, rrow_ptr=None, rcol_idx=None, flags=0):
@@ -233,6 +265,9 @@ class Context:
     def tune(self, **kw):
         tkc_ctx_set_tuning(self.h, **kw)
 
+    def tuning(self) -> dict:
+        return tkc_ctx_get_tuning(self.h)
+
     def close(self):
         if self.h:
             tkc_ctx_destroy(self.h)
@@ -265,6 +300,9 @@ class Graph:
         if self.h:
             tkc_graph_free(self.h)
             self.h = None
+
+    def autotune(self, k, variant="auto", budget_ms=10000.0):
+        return tkc_autotune(self.h, k, variant, budget_ms)
 
     def reach(self):
         a = np.zeros(self.n, np.int64)

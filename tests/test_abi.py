@@ -56,15 +56,21 @@ def test_no_device_is_a_clean_error():
     assert e.value.code == tkc.TKC_EDEVICE
 
 
-def test_stats_struct_layout_matches_header():
-    """sizeof(tkc_stats) seen by C equals the ctypes mirror."""
+@pytest.mark.parametrize("struct", ["tkc_stats", "tkc_tuning"])
+def test_struct_layout_matches_header(struct):
+    """sizeof and every field offset seen by C equal the ctypes mirror."""
     from paper_1704_01077_amd import tkc
     import ctypes
-    src = ('#include <stdio.h>\n#include "tkc.h"\n'
-           'int main(void){ printf("%zu", sizeof(tkc_stats)); return 0; }\n')
-    exe = "/tmp/tkc_sizeof_%d" % os.getpid()
+    mirror = getattr(tkc, struct)
+    fields = [f for f, _ in mirror._fields_]
+    body = 'printf("%zu", sizeof({s}));'.format(s=struct)
+    body += "".join(' printf(" %zu", offsetof({s}, {f}));'.format(s=struct, f=f) for f in fields)
+    src = ('#include <stdio.h>\n#include <stddef.h>\n#include "tkc.h"\n'
+           'int main(void){ %s return 0; }\n' % body)
+    exe = "/tmp/tkc_sizeof_%s_%d" % (struct, os.getpid())
     subprocess.run(["gcc", "-x", "c", "-I", os.path.dirname(HEADER), "-o", exe, "-"], input=src, text=True,
                    check=True)
-    size = int(subprocess.run([exe], capture_output=True, text=True, check=True).stdout)
+    out = [int(x) for x in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
     os.unlink(exe)
-    assert size == ctypes.sizeof(tkc.tkc_stats)
+    assert out[0] == ctypes.sizeof(mirror)
+    assert out[1:] == [getattr(mirror, f).offset for f in fields]

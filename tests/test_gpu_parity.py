@@ -281,16 +281,69 @@ def test_batch_widths_topk(ctx, width):
 
 
 def test_small_swarm_queue_defers(ctx):
-    """A tiny per-workgroup queue forces deferrals to the batched tail."""
-    ctx.tune(swarm_qcap=64)
+    """A tiny per-workgroup queue forces deferrals; past batch-width of them
+    the engine closes and the rest of the order runs batched."""
+    keep = ctx.tuning()
+    ctx.tune(swarm_qcap=64, batch_width=32)
     try:
-        dg = upload(ctx, "ba20k")
-        ids, S, r, f, st = tkc.topk_closeness(dg, 10, "degcut", "hybrid")
-        wids, wS, wr, wf = expect("ba20k", 10)
-        assert np.array_equal(ids, wids) and np.array_equal(S, wS)
-        assert st["deferred"] > 0
+        for name in ("ba20k", "rmat13"):
+            dg = upload(ctx, name)
+            ids, S, r, f, st = tkc.topk_closeness(dg, 10, "degcut", "hybrid")
+            wids, wS, wr, wf = expect(name, 10)
+            assert np.array_equal(ids, wids) and np.array_equal(S, wS) and np.array_equal(r, wr)
+            assert st["deferred"] > 0
     finally:
-        ctx.tune(swarm_qcap=16384)
+        ctx.tune(**keep)
+
+
+# ---------------------------------------------------------------- tuning
+def test_tuning_roundtrip_and_validation(ctx):
+    keep = ctx.tuning()
+    assert keep["batch_width"] in (32, 64, 128, 256) and keep["mode"] in (0, 1, 2)
+    try:
+        ctx.tune(batch_width=128, blocks_per_cu=3, mode="hybrid", batch_alpha=5)
+        t = ctx.tuning()
+        assert (t["batch_width"], t["blocks_per_cu"], t["mode"], t["batch_alpha"]) == (128, 3, 2, 5)
+        for bad in (dict(batch_width=96), dict(blocks_per_cu=0), dict(blocks_per_cu=9), dict(mode=3),
+                    dict(swarm_qcap=8), dict(batch_alpha=0), dict(seed_lanes=300)):
+            with pytest.raises(tkc.TkcError) as e:
+                ctx.tune(**bad)
+            assert e.value.code == tkc.TKC_EINVAL
+        assert ctx.tuning() == t        # a refused setting changes nothing
+    finally:
+        ctx.tune(**keep)
+
+
+@pytest.mark.parametrize("blocks", [1, 3, 4])
+def test_blocks_per_cu_topk(ctx, blocks):
+    keep = ctx.tuning()
+    ctx.tune(blocks_per_cu=blocks)
+    try:
+        for name in ("ba20k", "gnp_d", "grid60"):
+            dg = upload(ctx, name)
+            for variant, mode in (("nbcut", "plain"), ("nbcut", "batched"), ("nbbound", "batched"),
+                                  ("degcut", "hybrid")):
+                ids, S, r, f, st = tkc.topk_closeness(dg, 10, variant, mode)
+                wids, wS, wr, wf = expect(name, 10)
+                assert np.array_equal(ids, wids) and np.array_equal(S, wS) and np.array_equal(r, wr)
+    finally:
+        ctx.tune(**keep)
+
+
+@pytest.mark.parametrize("name", ["ba20k", "rmat13", "grid150"])
+def test_autotune_then_auto_mode(ctx, name):
+    keep = ctx.tuning()
+    dg = upload(ctx, name)
+    best, ms = dg.autotune(10, "auto", budget_ms=3000.0)
+    assert ms > 0 and best["batch_width"] in (32, 64, 128, 256) and best["mode"] in (1, 2)
+    assert 1 <= best["blocks_per_cu"] <= 8
+    assert ctx.tuning() == keep       # the context's own knobs are untouched
+    for k in (1, 10, 37):
+        ids, S, r, f, st = tkc.topk_closeness(dg, k, "auto", "auto")
+        wids, wS, wr, wf = expect(name, k)
+        assert np.array_equal(ids, wids) and np.array_equal(S, wS) and np.array_equal(r, wr)
+        assert np.array_equal(f, wf)
+        assert st["batch_width"] == best["batch_width"] and st["mode_used"] == best["mode"]
 
 
 # ---------------------------------------------------------------- errors
