@@ -45,9 +45,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary,
-    null when the kernels changed since the counters were taken."""
+def load_traffic(kernel: str, workload: str, mode: str, width: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary;
+    null when the kernels changed since the counters were taken or the
+    counters belong to another mode or batch width."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -56,9 +57,96 @@ def load_traffic(kernel: str, workload: str):
         rec = d.get(workload, {}).get(kernel)
         if not rec or rec.get("source_hash") != kernel_source_hash():
             return None
+        if rec.get("mode") != mode or rec.get("batch_width") != width:
+            return None
         return rec.get("bytes_per_launch")
     except Exception:
         return None
+
+
+def _read_csvs(d: str, suffix: str):
+    import csv
+    rows = []
+    for root, _, files in os.walk(d):
+        for f in files:
+            if f.endswith(suffix):
+                with open(os.path.join(root, f)) as fh:
+                    rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _kernel_durations(d: str):
+    """{kernel name: [durations in ns]} from a rocprofv3 --kernel-trace folder
+    (CSV output, or the rocpd SQLite database that is its default format)."""
+    out = {}
+    for r in _read_csvs(d, "kernel_trace.csv"):
+        out.setdefault(r["Kernel_Name"], []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    if not out:
+        import sqlite3
+        for root, _, files in os.walk(d):
+            for f in files:
+                if f.endswith("results.db"):
+                    db = sqlite3.connect(os.path.join(root, f))
+                    for name, dur in db.execute("select name, duration from kernels"):
+                        out.setdefault(name, []).append(int(dur))
+                    db.close()
+    return out
+
+
+def stats_table(d: str) -> str:
+    """Markdown table of per-kernel durations from a rocprofv3 --kernel-trace folder."""
+    rows = sorted(_kernel_durations(d).items(), key=lambda kv: -sum(kv[1]))
+    out = ["| kernel | calls | total us | avg us | min us | max us |", "|---|---|---|---|---|---|"]
+    for name, ds in rows:
+        out.append("| %s | %d | %.1f | %.1f | %.1f | %.1f |" % (
+            name.split("(")[0], len(ds), sum(ds) / 1e3, sum(ds) / len(ds) / 1e3, min(ds) / 1e3, max(ds) / 1e3))
+    return "\n".join(out)
+
+
+def traffic_from(fetch_dir: str, write_dir: str, workload: str, kernel: str, last: int, copy_bytes: int,
+                 mode: str, width: int):
+    """HBM bytes per launch of `kernel` from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled so that the
+    largest copy dispatch (a device copy of copy_bytes) reads and writes
+    exactly copy_bytes; the mean over the last `last` dispatches of the
+    kernel.  Stores the record in profiles/traffic.json and returns it."""
+    def per_dispatch(d, counter):
+        vals = {}
+        rows = [(r["Dispatch_Id"], r["Kernel_Name"], r["Counter_Name"], r["Counter_Value"])
+                for r in _read_csvs(d, "counter_collection.csv")]
+        if not rows:   # rocpd SQLite output (the default format of rocprofv3)
+            import sqlite3
+            for root, _, files in os.walk(d):
+                for f in files:
+                    if f.endswith("results.db"):
+                        db = sqlite3.connect(os.path.join(root, f))
+                        rows += db.execute("select dispatch_id, kernel_name, counter_name, value "
+                                           "from counters_collection").fetchall()
+                        db.close()
+        for disp, name, cname, value in rows:
+            if cname != counter:
+                continue
+            key = (int(disp), name)
+            vals[key] = vals.get(key, 0.0) + float(value)
+        return sorted(vals.items(), key=lambda kv: kv[0][0])
+    rec = {"source_hash": kernel_source_hash(), "copy_bytes": copy_bytes, "mode": mode, "batch_width": width}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        disp = per_dispatch(d, counter)
+        copies = [v for (i, name), v in disp if "copy" in name.lower()]
+        mine = [v for (i, name), v in disp if name.split("(")[0].split("<")[0].endswith(kernel)]
+        if not copies or not mine:
+            raise SystemExit("no %s dispatches of the copy or of %s under %s" % (counter, kernel, d))
+        scale = copy_bytes / (max(copies) * 1024.0)
+        mine = mine[-last:]
+        rec[counter.lower() + "_kib"] = [round(v, 1) for v in mine]
+        rec[counter.lower() + "_scale"] = round(scale, 5)
+        rec[counter.lower() + "_bytes"] = float(np.mean(mine)) * 1024.0 * scale
+    rec["bytes_per_launch"] = int(rec["fetch_size_bytes"] + rec["write_size_bytes"])
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    d = json.load(open(path)) if os.path.exists(path) else {}
+    d.setdefault(workload, {})[kernel] = rec
+    json.dump(d, open(path, "w"), indent=1, sort_keys=True)
+    return rec
 
 
 def cpu_baseline(g, seconds: float):
@@ -75,19 +163,17 @@ def cpu_baseline(g, seconds: float):
     t0 = time.perf_counter()
     S, r = oracle.sums(g.n, g.edges, g.directed, sources=src)
     wall = time.perf_counter() - t0
-    # arcs scanned by each textbook BFS = sum of out-degrees over R(s)
-    deg = np.diff(g.row_ptr).astype(np.int64)
-    arcs = int(g.arcs) * count if (r == g.n).all() else None
-    if arcs is None:
-        arcs = 0
-        for s_ in src[:256]:
-            arcs += int(g.arcs)
-        arcs = arcs * count // 256
+    # arcs scanned by a textbook BFS from s = sum of out-degrees over R(s):
+    # every arc when the graph is connected; otherwise estimated as
+    # r(s) times the average out-degree
+    exact = bool((r == g.n).all())
+    arcs = int(g.arcs) * count if exact else int(float(np.sum(r)) * g.arcs / g.n)
     teps = arcs / wall
     full_s = wall / count * g.n
     return {"value": teps / 1e9, "unit": "GTEPS", "cores": oracle.threads(), "kind": "oracle",
-            "sample": "textbook BFS from %d seeded random sources of the same graph (%.1f s); "
-                      "all-sources extrapolation %.0f s" % (count, wall, full_s),
+            "sample": "textbook BFS from %d seeded random sources of the same graph (%.1f s)%s; "
+                      "all-sources extrapolation %.0f s" % (count, wall, "" if exact else
+                                                            ", arcs estimated from reach", full_s),
             "wall_s": wall, "sources": count, "all_sources_extrapolated_s": full_s}
 
 
@@ -98,8 +184,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--variant", default="auto")
-    ap.add_argument("--mode", default="auto",
-                    help="plain | batched | hybrid | auto (the autotuned setting of this graph and query)")
+    ap.add_argument("--mode", default="hybrid",
+                    help="plain | batched | hybrid | auto (autotune this graph and query first)")
     ap.add_argument("--autotune-ms", type=float, default=8000.0,
                     help="time budget of the autotuner that runs before the warm-up when --mode auto")
     ap.add_argument("--workload", default="ba1m")
@@ -110,7 +196,23 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the comparison runs")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration)")
+    ap.add_argument("--stats-from", default="",
+                    help="print the kernel table of a rocprofv3 --stats folder and exit")
+    ap.add_argument("--traffic-from", default="",
+                    help="FETCH_DIR,WRITE_DIR of two rocprofv3 --pmc runs: store bytes per launch and exit")
+    ap.add_argument("--traffic-kernel", default="k_batch")
+    ap.add_argument("--traffic-last", type=int, default=3)
+    ap.add_argument("--traffic-width", type=int, default=64, help="batch width of the profiled runs")
     args = ap.parse_args()
+    if args.stats_from:
+        print(stats_table(args.stats_from))
+        return
+    if args.traffic_from:
+        fd, wd = args.traffic_from.split(",")
+        rec = traffic_from(fd, wd, args.workload, args.traffic_kernel, args.traffic_last,
+                           args.calib_copy_mb << 20, args.mode, args.traffic_width)
+        print(json.dumps(rec, indent=1))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the searches would shard by candidate ranges with a top-k merge)",
@@ -167,7 +269,7 @@ def main():
     per_launch_ms = kern_ms / max(1, launches)
     achieved = (bytes_main / max(1, launches)) / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
     kname = KERNEL_NAMES.get(st["main_kernel"], "?")
-    traffic = load_traffic(kname, args.workload)
+    traffic = load_traffic(kname, args.workload, MODE_NAMES.get(st["mode_used"], "?"), st["batch_width"])
 
     undirected = not g.directed
     mn = (2 if undirected else 1) * (g.arcs // (2 if undirected else 1)) * g.n

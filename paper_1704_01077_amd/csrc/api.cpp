@@ -786,6 +786,9 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
             HIPCHK(hipMemcpyAsync(pin, small + 4, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             const int32_t ndef = pin[0], fetched = pin[1], sw_stop = pin[2];
+            if (c->ws.trace)
+                fprintf(stderr, "trace hybrid: seed cursor %d, swarm deferred %d, fetched %d, stop bits %d\n",
+                        cursor, ndef, fetched, sw_stop);
             if (ndef > 0) {
                 trace_reset(c);
                 EngineTimer tm(c, &ms_eng[1], &nl_eng[1]);

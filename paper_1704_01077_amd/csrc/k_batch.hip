@@ -323,6 +323,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
         bool bu = false;
         int64_t tslot = -1;
         int64_t mvis = 0, bytes = 0;
+        int64_t my_scan = 0;   // in-arcs this thread scanned in pull steps (traffic count)
         for (;;) {
             // ------------------------------------ per-lane control (replicated)
             if (tid < MAXW) {
@@ -389,7 +390,12 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             const uint64_t* fcur = q ? a.w.frt1 : a.w.frt0;
             uint64_t* fnxt = q ? a.w.frt0 : a.w.frt1;
             const int32_t stamp = (int32_t)(D + 1);
-            bytes += bu ? (int64_t)n * (8 * NW) : (fl_len + fh_len) * (8 + 8 * NW);
+            // algorithmic bytes: push reads each frontier vertex's row and
+            // frontier word, then per out-arc the index, the target's visited
+            // word and its next word; pull reads every vertex's visited word
+            // and row, and per scanned in-arc the index and a frontier word
+            // (counted in my_scan)
+            bytes += bu ? (int64_t)n * (8 + 8 * NW) : (fl_len + fh_len) * (8 + 8 * NW) + udeg * (4 + 16 * NW);
             Stage stg{&s_stage[tid >> 6][0], 0};
             if (!bu) {
                 // push, light frontier vertices: one per lane
@@ -468,6 +474,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                             // in-arcs in groups of four: four independent index
                             // loads, then four independent frontier loads
                             for (int32_t e = eb; e < ee; e += 4) {
+                                my_scan += (ee - e < 4 ? ee - e : 4);
                                 int32_t u[4];
 #pragma unroll
                                 for (int t = 0; t < 4; t++) u[t] = e + t < ee ? a.g.rci[e + t] : -1;
@@ -506,6 +513,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                     int32_t eb = a.g.rch_beg[c], ee = a.g.rch_end[c];
                     for (int32_t e0 = eb; e0 < ee; e0 += 64) {
                         int32_t e = e0 + lane;
+                        my_scan += e < ee ? 1 : 0;
                         if (e < ee) {
                             int32_t u = a.g.rci[e];
 #pragma unroll
@@ -672,6 +680,15 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             D++;
             __syncthreads();
         }
+        // pull traffic of the batch: one count per workgroup
+        {
+            const int64_t t = wave_sum_i64(my_scan);
+            if (tid == 0) s_blk[0] = 0;
+            __syncthreads();
+            if (lane == 0 && t) atomicAdd((unsigned long long*)&s_blk[0], (unsigned long long)t);
+            __syncthreads();
+            if (tid == 0 && s_blk[0]) fadd_rlx(&stats[ST_BYTES], s_blk[0] * (int64_t)(4 + 8 * NW));
+        }
         // ----------------------------------------------------- batch results
         if (boss) {
             int64_t ex = 0, cu = 0, md = stats[ST_MAXLEVEL];
@@ -687,7 +704,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             stats[ST_EXACT] += ex;
             stats[ST_CUT] += cu;
             stats[ST_MVIS] += mvis;
-            stats[ST_BYTES] += bytes;
+            fadd_rlx(&stats[ST_BYTES], bytes);
             stats[ST_MAXLEVEL] = md;
         }
         if (a.no_cut && blockIdx.x == 0 && tid < nsel) {
