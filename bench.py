@@ -177,6 +177,106 @@ def cpu_baseline(g, seconds: float):
             "wall_s": wall, "sources": count, "all_sources_extrapolated_s": full_s}
 
 
+def serve_bench(args):
+    """Serving mix: a resident pool of seeded graphs (BA, R-MAT, king-move
+    lattices; n log-uniform in [1e3, 1e6], average degree 8-16), top-k
+    requests with k uniform over {1, 10, 100} on a uniform graph.  First the
+    saturation throughput (every request submitted at once), then Poisson
+    arrivals at a fraction of it; latency = completion - submission."""
+    import threading
+    import torch
+    import graphgen
+    from paper_1704_01077_amd import tkc
+    torch.cuda.init()
+    t0 = time.perf_counter()
+    pool = graphgen.serving_pool(args.serve_graphs)
+    print("serve: %d graphs generated in %.1f s" % (len(pool), time.perf_counter() - t0), file=sys.stderr, flush=True)
+    ctx = tkc.Context(0)
+    dgs = [tkc.Graph.from_graphgen(ctx, g) for g in pool]
+    srv = tkc.Server(ctx, int(args.serve_budget_gb * (1 << 30)), args.serve_slots)
+    gids = [srv.add(d) for d in dgs]
+    rng = np.random.default_rng(args.serve_seed)
+    answers = {}
+
+    def run(reqs, gaps=None):
+        """Submit (graph, k) requests (with arrival gaps in seconds) and
+        collect them; returns (wall seconds, latencies in ms)."""
+        tickets = [None] * len(reqs)
+        lat = [0.0] * len(reqs)
+
+        def submitter():
+            t_next = time.perf_counter()
+            for i, (gi, k) in enumerate(reqs):
+                if gaps is not None:
+                    t_next += gaps[i]
+                    d = t_next - time.perf_counter()
+                    if d > 0:
+                        time.sleep(d)
+                tickets[i] = srv.submit(gids[gi], k, "auto")
+        th = threading.Thread(target=submitter)
+        start = time.perf_counter()
+        th.start()
+        for i, (gi, k) in enumerate(reqs):
+            while tickets[i] is None:
+                time.sleep(0.0002)
+            ids, S, r, f, ms = srv.result(tickets[i], k)
+            lat[i] = ms
+            key = (gi, k)
+            if key in answers:
+                assert np.array_equal(answers[key], ids), "served answers differ for graph %d k=%d" % key
+            else:
+                answers[key] = ids.copy()
+        th.join()
+        return time.perf_counter() - start, np.array(lat)
+
+    # warm-up: one request per graph and k, one at a time (fills the per-graph
+    # preprocessing caches; gives the solo time of every request kind)
+    solo = {}
+    for gi in range(len(pool)):
+        for k in (1, 10, 100):
+            w, l = run([(gi, k)])
+            solo[(gi, k)] = l[0]
+        if gi % 8 == 7:
+            print("serve: warm-up %d/%d graphs" % (gi + 1, len(pool)), file=sys.stderr, flush=True)
+    print("serve: warm-up done, solo latency p50 %.2f ms max %.1f ms (graph %s)" % (
+        np.percentile(list(solo.values()), 50), max(solo.values()),
+        pool[max(solo, key=solo.get)[0]].name), file=sys.stderr, flush=True)
+
+    def draw(count):
+        return [(int(rng.integers(len(pool))), int(rng.choice([1, 10, 100]))) for _ in range(count)]
+
+    sat_reqs = draw(args.serve_sat)
+    wall, lat_sat = run(sat_reqs)
+    lam_sat = len(sat_reqs) / wall
+    print("serve: saturation %.1f req/s" % lam_sat, file=sys.stderr, flush=True)
+    lam = args.serve_load * lam_sat
+    reqs = draw(args.serve_requests)
+    gaps = rng.exponential(1.0 / lam, size=len(reqs))
+    wall, lat = run(reqs, gaps)
+    solo_sum = sum(solo[q] for q in reqs)
+    out = {
+        "metric": "serving mix: throughput and latency (continuous batching)",
+        "value": round(len(reqs) / wall, 3), "unit": "requests/s", "higher_is_better": True,
+        "n_gpus": 1, "data": "synthetic",
+        "config": {"workload": "%d seeded graphs (BA, R-MAT, king lattices), n log-uniform 1e3-1e6, "
+                               "k uniform in {1,10,100}, Poisson arrivals" % len(pool),
+                   "requests": len(reqs), "slots": args.serve_slots, "hbm_budget_gb": args.serve_budget_gb,
+                   "arrival_rate": round(lam, 3), "load": args.serve_load,
+                   "resident_arcs": int(sum(g.arcs for g in pool))},
+        "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
+        "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
+        "latency_ms_max": round(float(lat.max()), 3),
+        "saturation_req_s": round(lam_sat, 3),
+        "saturation_latency_ms_p50": round(float(np.percentile(lat_sat, 50)), 3),
+        "solo_sum_s": round(solo_sum / 1e3, 3), "wall_s": round(wall, 3),
+    }
+    print(json.dumps(out), flush=True)
+    srv.close()
+    for d in dgs:
+        d.free()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +296,14 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the comparison runs")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration)")
+    ap.add_argument("--serve", action="store_true", help="run the serving-mix benchmark instead")
+    ap.add_argument("--serve-graphs", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-sat", type=int, default=400, help="requests of the saturation run")
+    ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate / saturation throughput")
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-budget-gb", type=float, default=32.0)
+    ap.add_argument("--serve-seed", type=int, default=7)
     ap.add_argument("--stats-from", default="",
                     help="print the kernel table of a rocprofv3 --stats folder and exit")
     ap.add_argument("--traffic-from", default="",
@@ -214,10 +322,13 @@ def main():
         print(json.dumps(rec, indent=1))
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the searches would shard by candidate ranges with a top-k merge)",
               file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        serve_bench(args)
+        return
 
     import torch
     import graphgen

@@ -333,6 +333,42 @@ class Graph:
         return S[: src.size], R[: src.size]
 
 
+class Server:
+    """Request server over resident graphs (continuous batching)."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_inflight: int = 4):
+        self.h = tkc_server_create(ctx.h, int(hbm_budget_bytes), int(max_inflight))
+        self.graphs = []
+
+    def add(self, g: "Graph") -> int:
+        gid = tkc_server_add_graph(self.h, g.h)
+        self.graphs.append(g)
+        return gid
+
+    def submit(self, graph_id: int, k: int, variant="auto") -> int:
+        return tkc_server_submit(self.h, int(graph_id), int(k), VARIANTS.get(variant, variant))
+
+    def poll(self, ticket: int) -> bool:
+        return tkc_server_poll(self.h, ticket)
+
+    def result(self, ticket: int, k: int):
+        """(ids, S, r, farness, latency_ms); blocks until the request is done."""
+        ids = np.zeros(max(1, k), np.int32)
+        S = np.zeros(max(1, k), np.int64)
+        r = np.zeros(max(1, k), np.int64)
+        f = np.zeros(max(1, k), np.float64)
+        c, lat = tkc_server_result(self.h, ticket, ids, S, r, f)
+        return ids[:c], S[:c], r[:c], f[:c], lat
+
+    def cancel(self, ticket: int):
+        tkc_server_cancel(self.h, ticket)
+
+    def close(self):
+        if self.h:
+            tkc_server_destroy(self.h)
+            self.h = None
+
+
 def _as_i32(a):
     if isinstance(a, np.ndarray):
         return np.ascontiguousarray(a, dtype=np.int32)
