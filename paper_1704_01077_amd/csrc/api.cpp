@@ -91,7 +91,7 @@ static size_t ws_items(Workspace& ws, const WsShape& sh, std::vector<WsItem>& it
         // batched engine
         {(void**)&ws.b_vis, 8 * n * nw, true}, {(void**)&ws.b_frt0, 8 * n * nw, true},
         {(void**)&ws.b_frt1, 8 * n * nw, true}, {(void**)&ws.b_nxt, 8 * n * nw, true},
-        {(void**)&ws.b_list, 16 * n + 16 * ((size_t)sh.nchunks + 64), false}, {(void**)&ws.b_mark, 4 * n, true},
+        {(void**)&ws.b_list, 32 * n + 16 * ((size_t)sh.nchunks + 64), false}, {(void**)&ws.b_mark, 4 * n, true},
         {(void**)&ws.b_ctr, 8 * 2048, true}, {(void**)&ws.b_cand, 4 * 256, false},
         {(void**)&ws.b_hist, sh.lb ? 8 * lcap * W : 8, false},
         {(void**)&ws.b_levtab, sh.lb ? 8 * lcap * W : 8, false},

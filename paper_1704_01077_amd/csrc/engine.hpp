@@ -127,7 +127,7 @@ struct BatchWork {
     uint64_t* frt0;      // n * nw
     uint64_t* frt1;      // n * nw
     uint64_t* nxt;       // n * nw
-    int32_t* list;       // frontier lists: 4 n vertex entries + 4 ccap chunk entries
+    int32_t* list;       // level lists: 8 n vertex entries (4 slots x light/heavy) + 4 ccap chunk entries
     int64_t ccap;        // chunk entries per list
     int32_t* touched;    // every vertex touched in the batch (for clearing), cap n
     int64_t* ctr;        // per-lane level counters, 3 * 2 * 256 + misc

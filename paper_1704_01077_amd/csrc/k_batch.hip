@@ -1,13 +1,25 @@
 // Batched engine: W candidates of Alg. 1 searched together, one bit lane
-// per source in W-bit words per vertex (visited, frontier, next).  A push
-// step reads each frontier vertex's adjacency once for all its lanes and
-// ORs the lanes into its neighbours' next words; a pull step lets every
-// vertex with unreached lanes scan its in-arcs for frontier lanes.  Each
-// lane keeps its own BFSCut state (Sect. 6): after every level the exact
-// per-lane counts give the bound, and a lane whose bound passes the k-th
-// farness x retires (its bits are masked out of later steps).  Bound
-// variants run every lane to the end and then apply the level-based update
-// (Sect. 7) of all lanes at once.
+// per source in W-bit words per vertex.  A push step reads each frontier
+// vertex's adjacency once for all its lanes and ORs the lanes into its
+// neighbours' next-frontier words; a pull step lets every vertex with
+// unreached lanes scan its in-arcs for frontier lanes.  Each lane keeps its
+// own BFSCut state (Sect. 6): after every level the exact per-lane counts
+// give the bound, and a lane whose bound passes the k-th farness x retires
+// (its bits are masked out of later steps).  Bound variants run every lane
+// to the end and then apply the level-based update (Sect. 7) of all lanes
+// at once.
+//
+// One grid barrier per level.  F_D, the lanes that first reached each
+// vertex at level D, lives in one of three rotating word arrays; the
+// visited words `vis` hold the levels before D, so "seen" means vis | F_D.
+// During level D every frontier vertex's owner folds F_D into vis, the
+// expansion writes F_{D+1} and counts each newly reached (vertex, lane) at
+// the moment it is set (the atomic OR that sets a bit returns the bits set
+// before, so exactly one caller sees each bit as new), and the words of
+// F_{D-1} are cleared through the level list L_{D-1}.  Lists rotate over
+// four slots and counters over three parities so that no slot is reset or
+// rewritten before every workgroup has passed the barrier after its last
+// reader.
 //
 // One cooperative launch processes batch after batch; block 0's first wave
 // selects the next candidates from the order (stop and skip rules of
@@ -23,15 +35,19 @@
 #define C_CNT(p, l) ((p) * 2 * MAXW + (l))
 #define C_DEG(p, l) ((p) * 2 * MAXW + MAXW + (l))
 #define C_BASE (3 * 2 * MAXW)
-#define C_UCNT(p) (C_BASE + (p) * 8 + 0)
-#define C_UDEG(p) (C_BASE + (p) * 8 + 1)
-#define C_T(p, c) (C_BASE + (p) * 8 + 2 + (c))   // next list tails: light, heavy, giant
-#define C_DDONE(p) (C_BASE + (p) * 8 + 5)       // out-degrees of vertices now seen by every active lane
-#define C_L0 (C_BASE + 28)                    // level-0 list lengths (3)
+// per parity p = level % 3, for the vertices first reached in that level's
+// expansion: their out-degree sum, and the out-degrees of vertices that
+// became seen by every active lane when folded
+#define C_UDEG(p) (C_BASE + (p) * 4 + 0)
+#define C_DDONE(p) (C_BASE + (p) * 4 + 1)
+// vertex list tails per slot s = level % 4: [0] light, [1] heavy
+#define C_LT(s, c) (C_BASE + 12 + 2 * (s) + (c))
+// heavy-vertex chunk list tail per level % 3
+#define C_CT(q) (C_BASE + 20 + (q))
 #define C_NSEL (C_BASE + 24)
 #define C_POS (C_BASE + 25)
 #define C_STOP (C_BASE + 26)
-#define C_TOTAL (C_BASE + 32)   // C_L0 + 2 < C_TOTAL
+#define C_TOTAL (C_BASE + 32)
 
 struct BatchArgs {
     DevGraph g;
@@ -83,11 +99,20 @@ struct Mask {
 // takes every append, and a large level makes tens of thousands of them, so
 // light vertices (the vast majority) are first staged in a per-wave LDS
 // buffer and reserved in the list once per STAGE entries; heavy vertices
-// (rare) are appended directly.
+// (rare) are appended directly, together with their arc chunks.
 #define STAGE 1024
 struct Stage {
     int32_t* buf;   // this wave's LDS slots
     int32_t n;      // filled slots (wave-uniform)
+};
+struct NextLists {
+    int32_t* light;
+    int32_t* heavy;
+    int64_t* tails;     // [0] light, [1] heavy
+    int32_t* cu;        // chunk owners
+    int32_t* cb;        // chunk first arcs
+    int64_t* ctail;
+    const int32_t* rp;
 };
 TKC_DEV void stage_flush(Stage& st, int32_t* list, int64_t* tail) {
     if (st.n == 0) return;
@@ -100,52 +125,148 @@ TKC_DEV void stage_flush(Stage& st, int32_t* list, int64_t* tail) {
     st.n = 0;
 }
 // called by all 64 lanes of a wave
-TKC_DEV void list_append(bool isnew, int32_t w, int32_t dw, int32_t* const* lists, int64_t* tails, Stage& st) {
+TKC_DEV void list_append(bool isnew, int32_t w, int32_t dw, const NextLists& L, Stage& st) {
     const bool heavy = dw > HEAVY_DEG;
     const uint64_t ml = __ballot(isnew && !heavy);
     const uint64_t mh = __ballot(isnew && heavy);
     const uint64_t bm = below_mask();
     if (mh) {
         int64_t b = 0;
-        if (lane_id() == 0) b = fadd_rlx(&tails[1], (int64_t)__popcll(mh));
+        if (lane_id() == 0) b = fadd_rlx(&L.tails[1], (int64_t)__popcll(mh));
         b = shfl64b(b, 0);
-        if (isnew && heavy) lists[1][b + __popcll(mh & bm)] = w;
+        const int32_t nck = (isnew && heavy) ? (dw + CHUNK_ARCS - 1) / CHUNK_ARCS : 0;
+        int32_t pre = nck;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            int32_t y = __shfl_up(pre, o, 64);
+            if (lane_id() >= o) pre += y;
+        }
+        const int32_t tot = __shfl(pre, 63, 64);
+        pre -= nck;
+        int64_t c0 = 0;
+        if (lane_id() == 0) c0 = fadd_rlx(L.ctail, (int64_t)tot);
+        c0 = shfl64b(c0, 0);
+        if (isnew && heavy) {
+            L.heavy[b + __popcll(mh & bm)] = w;
+            const int32_t r0 = L.rp[w];
+            for (int32_t j = 0; j < nck; j++) {
+                L.cu[c0 + pre + j] = w;
+                L.cb[c0 + pre + j] = r0 + j * CHUNK_ARCS;
+            }
+        }
     }
     if (ml) {
         const int32_t c = __popcll(ml);
-        if (st.n + c > STAGE) stage_flush(st, lists[0], &tails[0]);
+        if (st.n + c > STAGE) stage_flush(st, L.light, &L.tails[0]);
         if (isnew && !heavy) st.buf[st.n + __popcll(ml & bm)] = w;
         st.n += c;
     }
 }
 
-// OR the lanes nb into w's next word(s); true for exactly one caller per
-// vertex and level (the one that makes it appear in the next list)
-// (the visited words are read with plain loads: they only change in the
-// epilogue, which barriers separate from the expansion; a plain read of the
-// next word that already holds every lane in nb proves another caller has
-// set it first, since the word only gains bits during the expansion)
+// Per-lane tallies of newly reached vertices: count and out-degree sum per
+// lane, in the workgroup's LDS.
+// Sparse masks (push): each thread adds its own bits.
 template <int NW>
-TKC_DEV bool push_lanes(uint64_t* nxt, int32_t* mark, int32_t w, const Mask<NW>& nb, int32_t stamp) {
+TKC_DEV void tally_bits(const Mask<NW>& nb, int32_t dw, int32_t* cnt, int64_t* dsum) {
+#pragma unroll
+    for (int j = 0; j < NW; j++) {
+        uint64_t m = nb.w[j];
+        while (m) {
+            int l = j * 64 + __ffsll((long long)m) - 1;
+            m &= m - 1;
+            atomicAdd(&cnt[l], 1);
+            atomicAdd((unsigned long long*)&dsum[l], (unsigned long long)dw);
+        }
+    }
+}
+// Dense masks (pull, one vertex per lane): the wave transposes its bit
+// matrix lane by lane; called by all 64 lanes.
+template <int NW>
+TKC_DEV void tally_wave(const Mask<NW>& nb, int32_t dw, int32_t* cnt, int64_t* dsum) {
+#pragma unroll
+    for (int j = 0; j < NW; j++) {
+        uint64_t here = wave_or_u64(nb.w[j]);
+        while (here) {
+            int l = __ffsll((long long)here) - 1;
+            here &= here - 1;
+            const bool has = (nb.w[j] >> l) & 1ull;
+            const int c = __popcll(__ballot(has));
+            const int64_t d = wave_sum_i64(has ? (int64_t)dw : 0);
+            if (lane_id() == 0) {
+                atomicAdd(&cnt[j * 64 + l], c);
+                atomicAdd((unsigned long long*)&dsum[j * 64 + l], (unsigned long long)d);
+            }
+        }
+    }
+}
+// Called by all 64 lanes: the wave picks the cheaper way.  Many vertices
+// per distinct lane (dense bit matrix) -> transposition; few -> each thread
+// adds its own bits; no new bits -> nothing.
+template <int NW>
+TKC_DEV void tally(const Mask<NW>& nb, int32_t dw, int32_t* cnt, int64_t* dsum) {
+    int32_t lanes = 0, bits = 0;
+#pragma unroll
+    for (int j = 0; j < NW; j++) {
+        lanes += __popcll(wave_or_u64(nb.w[j]));
+        bits += __popcll(nb.w[j]);
+    }
+    if (lanes == 0) return;   // wave-uniform
+    bits = wave_sum_i32(bits);
+    if (lanes * 8 <= bits) tally_wave<NW>(nb, dw, cnt, dsum);
+    else tally_bits<NW>(nb, dw, cnt, dsum);
+}
+
+// level of every newly reached lane (level-based bound of Sect. 7)
+template <int NW>
+TKC_DEV void record_levels(const Mask<NW>& nb, int32_t w, uint16_t* lvl, int W, int64_t level) {
+#pragma unroll
+    for (int j = 0; j < NW; j++) {
+        uint64_t m = nb.w[j];
+        while (m) {
+            int l = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            lvl[(int64_t)w * W + j * 64 + l] = (uint16_t)level;
+        }
+    }
+}
+
+// OR the lanes nb into w's next-frontier word(s).  *fresh receives the
+// lanes this call set first (each (vertex, lane) is fresh for exactly one
+// caller); the result is true for exactly one caller per vertex and level,
+// the one that appends it to the next list.  A plain read of the word that
+// already holds every lane in nb proves other callers set them first: the
+// word only gains bits during the expansion.
+template <int NW>
+TKC_DEV bool discover(uint64_t* Fn, int32_t* mark, int32_t w, const Mask<NW>& nb, int32_t stamp,
+                      Mask<NW>* fresh) {
     if (NW == 1) {
-        uint64_t seen = nxt[w];
+        fresh->w[0] = 0;
+        const uint64_t seen = Fn[w];
         if ((seen & nb.w[0]) == nb.w[0]) return false;
-        uint64_t old = for_rlx(&nxt[w], nb.w[0]);
+        const uint64_t old = for_rlx(&Fn[w], nb.w[0]);
+        fresh->w[0] = nb.w[0] & ~old;
         return old == 0;
     } else {
 #pragma unroll
-        for (int j = 0; j < NW; j++)
-            if (nb.w[j]) for_rlx(&nxt[(int64_t)w * NW + j], nb.w[j]);
-        int32_t old = __hip_atomic_fetch_max(&mark[w], stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int j = 0; j < NW; j++) {
+            fresh->w[j] = 0;
+            if (nb.w[j]) fresh->w[j] = nb.w[j] & ~for_rlx(&Fn[(int64_t)w * NW + j], nb.w[j]);
+        }
+        const int32_t old = __hip_atomic_fetch_max(&mark[w], stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return old < stamp;
     }
 }
 
-// vertex list of class c (0 light, 1 heavy) at parity q, and the chunk
-// lists (owner vertex, first arc) at parity q
-#define VL(c, q) (a.w.list + (int64_t)(2 * (c) + (q)) * n)
-#define CU(q) (a.w.list + 4 * (int64_t)n + (int64_t)(2 * (q)) * a.w.ccap)
-#define CB(q) (a.w.list + 4 * (int64_t)n + (int64_t)(2 * (q) + 1) * a.w.ccap)
+TKC_DEV uint64_t* fsel(const BatchWork& w, int64_t level) {
+    const int i = (int)(level % 3);
+    return i == 0 ? w.frt0 : (i == 1 ? w.frt1 : w.nxt);
+}
+
+// vertex list of class c (0 light, 1 heavy) in slot s (level % 4), and the
+// heavy-vertex chunk lists (owner, first arc) in slot q (level % 2)
+#define VL(c, s) (a.w.list + (int64_t)(2 * (s) + (c)) * n)
+#define CU(q) (a.w.list + 8 * (int64_t)n + (int64_t)(2 * (q)) * a.w.ccap)
+#define CB(q) (a.w.list + 8 * (int64_t)n + (int64_t)(2 * (q) + 1) * a.w.ccap)
 
 template <int NW>
 __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
@@ -178,7 +299,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
     __shared__ int64_t s_red_deg[MAXW];
     __shared__ int64_t s_scal[8];
     __shared__ int32_t s_stage[BB / 64][STAGE];
-    __shared__ int64_t s_blk[3];
+    __shared__ int64_t s_blk[4];
 
     int32_t pos = a.start_pos;
     int32_t batches = 0;
@@ -277,9 +398,8 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
         if (blockIdx.x == 0 && tid < nsel) {
             int l = tid;
             int32_t v = a.w.cand[l];
-            // a source list may name one vertex twice: atomic ORs
-            for_rlx(&vis[(int64_t)v * NW + (l >> 6)], (uint64_t)1 << (l & 63));
-            for_rlx(&a.w.frt0[(int64_t)v * NW + (l >> 6)], (uint64_t)1 << (l & 63));
+            // level 0 is F_0; a source list may name one vertex twice: atomic OR
+            for_rlx(&fsel(a.w, 0)[(int64_t)v * NW + (l >> 6)], (uint64_t)1 << (l & 63));
             if (a.lb_mode) { a.w.lvl[(int64_t)v * W + l] = 0; a.w.hist[l] = 1; }
         }
         if (boss) {
@@ -302,19 +422,20 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                     VL(0, 0)[nl0++] = v;
                 }
             }
-            for (int p = 0; p < 3; p++) {
-                ctr[C_UCNT(p)] = 0; ctr[C_UDEG(p)] = 0; ctr[C_DDONE(p)] = 0;
-                for (int c = 0; c < 3; c++) ctr[C_T(p, c)] = 0;
-            }
-            ctr[C_L0 + 0] = nl0; ctr[C_L0 + 1] = nh0; ctr[C_L0 + 2] = nc0;
+            for (int p = 0; p < 3; p++) { ctr[C_UDEG(p)] = 0; ctr[C_DDONE(p)] = 0; ctr[C_CT(p)] = 0; }
+            for (int q = 0; q < 4; q++) { ctr[C_LT(q, 0)] = 0; ctr[C_LT(q, 1)] = 0; }
+            ctr[C_LT(0, 0)] = nl0; ctr[C_LT(0, 1)] = nh0; ctr[C_CT(0)] = nc0;
             for (int p = 0; p < 3; p++)
                 for (int l = 0; l < MAXW; l++) { ctr[C_CNT(p, l)] = 0; ctr[C_DEG(p, l)] = 0; }
         }
         grid_barrier(a.bar, gridDim.x);
 
         int64_t D = 0;
-        // current frontier: light / heavy vertex lists and the heavy chunk list
-        int64_t fl_len = ld_rlx(&ctr[C_L0 + 0]), fh_len = ld_rlx(&ctr[C_L0 + 1]), fc_len = ld_rlx(&ctr[C_L0 + 2]);
+        // lengths of the current level's lists (L_D) and of the previous
+        // level's (L_{D-1}, whose frontier words are cleared during level D)
+        int64_t fl_len = ld_rlx(&ctr[C_LT(0, 0)]), fh_len = ld_rlx(&ctr[C_LT(0, 1)]);
+        int64_t fc_len = ld_rlx(&ctr[C_CT(0)]);
+        int64_t ol_len = 0, oh_len = 0;
         int64_t ucnt = fl_len + fh_len, udeg = 0;
         for (int l = 0; l < nsel; l++) udeg += s_mf[l];
         // out-arcs of vertices that every active lane has reached: a pull
@@ -341,7 +462,10 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                         }
                     }
                 }
+                s_red_cnt[l] = 0;
+                s_red_deg[l] = 0;
             }
+            if (tid < 4) s_blk[tid] = 0;
             __syncthreads();
             if (tid < 64 * NW) {
                 int l = tid;
@@ -381,24 +505,43 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 }
             }
             const int p = (int)(D % 3);
-            const int q = (int)(D & 1);
-            const int32_t* fl = VL(0, q);
-            const int32_t* fh = VL(1, q);
-            const int32_t* fcu = CU(q);
-            const int32_t* fcb = CB(q);
-            int32_t* const nls[2] = {VL(0, q ^ 1), VL(1, q ^ 1)};
-            const uint64_t* fcur = q ? a.w.frt1 : a.w.frt0;
-            uint64_t* fnxt = q ? a.w.frt0 : a.w.frt1;
+            const int sC = (int)(D & 3), sN = (int)((D + 1) & 3), sO = (int)((D + 3) & 3);
+            const uint64_t* Fc = fsel(a.w, D);
+            uint64_t* Fn = fsel(a.w, D + 1);
+            uint64_t* Fo = fsel(a.w, D + 2);   // F_{D-1}
+            const int32_t* fl = VL(0, sC);
+            const int32_t* fh = VL(1, sC);
+            const int32_t* fcu = CU(D & 1);
+            const int32_t* fcb = CB(D & 1);
+            const NextLists nl{VL(0, sN), VL(1, sN), &ctr[C_LT(sN, 0)], CU((D + 1) & 1), CB((D + 1) & 1),
+                               &ctr[C_CT((D + 1) % 3)], rp};
             const int32_t stamp = (int32_t)(D + 1);
-            // algorithmic bytes: push reads each frontier vertex's row and
-            // frontier word, then per out-arc the index, the target's visited
-            // word and its next word; pull reads every vertex's visited word
-            // and row, and per scanned in-arc the index and a frontier word
-            // (counted in my_scan)
-            bytes += bu ? (int64_t)n * (8 + 8 * NW) : (fl_len + fh_len) * (8 + 8 * NW) + udeg * (4 + 16 * NW);
+            const bool rec_lvl = a.lb_mode && D + 1 < a.w.lcap;
             Stage stg{&s_stage[tid >> 6][0], 0};
+            int64_t my_dd = 0, my_ud = 0;
+            // algorithmic bytes: clearing reads a list entry and writes the
+            // old frontier word; push reads each frontier vertex's row and
+            // frontier word and folds it into its visited word, then per
+            // out-arc the index, the target's visited and frontier words and
+            // its next word; pull reads every vertex's row, frontier and
+            // visited words, and per scanned in-arc the index and a frontier
+            // word (counted in my_scan)
+            bytes += (ol_len + oh_len) * (4 + 8 * NW) +
+                     (bu ? (int64_t)n * (8 + 16 * NW) + (fl_len + fh_len) * (4 + 24 * NW)
+                         : (fl_len + fh_len) * (8 + 24 * NW) + udeg * (4 + 24 * NW));
+            // (1) F_{D-1} is no longer read: clear its words through L_{D-1}
+            {
+                const int32_t* ofl = VL(0, sO);
+                const int32_t* ofh = VL(1, sO);
+                for (int64_t i = gtid; i < ol_len + oh_len; i += nthreads) {
+                    const int32_t u = i < ol_len ? ofl[i] : ofh[i - ol_len];
+#pragma unroll
+                    for (int j = 0; j < NW; j++) Fo[(int64_t)u * NW + j] = 0;
+                }
+            }
             if (!bu) {
-                // push, light frontier vertices: one per lane
+                // push, light frontier vertices: one per lane; the owner
+                // folds F_D into the visited word
                 for (int64_t base = gwave * 64; base < fl_len; base += nwaves * 64) {
                     int64_t i = base + lane;
                     int32_t e = 0, end = 0;
@@ -406,73 +549,123 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
 #pragma unroll
                     for (int j = 0; j < NW; j++) f.w[j] = 0;
                     if (i < fl_len) {
-                        int32_t u = fl[i];
+                        const int32_t u = fl[i];
+                        bool done = true;
 #pragma unroll
-                        for (int j = 0; j < NW; j++) f.w[j] = fcur[(int64_t)u * NW + j] & act.w[j];
-                        if (f.any()) { e = rp[u]; end = rp[u + 1]; }
+                        for (int j = 0; j < NW; j++) {
+                            const uint64_t fw = Fc[(int64_t)u * NW + j];
+                            const uint64_t vn = vis[(int64_t)u * NW + j] | fw;
+                            vis[(int64_t)u * NW + j] = vn;
+                            f.w[j] = fw & act.w[j];
+                            done &= (act.w[j] & ~vn) == 0;
+                        }
+                        e = rp[u];
+                        end = rp[u + 1];
+                        if (done) my_dd += end - e;
+                        if (!f.any()) end = e;
                     }
                     while (__any(e < end)) {
                         bool isnew = false;
                         int32_t w = 0, dw = 0;
+                        Mask<NW> fr;
+#pragma unroll
+                        for (int j = 0; j < NW; j++) fr.w[j] = 0;
                         if (e < end) {
-                            w = ci[e]; e++;
+                            w = ci[e];
+                            e++;
                             Mask<NW> nb;
 #pragma unroll
-                            for (int j = 0; j < NW; j++) nb.w[j] = f.w[j] & ~vis[(int64_t)w * NW + j];
-                            if (nb.any() && push_lanes<NW>(a.w.nxt, a.mark, w, nb, stamp)) {
-                                isnew = true;
-                                dw = deg[w];
+                            for (int j = 0; j < NW; j++)
+                                nb.w[j] = f.w[j] & ~(vis[(int64_t)w * NW + j] | Fc[(int64_t)w * NW + j]);
+                            if (nb.any()) {
+                                isnew = discover<NW>(Fn, a.mark, w, nb, stamp, &fr);
+                                if (isnew || fr.any()) dw = deg[w];
+                                if (rec_lvl && fr.any()) record_levels<NW>(fr, w, a.w.lvl, W, D + 1);
                             }
                         }
-                        list_append(isnew, w, dw, nls, &ctr[C_T(p, 0)], stg);
+                        tally<NW>(fr, dw, s_red_cnt, s_red_deg);
+                        if (isnew) my_ud += dw;
+                        list_append(isnew, w, dw, nl, stg);
                     }
+                }
+                // heavy frontier vertices: the owner folds; their arcs go
+                // through the chunk list
+                for (int64_t i = gtid; i < fh_len; i += nthreads) {
+                    const int32_t u = fh[i];
+                    bool done = true;
+#pragma unroll
+                    for (int j = 0; j < NW; j++) {
+                        const uint64_t vn = vis[(int64_t)u * NW + j] | Fc[(int64_t)u * NW + j];
+                        vis[(int64_t)u * NW + j] = vn;
+                        done &= (act.w[j] & ~vn) == 0;
+                    }
+                    if (done) my_dd += deg[u];
                 }
                 // push, heavy frontier vertices: one wave per chunk of arcs
                 for (int64_t c = gwave; c < fc_len; c += nwaves) {
-                    int32_t u = fcu[c];
+                    const int32_t u = fcu[c];
                     Mask<NW> f;
 #pragma unroll
-                    for (int j = 0; j < NW; j++) f.w[j] = fcur[(int64_t)u * NW + j] & act.w[j];
-                    if (!f.any()) continue;
-                    int32_t b = fcb[c];
-                    int32_t end = b + CHUNK_ARCS < rp[u + 1] ? b + CHUNK_ARCS : rp[u + 1];
+                    for (int j = 0; j < NW; j++) f.w[j] = Fc[(int64_t)u * NW + j] & act.w[j];
+                    if (!f.any()) continue;   // wave-uniform
+                    const int32_t b = fcb[c];
+                    const int32_t end = b + CHUNK_ARCS < rp[u + 1] ? b + CHUNK_ARCS : rp[u + 1];
                     for (int32_t e0 = b; e0 < end; e0 += 64) {
-                        int32_t e = e0 + lane;
+                        const int32_t e = e0 + lane;
                         bool isnew = false;
                         int32_t w = 0, dw = 0;
+                        Mask<NW> fr;
+#pragma unroll
+                        for (int j = 0; j < NW; j++) fr.w[j] = 0;
                         if (e < end) {
                             w = ci[e];
                             Mask<NW> nb;
 #pragma unroll
-                            for (int j = 0; j < NW; j++) nb.w[j] = f.w[j] & ~vis[(int64_t)w * NW + j];
-                            if (nb.any() && push_lanes<NW>(a.w.nxt, a.mark, w, nb, stamp)) {
-                                isnew = true;
-                                dw = deg[w];
+                            for (int j = 0; j < NW; j++)
+                                nb.w[j] = f.w[j] & ~(vis[(int64_t)w * NW + j] | Fc[(int64_t)w * NW + j]);
+                            if (nb.any()) {
+                                isnew = discover<NW>(Fn, a.mark, w, nb, stamp, &fr);
+                                if (isnew || fr.any()) dw = deg[w];
+                                if (rec_lvl && fr.any()) record_levels<NW>(fr, w, a.w.lvl, W, D + 1);
                             }
                         }
-                        list_append(isnew, w, dw, nls, &ctr[C_T(p, 0)], stg);
+                        tally<NW>(fr, dw, s_red_cnt, s_red_deg);
+                        if (isnew) my_ud += dw;
+                        list_append(isnew, w, dw, nl, stg);
                     }
                 }
             } else {
-                // pull, light vertices (few in-arcs): one per lane, scanning
-                // in-arcs until every missing active lane is found
+                // pull: the level list's vertices fold F_D into their visited
+                // words (readers use vis | F_D, so the fold's timing does not
+                // matter); light vertices (few in-arcs) scan their in-arcs, in
+                // groups of four (four independent index loads, then four
+                // independent frontier loads), until every missing active
+                // lane is found
+                for (int64_t i = gtid; i < fl_len + fh_len; i += nthreads) {
+                    const int32_t u = i < fl_len ? fl[i] : fh[i - fl_len];
+                    bool done = true;
+#pragma unroll
+                    for (int j = 0; j < NW; j++) {
+                        const uint64_t vn = vis[(int64_t)u * NW + j] | Fc[(int64_t)u * NW + j];
+                        vis[(int64_t)u * NW + j] = vn;
+                        done &= (act.w[j] & ~vn) == 0;
+                    }
+                    if (done) my_dd += deg[u];
+                }
                 for (int64_t base = gwave * 64; base < n; base += nwaves * 64) {
-                    int32_t w = (int32_t)(base + lane);
+                    const int32_t w = (int32_t)(base + lane);
                     bool isnew = false;
                     int32_t dw = 0;
-                    if (w < n) {
-                        int32_t eb = a.g.rrp[w], ee = a.g.rrp[w + 1];
-                        Mask<NW> miss, acc;
-                        bool need = ee - eb <= HEAVY_DEG;
+                    Mask<NW> acc;
 #pragma unroll
-                        for (int j = 0; j < NW; j++) {
-                            miss.w[j] = act.w[j] & ~vis[(int64_t)w * NW + j];
-                            acc.w[j] = 0;
-                        }
-                        need = need && miss.any();
-                        if (need) {
-                            // in-arcs in groups of four: four independent index
-                            // loads, then four independent frontier loads
+                    for (int j = 0; j < NW; j++) acc.w[j] = 0;
+                    if (w < n) {
+                        Mask<NW> miss;
+#pragma unroll
+                        for (int j = 0; j < NW; j++)
+                            miss.w[j] = act.w[j] & ~(vis[(int64_t)w * NW + j] | Fc[(int64_t)w * NW + j]);
+                        const int32_t eb = a.g.rrp[w], ee = a.g.rrp[w + 1];
+                        if (ee - eb <= HEAVY_DEG && miss.any()) {
                             for (int32_t e = eb; e < ee; e += 4) {
                                 my_scan += (ee - e < 4 ? ee - e : 4);
                                 int32_t u[4];
@@ -481,43 +674,47 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                                 bool full = true;
 #pragma unroll
                                 for (int j = 0; j < NW; j++) {
-                                    uint64_t f = 0;
+                                    uint64_t fo = 0;
 #pragma unroll
                                     for (int t = 0; t < 4; t++)
-                                        if (u[t] >= 0) f |= fcur[(int64_t)u[t] * NW + j];
-                                    acc.w[j] |= f & miss.w[j];
+                                        if (u[t] >= 0) fo |= Fc[(int64_t)u[t] * NW + j];
+                                    acc.w[j] |= fo & miss.w[j];
                                     full &= acc.w[j] == miss.w[j];
                                 }
                                 if (full) break;
                             }
                             if (acc.any()) {
+                                // a light vertex has one pulling thread: plain stores
 #pragma unroll
-                                for (int j = 0; j < NW; j++) a.w.nxt[(int64_t)w * NW + j] = acc.w[j];
+                                for (int j = 0; j < NW; j++) Fn[(int64_t)w * NW + j] = acc.w[j];
                                 isnew = true;
                                 dw = deg[w];
+                                if (rec_lvl) record_levels<NW>(acc, w, a.w.lvl, W, D + 1);
                             }
                         }
                     }
-                    list_append(isnew, w, dw, nls, &ctr[C_T(p, 0)], stg);
+                    tally<NW>(acc, dw, s_red_cnt, s_red_deg);
+                    if (isnew) my_ud += dw;
+                    list_append(isnew, w, dw, nl, stg);
                 }
                 // pull, heavy vertices: one wave per chunk of their in-arcs
                 for (int64_t c = gwave; c < a.g.rnchunks; c += nwaves) {
-                    int32_t w = a.g.rch_vtx[c];
+                    const int32_t w = a.g.rch_vtx[c];
                     Mask<NW> miss, acc;
 #pragma unroll
                     for (int j = 0; j < NW; j++) {
-                        miss.w[j] = __shfl(act.w[j] & ~vis[(int64_t)w * NW + j], 0, 64);
+                        miss.w[j] = __shfl(act.w[j] & ~(vis[(int64_t)w * NW + j] | Fc[(int64_t)w * NW + j]), 0, 64);
                         acc.w[j] = 0;
                     }
                     if (!miss.any()) continue;   // wave-uniform
-                    int32_t eb = a.g.rch_beg[c], ee = a.g.rch_end[c];
+                    const int32_t eb = a.g.rch_beg[c], ee = a.g.rch_end[c];
                     for (int32_t e0 = eb; e0 < ee; e0 += 64) {
-                        int32_t e = e0 + lane;
+                        const int32_t e = e0 + lane;
                         my_scan += e < ee ? 1 : 0;
                         if (e < ee) {
-                            int32_t u = a.g.rci[e];
+                            const int32_t u = a.g.rci[e];
 #pragma unroll
-                            for (int j = 0; j < NW; j++) acc.w[j] |= fcur[(int64_t)u * NW + j] & miss.w[j];
+                            for (int j = 0; j < NW; j++) acc.w[j] |= Fc[(int64_t)u * NW + j] & miss.w[j];
                         }
                         bool full = true;
 #pragma unroll
@@ -529,125 +726,38 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                     }
                     bool isnew = false;
                     int32_t dw = 0;
-                    if (lane == 0 && acc.any() && push_lanes<NW>(a.w.nxt, a.mark, w, acc, stamp)) {
-                        isnew = true;
-                        dw = deg[w];
+                    Mask<NW> fr;
+#pragma unroll
+                    for (int j = 0; j < NW; j++) fr.w[j] = 0;
+                    if (lane == 0 && acc.any()) {
+                        isnew = discover<NW>(Fn, a.mark, w, acc, stamp, &fr);
+                        if (isnew || fr.any()) dw = deg[w];
+                        if (rec_lvl && fr.any()) record_levels<NW>(fr, w, a.w.lvl, W, D + 1);
                     }
-                    list_append(isnew, w, dw, nls, &ctr[C_T(p, 0)], stg);
+                    tally<NW>(fr, dw, s_red_cnt, s_red_deg);
+                    if (isnew) my_ud += dw;
+                    list_append(isnew, w, dw, nl, stg);
                 }
             }
-            stage_flush(stg, nls[0], &ctr[C_T(p, 0)]);
-            grid_barrier(a.bar, gridDim.x);
-            if (boss && tslot >= 0) a.w.trace[8 + 16 * tslot + 8] = (int64_t)wall_clock64();
-            // ------------------------------------------------------ epilogue
-            const int64_t nl_len = ld_rlx(&ctr[C_T(p, 0)]), nh_len = ld_rlx(&ctr[C_T(p, 1)]);
-            const int64_t nall = nl_len + nh_len;
-            int64_t* ctail = &ctr[C_T((D + 1) % 3, 2)];   // chunk list of the next level
-            int32_t* ncu = CU(q ^ 1);
-            int32_t* ncb = CB(q ^ 1);
-            if (tid < MAXW) { s_red_cnt[tid] = 0; s_red_deg[tid] = 0; }
-            if (tid < 3) s_blk[tid] = 0;
-            __syncthreads();
-            // old frontier words are cleared (the next level uses the other array)
-            uint64_t* fcur_w = (uint64_t*)fcur;
-            for (int64_t i = gtid; i < fl_len + fh_len; i += nthreads) {
-                int32_t u = i < fl_len ? fl[i] : fh[i - fl_len];
-#pragma unroll
-                for (int j = 0; j < NW; j++) fcur_w[(int64_t)u * NW + j] = 0;
-            }
-            int64_t my_u = 0, my_ud = 0, my_dd = 0;
-            for (int64_t base = gwave * 64; base < nall; base += nwaves * 64) {
-                int64_t i = base + lane;
-                Mask<NW> nb;
-#pragma unroll
-                for (int j = 0; j < NW; j++) nb.w[j] = 0;
-                int32_t dw = 0, w = 0;
-                if (i < nall) {
-                    w = i < nl_len ? nls[0][i] : nls[1][i - nl_len];
-                    dw = deg[w];
-                    bool done = true;
-#pragma unroll
-                    for (int j = 0; j < NW; j++) {
-                        uint64_t b = a.w.nxt[(int64_t)w * NW + j];
-                        nb.w[j] = b;
-                        a.w.nxt[(int64_t)w * NW + j] = 0;
-                        uint64_t vn = vis[(int64_t)w * NW + j] | b;
-                        vis[(int64_t)w * NW + j] = vn;
-                        fnxt[(int64_t)w * NW + j] = b;
-                        done &= (act.w[j] & ~vn) == 0;
-                    }
-                    if (done) my_dd += dw;
-                    if (a.lb_mode && D + 1 < a.w.lcap) {
-#pragma unroll
-                        for (int j = 0; j < NW; j++) {
-                            uint64_t m = nb.w[j];
-                            while (m) {
-                                int l = __ffsll((long long)m) - 1;
-                                m &= m - 1;
-                                a.w.lvl[(int64_t)w * W + j * 64 + l] = (uint16_t)(D + 1);
-                            }
-                        }
-                    }
-                    my_u += 1;
-                    my_ud += dw;
-                }
-                // heavy vertices of the next frontier: their arc chunks
-                int32_t nck = (i < nall && dw > HEAVY_DEG) ? (dw + CHUNK_ARCS - 1) / CHUNK_ARCS : 0;
-                int32_t pre = nck;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    int32_t y = __shfl_up(pre, o, 64);
-                    if (lane >= o) pre += y;
-                }
-                int32_t tot = __shfl(pre, 63, 64);
-                pre -= nck;
-                if (tot) {
-                    int64_t cbase = 0;
-                    if (lane == 0) cbase = fadd_rlx(ctail, (int64_t)tot);
-                    cbase = shfl64b(cbase, 0);
-                    int32_t b0 = nck ? rp[w] : 0;
-                    for (int32_t j = 0; j < nck; j++) {
-                        ncu[cbase + pre + j] = w;
-                        ncb[cbase + pre + j] = b0 + j * CHUNK_ARCS;
-                    }
-                }
-                // per-lane counts: transpose the wave's bit matrix lane by lane
-#pragma unroll
-                for (int j = 0; j < NW; j++) {
-                    uint64_t lanes_here = wave_or_u64(nb.w[j]);
-                    while (lanes_here) {
-                        int l = __ffsll((long long)lanes_here) - 1;
-                        lanes_here &= lanes_here - 1;
-                        bool has = (nb.w[j] >> l) & 1ull;
-                        int c = __popcll(__ballot(has));
-                        int64_t d = wave_sum_i64(has ? (int64_t)dw : 0);
-                        if (lane == 0) {
-                            atomicAdd(&s_red_cnt[j * 64 + l], c);
-                            atomicAdd((unsigned long long*)&s_red_deg[j * 64 + l], (unsigned long long)d);
-                        }
-                    }
-                }
-            }
-            my_u = wave_sum_i64(my_u);
-            my_ud = wave_sum_i64(my_ud);
+            stage_flush(stg, nl.light, nl.tails);
+            // workgroup totals into this level's counters
             my_dd = wave_sum_i64(my_dd);
-            if (lane == 0 && my_u) {
-                atomicAdd((unsigned long long*)&s_blk[0], (unsigned long long)my_u);
-                atomicAdd((unsigned long long*)&s_blk[1], (unsigned long long)my_ud);
-                atomicAdd((unsigned long long*)&s_blk[2], (unsigned long long)my_dd);
+            my_ud = wave_sum_i64(my_ud);
+            if (lane == 0) {
+                if (my_ud) atomicAdd((unsigned long long*)&s_blk[0], (unsigned long long)my_ud);
+                if (my_dd) atomicAdd((unsigned long long*)&s_blk[1], (unsigned long long)my_dd);
             }
             __syncthreads();
-            if (tid == 0 && s_blk[0]) {
-                fadd_rlx(&ctr[C_UCNT(p)], s_blk[0]);
-                fadd_rlx(&ctr[C_UDEG(p)], s_blk[1]);
-                if (s_blk[2]) fadd_rlx(&ctr[C_DDONE(p)], s_blk[2]);
-            }
             if (tid < W && s_red_cnt[tid]) {
                 fadd_rlx(&ctr[C_CNT(p, tid)], (int64_t)s_red_cnt[tid]);
                 fadd_rlx(&ctr[C_DEG(p, tid)], s_red_deg[tid]);
             }
+            if (tid == 0) {
+                if (s_blk[0]) fadd_rlx(&ctr[C_UDEG(p)], s_blk[0]);
+                if (s_blk[1]) fadd_rlx(&ctr[C_DDONE(p)], s_blk[1]);
+            }
             grid_barrier(a.bar, gridDim.x);
-            if (boss && tslot >= 0) a.w.trace[8 + 16 * tslot + 9] = (int64_t)wall_clock64();
+            if (boss && tslot >= 0) a.w.trace[8 + 16 * tslot + 8] = (int64_t)wall_clock64();
             // --------------------------------------------- advance lane state
             if (tid < MAXW) {
                 int l = tid;
@@ -664,19 +774,31 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                     }
                 }
             }
-            ucnt = ld_rlx(&ctr[C_UCNT(p)]);
+            ol_len = fl_len;
+            oh_len = fh_len;
+            fl_len = ld_rlx(&ctr[C_LT(sN, 0)]);
+            fh_len = ld_rlx(&ctr[C_LT(sN, 1)]);
+            fc_len = ld_rlx(&ctr[C_CT((D + 1) % 3)]);
+            ucnt = fl_len + fh_len;
             udeg = ld_rlx(&ctr[C_UDEG(p)]);
             ddone += ld_rlx(&ctr[C_DDONE(p)]);
-            bytes += ucnt * 8 * (3 * NW) + nall * 4;
-            fc_len = ld_rlx(ctail);
+            bytes += ucnt * (8 * NW + 4);
             if (boss) {
-                int q3 = (int)((D + 2) % 3);
+                // Reset what the next barrier's far side reuses: every
+                // workgroup read these before the barrier just passed, and
+                // none writes them before the next one.  Per-lane and union
+                // counters of parity (D+2)%3 were last read after level D-1;
+                // slot sO held L_{D-1} (cleared during this level) and is next
+                // filled during level D+2; chunk tail D%3 was read after
+                // level D-1 and is next filled during level D+2.
+                const int q3 = (int)((D + 2) % 3);
                 for (int l = 0; l < W; l++) { ctr[C_CNT(q3, l)] = 0; ctr[C_DEG(q3, l)] = 0; }
-                ctr[C_UCNT(q3)] = 0; ctr[C_UDEG(q3)] = 0; ctr[C_DDONE(q3)] = 0;
-                for (int c = 0; c < 3; c++) ctr[C_T(q3, c)] = 0;
+                ctr[C_UDEG(q3)] = 0;
+                ctr[C_DDONE(q3)] = 0;
+                ctr[C_LT(sO, 0)] = 0;
+                ctr[C_LT(sO, 1)] = 0;
+                ctr[C_CT(D % 3)] = 0;
             }
-            fl_len = nl_len;
-            fh_len = nh_len;
             D++;
             __syncthreads();
         }
@@ -772,6 +894,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 vis[q] = 0;
                 a.w.frt0[q] = 0;
                 a.w.frt1[q] = 0;
+                a.w.nxt[q] = 0;
             }
             if (NW > 1)
                 for (int64_t q = gtid; q < n; q += nthreads) a.mark[q] = 0;
