@@ -395,38 +395,48 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 s_st[l] = 0;
             }
         }
-        if (blockIdx.x == 0 && tid < nsel) {
-            int l = tid;
-            int32_t v = a.w.cand[l];
-            // level 0 is F_0; a source list may name one vertex twice: atomic OR
-            for_rlx(&fsel(a.w, 0)[(int64_t)v * NW + (l >> 6)], (uint64_t)1 << (l & 63));
-            if (a.lb_mode) { a.w.lvl[(int64_t)v * W + l] = 0; a.w.hist[l] = 1; }
-        }
-        if (boss) {
-            // level-0 frontier (parity 0): light sources, heavy sources and
-            // the heavy sources' arc chunks
-            int64_t nl0 = 0, nh0 = 0, nc0 = 0;
-            for (int l = 0; l < nsel; l++) {
-                int32_t v = a.w.cand[l];
+        __syncthreads();   // every lane's source is in s_v
+        if (blockIdx.x == 0) {
+            // level-0 frontier (list slot 0): light sources, heavy sources
+            // and the heavy sources' arc chunks.  A source list may name one
+            // vertex twice: F_0 takes atomic ORs, the lists take it once.
+            if (tid < 3) s_blk[tid] = 0;
+            __syncthreads();
+            if (tid < nsel) {
+                const int l = tid;
+                const int32_t v = s_v[l];
+                for_rlx(&fsel(a.w, 0)[(int64_t)v * NW + (l >> 6)], (uint64_t)1 << (l & 63));
+                if (a.lb_mode) { a.w.lvl[(int64_t)v * W + l] = 0; a.w.hist[l] = 1; }
                 bool dup = false;
-                for (int q = 0; q < l; q++) dup |= a.w.cand[q] == v;
-                if (dup) continue;
-                if (deg[v] > HEAVY_DEG) {
-                    VL(1, 0)[nh0++] = v;
-                    for (int32_t b = rp[v]; b < rp[v + 1]; b += CHUNK_ARCS) {
-                        CU(0)[nc0] = v;
-                        CB(0)[nc0] = b;
-                        nc0++;
+                for (int q = 0; q < l; q++) dup |= s_v[q] == v;
+                if (!dup) {
+                    const int32_t dv = deg[v];
+                    if (dv > HEAVY_DEG) {
+                        const int32_t nck = (dv + CHUNK_ARCS - 1) / CHUNK_ARCS;
+                        const int64_t h = (int64_t)atomicAdd((unsigned long long*)&s_blk[1], 1ull);
+                        const int64_t c0 = (int64_t)atomicAdd((unsigned long long*)&s_blk[2], (unsigned long long)nck);
+                        VL(1, 0)[h] = v;
+                        const int32_t r0 = rp[v];
+                        for (int32_t j = 0; j < nck; j++) {
+                            CU(0)[c0 + j] = v;
+                            CB(0)[c0 + j] = r0 + j * CHUNK_ARCS;
+                        }
+                    } else {
+                        const int64_t h = (int64_t)atomicAdd((unsigned long long*)&s_blk[0], 1ull);
+                        VL(0, 0)[h] = v;
                     }
-                } else {
-                    VL(0, 0)[nl0++] = v;
                 }
             }
-            for (int p = 0; p < 3; p++) { ctr[C_UDEG(p)] = 0; ctr[C_DDONE(p)] = 0; ctr[C_CT(p)] = 0; }
-            for (int q = 0; q < 4; q++) { ctr[C_LT(q, 0)] = 0; ctr[C_LT(q, 1)] = 0; }
-            ctr[C_LT(0, 0)] = nl0; ctr[C_LT(0, 1)] = nh0; ctr[C_CT(0)] = nc0;
-            for (int p = 0; p < 3; p++)
-                for (int l = 0; l < MAXW; l++) { ctr[C_CNT(p, l)] = 0; ctr[C_DEG(p, l)] = 0; }
+            // per-lane counters of every parity (C_CNT, C_DEG)
+            for (int i = tid; i < C_BASE; i += BB) ctr[i] = 0;
+            __syncthreads();
+            if (tid == 0) {
+                for (int p = 0; p < 3; p++) { ctr[C_UDEG(p)] = 0; ctr[C_DDONE(p)] = 0; ctr[C_CT(p)] = 0; }
+                for (int q = 0; q < 4; q++) { ctr[C_LT(q, 0)] = 0; ctr[C_LT(q, 1)] = 0; }
+                ctr[C_LT(0, 0)] = s_blk[0];
+                ctr[C_LT(0, 1)] = s_blk[1];
+                ctr[C_CT(0)] = s_blk[2];
+            }
         }
         grid_barrier(a.bar, gridDim.x);
 
