@@ -342,11 +342,45 @@ extern "C" int tkc_graph_upload(tkc_ctx* c, int32_t n, int64_t m, const int32_t*
             }
         }
     }
+    // in-arc chunks of the hubs (in-degree above HUB_IN_DEG)
+    std::vector<int32_t> bcb, bce, bcv;
+    {
+        const int32_t* irp = directed ? hrrp.data() : hrp.data();
+        for (int32_t u = 0; u < n; u++) {
+            if (irp[u + 1] - irp[u] <= HUB_IN_DEG) continue;
+            for (int32_t b = irp[u]; b < irp[u + 1]; b += CHUNK_ARCS) {
+                bcb.push_back(b);
+                bce.push_back(std::min(b + CHUNK_ARCS, irp[u + 1]));
+                bcv.push_back(u);
+            }
+        }
+    }
+    g->bnchunks = (int32_t)bcb.size();
+    // mid in-degree vertices packed into segments (edge-balanced pulls)
+    std::vector<int32_t> mvtx, mseg(1, 0);
+    {
+        const int32_t* irp = directed ? hrrp.data() : hrp.data();
+        int64_t arcs = 0;
+        for (int32_t u = 0; u < n; u++) {
+            const int32_t d = irp[u + 1] - irp[u];
+            if (d <= HEAVY_DEG || d > HUB_IN_DEG) continue;
+            const int32_t cnt = (int32_t)mvtx.size() - mseg.back();
+            if (cnt > 0 && (cnt == 64 || arcs + d > MID_ARCS)) {
+                mseg.push_back((int32_t)mvtx.size());
+                arcs = 0;
+            }
+            mvtx.push_back(u);
+            arcs += d;
+        }
+        if ((int32_t)mvtx.size() > mseg.back()) mseg.push_back((int32_t)mvtx.size());
+    }
+    g->nmseg = (int32_t)mseg.size() - 1;
     g->nheavy = (int32_t)hv.size();
     g->nchunks = (int32_t)cb.size();
     g->rnchunks = directed ? (int32_t)rcb.size() : g->nchunks;
     size_t bytes = 4 * (size_t)(n + 1) + 4 * (size_t)(m ? m : 1) + 4 * (size_t)n + 4 * (hv.size() + 1) +
-                   4 * hcb.size() + 12 * (cb.size() + 1) + 12 * (rcb.size() + 1) + 16 * 256;
+                   4 * hcb.size() + 12 * (cb.size() + 1) + 12 * (rcb.size() + 1) + 12 * (bcb.size() + 1) +
+                   4 * (mvtx.size() + 1) + 4 * mseg.size() + 16 * 256;
     if (directed) bytes += 4 * (size_t)(n + 1) + 4 * (size_t)(m ? m : 1);
     if (hipMalloc(&g->dbase, bytes + 1024) != hipSuccess) {
         hipGetLastError();
@@ -372,6 +406,11 @@ extern "C" int tkc_graph_upload(tkc_ctx* c, int32_t n, int64_t m, const int32_t*
         g->rch_end = g->ch_end;
         g->rch_vtx = g->ch_vtx;
     }
+    g->bch_beg = (int32_t*)take(4 * (bcb.size() + 1));
+    g->bch_end = (int32_t*)take(4 * (bcb.size() + 1));
+    g->bch_vtx = (int32_t*)take(4 * (bcb.size() + 1));
+    g->mid_vtx = (int32_t*)take(4 * (mvtx.size() + 1));
+    g->mseg = (int32_t*)take(4 * mseg.size());
     if (directed) {
         g->rrp = (int32_t*)take(4 * (size_t)(n + 1));
         g->rci = (int32_t*)take(4 * (size_t)(m ? m : 1));
@@ -395,7 +434,12 @@ extern "C" int tkc_graph_upload(tkc_ctx* c, int32_t n, int64_t m, const int32_t*
                                hipMemcpyAsync(g->ch_vtx, cv.data(), 4 * cv.size(), hipMemcpyHostToDevice, s))) ||
                 (rcb.size() && (hipMemcpyAsync(g->rch_beg, rcb.data(), 4 * rcb.size(), hipMemcpyHostToDevice, s) ||
                                 hipMemcpyAsync(g->rch_end, rce.data(), 4 * rce.size(), hipMemcpyHostToDevice, s) ||
-                                hipMemcpyAsync(g->rch_vtx, rcv.data(), 4 * rcv.size(), hipMemcpyHostToDevice, s)))))
+                                hipMemcpyAsync(g->rch_vtx, rcv.data(), 4 * rcv.size(), hipMemcpyHostToDevice, s))) ||
+                (bcb.size() && (hipMemcpyAsync(g->bch_beg, bcb.data(), 4 * bcb.size(), hipMemcpyHostToDevice, s) ||
+                                hipMemcpyAsync(g->bch_end, bce.data(), 4 * bce.size(), hipMemcpyHostToDevice, s) ||
+                                hipMemcpyAsync(g->bch_vtx, bcv.data(), 4 * bcv.size(), hipMemcpyHostToDevice, s))) ||
+                (mvtx.size() && hipMemcpyAsync(g->mid_vtx, mvtx.data(), 4 * mvtx.size(), hipMemcpyHostToDevice, s)) ||
+                hipMemcpyAsync(g->mseg, mseg.data(), 4 * mseg.size(), hipMemcpyHostToDevice, s)))
         rc = tkc_fail(TKC_EDEVICE, "heavy-vertex table copy failed");
     if (!rc) {
         DevGraph dg = g->view();
@@ -545,12 +589,14 @@ static void trace_dump(tkc_ctx* c, const char* tag) {
         const int64_t* r = h.data() + 8 + 16 * i;
         double dt = i + 1 < cnt ? (h[8 + 16 * (i + 1) + 5] - r[5]) / khz * 1e3 : 0.0;
         double te = r[8] ? (r[8] - r[5]) / khz * 1e3 : 0.0;
-        double tp = r[9] ? (r[9] - r[8]) / khz * 1e3 : 0.0;
+        const double us = 1e3 / khz;
         fprintf(stderr,
                 "trace %s batch %lld level %lld %s frontier %lld arcs %lld lanes %lld/%lld  %.1f us"
-                " (expand %.1f, epilogue %.1f)\n",
+                " (to barrier exit %.1f; slowest wave of workgroup 0: clear %.1f fold %.1f vertices %.1f"
+                " chunks %.1f flush %.1f barrier %.1f)\n",
                 tag, (long long)r[0], (long long)r[1], r[2] ? "pull" : "push", (long long)r[3], (long long)r[4],
-                (long long)r[7], (long long)r[6], dt, te, tp);
+                (long long)r[7], (long long)r[6], dt, te, r[9] * us, r[10] * us, r[11] * us, r[12] * us,
+                r[13] * us, r[14] * us);
     }
 }
 

@@ -30,9 +30,24 @@ struct DevGraph {
     const int32_t* rch_beg;
     const int32_t* rch_end;
     int32_t rnchunks;
+    // in-arc chunks of the hubs only (more than HUB_IN_DEG in-arcs): the
+    // batched engine's pull sends every other vertex through its
+    // edge-balanced path, which shares a wave's in-arcs over all its lanes
+    const int32_t* bch_vtx;
+    const int32_t* bch_beg;
+    const int32_t* bch_end;
+    int32_t bnchunks;
+    // vertices with HEAVY_DEG < in-degree <= HUB_IN_DEG, ascending, packed
+    // into segments of at most 64 vertices and MID_ARCS in-arcs (a segment
+    // of one vertex may exceed it); segment s is mid_vtx[mseg[s] .. mseg[s+1])
+    const int32_t* mid_vtx;
+    const int32_t* mseg;
+    int32_t nmseg;
 };
 #define HEAVY_DEG 64
 #define CHUNK_ARCS 512
+#define HUB_IN_DEG 1024
+#define MID_ARCS 1024
 
 // reachability and bounds of one query
 struct DevReach {

@@ -80,6 +80,10 @@ struct tkc_graph {
     int32_t *hcb = nullptr, *ch_beg = nullptr, *ch_end = nullptr, *ch_vtx = nullptr;
     int32_t *rch_beg = nullptr, *rch_end = nullptr, *rch_vtx = nullptr;
     int32_t nchunks = 0, rnchunks = 0;
+    int32_t *bch_beg = nullptr, *bch_end = nullptr, *bch_vtx = nullptr;
+    int32_t bnchunks = 0;
+    int32_t *mid_vtx = nullptr, *mseg = nullptr;
+    int32_t nmseg = 0;
     int32_t server_refs = 0;
     int32_t auto_variant = 0;
     // directed graphs keep a host copy for the reachability bounds
@@ -104,6 +108,8 @@ struct tkc_graph {
         g.heavy = heavy; g.nheavy = nheavy; g.hcb = hcb; g.ch_beg = ch_beg; g.ch_end = ch_end;
         g.nchunks = nchunks;
         g.rch_vtx = rch_vtx; g.rch_beg = rch_beg; g.rch_end = rch_end; g.rnchunks = rnchunks;
+        g.bch_vtx = bch_vtx; g.bch_beg = bch_beg; g.bch_end = bch_end; g.bnchunks = bnchunks;
+        g.mid_vtx = mid_vtx; g.mseg = mseg; g.nmseg = nmseg;
         return g;
     }
 };

@@ -230,6 +230,53 @@ TKC_DEV void record_levels(const Mask<NW>& nb, int32_t w, uint16_t* lvl, int W, 
     }
 }
 
+// Edge-balanced pull over up to 64 vertices, one per lane: the lane's
+// vertex has in-arcs [eb, eb + len) and misses the lanes in `miss`; *acc
+// receives the frontier lanes among its in-neighbours, restricted to miss.
+// The wave's lanes share all the arcs: each arc finds its vertex by binary
+// search over the prefix sums and ORs into the vertex's LDS accumulator.
+// Called by all 64 lanes; the LDS slots belong to the calling wave.
+template <int NW>
+TKC_DEV void pull_shared(int32_t eb, int32_t len, const Mask<NW>& miss, const uint64_t* Fc,
+                         const int32_t* __restrict__ rci, int32_t* c_pre, int32_t* c_beg, uint64_t* c_miss,
+                         uint64_t* c_acc, Mask<NW>* acc, int64_t* scanned) {
+    const int lane = lane_id();
+    int32_t pre = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int32_t y = __shfl_up(pre, o, 64);
+        if (lane >= o) pre += y;
+    }
+    const int32_t tot = __shfl(pre, 63, 64);
+    pre -= len;
+    c_pre[lane] = pre;
+    c_beg[lane] = eb;
+#pragma unroll
+    for (int j = 0; j < NW; j++) {
+        c_miss[lane * NW + j] = miss.w[j];
+        c_acc[lane * NW + j] = 0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int32_t t = lane; t < tot; t += 64) {
+        int32_t lo = 0, hi = 64;   // owner: last vertex whose range starts at or before t
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (c_pre[mid] <= t) lo = mid; else hi = mid;
+        }
+        const int32_t u = rci[c_beg[lo] + (t - c_pre[lo])];
+        (*scanned)++;
+#pragma unroll
+        for (int j = 0; j < NW; j++) {
+            const uint64_t f = Fc[(int64_t)u * NW + j] & c_miss[lo * NW + j];
+            if (f) atomicOr((unsigned long long*)&c_acc[lo * NW + j], (unsigned long long)f);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int j = 0; j < NW; j++) acc->w[j] = c_acc[lane * NW + j];
+    __builtin_amdgcn_wave_barrier();
+}
+
 // OR the lanes nb into w's next-frontier word(s).  *fresh receives the
 // lanes this call set first (each (vertex, lane) is fresh for exactly one
 // caller); the result is true for exactly one caller per vertex and level,
@@ -268,7 +315,9 @@ TKC_DEV uint64_t* fsel(const BatchWork& w, int64_t level) {
 #define CU(q) (a.w.list + 8 * (int64_t)n + (int64_t)(2 * (q)) * a.w.ccap)
 #define CB(q) (a.w.list + 8 * (int64_t)n + (int64_t)(2 * (q) + 1) * a.w.ccap)
 
-template <int NW>
+// TR: per-level phase timing of workgroup 0's waves into the trace (the
+// diagnostic TKC_TRACE mode); the untraced kernel carries none of it.
+template <int NW, bool TR>
 __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
     const int32_t n = a.g.n;
     const bool dir = a.g.directed;
@@ -300,6 +349,21 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
     __shared__ int64_t s_scal[8];
     __shared__ int32_t s_stage[BB / 64][STAGE];
     __shared__ int64_t s_blk[4];
+    __shared__ int64_t s_ph[BB / 64][6];
+    int64_t ph[6] = {0, 0, 0, 0, 0, 0};
+    uint64_t tp = 0;
+    const bool trb = TR && blockIdx.x == 0;
+#define PHASE(i)                                   \
+    if (trb) {                                     \
+        const uint64_t t_ = wall_clock64();        \
+        ph[i] += (int64_t)(t_ - tp);               \
+        tp = t_;                                   \
+    }
+    // edge-balanced pull: per-wave vertex ranges, missing lanes, accumulators
+    __shared__ int32_t s_cpre[BB / 64][64];
+    __shared__ int32_t s_cbeg[BB / 64][64];
+    __shared__ uint64_t s_cmiss[BB / 64][64 * NW];
+    __shared__ uint64_t s_cacc[BB / 64][64 * NW];
 
     int32_t pos = a.start_pos;
     int32_t batches = 0;
@@ -529,6 +593,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             const bool rec_lvl = a.lb_mode && D + 1 < a.w.lcap;
             Stage stg{&s_stage[tid >> 6][0], 0};
             int64_t my_dd = 0, my_ud = 0;
+            if (trb) tp = wall_clock64();
             // algorithmic bytes: clearing reads a list entry and writes the
             // old frontier word; push reads each frontier vertex's row and
             // frontier word and folds it into its visited word, then per
@@ -549,40 +614,34 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                     for (int j = 0; j < NW; j++) Fo[(int64_t)u * NW + j] = 0;
                 }
             }
+            PHASE(0);
             if (!bu) {
-                // push, light frontier vertices: one per lane; the owner
-                // folds F_D into the visited word
-                for (int64_t base = gwave * 64; base < fl_len; base += nwaves * 64) {
-                    int64_t i = base + lane;
-                    int32_t e = 0, end = 0;
-                    Mask<NW> f;
-#pragma unroll
-                    for (int j = 0; j < NW; j++) f.w[j] = 0;
-                    if (i < fl_len) {
+                if (fl_len <= nwaves) {
+                    // small frontier: one wave per light vertex, one out-arc
+                    // per lane (light vertices have at most 64)
+                    for (int64_t i = gwave; i < fl_len; i += nwaves) {
                         const int32_t u = fl[i];
+                        Mask<NW> f;
                         bool done = true;
 #pragma unroll
                         for (int j = 0; j < NW; j++) {
                             const uint64_t fw = Fc[(int64_t)u * NW + j];
                             const uint64_t vn = vis[(int64_t)u * NW + j] | fw;
-                            vis[(int64_t)u * NW + j] = vn;
                             f.w[j] = fw & act.w[j];
                             done &= (act.w[j] & ~vn) == 0;
+                            if (lane == 0) vis[(int64_t)u * NW + j] = vn;
                         }
-                        e = rp[u];
-                        end = rp[u + 1];
-                        if (done) my_dd += end - e;
-                        if (!f.any()) end = e;
-                    }
-                    while (__any(e < end)) {
+                        const int32_t b = rp[u], e1 = rp[u + 1];
+                        if (lane == 0 && done) my_dd += e1 - b;
+                        if (!f.any()) continue;   // wave-uniform
+                        const int32_t e = b + lane;
                         bool isnew = false;
                         int32_t w = 0, dw = 0;
                         Mask<NW> fr;
 #pragma unroll
                         for (int j = 0; j < NW; j++) fr.w[j] = 0;
-                        if (e < end) {
+                        if (e < e1) {
                             w = ci[e];
-                            e++;
                             Mask<NW> nb;
 #pragma unroll
                             for (int j = 0; j < NW; j++)
@@ -597,7 +656,57 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                         if (isnew) my_ud += dw;
                         list_append(isnew, w, dw, nl, stg);
                     }
+                } else {
+                    // push, light frontier vertices: one per lane; the owner
+                    // folds F_D into the visited word
+                    for (int64_t base = gwave * 64; base < fl_len; base += nwaves * 64) {
+                        int64_t i = base + lane;
+                        int32_t e = 0, end = 0;
+                        Mask<NW> f;
+#pragma unroll
+                        for (int j = 0; j < NW; j++) f.w[j] = 0;
+                        if (i < fl_len) {
+                            const int32_t u = fl[i];
+                            bool done = true;
+#pragma unroll
+                            for (int j = 0; j < NW; j++) {
+                                const uint64_t fw = Fc[(int64_t)u * NW + j];
+                                const uint64_t vn = vis[(int64_t)u * NW + j] | fw;
+                                vis[(int64_t)u * NW + j] = vn;
+                                f.w[j] = fw & act.w[j];
+                                done &= (act.w[j] & ~vn) == 0;
+                            }
+                            e = rp[u];
+                            end = rp[u + 1];
+                            if (done) my_dd += end - e;
+                            if (!f.any()) end = e;
+                        }
+                        while (__any(e < end)) {
+                            bool isnew = false;
+                            int32_t w = 0, dw = 0;
+                            Mask<NW> fr;
+#pragma unroll
+                            for (int j = 0; j < NW; j++) fr.w[j] = 0;
+                            if (e < end) {
+                                w = ci[e];
+                                e++;
+                                Mask<NW> nb;
+#pragma unroll
+                                for (int j = 0; j < NW; j++)
+                                    nb.w[j] = f.w[j] & ~(vis[(int64_t)w * NW + j] | Fc[(int64_t)w * NW + j]);
+                                if (nb.any()) {
+                                    isnew = discover<NW>(Fn, a.mark, w, nb, stamp, &fr);
+                                    if (isnew || fr.any()) dw = deg[w];
+                                    if (rec_lvl && fr.any()) record_levels<NW>(fr, w, a.w.lvl, W, D + 1);
+                                }
+                            }
+                            tally<NW>(fr, dw, s_red_cnt, s_red_deg);
+                            if (isnew) my_ud += dw;
+                            list_append(isnew, w, dw, nl, stg);
+                        }
+                    }
                 }
+                PHASE(2);
                 // heavy frontier vertices: the owner folds; their arcs go
                 // through the chunk list
                 for (int64_t i = gtid; i < fh_len; i += nthreads) {
@@ -611,6 +720,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                     }
                     if (done) my_dd += deg[u];
                 }
+                PHASE(1);
                 // push, heavy frontier vertices: one wave per chunk of arcs
                 for (int64_t c = gwave; c < fc_len; c += nwaves) {
                     const int32_t u = fcu[c];
@@ -662,20 +772,33 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                     }
                     if (done) my_dd += deg[u];
                 }
+                PHASE(1);
                 for (int64_t base = gwave * 64; base < n; base += nwaves * 64) {
                     const int32_t w = (int32_t)(base + lane);
                     bool isnew = false;
                     int32_t dw = 0;
-                    Mask<NW> acc;
+                    Mask<NW> acc, miss;
+                    int32_t eb = 0, len = 0;
 #pragma unroll
-                    for (int j = 0; j < NW; j++) acc.w[j] = 0;
+                    for (int j = 0; j < NW; j++) { acc.w[j] = 0; miss.w[j] = 0; }
                     if (w < n) {
-                        Mask<NW> miss;
 #pragma unroll
                         for (int j = 0; j < NW; j++)
                             miss.w[j] = act.w[j] & ~(vis[(int64_t)w * NW + j] | Fc[(int64_t)w * NW + j]);
-                        const int32_t eb = a.g.rrp[w], ee = a.g.rrp[w + 1];
-                        if (ee - eb <= HEAVY_DEG && miss.any()) {
+                        eb = a.g.rrp[w];
+                        const int32_t d_in = a.g.rrp[w + 1] - eb;
+                        if (d_in <= HEAVY_DEG && miss.any()) len = d_in;
+                    }
+                    int32_t* c_pre = &s_cpre[tid >> 6][0];
+                    int32_t* c_beg = &s_cbeg[tid >> 6][0];
+                    uint64_t* c_miss = &s_cmiss[tid >> 6][0];
+                    uint64_t* c_acc = &s_cacc[tid >> 6][0];
+                    if (wave_max_i32(len) > 8) {
+                        // skewed in-degrees: the wave's lanes share the arcs
+                        pull_shared<NW>(eb, len, miss, Fc, a.g.rci, c_pre, c_beg, c_miss, c_acc, &acc, &my_scan);
+                    } else if (len > 0) {
+                        {
+                            const int32_t ee = eb + len;
                             for (int32_t e = eb; e < ee; e += 4) {
                                 my_scan += (ee - e < 4 ? ee - e : 4);
                                 int32_t u[4];
@@ -693,23 +816,58 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                                 }
                                 if (full) break;
                             }
-                            if (acc.any()) {
-                                // a light vertex has one pulling thread: plain stores
-#pragma unroll
-                                for (int j = 0; j < NW; j++) Fn[(int64_t)w * NW + j] = acc.w[j];
-                                isnew = true;
-                                dw = deg[w];
-                                if (rec_lvl) record_levels<NW>(acc, w, a.w.lvl, W, D + 1);
-                            }
                         }
+                    }
+                    if (acc.any()) {
+                        // a light vertex has one pulling thread: plain stores
+#pragma unroll
+                        for (int j = 0; j < NW; j++) Fn[(int64_t)w * NW + j] = acc.w[j];
+                        isnew = true;
+                        dw = deg[w];
+                        if (rec_lvl) record_levels<NW>(acc, w, a.w.lvl, W, D + 1);
                     }
                     tally<NW>(acc, dw, s_red_cnt, s_red_deg);
                     if (isnew) my_ud += dw;
                     list_append(isnew, w, dw, nl, stg);
                 }
-                // pull, heavy vertices: one wave per chunk of their in-arcs
-                for (int64_t c = gwave; c < a.g.rnchunks; c += nwaves) {
-                    const int32_t w = a.g.rch_vtx[c];
+                PHASE(2);
+                // pull, mid in-degree vertices: packed segments of about
+                // MID_ARCS in-arcs, one wave each, edge-balanced
+                for (int64_t sg = gwave; sg < a.g.nmseg; sg += nwaves) {
+                    const int32_t v0 = a.g.mseg[sg], v1 = a.g.mseg[sg + 1];
+                    const int32_t idx = v0 + lane;
+                    int32_t w = 0, eb = 0, len = 0;
+                    Mask<NW> miss, acc;
+#pragma unroll
+                    for (int j = 0; j < NW; j++) { miss.w[j] = 0; acc.w[j] = 0; }
+                    if (idx < v1) {
+                        w = a.g.mid_vtx[idx];
+#pragma unroll
+                        for (int j = 0; j < NW; j++)
+                            miss.w[j] = act.w[j] & ~(vis[(int64_t)w * NW + j] | Fc[(int64_t)w * NW + j]);
+                        eb = a.g.rrp[w];
+                        if (miss.any()) len = a.g.rrp[w + 1] - eb;
+                    }
+                    if (wave_max_i32(len) > 0)
+                        pull_shared<NW>(eb, len, miss, Fc, a.g.rci, &s_cpre[tid >> 6][0], &s_cbeg[tid >> 6][0],
+                                        &s_cmiss[tid >> 6][0], &s_cacc[tid >> 6][0], &acc, &my_scan);
+                    bool isnew = false;
+                    int32_t dw = 0;
+                    if (acc.any()) {
+                        // a mid vertex lies in one segment: one pulling wave, plain stores
+#pragma unroll
+                        for (int j = 0; j < NW; j++) Fn[(int64_t)w * NW + j] = acc.w[j];
+                        isnew = true;
+                        dw = deg[w];
+                        if (rec_lvl) record_levels<NW>(acc, w, a.w.lvl, W, D + 1);
+                    }
+                    tally<NW>(acc, dw, s_red_cnt, s_red_deg);
+                    if (isnew) my_ud += dw;
+                    list_append(isnew, w, dw, nl, stg);
+                }
+                // pull, hubs: one wave per chunk of their in-arcs
+                for (int64_t c = gwave; c < a.g.bnchunks; c += nwaves) {
+                    const int32_t w = a.g.bch_vtx[c];
                     Mask<NW> miss, acc;
 #pragma unroll
                     for (int j = 0; j < NW; j++) {
@@ -717,7 +875,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                         acc.w[j] = 0;
                     }
                     if (!miss.any()) continue;   // wave-uniform
-                    const int32_t eb = a.g.rch_beg[c], ee = a.g.rch_end[c];
+                    const int32_t eb = a.g.bch_beg[c], ee = a.g.bch_end[c];
                     for (int32_t e0 = eb; e0 < ee; e0 += 64) {
                         const int32_t e = e0 + lane;
                         my_scan += e < ee ? 1 : 0;
@@ -749,6 +907,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                     list_append(isnew, w, dw, nl, stg);
                 }
             }
+            PHASE(3);
             stage_flush(stg, nl.light, nl.tails);
             // workgroup totals into this level's counters
             my_dd = wave_sum_i64(my_dd);
@@ -766,8 +925,22 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 if (s_blk[0]) fadd_rlx(&ctr[C_UDEG(p)], s_blk[0]);
                 if (s_blk[1]) fadd_rlx(&ctr[C_DDONE(p)], s_blk[1]);
             }
+            PHASE(4);
             grid_barrier(a.bar, gridDim.x);
+            PHASE(5);
             if (boss && tslot >= 0) a.w.trace[8 + 16 * tslot + 8] = (int64_t)wall_clock64();
+            if (trb) {
+                if (lane == 0)
+                    for (int i = 0; i < 6; i++) s_ph[tid >> 6][i] = ph[i];
+                __syncthreads();
+                if (tid == 0 && tslot >= 0)
+                    for (int i = 0; i < 6; i++) {
+                        int64_t mx = 0;
+                        for (int wv = 0; wv < BB / 64; wv++) mx = s_ph[wv][i] > mx ? s_ph[wv][i] : mx;
+                        a.w.trace[8 + 16 * tslot + 9 + i] = mx;
+                    }
+                for (int i = 0; i < 6; i++) ph[i] = 0;
+            }
             // --------------------------------------------- advance lane state
             if (tid < MAXW) {
                 int l = tid;
@@ -931,12 +1104,13 @@ int tkc_launch_batch(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv
     if (hipGetDevice(&dev) != hipSuccess) return -1;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return -1;
-    const void* fn = NW == 1 ? (const void*)k_batch<1> : (NW == 2 ? (const void*)k_batch<2> : (const void*)k_batch<4>);
+    const bool tr = w.trace != nullptr;
+    const void* fn = NW == 1 ? (tr ? (const void*)k_batch<1, true> : (const void*)k_batch<1, false>)
+                   : NW == 2 ? (tr ? (const void*)k_batch<2, true> : (const void*)k_batch<2, false>)
+                             : (tr ? (const void*)k_batch<4, true> : (const void*)k_batch<4, false>);
     int occ = 0;
     hipError_t e;
-    if (NW == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch<1>, BB, 0);
-    else if (NW == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch<2>, BB, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch<4>, BB, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, BB, 0);
     if (e != hipSuccess || occ < 1) return -1;
     const int want = tune.blocks_per_cu > 0 ? tune.blocks_per_cu : 2;
     int per = occ < want ? occ : want;
