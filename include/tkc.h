@@ -168,8 +168,8 @@ int tkc_topk_closeness(tkc_graph *g, int32_t k, int32_t variant, int32_t mode,
                        int32_t *n_out, tkc_stats *stats);
 
 /* Autotuner: times the query (k, variant) on g under candidate knob
- * settings, one knob at a time (batch width, mode, workgroups per CU, batch
- * alpha), keeping each improvement, until the settings are exhausted or the
+ * settings, one knob at a time (batch width, mode, workgroups per CU, the
+ * pull threshold beta, batch alpha), keeping each improvement, until the settings are exhausted or the
  * measured time passes budget_ms (at least the context's own settings run).
  * Every trial's ids must agree (TKC_EDEVICE otherwise: an internal error).
  * The fastest setting is stored on the graph, where TKC_MODE_AUTO queries

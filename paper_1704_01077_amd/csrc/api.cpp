@@ -689,6 +689,7 @@ extern "C" int tkc_autotune(tkc_graph* g, int32_t k, int32_t variant, double bud
         {&EngineTuning::batch_width, {64, 128, 256, 32}},
         {&EngineTuning::mode, lb ? std::vector<int32_t>{TKC_BATCHED} : std::vector<int32_t>{TKC_BATCHED, TKC_HYBRID}},
         {&EngineTuning::blocks_per_cu, {1, 2, 3, 4}},
+        {&EngineTuning::bu_td_beta, {24, 4, 1}},
         {&EngineTuning::batch_alpha, {4, 14, 40}},
     };
     for (const Axis& ax : axes) {

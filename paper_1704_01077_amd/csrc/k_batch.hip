@@ -30,6 +30,7 @@
 
 #define BB 256
 #define MAXW 256
+#define PUSH_SUB 4   // work items per heavy-vertex chunk in a push
 
 // ctr layout (int64)
 #define C_CNT(p, l) ((p) * 2 * MAXW + (l))
@@ -721,15 +722,18 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                     if (done) my_dd += deg[u];
                 }
                 PHASE(1);
-                // push, heavy frontier vertices: one wave per chunk of arcs
-                for (int64_t c = gwave; c < fc_len; c += nwaves) {
+                // push, heavy frontier vertices: one wave per quarter chunk
+                // (a few hubs then still spread over many waves)
+                for (int64_t cq = gwave; cq < fc_len * PUSH_SUB; cq += nwaves) {
+                    const int64_t c = cq / PUSH_SUB;
                     const int32_t u = fcu[c];
                     Mask<NW> f;
 #pragma unroll
                     for (int j = 0; j < NW; j++) f.w[j] = Fc[(int64_t)u * NW + j] & act.w[j];
                     if (!f.any()) continue;   // wave-uniform
-                    const int32_t b = fcb[c];
-                    const int32_t end = b + CHUNK_ARCS < rp[u + 1] ? b + CHUNK_ARCS : rp[u + 1];
+                    const int32_t b = fcb[c] + (int32_t)(cq % PUSH_SUB) * (CHUNK_ARCS / PUSH_SUB);
+                    const int32_t lim = b + CHUNK_ARCS / PUSH_SUB;
+                    const int32_t end = lim < rp[u + 1] ? lim : rp[u + 1];
                     for (int32_t e0 = b; e0 < end; e0 += 64) {
                         const int32_t e = e0 + lane;
                         bool isnew = false;
