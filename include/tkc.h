@@ -74,6 +74,10 @@ extern "C" {
 #define TKC_DIRECTED 1u     /* arcs are directed; reverse CSR required    */
 #define TKC_VALIDATE 2u     /* check CSR shape, ids, loops, repeats, symmetry */
 #define TKC_DEVICE_PTRS 4u  /* input arrays are device pointers           */
+#define TKC_REVERSE 8u      /* in-closeness: distances run along in-arcs,
+                               i.e. out-closeness of the reversed graph
+                               (the reversed-graph case study, Sect. 10);
+                               no effect on undirected graphs              */
 
 typedef struct tkc_ctx tkc_ctx;
 typedef struct tkc_graph tkc_graph;
@@ -177,6 +181,18 @@ int tkc_topk_closeness(tkc_graph *g, int32_t k, int32_t variant, int32_t mode,
  * NULL).  The context's own settings are left as they were. */
 int tkc_autotune(tkc_graph *g, int32_t k, int32_t variant, double budget_ms, tkc_tuning *best,
                  double *best_ms);
+
+/* Top-k with every tie (the output of Alg. 1 as stated: all vertices whose
+ * farness equals the k-th one are returned, possibly more than k).  Results
+ * are the min(k, n) of tkc_topk_closeness followed by the vertices tied
+ * with the k-th, by increasing id.  cap is the capacity of the output
+ * arrays (>= min(k, n)); if the answer has more entries, TKC_EINVAL is
+ * returned with *n_out set to the number needed and nothing else written.
+ * Ties are found by cutting only searches whose bound is strictly above the
+ * k-th farness (ids no longer break ties), so they cost more work. */
+int tkc_topk_closeness_ties(tkc_graph *g, int32_t k, int32_t variant, int32_t mode, int32_t cap,
+                            int32_t *ids, int64_t *sum_dist, int64_t *reach, double *farness,
+                            int32_t *n_out, tkc_stats *stats);
 
 /* ---- inspection of the individual steps (host output arrays of n items) */
 /* Reachability (Sect. 4 and Sect. 8.4, Alg. 6): undirected graphs get

@@ -81,6 +81,8 @@ static size_t ws_items(Workspace& ws, const WsShape& sh, std::vector<WsItem>& it
         {(void**)&ws.tstate, 4096, false}, {(void**)&ws.ring, sizeof(XRec) * TKC_XRING, false},
         {(void**)&ws.tS, 8 * (size_t)sh.kcap, false}, {(void**)&ws.tR, 8 * (size_t)sh.kcap, false},
         {(void**)&ws.tI, 4 * (size_t)sh.kcap, false},
+        {(void**)&ws.tieS, sh.ties ? 8 * n : 8, false}, {(void**)&ws.tieR, sh.ties ? 8 * n : 8, false},
+        {(void**)&ws.tieI, sh.ties ? 4 * n : 4, false},
         {(void**)&ws.stats, 8 * 4 * ST_COUNT, false},
         {(void**)&ws.bar, 4 * tkc_bar_words(4096), true},
         // plain engine
@@ -284,6 +286,11 @@ extern "C" int tkc_graph_upload(tkc_ctx* c, int32_t n, int64_t m, const int32_t*
     if (n < 1) return tkc_fail(TKC_EINVAL, "n must be >= 1");
     if (m < 0 || m > 0x7fffffffLL) return tkc_fail(TKC_EINVAL, "m_arcs must be in [0, 2^31)");
     const bool directed = (flags & TKC_DIRECTED) != 0;
+    if (directed && (flags & TKC_REVERSE)) {
+        // in-closeness: the reversed graph's out-arcs are the in-arcs
+        std::swap(row_ptr, rrow_ptr);
+        std::swap(col_idx, rcol_idx);
+    }
     if (directed && (!rrow_ptr || (!rcol_idx && m > 0)))
         return tkc_fail(TKC_EINVAL, "directed graph needs the reverse CSR");
     if (!directed && (rrow_ptr || rcol_idx))
@@ -637,6 +644,19 @@ extern "C" int tkc_topk_closeness(tkc_graph* g, int32_t k, int32_t variant, int3
     return tkc_run_query(c, g, k, variant, mode, ids, sum_dist, reach, farness, n_out, stats);
 }
 
+extern "C" int tkc_topk_closeness_ties(tkc_graph* g, int32_t k, int32_t variant, int32_t mode, int32_t cap,
+                                       int32_t* ids, int64_t* sum_dist, int64_t* reach, double* farness,
+                                       int32_t* n_out, tkc_stats* stats) {
+    if (!g || !ids || !n_out) return tkc_fail(TKC_EINVAL, "NULL argument");
+    if (k < 1) return tkc_fail(TKC_EINVAL, "k must be >= 1");
+    if (variant < TKC_AUTO || variant > TKC_NB_BOUND) return tkc_fail(TKC_EINVAL, "unknown variant %d", variant);
+    if (mode < TKC_PLAIN || mode > TKC_MODE_AUTO) return tkc_fail(TKC_EINVAL, "unknown mode %d", mode);
+    if (cap < std::min(k, g->n)) return tkc_fail(TKC_EINVAL, "cap must be >= min(k, n)");
+    tkc_ctx* c = g->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    return tkc_run_query(c, g, k, variant, mode, ids, sum_dist, reach, farness, n_out, stats, cap);
+}
+
 // Runs one query under knobs t (on the graph's context, whose own knobs are
 // restored afterwards) and returns its wall time.
 static int autotune_trial(tkc_graph* g, int32_t k, int32_t variant, const EngineTuning& t,
@@ -717,7 +737,9 @@ extern "C" int tkc_autotune(tkc_graph* g, int32_t k, int32_t variant, double bud
 }
 
 int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t mode, int32_t* ids,
-                  int64_t* sum_dist, int64_t* reach, double* farness, int32_t* n_out, tkc_stats* stats) {
+                  int64_t* sum_dist, int64_t* reach, double* farness, int32_t* n_out, tkc_stats* stats,
+                  int32_t ties_cap) {
+    const bool ties = ties_cap > 0;
     Workspace& ws = c->ws;
     hipStream_t s = c->stream;
     const int32_t n = g->n;
@@ -731,7 +753,7 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
     if (mode == TKC_MODE_AUTO) {
         const EngineTuning keep = c->tune;
         c->tune = tkc_effective_tuning(keep, g);
-        rc = tkc_run_query(c, g, k, variant, c->tune.mode, ids, sum_dist, reach, farness, n_out, stats);
+        rc = tkc_run_query(c, g, k, variant, c->tune.mode, ids, sum_dist, reach, farness, n_out, stats, ties_cap);
         c->tune = keep;
         return rc;
     }
@@ -739,7 +761,11 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
     if (variant == TKC_AUTO) variant = tkc_auto_variant(c, g);
     const bool lb = (variant == TKC_DEG_BOUND || variant == TKC_NB_BOUND);
     const bool nb = (variant == TKC_NB_CUT || variant == TKC_NB_BOUND);
-    rc = tkc_ws_reserve(c, ws, tkc_shape_for(c->tune, g, k, lb));
+    {
+        WsShape sh = tkc_shape_for(c->tune, g, k, lb);
+        sh.ties = ties;
+        rc = tkc_ws_reserve(c, ws, sh);
+    }
     if (rc) return rc;
     int32_t rounds = 0;
     double t1;
@@ -758,7 +784,8 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
         }
     }
     DevTopk tk = topk_view(ws);
-    if (tkc_launch_topk_init(tk, k, s)) return tkc_fail(TKC_EDEVICE, "top-k init failed");
+    const TieBuf tb{ws.tieS, ws.tieR, ws.tieI, n};
+    if (tkc_launch_topk_init(tk, k, s, ties ? &tb : nullptr)) return tkc_fail(TKC_EDEVICE, "top-k init failed");
     HIPCHK(hipMemsetAsync(ws.stats, 0, 8 * 4 * ST_COUNT, s));
     HIPCHK(hipMemsetAsync(ws.p_vis, 0, 4 * (((size_t)n + 31) / 32), s));
     HIPCHK(hipStreamSynchronize(s));
@@ -875,6 +902,43 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
     int32_t cnt = std::min(hst.cnt, k);
     if (cnt != k)
         return tkc_fail(TKC_EDEVICE, "internal error: %d results for k = %d", cnt, k);
+    if (ties) {
+        // entries that left or were refused by the top k and tie with the
+        // final k-th farness, by increasing id (all of them have ids above
+        // the k-th's: a tied smaller id would precede it)
+        if (hst.tcnt > n) return tkc_fail(TKC_EDEVICE, "internal error: tie buffer overflow");
+        const int32_t tc = hst.tcnt;
+        std::vector<int64_t> tS(tc), tR(tc);
+        std::vector<int32_t> tI(tc);
+        if (tc) {
+            HIPCHK(hipMemcpyAsync(tS.data(), ws.tieS, 8 * (size_t)tc, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(tR.data(), ws.tieR, 8 * (size_t)tc, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(tI.data(), ws.tieI, 4 * (size_t)tc, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        const int64_t Sk = hS[k - 1], Rk = hR[k - 1];
+        auto same_farness = [&](int64_t S2, int64_t R2) {
+            if (R2 <= 1 || Rk <= 1) return R2 <= 1 && Rk <= 1;
+            const unsigned __int128 a = (unsigned __int128)S2 * (unsigned __int128)((Rk - 1) * (Rk - 1));
+            const unsigned __int128 b = (unsigned __int128)Sk * (unsigned __int128)((R2 - 1) * (R2 - 1));
+            return a == b;
+        };
+        std::vector<int32_t> extra;
+        for (int32_t i = 0; i < tc; i++)
+            if (same_farness(tS[i], tR[i])) extra.push_back(i);
+        std::sort(extra.begin(), extra.end(), [&](int32_t a, int32_t b) { return tI[a] < tI[b]; });
+        const int32_t total = k + (int32_t)extra.size();
+        if (total > ties_cap) {
+            *n_out = total;
+            return tkc_fail(TKC_EINVAL, "%d results (with ties) do not fit cap %d", total, ties_cap);
+        }
+        for (int32_t i : extra) {
+            hS.push_back(tS[i]);
+            hR.push_back(tR[i]);
+            hI.push_back(tI[i]);
+        }
+        cnt = total;
+    }
     for (int32_t i = 0; i < cnt; i++) {
         ids[i] = hI[i];
         if (sum_dist) sum_dist[i] = hS[i];

@@ -175,8 +175,14 @@ struct TopkState {
     int32_t cnt;
     int64_t seq;      // number of published records - 1
     int32_t k;
-    int32_t pad;
+    int32_t ties;     // all-ties mode: x is published with id +inf
     int64_t n_inserts;
+    // all-ties mode: every entry pushed out of the top k or rejected there
+    int32_t tcnt;
+    int32_t tcap;
+    int64_t* tieS;
+    int64_t* tieR;
+    int32_t* tieI;
 };
 struct XVal {
     int64_t num;      // S
@@ -201,8 +207,20 @@ TKC_DEV XVal read_x(TopkState* st, const XRec* ring) {
     }
 }
 
+TKC_DEV void tie_keep(TopkState* st, int64_t S, int64_t r, int32_t id) {
+    const int32_t t = ld_rlx(&st->tcnt);
+    if (t < st->tcap) {
+        st_rlx(&st->tieS[t], S);
+        st_rlx(&st->tieR[t], r);
+        st_rlx(&st->tieI[t], id);
+    }
+    st_rlx(&st->tcnt, t + 1);
+}
 // Insert an exact result; the caller is one thread.  topk arrays hold the
-// min(k, inserted) best (S, r, id) in exact order.  Spins on st->lock.
+// min(k, inserted) best (S, r, id) in exact order.  Spins on st->lock.  In
+// all-ties mode every entry that leaves the top k, or is refused by it, is
+// kept for the final tie filter, and x carries id +inf, which turns every
+// lexicographic cut, skip and stop test into a strict "farness above x".
 TKC_DEV void topk_insert(TopkState* st, XRec* ring, int64_t* tS, int64_t* tR, int32_t* tI,
                          int64_t S, int64_t r, int32_t id) {
     while (__hip_atomic_exchange(&st->lock, 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0)
@@ -218,6 +236,10 @@ TKC_DEV void topk_insert(TopkState* st, XRec* ring, int64_t* tS, int64_t* tR, in
         if (lex_after(ld_rlx(&tS[p - 1]), pd, ld_rlx(&tI[p - 1]), S, den, id)) p--;
         else break;
     }
+    if (st->ties) {
+        if (p >= k) tie_keep(st, S, r, id);
+        else if (cnt == k) tie_keep(st, ld_rlx(&tS[k - 1]), ld_rlx(&tR[k - 1]), ld_rlx(&tI[k - 1]));
+    }
     if (p < k) {
         int32_t last = cnt < k ? cnt : k - 1;
         for (int32_t q = last; q > p; q--) {
@@ -232,7 +254,7 @@ TKC_DEV void topk_insert(TopkState* st, XRec* ring, int64_t* tS, int64_t* tR, in
             XRec* rc = ring + (s % TKC_XRING);
             st_rlx(&rc->S, ld_rlx(&tS[k - 1]));
             st_rlx(&rc->r, ld_rlx(&tR[k - 1]));
-            st_rlx(&rc->id, (int64_t)ld_rlx(&tI[k - 1]));
+            st_rlx(&rc->id, st->ties ? (int64_t)0x7fffffff : (int64_t)ld_rlx(&tI[k - 1]));
             st_rel(&st->seq, s);
         }
     }

@@ -116,7 +116,14 @@ int tkc_sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* tmp_keys, int32_t* t
                    hipStream_t s);
 
 // k_topk.hip
-int tkc_launch_topk_init(DevTopk t, int32_t k, hipStream_t s);
+// all-ties mode: buffers for the entries that leave or are refused by the top k
+struct TieBuf {
+    int64_t* S;
+    int64_t* R;
+    int32_t* I;
+    int32_t cap;
+};
+int tkc_launch_topk_init(DevTopk t, int32_t k, hipStream_t s, const TieBuf* tb = nullptr);
 
 // k_plain.hip: one source at a time on the whole GPU (cooperative kernel).
 struct PlainWork {

@@ -12,9 +12,10 @@
 struct WsShape {
     int32_t n = 0, W = 64, nw = 1, kcap = 1, lcap = 0, qcap = 0, swarm_blocks = 0, nchunks = 0;
     bool lb = false;
+    bool ties = false;   // all-ties buffers
     bool covers(const WsShape& o) const {
         return n >= o.n && nw >= o.nw && W >= o.W && kcap >= o.kcap && lcap >= o.lcap && qcap >= o.qcap &&
-               swarm_blocks >= o.swarm_blocks && nchunks >= o.nchunks && (lb || !o.lb);
+               swarm_blocks >= o.swarm_blocks && nchunks >= o.nchunks && (lb || !o.lb) && (ties || !o.ties);
     }
 };
 
@@ -40,6 +41,8 @@ struct Workspace {
     void* ring;
     int64_t *tS, *tR;
     int32_t* tI;
+    int64_t *tieS, *tieR;
+    int32_t* tieI;
     int64_t* stats;
     uint32_t* bar;
     // plain engine
@@ -116,8 +119,10 @@ struct tkc_graph {
 
 int tkc_fail(int code, const char* fmt, ...);
 int tkc_ws_reserve(tkc_ctx* ctx, Workspace& ws, const WsShape& sh);
+// ties_cap > 0: all-ties mode, output arrays of ties_cap entries
 int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t mode, int32_t* ids,
-                  int64_t* sum_dist, int64_t* reach, double* farness, int32_t* n_out, tkc_stats* stats);
+                  int64_t* sum_dist, int64_t* reach, double* farness, int32_t* n_out, tkc_stats* stats,
+                  int32_t ties_cap = 0);
 int tkc_sums_impl(tkc_ctx* c, tkc_graph* g, const int32_t* sources, int32_t count, int64_t* S, int64_t* R,
                   tkc_stats* st);
 int32_t tkc_auto_variant(tkc_ctx* c, tkc_graph* g);

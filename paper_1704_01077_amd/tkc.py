@@ -26,7 +26,7 @@ TKC_ECANCELED = -6
 
 TKC_AUTO, TKC_DEG_CUT, TKC_NB_CUT, TKC_DEG_BOUND, TKC_NB_BOUND = 0, 1, 2, 3, 4
 TKC_PLAIN, TKC_BATCHED, TKC_HYBRID, TKC_MODE_AUTO = 0, 1, 2, 3
-TKC_DIRECTED, TKC_VALIDATE, TKC_DEVICE_PTRS = 1, 2, 4
+TKC_DIRECTED, TKC_VALIDATE, TKC_DEVICE_PTRS, TKC_REVERSE = 1, 2, 4, 8
 
 VARIANTS = {"auto": TKC_AUTO, "degcut": TKC_DEG_CUT, "nbcut": TKC_NB_CUT,
             "degbound": TKC_DEG_BOUND, "nbbound": TKC_NB_BOUND}
@@ -34,7 +34,7 @@ MODES = {"plain": TKC_PLAIN, "batched": TKC_BATCHED, "hybrid": TKC_HYBRID, "auto
 
 EXPORTS = [
     "tkc_ctx_create", "tkc_ctx_destroy", "tkc_ctx_get_tuning", "tkc_ctx_set_tuning", "tkc_graph_upload",
-    "tkc_graph_free", "tkc_topk_closeness", "tkc_autotune", "tkc_graph_reach", "tkc_graph_bounds", "tkc_graph_lb_update",
+    "tkc_graph_free", "tkc_topk_closeness", "tkc_topk_closeness_ties", "tkc_autotune", "tkc_graph_reach", "tkc_graph_bounds", "tkc_graph_lb_update",
     "tkc_graph_sums", "tkc_server_create", "tkc_server_add_graph", "tkc_server_submit",
     "tkc_server_poll", "tkc_server_result", "tkc_server_cancel", "tkc_server_destroy",
     "tkc_last_error", "tkc_version",
@@ -87,6 +87,7 @@ def _load():
         "tkc_graph_upload": [vp, i32, i64, vp, vp, vp, vp, u32, P(vp)],
         "tkc_graph_free": [vp],
         "tkc_topk_closeness": [vp, i32, i32, i32, vp, vp, vp, vp, P(i32), P(tkc_stats)],
+        "tkc_topk_closeness_ties": [vp, i32, i32, i32, i32, vp, vp, vp, vp, P(i32), P(tkc_stats)],
         "tkc_graph_reach": [vp, vp, vp, vp],
         "tkc_graph_bounds": [vp, i32, vp, vp, vp],
         "tkc_graph_lb_update": [vp, vp, i32, vp, vp],
@@ -186,6 +187,18 @@ def tkc_topk_closeness(g, k, variant, mode, ids, sum_dist=None, reach=None, farn
     return n_out.value, st
 
 
+def tkc_topk_closeness_ties(g, k, variant, mode, cap, ids, sum_dist=None, reach=None, farness=None):
+    """Returns (rc, n_out, stats): rc is TKC_EINVAL with n_out = the needed
+    capacity when the answer does not fit cap; other errors raise."""
+    n_out = ctypes.c_int32(0)
+    st = tkc_stats()
+    rc = lib.tkc_topk_closeness_ties(g, k, variant, mode, cap, _ptr(ids), _ptr(sum_dist), _ptr(reach),
+                                     _ptr(farness), ctypes.byref(n_out), ctypes.byref(st))
+    if rc != TKC_OK and not (rc == TKC_EINVAL and n_out.value > cap):
+        _check(rc)
+    return rc, n_out.value, st
+
+
 def tkc_graph_reach(g, alpha, omega, scc=None):
     _check(lib.tkc_graph_reach(g, _ptr(alpha), _ptr(omega), _ptr(scc)))
 
@@ -278,12 +291,14 @@ class Graph:
     """A graph resident on the device (CSR copied at construction)."""
 
     def __init__(self, ctx: Context, n, row_ptr, col_idx, rrow_ptr=None, rcol_idx=None,
-                 validate=False, device_ptrs=False):
+                 validate=False, device_ptrs=False, reverse=False):
         row_ptr = _as_i32(row_ptr)
         col_idx = _as_i32(col_idx)
         flags = (TKC_DIRECTED if rrow_ptr is not None else 0) | (TKC_VALIDATE if validate else 0)
         if device_ptrs:
             flags |= TKC_DEVICE_PTRS
+        if reverse:
+            flags |= TKC_REVERSE
         if rrow_ptr is not None:
             rrow_ptr, rcol_idx = _as_i32(rrow_ptr), _as_i32(rcol_idx)
         self.n = int(n)
@@ -293,8 +308,8 @@ class Graph:
         self.h = tkc_graph_upload(ctx.h, self.n, self.m, row_ptr, col_idx, rrow_ptr, rcol_idx, flags)
 
     @classmethod
-    def from_graphgen(cls, ctx, g, validate=False):
-        return cls(ctx, g.n, g.row_ptr, g.col_idx, g.rrow_ptr, g.rcol_idx, validate=validate)
+    def from_graphgen(cls, ctx, g, validate=False, reverse=False):
+        return cls(ctx, g.n, g.row_ptr, g.col_idx, g.rrow_ptr, g.rcol_idx, validate=validate, reverse=reverse)
 
     def free(self):
         if self.h:
@@ -386,3 +401,21 @@ def topk_closeness(g: Graph, k: int, variant="auto", mode="hybrid"):
     n_out, st = tkc_topk_closeness(g.h, int(k), VARIANTS.get(variant, variant), MODES.get(mode, mode),
                                    ids, S, R, F)
     return ids[:n_out], S[:n_out], R[:n_out], F[:n_out], st.as_dict()
+
+
+def topk_closeness_ties(g: Graph, k: int, variant="auto", mode="hybrid", cap=None):
+    """Top k with every vertex tied with the k-th: (ids, S, r, farness, stats).
+    Retries once with the capacity the library reports when cap is short."""
+    kk = min(int(k), g.n)
+    cap = max(kk, int(cap) if cap else kk + 64)
+    for _ in range(2):
+        ids = np.zeros(cap, np.int32)
+        S = np.zeros(cap, np.int64)
+        R = np.zeros(cap, np.int64)
+        F = np.zeros(cap, np.float64)
+        rc, n_out, st = tkc_topk_closeness_ties(g.h, int(k), VARIANTS.get(variant, variant), MODES.get(mode, mode),
+                                                cap, ids, S, R, F)
+        if rc == TKC_OK:
+            return ids[:n_out], S[:n_out], R[:n_out], F[:n_out], st.as_dict()
+        cap = n_out
+    raise TkcError(TKC_EINVAL, "tie output did not fit")
