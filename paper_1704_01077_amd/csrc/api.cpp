@@ -753,6 +753,7 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
     if (mode == TKC_MODE_AUTO) {
         const EngineTuning keep = c->tune;
         c->tune = tkc_effective_tuning(keep, g);
+        c->tune.slice_batches = keep.slice_batches;
         rc = tkc_run_query(c, g, k, variant, c->tune.mode, ids, sum_dist, reach, farness, n_out, stats, ties_cap);
         c->tune = keep;
         return rc;
@@ -810,11 +811,26 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
         tm.done();
     } else if (mode == TKC_BATCHED) {
         trace_reset(c);
-        EngineTimer tm(c, &ms_eng[1], &nl_eng[1]);
-        int e = tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_batch, nullptr, 0, 0, 0, lb, false,
-                                 nullptr, nullptr, c->tune, s, &grid);
-        if (e) return tkc_fail(TKC_EDEVICE, "batched engine launch failed: %s", hipGetErrorString(hipGetLastError()));
-        tm.done();
+        // one launch, or slices of slice_batches batches (the cursor, stop
+        // flag, top k and bounds live in device memory between them)
+        const int32_t slice = c->tune.slice_batches > 0 ? c->tune.slice_batches : 0;
+        int32_t pos = 0;
+        for (;;) {
+            {
+                EngineTimer tm(c, &ms_eng[1], &nl_eng[1]);
+                int e = tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_batch, nullptr, 0, pos, slice, lb,
+                                         false, nullptr, nullptr, c->tune, s, &grid);
+                if (e)
+                    return tkc_fail(TKC_EDEVICE, "batched engine launch failed: %s", hipGetErrorString(hipGetLastError()));
+                tm.done();
+            }
+            if (!slice) break;
+            int64_t hs[ST_COUNT];
+            rc = read_stats(c, st_batch, hs);
+            if (rc) return rc;
+            if (hs[ST_STOP] || hs[ST_CURSOR] >= n) break;
+            pos = (int32_t)hs[ST_CURSOR];
+        }
         trace_dump(c, "batched");
     } else {
         // hybrid: batched seed until x is known, then one search per workgroup,

@@ -92,7 +92,17 @@ struct EngineTuning {
     int32_t lanes_cap = 0;       // lanes used per batch in one launch (0: batch_width)
     int32_t blocks_per_cu = 2;   // workgroups per CU of the persistent kernels
     int32_t mode = 1;            // preferred mode (TKC_BATCHED) for TKC_MODE_AUTO
+    int32_t slice_batches = 0;   // batched searches per launch (0: all in one); servers
+                                 // slice long queries so other requests interleave
 };
+// workgroups of a persistent grid for a graph of n vertices: the whole GPU
+// for big graphs, fewer (cheaper grid barriers) for small ones
+static inline int tkc_grid_for(int cus, int per, int32_t n) {
+    int64_t want = ((int64_t)n + 2047) / 2048;
+    if (want < 64) want = 64;
+    const int64_t full = (int64_t)cus * per;
+    return (int)(want < full ? want : full);
+}
 
 // k_prep.hip
 int tkc_launch_degrees(const DevGraph& g, hipStream_t s);

@@ -1118,7 +1118,7 @@ int tkc_launch_batch(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv
     if (e != hipSuccess || occ < 1) return -1;
     const int want = tune.blocks_per_cu > 0 ? tune.blocks_per_cu : 2;
     int per = occ < want ? occ : want;
-    int grid = prop.multiProcessorCount * per;
+    const int grid = tkc_grid_for(prop.multiProcessorCount, per, g.n);
     if (grid_out) *grid_out = grid;
     BatchArgs a{};
     a.g = g; a.rc = rc; a.ov = ov; a.bv = bv; a.tk = tk; a.w = w;

@@ -153,6 +153,9 @@ extern "C" int tkc_server_create(tkc_ctx* ctx, size_t hbm_budget_bytes, int32_t 
             return rc;
         }
         c->tune = ctx->tune;
+        // long batched queries run a few batches per launch, so requests in
+        // other slots interleave instead of waiting for the whole query
+        c->tune.slice_batches = 2;
         s->slot_ctx.push_back(c);
         s->slot_bytes.push_back(0);
     }
