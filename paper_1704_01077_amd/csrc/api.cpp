@@ -473,6 +473,7 @@ extern "C" int tkc_graph_free(tkc_graph* g) {
     hipSetDevice(g->ctx->device);
     hipStreamSynchronize(g->ctx->stream);
     hipFree(g->dbase);
+    if (g->reach_base) hipFree(g->reach_base);
     for (auto& p : g->prep)
         if (p.base) hipFree(p.base);
     delete g;
@@ -514,12 +515,44 @@ int tkc_step_reach(tkc_ctx* c, tkc_graph* g, Workspace& ws) {
     }
     {
         std::lock_guard<std::mutex> lk(g->mu);
-        if (g->h_alpha.empty())
-            tkc_host_alpha_omega(g->n, g->h_rp.data(), g->h_ci.data(), g->h_alpha, g->h_omega, g->h_scc);
+        if (!g->reach_path) {
+            const size_t n = g->n;
+            if (!g->reach_base) {
+                HIPCHK(hipMalloc(&g->reach_base, 16 * n + 4 * n + 256));
+                g->d_alpha = (int64_t*)g->reach_base;
+                g->d_omega = g->d_alpha + n;
+                g->d_scc = (int32_t*)(g->d_omega + n);
+            }
+            const double t0 = now_ms();
+            const char* e = getenv("TKC_REACH");
+            int r = 1;
+            if (!(e && strcmp(e, "host") == 0))
+                r = tkc_device_alpha_omega(dg, g->d_alpha, g->d_omega, g->d_scc, c->pinned, s);
+            if (r < 0) return tkc_fail(TKC_EDEVICE, "reachability kernels failed");
+            if (r == 1) {
+                // a round budget ran out (long chains of components): Tarjan on the host
+                std::vector<int64_t> ha, ho;
+                std::vector<int32_t> hs;
+                tkc_host_alpha_omega(g->n, g->h_rp.data(), g->h_ci.data(), ha, ho, hs);
+                HIPCHK(hipMemcpyAsync(g->d_alpha, ha.data(), 8 * n, hipMemcpyHostToDevice, s));
+                HIPCHK(hipMemcpyAsync(g->d_omega, ho.data(), 8 * n, hipMemcpyHostToDevice, s));
+                HIPCHK(hipMemcpyAsync(g->d_scc, hs.data(), 4 * n, hipMemcpyHostToDevice, s));
+                HIPCHK(hipStreamSynchronize(s));
+            }
+            g->reach_ms = now_ms() - t0;
+            g->reach_path = r == 1 ? 2 : 1;
+        }
     }
-    HIPCHK(hipMemcpyAsync(ws.alpha, g->h_alpha.data(), 8 * (size_t)g->n, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(ws.omega, g->h_omega.data(), 8 * (size_t)g->n, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(ws.scc, g->h_scc.data(), 4 * (size_t)g->n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ws.alpha, g->d_alpha, 8 * (size_t)g->n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(ws.omega, g->d_omega, 8 * (size_t)g->n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(ws.scc, g->d_scc, 4 * (size_t)g->n, hipMemcpyDeviceToDevice, s));
+    return TKC_OK;
+}
+
+extern "C" int tkc_graph_reach_info(const tkc_graph* g, int32_t* path, double* ms) {
+    if (!g) return tkc_fail(TKC_EINVAL, "null graph");
+    if (path) *path = g->directed ? g->reach_path : 1;
+    if (ms) *ms = g->reach_ms;
     return TKC_OK;
 }
 

@@ -118,6 +118,12 @@ int tkc_launch_deg_bounds(const DevGraph& g, const int64_t* omega, int64_t* num,
 int tkc_launch_nb_keys(int32_t n, const int64_t* num, const int64_t* den, uint32_t* key,
                        int32_t* val, hipStream_t s);
 
+// k_scc.hip: alpha / omega / topological SCC ids of a directed graph.
+// 0 on success, 1 when a round budget ran out (the caller uses the host
+// path), -1 on a device error.  pinned: 256 bytes of pinned host memory.
+int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, int32_t* scc_topo, void* pinned,
+                           hipStream_t s);
+
 // k_sort.hip: stable ascending sort of (key, val) pairs; the result ends in
 // keys/vals.  tmp_* hold n items, hist holds sort_hist_words(n) int32.
 int64_t tkc_sort_hist_words(int32_t n);

@@ -1,0 +1,877 @@
+// Reachability bounds of a directed graph on the device (Sect. 8.4, Alg. 6):
+// strongly connected components, their DAG, and
+//   alpha(C) = w(C) + max over successors D of alpha(D)
+//   omega(C) = w(C) + sum over successors D of omega(D)
+// with the refinement through the largest component C~ (its reach is
+// counted exactly; a component that reaches C~ sums only the successors C~
+// does not reach, plus omega(C~) once), omega capped at n.  The values
+// depend only on the component partition and its DAG, so they equal the
+// host computation exactly.
+//
+// Components: (1) trimming -- a vertex with no remaining in-arcs or
+// out-arcs is a component of its own, repeated; (2) one forward/backward
+// search from a high-degree pivot (the giant component of complex
+// networks); (3) trimming again; (4) max-colour propagation (a vertex takes
+// the largest id that reaches it), then each colour root collects the
+// vertices of its colour that reach it -- repeated until every vertex has a
+// component.  Steps that would need more rounds than a fixed budget (long
+// chains) give up, and the caller falls back to the host.
+//
+// The DAG: every arc between components as a (source, target) pair, sorted
+// by two stable radix passes and deduplicated.  Heights (longest path to a
+// sink) order the dynamic programme, and components are numbered in
+// decreasing height, a topological order.
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "dev_common.hpp"
+#include "engine.hpp"
+
+#define SB 256
+#define SCAN_T 1024
+#define SCAN_I 4
+
+static inline int nblk(int64_t n, int per = SB) { return (int)((n + per - 1) / per); }
+// blocks for one wave per item, grid-strided beyond 16384 blocks
+static inline int wblk(int64_t items) {
+    const int64_t b = (items * 64 + SB - 1) / SB;
+    return (int)(b < 1 ? 1 : (b < 16384 ? b : 16384));
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(v, o, 64);
+        v = y > v ? y : v;
+    }
+    return v;
+}
+__device__ __forceinline__ int64_t wave_max_i64(int64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t y = __shfl_xor(v, o, 64);
+        v = y > v ? y : v;
+    }
+    return v;
+}
+
+// ------------------------------------------------------------------ scan
+// exclusive scan of n int32 in place (three passes)
+__global__ void __launch_bounds__(SCAN_T) k_scan_blocks(int32_t* a, int64_t n, int32_t* bsum) {
+    __shared__ int32_t ws[SCAN_T / 64];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_T * SCAN_I + (int64_t)threadIdx.x * SCAN_I;
+    int32_t v[SCAN_I], s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_I; j++) {
+        v[j] = base + j < n ? a[base + j] : 0;
+        s += v[j];
+    }
+    int32_t x = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int32_t y = __shfl_up(x, o, 64);
+        if (lane_id() >= o) x += y;
+    }
+    const int wv = threadIdx.x >> 6;
+    if (lane_id() == 63) ws[wv] = x;
+    __syncthreads();
+    int32_t pre = 0, tot = 0;
+    for (int w = 0; w < SCAN_T / 64; w++) {
+        if (w < wv) pre += ws[w];
+        tot += ws[w];
+    }
+    int32_t run = pre + x - s;
+#pragma unroll
+    for (int j = 0; j < SCAN_I; j++) {
+        if (base + j < n) a[base + j] = run;
+        run += v[j];
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+__global__ void __launch_bounds__(SCAN_T) k_scan_top(int32_t* b, int32_t nb, int32_t* total) {
+    __shared__ int32_t ws[SCAN_T / 64];
+    const int32_t per = (nb + SCAN_T - 1) / SCAN_T;
+    const int32_t lo = threadIdx.x * per;
+    const int32_t hi = lo + per < nb ? lo + per : nb;
+    int32_t s = 0;
+    for (int32_t i = lo; i < hi; i++) s += b[i];
+    int32_t x = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int32_t y = __shfl_up(x, o, 64);
+        if (lane_id() >= o) x += y;
+    }
+    const int wv = threadIdx.x >> 6;
+    if (lane_id() == 63) ws[wv] = x;
+    __syncthreads();
+    int32_t pre = 0, tot = 0;
+    for (int w = 0; w < SCAN_T / 64; w++) {
+        if (w < wv) pre += ws[w];
+        tot += ws[w];
+    }
+    int32_t run = pre + x - s;
+    for (int32_t i = lo; i < hi; i++) {
+        const int32_t t = b[i];
+        b[i] = run;
+        run += t;
+    }
+    if (threadIdx.x == 0) *total = tot;
+}
+__global__ void k_scan_add(int32_t* a, int64_t n, const int32_t* bsum) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] += bsum[i / (SCAN_T * SCAN_I)];
+}
+
+// ------------------------------------------------------ components: state
+__global__ void k_scc_init(int32_t n, const int32_t* rp, const int32_t* rrp, int32_t* scc, int32_t* in_rem,
+                           int32_t* out_rem, uint32_t* mark) {
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    scc[v] = -1;
+    in_rem[v] = rrp[v + 1] - rrp[v];
+    out_rem[v] = rp[v + 1] - rp[v];
+    mark[v] = 0;
+}
+
+// a vertex without remaining in-arcs or out-arcs is a component of its own
+__global__ void k_scc_trim(int32_t n, int32_t* scc, const int32_t* in_rem, const int32_t* out_rem, int32_t* list,
+                           int32_t* cnt) {
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool take = v < n && scc[v] < 0 && (in_rem[v] <= 0 || out_rem[v] <= 0);
+    const uint64_t m = __ballot(take);
+    if (!m) return;
+    int32_t b = 0;
+    const int leader = __ffsll((long long)__ballot(1)) - 1;
+    if (lane_id() == leader) b = atomicAdd(cnt, __popcll(m));
+    b = __shfl(b, leader, 64);
+    if (take) {
+        scc[v] = v;
+        const uint64_t below = lane_id() ? (~0ull >> (64 - lane_id())) : 0ull;
+        list[b + __popcll(m & below)] = v;
+    }
+}
+// removed vertices take their arcs away from their neighbours' counts
+__global__ void k_scc_trim_update(const int32_t* list, int32_t cnt, const int32_t* rp, const int32_t* ci,
+                                  const int32_t* rrp, const int32_t* rci, int32_t* in_rem, int32_t* out_rem) {
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    for (int64_t i = gw; i < cnt; i += nw) {
+        const int32_t v = list[i];
+        for (int32_t e = rp[v] + lane_id(); e < rp[v + 1]; e += 64) atomicSub(&in_rem[ci[e]], 1);
+        for (int32_t e = rrp[v] + lane_id(); e < rrp[v + 1]; e += 64) atomicSub(&out_rem[rci[e]], 1);
+    }
+}
+
+// pivot: the unassigned vertex with the largest (in+1)(out+1), smallest id on ties
+__global__ void k_scc_pivot(int32_t n, const int32_t* scc, const int32_t* in_rem, const int32_t* out_rem,
+                            unsigned long long* best) {
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long key = 0;
+    if (v < n && scc[v] < 0) {
+        uint64_t p = (uint64_t)(in_rem[v] + 1) * (uint64_t)(out_rem[v] + 1);
+        if (p > 0x7fffffffull) p = 0x7fffffffull;
+        key = ((unsigned long long)p << 32) | (0xffffffffull - (uint32_t)v);
+    }
+    key = wave_max_u64(key);
+    if (lane_id() == 0 && key) atomicMax(best, key);
+}
+
+// one level of a search over unassigned vertices (one wave per frontier
+// vertex); a vertex found first is given the next level number
+__global__ void k_scc_bfs(const int32_t* fr, int32_t fcnt, const int32_t* rp, const int32_t* ci, const int32_t* scc,
+                          uint32_t* mark, uint32_t bit, int32_t* lev, int32_t nl) {
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    for (int64_t i = gw; i < fcnt; i += nw) {
+        const int32_t u = fr[i];
+        for (int32_t e = rp[u] + lane_id(); e < rp[u + 1]; e += 64) {
+            const int32_t w = ci[e];
+            if (scc[w] < 0 && !(mark[w] & bit) && !(atomicOr(&mark[w], bit) & bit)) lev[w] = nl;
+        }
+    }
+}
+// the vertices of level nl, in id order: flags, then (after a scan) scatter
+__global__ void k_lev_flag(int32_t n, const int32_t* lev, int32_t nl, int32_t* flag) {
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) flag[v] = lev[v] == nl;
+}
+__global__ void k_lev_scatter(int32_t n, const int32_t* lev, int32_t nl, const int32_t* pos, int32_t* out) {
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n && lev[v] == nl) out[pos[v]] = v;
+}
+__global__ void k_scc_seed(int32_t* list, uint32_t* mark, int32_t* lev, int32_t pivot, uint32_t bit) {
+    if (threadIdx.x == 0) {
+        list[0] = pivot;
+        mark[pivot] |= bit;
+        lev[pivot] = 0;
+    }
+}
+__global__ void k_scc_assign_fb(int32_t n, int32_t* scc, uint32_t* mark, int32_t pivot) {
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    if (scc[v] < 0 && (mark[v] & 3u) == 3u) scc[v] = pivot;
+    mark[v] = 0;
+}
+
+// arcs between unassigned vertices only (one wave per vertex)
+__global__ void k_scc_recount(int32_t n, const int32_t* rp, const int32_t* ci, const int32_t* rrp, const int32_t* rci,
+                              const int32_t* scc, int32_t* in_rem, int32_t* out_rem) {
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    for (int64_t v = gw; v < n; v += nw) {
+        if (scc[v] >= 0) continue;
+        int32_t a = 0, b = 0;
+        for (int32_t e = rrp[v] + lane_id(); e < rrp[v + 1]; e += 64) a += scc[rci[e]] < 0;
+        for (int32_t e = rp[v] + lane_id(); e < rp[v + 1]; e += 64) b += scc[ci[e]] < 0;
+        a = wave_sum_i32(a);
+        b = wave_sum_i32(b);
+        if (lane_id() == 0) {
+            in_rem[v] = a;
+            out_rem[v] = b;
+        }
+    }
+}
+
+// colouring: every unassigned vertex takes the largest id that reaches it
+__global__ void k_col_init(int32_t n, const int32_t* scc, int32_t* color, int32_t* unassigned) {
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool un = v < n && scc[v] < 0;
+    if (v < n) color[v] = un ? v : -1;
+    const uint64_t m = __ballot(un);
+    if (m && lane_id() == __ffsll((long long)__ballot(1)) - 1) atomicAdd(unassigned, __popcll(m));
+}
+__global__ void k_col_prop(int32_t n, const int32_t* rrp, const int32_t* rci, const int32_t* scc, int32_t* color,
+                           int32_t* changed) {
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n || scc[v] >= 0) return;
+    int32_t c = color[v];
+    const int32_t c0 = c;
+    for (int32_t e = rrp[v]; e < rrp[v + 1]; e++) {
+        const int32_t cu = __hip_atomic_load(&color[rci[e]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cu > c) c = cu;
+    }
+    if (c > c0) {
+        atomicMax(&color[v], c);
+        *changed = 1;
+    }
+}
+// roots collect the vertices of their colour that reach them
+__global__ void k_col_close_init(int32_t n, const int32_t* scc, const int32_t* color, uint32_t* mark) {
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) mark[v] = (scc[v] < 0 && color[v] == v) ? 1u : 0u;
+}
+__global__ void k_col_close(int32_t n, const int32_t* rp, const int32_t* ci, const int32_t* scc,
+                            const int32_t* color, uint32_t* mark, int32_t* changed) {
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n || scc[v] >= 0 || mark[v]) return;
+    const int32_t c = color[v];
+    for (int32_t e = rp[v]; e < rp[v + 1]; e++) {
+        const int32_t w = ci[e];
+        if (color[w] == c && __hip_atomic_load(&mark[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            mark[v] = 1u;
+            *changed = 1;
+            return;
+        }
+    }
+}
+__global__ void k_col_assign(int32_t n, int32_t* scc, const int32_t* color, uint32_t* mark) {
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    if (scc[v] < 0 && mark[v]) scc[v] = color[v];
+    mark[v] = 0;
+}
+
+// ------------------------------------------------------- dense component ids
+__global__ void k_rep_flag(int32_t n, const int32_t* scc, int32_t* cid) {
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) cid[v] = scc[v] == v ? 1 : 0;
+}
+__global__ void k_comp_of(int32_t n, const int32_t* scc, const int32_t* cid, int32_t* comp) {
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) comp[v] = cid[scc[v]];
+}
+__global__ void k_comp_stats(int32_t n, const int32_t* comp, int32_t pivot, int32_t* wt, int32_t* minid) {
+    // the pivot's component holds most vertices: one atomic per wave for it
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t hot = pivot >= 0 ? comp[pivot] : -1;
+    const bool in = v < n;
+    const int32_t c = in ? comp[v] : -1;
+    const bool h = in && c == hot;
+    const uint64_t m = __ballot(h);
+    if (m) {
+        const int32_t mn = -wave_max_i32(h ? -v : INT32_MIN);
+        if (lane_id() == __ffsll((long long)m) - 1) {
+            atomicAdd(&wt[hot], __popcll(m));
+            atomicMin(&minid[hot], mn);
+        }
+    }
+    if (in && !h) {
+        atomicAdd(&wt[c], 1);
+        atomicMin(&minid[c], v);
+    }
+}
+// the largest component, ties to the one holding the smallest vertex id
+__global__ void k_comp_big(int32_t nc, const int32_t* wt, const int32_t* minid, unsigned long long* best) {
+    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long key = 0;
+    if (c < nc) key = ((unsigned long long)(uint32_t)wt[c] << 32) | (0xffffffffull - (uint32_t)minid[c]);
+    key = wave_max_u64(key);
+    if (lane_id() == 0 && key) atomicMax(best, key);
+}
+
+__global__ void k_set_big(const int32_t* comp, int32_t bmin, int32_t* tob, int32_t* frb, int32_t* out) {
+    if (threadIdx.x == 0) {
+        const int32_t c = comp[bmin];
+        tob[c] = 1;
+        frb[c] = 1;
+        *out = c;
+    }
+}
+
+// --------------------------------------------------------------- the DAG
+__global__ void k_dag_count(int32_t n, const int32_t* rp, const int32_t* ci, const int32_t* comp, int32_t* cnt) {
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    for (int64_t u = gw; u < n; u += nw) {
+        const int32_t cu = comp[u];
+        int32_t c = 0;
+        for (int32_t e = rp[u] + lane_id(); e < rp[u + 1]; e += 64) c += comp[ci[e]] != cu;
+        c = wave_sum_i32(c);
+        if (lane_id() == 0) cnt[u] = c;
+    }
+}
+__global__ void k_dag_pairs(int32_t n, const int32_t* rp, const int32_t* ci, const int32_t* comp, const int32_t* off,
+                            uint32_t* key, int32_t* val) {
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const uint64_t below = lane_id() ? (~0ull >> (64 - lane_id())) : 0ull;
+    for (int64_t u = gw; u < n; u += nw) {
+        const int32_t cu = comp[u];
+        int32_t o = off[u];
+        for (int32_t e0 = rp[u]; e0 < rp[u + 1]; e0 += 64) {
+            const int32_t e = e0 + lane_id();
+            int32_t cw = cu;
+            if (e < rp[u + 1]) cw = comp[ci[e]];
+            const bool x = cw != cu;
+            const uint64_t m = __ballot(x);
+            if (x) {
+                const int32_t p = o + __popcll(m & below);
+                key[p] = (uint32_t)cw;   // first pass: by target
+                val[p] = cu;
+            }
+            o += __popcll(m);
+        }
+    }
+}
+// after the second pass (by source, stable): key = source, val = target
+__global__ void k_dag_uniq(int64_t E, const uint32_t* src, const int32_t* dst, int32_t* flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < E) flag[i] = (i == 0 || src[i] != src[i - 1] || dst[i] != dst[i - 1]) ? 1 : 0;
+}
+__global__ void k_dag_compact(int64_t E, const uint32_t* src, const int32_t* dst, const int32_t* pos,
+                              const int32_t* flag, int32_t* asrc, int32_t* adst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < E && flag[i]) {
+        asrc[pos[i]] = (int32_t)src[i];
+        adst[pos[i]] = dst[i];
+    }
+}
+
+// inclusive scan within runs of equal keys (runs are contiguous lanes)
+template <typename T, typename Op>
+__device__ __forceinline__ T seg_scan(T v, int32_t key, Op op) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const T y = __shfl_up(v, o, 64);
+        const int32_t yk = __shfl_up(key, o, 64);
+        if (lane_id() >= o && yk == key) v = op(v, y);
+    }
+    return v;
+}
+// the last lane of its run of equal keys within the wave (a shuffle: call
+// it from every lane, outside divergent branches)
+__device__ __forceinline__ bool seg_tail(int32_t key) {
+    const int32_t nk = __shfl_down(key, 1, 64);
+    return lane_id() == 63 || nk != key;
+}
+
+// one relaxation round over the DAG arcs (sorted by source): heights
+// (longest path to a sink), "reaches C~" and "reached from C~"
+__global__ void k_dag_relax(int32_t U, const int32_t* asrc, const int32_t* adst, int32_t* hgt, int32_t* tob,
+                            int32_t* frb, int32_t* changed) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool ok = j < U;
+    const int32_t c = ok ? asrc[j] : -1;
+    const int32_t d = ok ? adst[j] : 0;
+    int32_t h = 0, t = 0;
+    bool ch = false;
+    if (ok) {
+        h = __hip_atomic_load(&hgt[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+        t = __hip_atomic_load(&tob[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__hip_atomic_load(&frb[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &&
+            !__hip_atomic_load(&frb[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            __hip_atomic_store(&frb[d], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ch = true;
+        }
+    }
+    h = seg_scan(h, c, [](int32_t x, int32_t y) { return x > y ? x : y; });
+    t = seg_scan(t, c, [](int32_t x, int32_t y) { return x | y; });
+    const bool tail = seg_tail(c);   // every lane takes part in the shuffle
+    if (ok && tail) {
+        if (h > __hip_atomic_load(&hgt[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            atomicMax(&hgt[c], h);
+            ch = true;
+        }
+        if (t && !__hip_atomic_load(&tob[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            __hip_atomic_store(&tob[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ch = true;
+        }
+    }
+    if (__ballot(ch) && lane_id() == 0) *changed = 1;
+}
+// |reach of C~| and the largest height (one atomic per wave each)
+__global__ void k_dag_reach_big(int32_t nc, const int32_t* wt, const int32_t* frb, const int32_t* hgt,
+                                unsigned long long* rb, int32_t* hmax) {
+    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool ok = c < nc;
+    const int64_t w = ok && frb[c] ? wt[c] : 0;
+    const int32_t h = ok ? hgt[c] : 0;
+    const int64_t ws = wave_sum_i64(w);
+    const int32_t hm = wave_max_i32(h);
+    if (lane_id() == 0) {
+        if (ws) atomicAdd(rb, (unsigned long long)ws);
+        atomicMax(hmax, hm);
+    }
+}
+// sort keys: components and arcs by decreasing height (of the source)
+__global__ void k_comp_hkey(int32_t nc, const int32_t* hgt, int32_t hmax, uint32_t* key, int32_t* val) {
+    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    key[c] = (uint32_t)(hmax - hgt[c]);
+    val[c] = c;
+}
+__global__ void k_arc_hkey(int32_t U, const int32_t* asrc, const int32_t* hgt, int32_t hmax, uint32_t* key,
+                           int32_t* val) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= U) return;
+    key[j] = (uint32_t)(hmax - hgt[asrc[j]]);
+    val[j] = j;
+}
+// first position of every key in a sorted key array (-1 where absent)
+__global__ void k_bucket_starts(int32_t cnt, const uint32_t* key, int32_t* start) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt && (i == 0 || key[i] != key[i - 1])) start[key[i]] = i;
+}
+__global__ void k_topo_of(int32_t nc, const int32_t* byh, int32_t* topo) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nc) topo[byh[i]] = i;
+}
+__global__ void k_arc_gather(int32_t U, const int32_t* idx, const int32_t* asrc, const int32_t* adst, int32_t* hsrc,
+                             int32_t* hdst) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= U) return;
+    hsrc[i] = asrc[idx[i]];
+    hdst[i] = adst[idx[i]];
+}
+// Alg. 6 for one height: the successors' contributions (arcs [lo, hi),
+// sorted by source), one atomic per run of a source within a wave ...
+__global__ void k_dp_arcs(int32_t lo, int32_t hi, const int32_t* hsrc, const int32_t* hdst, const int64_t* ca,
+                          const int64_t* co, const int32_t* frb, unsigned long long* accA, unsigned long long* accO,
+                          unsigned long long* accO2) {
+    const int32_t j = lo + blockIdx.x * blockDim.x + threadIdx.x;
+    const bool ok = j < hi;
+    const int32_t c = ok ? hsrc[j] : -1;
+    int64_t a = 0, o = 0, o2 = 0;
+    if (ok) {
+        const int32_t d = hdst[j];
+        a = ca[d];
+        o = co[d];
+        o2 = frb[d] ? 0 : o;
+    }
+    a = seg_scan(a, c, [](int64_t x, int64_t y) { return x > y ? x : y; });
+    o = seg_scan(o, c, [](int64_t x, int64_t y) { return x + y; });
+    o2 = seg_scan(o2, c, [](int64_t x, int64_t y) { return x + y; });
+    const bool tail = seg_tail(c);   // every lane takes part in the shuffle
+    if (ok && tail) {
+        atomicMax(&accA[c], (unsigned long long)a);
+        atomicAdd(&accO[c], (unsigned long long)o);
+        atomicAdd(&accO2[c], (unsigned long long)o2);
+    }
+}
+// ... then the components of that height (byh[lo, hi))
+__global__ void k_dp_fin(int32_t lo, int32_t hi, const int32_t* byh, int32_t big, int64_t n, const int32_t* wt,
+                         const int32_t* tob, const unsigned long long* rb, const unsigned long long* accA,
+                         const unsigned long long* accO, const unsigned long long* accO2, int64_t* ca, int64_t* co) {
+    const int32_t i = lo + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= hi) return;
+    const int32_t c = byh[i];
+    if (c == big) {
+        ca[c] = co[c] = (int64_t)*rb;
+        return;
+    }
+    int64_t o = tob[c] ? (int64_t)accO2[c] + (int64_t)*rb : (int64_t)accO[c];
+    o += wt[c];
+    ca[c] = (int64_t)accA[c] + wt[c];
+    co[c] = o > n ? n : o;
+}
+__global__ void k_scc_out(int32_t n, const int32_t* comp, const int64_t* ca, const int64_t* co, const int32_t* topo,
+                          int64_t* alpha, int64_t* omega, int32_t* scc_topo) {
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int32_t c = comp[v];
+    alpha[v] = ca[c];
+    omega[v] = co[c];
+    scc_topo[v] = topo[c];
+}
+
+// ------------------------------------------------------------------ host
+namespace {
+
+struct Scratch {
+    void* base = nullptr;
+    char* p = nullptr;
+    template <typename T>
+    T* take(int64_t count) {
+        T* r = (T*)p;
+        p += ((int64_t)sizeof(T) * (count > 0 ? count : 1) + 255) / 256 * 256;
+        return r;
+    }
+};
+
+int scan(int32_t* a, int64_t n, int32_t* bsum, int32_t* total_dev, hipStream_t s) {
+    const int64_t per = SCAN_T * SCAN_I;
+    const int nb = (int)((n + per - 1) / per);
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(SCAN_T), 0, s, a, n, bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_T), 0, s, bsum, nb, total_dev);
+    hipLaunchKernelGGL(k_scan_add, dim3(nblk(n)), dim3(SB), 0, s, a, n, bsum);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+double wall_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int32_t read_i32(const int32_t* dev, int32_t* pin, hipStream_t s) {
+    if (hipMemcpyAsync(pin, dev, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
+    if (hipStreamSynchronize(s) != hipSuccess) return -1;
+    return *pin;
+}
+
+}  // namespace
+
+// Returns 0 on success, 1 when a round budget ran out (use the host), -1 on
+// a device error.  pinned: at least 256 bytes of pinned host memory.
+int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, int32_t* scc_topo, void* pinned,
+                           hipStream_t s) {
+    const int32_t n = g.n;
+    const int64_t m = g.m;
+    if (n <= 0) return 0;
+    const int gb = nblk(n);
+    const int64_t mx = m > n ? m : n;
+    const int64_t words_scan = mx / (SCAN_T * SCAN_I) + 2;
+    const int64_t hist_words = tkc_sort_hist_words((int32_t)mx);
+    Scratch sc;
+    // scratch: vertex arrays, component arrays, arc arrays, scan and sort
+    // state; the same sequence of takes sizes it (base null) and lays it out
+    int32_t* scc = nullptr;
+    int32_t* in_rem = nullptr;
+    int32_t* out_rem = nullptr;
+    uint32_t* mark = nullptr;
+    int32_t* color = nullptr;
+    int32_t* list = nullptr;
+    int32_t* next = nullptr;
+    int32_t* cid = nullptr;
+    int32_t* comp = nullptr;
+    int32_t* cnt = nullptr;
+    int32_t* wt = nullptr;
+    int32_t* minid = nullptr;
+    int32_t* hgt = nullptr;
+    int32_t* tob = nullptr;
+    int32_t* frb = nullptr;
+    int32_t* topo = nullptr;
+    int32_t* cstart = nullptr;
+    int32_t* astart = nullptr;
+    int64_t* ca = nullptr;
+    int64_t* co = nullptr;
+    unsigned long long *accA = nullptr, *accO = nullptr, *accO2 = nullptr;
+    uint32_t* key = nullptr;
+    int32_t* val = nullptr;
+    uint32_t* tkey = nullptr;
+    int32_t* tval = nullptr;
+    int32_t* flag = nullptr;
+    int32_t* pos = nullptr;
+    int32_t* asrc = nullptr;
+    int32_t* adst = nullptr;
+    int32_t* hsrc = nullptr;
+    int32_t* hdst = nullptr;
+    int32_t* bsum = nullptr;
+    int32_t* hist = nullptr;
+    int32_t* small = nullptr;
+    auto layout = [&](char* base) -> size_t {
+        sc.p = base;
+        scc = sc.take<int32_t>(n);
+        in_rem = sc.take<int32_t>(n);
+        out_rem = sc.take<int32_t>(n);
+        mark = sc.take<uint32_t>(n);
+        color = sc.take<int32_t>(n);
+        list = sc.take<int32_t>(n);
+        next = sc.take<int32_t>(n);
+        cid = sc.take<int32_t>(n);
+        comp = sc.take<int32_t>(n);
+        cnt = sc.take<int32_t>(n);
+        wt = sc.take<int32_t>(n);
+        minid = sc.take<int32_t>(n);
+        hgt = sc.take<int32_t>(n);
+        tob = sc.take<int32_t>(n);
+        frb = sc.take<int32_t>(n);
+        topo = sc.take<int32_t>(n);
+        cstart = sc.take<int32_t>((int64_t)n + 2);
+        astart = sc.take<int32_t>((int64_t)n + 2);
+        ca = sc.take<int64_t>(n);
+        co = sc.take<int64_t>(n);
+        accA = sc.take<unsigned long long>(n);
+        accO = sc.take<unsigned long long>(n);
+        accO2 = sc.take<unsigned long long>(n);
+        key = sc.take<uint32_t>(m);
+        val = sc.take<int32_t>(m);
+        tkey = sc.take<uint32_t>(m);
+        tval = sc.take<int32_t>(m);
+        flag = sc.take<int32_t>(m);
+        pos = sc.take<int32_t>(m);
+        asrc = sc.take<int32_t>(m);
+        adst = sc.take<int32_t>(m);
+        hsrc = sc.take<int32_t>(m);
+        hdst = sc.take<int32_t>(m);
+        bsum = sc.take<int32_t>(words_scan);
+        hist = sc.take<int32_t>(hist_words);
+        small = sc.take<int32_t>(256);
+        return (size_t)(sc.p - base);
+    };
+    const size_t bytes = layout(nullptr);
+    if (hipMalloc(&sc.base, bytes) != hipSuccess) {
+        hipGetLastError();
+        return -1;
+    }
+    layout((char*)sc.base);
+    unsigned long long* big_key = (unsigned long long*)(small + 64);
+    unsigned long long* rb = (unsigned long long*)(small + 66);
+    uint32_t* smask = (uint32_t*)(small + 70);
+    int32_t* pin = (int32_t*)pinned;
+    uint32_t* pin_mask = (uint32_t*)pinned + 16;
+    int rc = 0;
+    int32_t pivot = -1;
+    auto fail = [&](int code) { rc = code; return code; };
+    // TKC_REACH_TRACE: phase times and round counts on stderr
+    const bool tr = getenv("TKC_REACH_TRACE") != nullptr;
+    double tph = wall_ms();
+    auto phase = [&](const char* what, int64_t a, int64_t b) {
+        if (!tr) return;
+        hipStreamSynchronize(s);
+        const double t = wall_ms();
+        fprintf(stderr, "reach %-10s %9.3f ms  %lld %lld\n", what, t - tph, (long long)a, (long long)b);
+        tph = t;
+    };
+#define DEV_OK(x) \
+    if ((x) != hipSuccess) { fail(-1); goto done; }
+#define STEP_OK(x) \
+    if ((x) != 0) { fail(-1); goto done; }
+    {
+        const int RBUDGET = 4096;   // launch rounds of all the iterative steps together
+        int rounds = 0;
+        hipLaunchKernelGGL(k_scc_init, dim3(gb), dim3(SB), 0, s, n, g.rp, g.rrp, scc, in_rem, out_rem, mark);
+        auto trim = [&](int max_rounds) -> int {
+            for (int r = 0; r < max_rounds; r++) {
+                if (hipMemsetAsync(small, 0, 4, s) != hipSuccess) return -1;
+                hipLaunchKernelGGL(k_scc_trim, dim3(gb), dim3(SB), 0, s, n, scc, in_rem, out_rem, list, small);
+                const int32_t c = read_i32(small, pin, s);
+                if (c < 0) return -1;
+                if (c == 0) break;
+                hipLaunchKernelGGL(k_scc_trim_update, dim3(wblk(c)), dim3(SB), 0, s, list, c, g.rp, g.ci, g.rrp,
+                                   g.rci, in_rem, out_rem);
+            }
+            return hipGetLastError() == hipSuccess ? 0 : -1;
+        };
+        STEP_OK(trim(32));
+        phase("trim", rounds, 0);
+        // ---- forward / backward search from the pivot
+        DEV_OK(hipMemsetAsync(big_key, 0, 8, s));
+        hipLaunchKernelGGL(k_scc_pivot, dim3(gb), dim3(SB), 0, s, n, scc, in_rem, out_rem, big_key);
+        DEV_OK(hipMemcpyAsync(pin, big_key, 8, hipMemcpyDeviceToHost, s));
+        DEV_OK(hipStreamSynchronize(s));
+        if (*(unsigned long long*)pin != 0) {
+            pivot = (int32_t)(0xffffffffull - (*(unsigned long long*)pin & 0xffffffffull));
+            int32_t* lev = color;   // free until the colouring
+            for (int dir = 0; dir < 2; dir++) {
+                const uint32_t bit = dir == 0 ? 1u : 2u;
+                const int32_t* arp = dir == 0 ? g.rp : g.rrp;
+                const int32_t* aci = dir == 0 ? g.ci : g.rci;
+                DEV_OK(hipMemsetAsync(lev, 0xff, 4 * (size_t)n, s));
+                hipLaunchKernelGGL(k_scc_seed, dim3(1), dim3(64), 0, s, list, mark, lev, pivot, bit);
+                int32_t fcnt = 1;
+                for (int32_t nl = 1; fcnt > 0; nl++) {
+                    if (++rounds > RBUDGET) { fail(1); goto done; }
+                    hipLaunchKernelGGL(k_scc_bfs, dim3(wblk(fcnt)), dim3(SB), 0, s, list, fcnt, arp, aci, scc, mark,
+                                       bit, lev, nl);
+                    hipLaunchKernelGGL(k_lev_flag, dim3(gb), dim3(SB), 0, s, n, lev, nl, cid);
+                    STEP_OK(scan(cid, n, bsum, small, s));
+                    hipLaunchKernelGGL(k_lev_scatter, dim3(gb), dim3(SB), 0, s, n, lev, nl, cid, list);
+                    fcnt = read_i32(small, pin, s);
+                    if (fcnt < 0) { fail(-1); goto done; }
+                }
+            }
+            phase("fw-bw", rounds, pivot);
+            hipLaunchKernelGGL(k_scc_assign_fb, dim3(gb), dim3(SB), 0, s, n, scc, mark, pivot);
+            hipLaunchKernelGGL(k_scc_recount, dim3(wblk(n)), dim3(SB), 0, s, n, g.rp, g.ci, g.rrp, g.rci, scc, in_rem,
+                               out_rem);
+        }
+        STEP_OK(trim(32));
+        phase("trim2", rounds, 0);
+        // ---- colouring until every vertex has a component
+        for (int it = 0;; it++) {
+            DEV_OK(hipMemsetAsync(small + 1, 0, 4, s));
+            hipLaunchKernelGGL(k_col_init, dim3(gb), dim3(SB), 0, s, n, scc, color, small + 1);
+            const int32_t un = read_i32(small + 1, pin, s);
+            if (un < 0) { fail(-1); goto done; }
+            phase("col-init", it, un);
+            if (un == 0) break;
+            if (it >= 64) { fail(1); goto done; }
+            for (;;) {
+                if (++rounds > RBUDGET) { fail(1); goto done; }
+                DEV_OK(hipMemsetAsync(small + 2, 0, 4, s));
+                hipLaunchKernelGGL(k_col_prop, dim3(gb), dim3(SB), 0, s, n, g.rrp, g.rci, scc, color, small + 2);
+                const int32_t ch = read_i32(small + 2, pin, s);
+                if (ch < 0) { fail(-1); goto done; }
+                if (!ch) break;
+            }
+            phase("col-prop", rounds, 0);
+            hipLaunchKernelGGL(k_col_close_init, dim3(gb), dim3(SB), 0, s, n, scc, color, mark);
+            for (;;) {
+                if (++rounds > RBUDGET) { fail(1); goto done; }
+                DEV_OK(hipMemsetAsync(small + 2, 0, 4, s));
+                hipLaunchKernelGGL(k_col_close, dim3(gb), dim3(SB), 0, s, n, g.rp, g.ci, scc, color, mark, small + 2);
+                const int32_t ch = read_i32(small + 2, pin, s);
+                if (ch < 0) { fail(-1); goto done; }
+                if (!ch) break;
+            }
+            phase("col-close", rounds, 0);
+            hipLaunchKernelGGL(k_col_assign, dim3(gb), dim3(SB), 0, s, n, scc, color, mark);
+            hipLaunchKernelGGL(k_scc_recount, dim3(wblk(n)), dim3(SB), 0, s, n, g.rp, g.ci, g.rrp, g.rci, scc, in_rem,
+                               out_rem);
+            STEP_OK(trim(32));
+        }
+        // ---- dense component ids, sizes, the largest component
+        hipLaunchKernelGGL(k_rep_flag, dim3(gb), dim3(SB), 0, s, n, scc, cid);
+        STEP_OK(scan(cid, n, bsum, small + 3, s));
+        const int32_t nc = read_i32(small + 3, pin, s);
+        if (nc <= 0) { fail(-1); goto done; }
+        hipLaunchKernelGGL(k_comp_of, dim3(gb), dim3(SB), 0, s, n, scc, cid, comp);
+        DEV_OK(hipMemsetAsync(wt, 0, 4 * (size_t)nc, s));
+        DEV_OK(hipMemsetAsync(minid, 0x7f, 4 * (size_t)nc, s));
+        hipLaunchKernelGGL(k_comp_stats, dim3(gb), dim3(SB), 0, s, n, comp, pivot, wt, minid);
+        DEV_OK(hipMemsetAsync(big_key, 0, 8, s));
+        hipLaunchKernelGGL(k_comp_big, dim3(nblk(nc)), dim3(SB), 0, s, nc, wt, minid, big_key);
+        phase("ids", nc, 0);
+        // ---- DAG arcs, sorted by (source, target) and deduplicated
+        hipLaunchKernelGGL(k_dag_count, dim3(wblk(n)), dim3(SB), 0, s, n, g.rp, g.ci, comp, cnt);
+        STEP_OK(scan(cnt, n, bsum, small + 4, s));
+        const int32_t E = read_i32(small + 4, pin, s);
+        if (E < 0) { fail(-1); goto done; }
+        int32_t U = 0;
+        if (E > 0) {
+            hipLaunchKernelGGL(k_dag_pairs, dim3(wblk(n)), dim3(SB), 0, s, n, g.rp, g.ci, comp, cnt, key, val);
+            // by target, then (stable) by source
+            STEP_OK(tkc_sort_pairs(key, val, tkey, tval, E, hist, smask, pin_mask, s));
+            DEV_OK(hipMemcpyAsync(tkey, val, 4 * (size_t)E, hipMemcpyDeviceToDevice, s));
+            DEV_OK(hipMemcpyAsync(tval, key, 4 * (size_t)E, hipMemcpyDeviceToDevice, s));
+            STEP_OK(tkc_sort_pairs(tkey, tval, key, val, E, hist, smask, pin_mask, s));
+            hipLaunchKernelGGL(k_dag_uniq, dim3(nblk(E)), dim3(SB), 0, s, (int64_t)E, tkey, tval, flag);
+            DEV_OK(hipMemcpyAsync(pos, flag, 4 * (size_t)E, hipMemcpyDeviceToDevice, s));
+            STEP_OK(scan(pos, E, bsum, small + 5, s));
+            U = read_i32(small + 5, pin, s);
+            if (U < 0) { fail(-1); goto done; }
+            hipLaunchKernelGGL(k_dag_compact, dim3(nblk(E)), dim3(SB), 0, s, (int64_t)E, tkey, tval, pos, flag, asrc,
+                               adst);
+        }
+        phase("dag", E, U);
+        // ---- heights, "reaches C~", "reached from C~"
+        DEV_OK(hipMemcpyAsync(pin, big_key, 8, hipMemcpyDeviceToHost, s));
+        DEV_OK(hipStreamSynchronize(s));
+        const uint32_t bmin = 0xffffffffu - (uint32_t)(*(unsigned long long*)pin & 0xffffffffull);
+        DEV_OK(hipMemsetAsync(hgt, 0, 4 * (size_t)nc, s));
+        DEV_OK(hipMemsetAsync(tob, 0, 4 * (size_t)nc, s));
+        DEV_OK(hipMemsetAsync(frb, 0, 4 * (size_t)nc, s));
+        // the largest component is the one holding vertex bmin
+        hipLaunchKernelGGL(k_set_big, dim3(1), dim3(64), 0, s, comp, (int32_t)bmin, tob, frb, small + 9);
+        const int32_t big = read_i32(small + 9, pin, s);
+        if (big < 0) { fail(-1); goto done; }
+        while (U > 0) {
+            if (++rounds > RBUDGET) { fail(1); goto done; }
+            DEV_OK(hipMemsetAsync(small + 2, 0, 4, s));
+            hipLaunchKernelGGL(k_dag_relax, dim3(nblk(U)), dim3(SB), 0, s, U, asrc, adst, hgt, tob, frb, small + 2);
+            const int32_t ch = read_i32(small + 2, pin, s);
+            if (ch < 0) { fail(-1); goto done; }
+            if (!ch) break;
+        }
+        DEV_OK(hipMemsetAsync(rb, 0, 8, s));
+        DEV_OK(hipMemsetAsync(small + 7, 0, 4, s));
+        hipLaunchKernelGGL(k_dag_reach_big, dim3(nblk(nc)), dim3(SB), 0, s, nc, wt, frb, hgt, rb, small + 7);
+        const int32_t hmax = read_i32(small + 7, pin, s);
+        if (hmax < 0) { fail(-1); goto done; }
+        if (hmax > RBUDGET) { fail(1); goto done; }
+        phase("heights", rounds, hmax);
+        // ---- components and arcs grouped by decreasing height (of the
+        // source): a topological numbering, and the sweep order of Alg. 6
+        {
+            uint32_t* ck = (uint32_t*)in_rem;   // vertex arrays free from here on
+            int32_t* byh = out_rem;
+            hipLaunchKernelGGL(k_comp_hkey, dim3(nblk(nc)), dim3(SB), 0, s, nc, hgt, hmax, ck, byh);
+            STEP_OK(tkc_sort_pairs(ck, byh, (uint32_t*)list, next, nc, hist, smask, pin_mask, s));
+            hipLaunchKernelGGL(k_topo_of, dim3(nblk(nc)), dim3(SB), 0, s, nc, byh, topo);
+            DEV_OK(hipMemsetAsync(cstart, 0xff, 4 * ((size_t)hmax + 2), s));
+            DEV_OK(hipMemsetAsync(astart, 0xff, 4 * ((size_t)hmax + 2), s));
+            hipLaunchKernelGGL(k_bucket_starts, dim3(nblk(nc)), dim3(SB), 0, s, nc, ck, cstart);
+            if (U > 0) {
+                hipLaunchKernelGGL(k_arc_hkey, dim3(nblk(U)), dim3(SB), 0, s, U, asrc, hgt, hmax, tkey, tval);
+                STEP_OK(tkc_sort_pairs(tkey, tval, key, val, U, hist, smask, pin_mask, s));
+                hipLaunchKernelGGL(k_arc_gather, dim3(nblk(U)), dim3(SB), 0, s, U, tval, asrc, adst, hsrc, hdst);
+                hipLaunchKernelGGL(k_bucket_starts, dim3(nblk(U)), dim3(SB), 0, s, U, tkey, astart);
+            }
+            std::vector<int32_t> cb((size_t)hmax + 2), ab((size_t)hmax + 2);
+            DEV_OK(hipMemcpyAsync(cb.data(), cstart, 4 * cb.size(), hipMemcpyDeviceToHost, s));
+            DEV_OK(hipMemcpyAsync(ab.data(), astart, 4 * ab.size(), hipMemcpyDeviceToHost, s));
+            DEV_OK(hipStreamSynchronize(s));
+            cb[hmax + 1] = nc;
+            ab[hmax + 1] = U;
+            for (int32_t b = hmax; b >= 0; b--) {
+                if (cb[b] < 0) cb[b] = cb[b + 1];
+                if (ab[b] < 0) ab[b] = ab[b + 1];
+            }
+            DEV_OK(hipMemsetAsync(accA, 0, 8 * (size_t)nc, s));
+            DEV_OK(hipMemsetAsync(accO, 0, 8 * (size_t)nc, s));
+            DEV_OK(hipMemsetAsync(accO2, 0, 8 * (size_t)nc, s));
+            // sinks first: height h is bucket hmax - h
+            for (int32_t h = 0; h <= hmax; h++) {
+                const int32_t bk = hmax - h;
+                if (ab[bk + 1] > ab[bk])
+                    hipLaunchKernelGGL(k_dp_arcs, dim3(nblk(ab[bk + 1] - ab[bk])), dim3(SB), 0, s, ab[bk], ab[bk + 1],
+                                       hsrc, hdst, ca, co, frb, accA, accO, accO2);
+                if (cb[bk + 1] > cb[bk])
+                    hipLaunchKernelGGL(k_dp_fin, dim3(nblk(cb[bk + 1] - cb[bk])), dim3(SB), 0, s, cb[bk], cb[bk + 1],
+                                       byh, big, (int64_t)n, wt, tob, rb, accA, accO, accO2, ca, co);
+            }
+        }
+        hipLaunchKernelGGL(k_scc_out, dim3(gb), dim3(SB), 0, s, n, comp, ca, co, topo, alpha, omega, scc_topo);
+        DEV_OK(hipStreamSynchronize(s));
+        if (hipGetLastError() != hipSuccess) fail(-1);
+        phase("dp+out", 0, 0);
+    }
+done:
+#undef DEV_OK
+#undef STEP_OK
+    hipStreamSynchronize(s);
+    hipFree(sc.base);
+    return rc;
+}

@@ -34,7 +34,7 @@ MODES = {"plain": TKC_PLAIN, "batched": TKC_BATCHED, "hybrid": TKC_HYBRID, "auto
 
 EXPORTS = [
     "tkc_ctx_create", "tkc_ctx_destroy", "tkc_ctx_get_tuning", "tkc_ctx_set_tuning", "tkc_graph_upload",
-    "tkc_graph_free", "tkc_topk_closeness", "tkc_topk_closeness_ties", "tkc_autotune", "tkc_graph_reach", "tkc_graph_bounds", "tkc_graph_lb_update",
+    "tkc_graph_free", "tkc_topk_closeness", "tkc_topk_closeness_ties", "tkc_autotune", "tkc_graph_reach", "tkc_graph_reach_info", "tkc_graph_bounds", "tkc_graph_lb_update",
     "tkc_graph_sums", "tkc_server_create", "tkc_server_add_graph", "tkc_server_submit",
     "tkc_server_poll", "tkc_server_result", "tkc_server_cancel", "tkc_server_destroy",
     "tkc_last_error", "tkc_version",
@@ -74,6 +74,14 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libtkc.so is not built (run __graft_entry__.build() or "
                           "python -m paper_1704_01077_amd.build)")
+    # torch's HIP runtime must be the one this library binds to: streams and
+    # device pointers handed over from torch are only valid there, and a
+    # second runtime loaded first does not see the device once torch has
+    # initialised its own
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     c = ctypes
     vp, i32, i64, u32, u64 = c.c_void_p, c.c_int32, c.c_int64, c.c_uint32, c.c_uint64
@@ -89,6 +97,7 @@ def _load():
         "tkc_topk_closeness": [vp, i32, i32, i32, vp, vp, vp, vp, P(i32), P(tkc_stats)],
         "tkc_topk_closeness_ties": [vp, i32, i32, i32, i32, vp, vp, vp, vp, P(i32), P(tkc_stats)],
         "tkc_graph_reach": [vp, vp, vp, vp],
+        "tkc_graph_reach_info": [vp, P(i32), P(c.c_double)],
         "tkc_graph_bounds": [vp, i32, vp, vp, vp],
         "tkc_graph_lb_update": [vp, vp, i32, vp, vp],
         "tkc_graph_sums": [vp, vp, i32, vp, vp],
@@ -201,6 +210,13 @@ def tkc_topk_closeness_ties(g, k, variant, mode, cap, ids, sum_dist=None, reach=
 
 def tkc_graph_reach(g, alpha, omega, scc=None):
     _check(lib.tkc_graph_reach(g, _ptr(alpha), _ptr(omega), _ptr(scc)))
+
+
+def tkc_graph_reach_info(g):
+    path = ctypes.c_int32(0)
+    ms = ctypes.c_double(0)
+    _check(lib.tkc_graph_reach_info(g, ctypes.byref(path), ctypes.byref(ms)))
+    return path.value, ms.value
 
 
 def tkc_graph_bounds(g, variant, num, den, order=None):
@@ -325,6 +341,10 @@ class Graph:
         s = np.zeros(self.n, np.int32)
         tkc_graph_reach(self.h, a, o, s)
         return a, o, (s if self.directed else None)
+
+    def reach_info(self):
+        """(path, ms): 0 not computed yet, 1 device, 2 host fallback."""
+        return tkc_graph_reach_info(self.h)
 
     def bounds(self, variant):
         num = np.zeros(self.n, np.int64)
