@@ -60,6 +60,14 @@ extern "C" {
 #define TKC_NB_CUT 2        /* neighbourhood bound + BFSCut               */
 #define TKC_DEG_BOUND 3     /* degree order + level-based updates         */
 #define TKC_NB_BOUND 4      /* neighbourhood bound + level-based updates  */
+/* Cut and level-based updates combined (the combination Sect. 9.1 leaves
+ * open): the BFSCut bound may stop a search while it is shallow (at most 8
+ * levels deep), and every search that completes applies its level-based
+ * update to the other vertices' bounds.  Low-diameter graphs then behave
+ * like the Cut variants plus updates, high-diameter ones like the Bound
+ * variants.  Same exact result as every other variant. */
+#define TKC_DEG_CUTLB 5     /* degree order + BFSCut + level-based updates */
+#define TKC_NB_CUTLB 6      /* neighbourhood bound + BFSCut + level-based  */
 
 /* execution mode of the searches */
 #define TKC_PLAIN 0         /* one source at a time, whole GPU per search */

@@ -670,7 +670,7 @@ extern "C" int tkc_topk_closeness(tkc_graph* g, int32_t k, int32_t variant, int3
                                   tkc_stats* stats) {
     if (!g || !ids || !n_out) return tkc_fail(TKC_EINVAL, "NULL argument");
     if (k < 1) return tkc_fail(TKC_EINVAL, "k must be >= 1");
-    if (variant < TKC_AUTO || variant > TKC_NB_BOUND) return tkc_fail(TKC_EINVAL, "unknown variant %d", variant);
+    if (variant < TKC_AUTO || variant > TKC_NB_CUTLB) return tkc_fail(TKC_EINVAL, "unknown variant %d", variant);
     if (mode < TKC_PLAIN || mode > TKC_MODE_AUTO) return tkc_fail(TKC_EINVAL, "unknown mode %d", mode);
     tkc_ctx* c = g->ctx;
     HIPCHK(hipSetDevice(c->device));
@@ -682,7 +682,7 @@ extern "C" int tkc_topk_closeness_ties(tkc_graph* g, int32_t k, int32_t variant,
                                        int32_t* n_out, tkc_stats* stats) {
     if (!g || !ids || !n_out) return tkc_fail(TKC_EINVAL, "NULL argument");
     if (k < 1) return tkc_fail(TKC_EINVAL, "k must be >= 1");
-    if (variant < TKC_AUTO || variant > TKC_NB_BOUND) return tkc_fail(TKC_EINVAL, "unknown variant %d", variant);
+    if (variant < TKC_AUTO || variant > TKC_NB_CUTLB) return tkc_fail(TKC_EINVAL, "unknown variant %d", variant);
     if (mode < TKC_PLAIN || mode > TKC_MODE_AUTO) return tkc_fail(TKC_EINVAL, "unknown mode %d", mode);
     if (cap < std::min(k, g->n)) return tkc_fail(TKC_EINVAL, "cap must be >= min(k, n)");
     tkc_ctx* c = g->ctx;
@@ -717,11 +717,11 @@ extern "C" int tkc_autotune(tkc_graph* g, int32_t k, int32_t variant, double bud
                             double* best_ms) {
     if (!g) return tkc_fail(TKC_EINVAL, "graph is NULL");
     if (k < 1) return tkc_fail(TKC_EINVAL, "k must be >= 1");
-    if (variant < TKC_AUTO || variant > TKC_NB_BOUND) return tkc_fail(TKC_EINVAL, "unknown variant %d", variant);
+    if (variant < TKC_AUTO || variant > TKC_NB_CUTLB) return tkc_fail(TKC_EINVAL, "unknown variant %d", variant);
     tkc_ctx* c = g->ctx;
     HIPCHK(hipSetDevice(c->device));
     if (variant == TKC_AUTO) variant = tkc_auto_variant(c, g);
-    const bool lb = (variant == TKC_DEG_BOUND || variant == TKC_NB_BOUND);
+    const bool lb = tkc_lb_level(variant) != 0;
     const int32_t kk = std::min(k, g->n);
     std::vector<int32_t> ref(kk), ids(kk);
     EngineTuning cur = c->tune;
@@ -793,8 +793,9 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
     }
     // AUTO: high-diameter graphs favour level-based updates (Sect. 9.1)
     if (variant == TKC_AUTO) variant = tkc_auto_variant(c, g);
-    const bool lb = (variant == TKC_DEG_BOUND || variant == TKC_NB_BOUND);
-    const bool nb = (variant == TKC_NB_CUT || variant == TKC_NB_BOUND);
+    const int lbl = tkc_lb_level(variant);
+    const bool lb = lbl != 0;
+    const bool nb = tkc_is_nb(variant);
     {
         WsShape sh = tkc_shape_for(c->tune, g, k, lb);
         sh.ties = ties;
@@ -839,7 +840,7 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
     if (lb && mode == TKC_HYBRID) mode = TKC_BATCHED;
     if (mode == TKC_PLAIN) {
         EngineTimer tm(c, &ms_eng[0], &nl_eng[0]);
-        if (tkc_launch_plain(dg, rcv, ov, bv, tk, plain_view(ws), st_plain, nullptr, 0, lb, c->tune, s, &grid))
+        if (tkc_launch_plain(dg, rcv, ov, bv, tk, plain_view(ws), st_plain, nullptr, 0, lbl, c->tune, s, &grid))
             return tkc_fail(TKC_EDEVICE, "plain engine launch failed: %s", hipGetErrorString(hipGetLastError()));
         tm.done();
     } else if (mode == TKC_BATCHED) {
@@ -851,7 +852,7 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
         for (;;) {
             {
                 EngineTimer tm(c, &ms_eng[1], &nl_eng[1]);
-                int e = tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_batch, nullptr, 0, pos, slice, lb,
+                int e = tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_batch, nullptr, 0, pos, slice, lbl,
                                          false, nullptr, nullptr, c->tune, s, &grid);
                 if (e)
                     return tkc_fail(TKC_EDEVICE, "batched engine launch failed: %s", hipGetErrorString(hipGetLastError()));
@@ -1069,14 +1070,14 @@ extern "C" int tkc_graph_reach(tkc_graph* g, int64_t* alpha, int64_t* omega, int
 
 extern "C" int tkc_graph_bounds(tkc_graph* g, int32_t variant, int64_t* num, int64_t* den, int32_t* order) {
     if (!g || !num || !den) return tkc_fail(TKC_EINVAL, "NULL argument");
-    if (variant < TKC_DEG_CUT || variant > TKC_NB_BOUND) return tkc_fail(TKC_EINVAL, "bad variant");
+    if (variant < TKC_DEG_CUT || variant > TKC_NB_CUTLB) return tkc_fail(TKC_EINVAL, "bad variant");
     tkc_ctx* c = g->ctx;
     HIPCHK(hipSetDevice(c->device));
     int rc = tkc_ws_reserve(c, c->ws, tkc_shape_for(c->tune, g, 1, false));
     if (rc) return rc;
     rc = tkc_step_reach(c, g, c->ws);
     if (rc) return rc;
-    bool nb = (variant == TKC_NB_CUT || variant == TKC_NB_BOUND);
+    bool nb = tkc_is_nb(variant);
     rc = tkc_step_bounds(c, g, c->ws, nb, nullptr);
     if (rc) return rc;
     HIPCHK(hipMemcpyAsync(num, c->ws.lnum, 8 * (size_t)g->n, hipMemcpyDeviceToHost, c->stream));

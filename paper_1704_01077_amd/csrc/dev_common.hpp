@@ -62,6 +62,18 @@ TKC_DEV T for_wg(T* p, T v) {
 // 13 us per barrier at 512 workgroups).
 #define TKC_BAR_FAN 16
 #define TKC_BAR_PAD 32
+// Which searches the BFSCut bound may stop (lb_mode as the engines take
+// it).  Cut variants: any.  Level-based variants: none, since only complete
+// searches give level-based updates.  The combination: only shallow ones
+// (level <= CUTLB_DEPTH).  A search that the bound stops early costs little
+// and its update would be worth little; one that runs deep (high-diameter
+// graphs, where the cut bound fires late) is completed and feeds the
+// level-based update instead.
+#define CUTLB_DEPTH 8
+TKC_DEV bool cut_allowed(int32_t lb_mode, int64_t level) {
+    return lb_mode == 0 || (lb_mode == 2 && level <= CUTLB_DEPTH);
+}
+
 TKC_DEV void grid_barrier(uint32_t* bar, uint32_t nblocks) {
     __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's stores done
     __syncthreads();

@@ -155,9 +155,12 @@ struct PlainWork {
     int64_t* levtab;     // Lev(i) table (n + 2)
     uint32_t* bar;       // grid barrier state (zeroed once)
 };
+// lb_mode: 0 cut searches (Cut variants), 1 complete searches feeding
+// level-based updates (Bound variants), 2 both: shallow searches may be cut
+// (cut_allowed), and the complete ones feed level-based updates
 int tkc_launch_plain(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv, DevTopk tk,
                      PlainWork w, int64_t* stats, const int32_t* list, int32_t list_count,
-                     bool lb_mode, const EngineTuning& tune, hipStream_t s, int* grid_out);
+                     int lb_mode, const EngineTuning& tune, hipStream_t s, int* grid_out);
 
 // k_batch.hip: W sources per launch, one bit lane each (cooperative kernel).
 struct BatchWork {
@@ -181,7 +184,7 @@ struct BatchWork {
 };
 int tkc_launch_batch(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv, DevTopk tk,
                      BatchWork w, int64_t* stats, const int32_t* list, int32_t list_count,
-                     int32_t start_pos, int32_t max_batches, bool lb_mode, bool no_cut,
+                     int32_t start_pos, int32_t max_batches, int lb_mode, bool no_cut,
                      int64_t* out_S, int64_t* out_r, const EngineTuning& tune, hipStream_t s,
                      int* grid_out);
 

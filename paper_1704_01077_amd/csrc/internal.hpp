@@ -124,6 +124,15 @@ struct tkc_graph {
 };
 
 int tkc_fail(int code, const char* fmt, ...);
+// level-based updates of a variant: 0 none (Cut), 1 only (Bound), 2 with cuts
+static inline int tkc_lb_level(int32_t variant) {
+    if (variant == TKC_DEG_BOUND || variant == TKC_NB_BOUND) return 1;
+    if (variant == TKC_DEG_CUTLB || variant == TKC_NB_CUTLB) return 2;
+    return 0;
+}
+static inline bool tkc_is_nb(int32_t variant) {
+    return variant == TKC_NB_CUT || variant == TKC_NB_BOUND || variant == TKC_NB_CUTLB;
+}
 int tkc_ws_reserve(tkc_ctx* ctx, Workspace& ws, const WsShape& sh);
 // ties_cap > 0: all-ties mode, output arrays of ties_cap entries
 int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t mode, int32_t* ids,

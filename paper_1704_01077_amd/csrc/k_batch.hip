@@ -528,7 +528,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                     if (s_nf[l] == 0) {
                         s_st[l] = 2;
                         s_maxD[l] = (int32_t)(D - 1);
-                    } else if (!a.lb_mode && !a.no_cut) {
+                    } else if (cut_allowed(a.lb_mode, D) && !a.no_cut) {
                         int64_t bn, bd;
                         cut_bound(s_SD[l], s_nD[l], s_U[l], D, s_a[l], s_o[l], &bn, &bd);
                         if (lex_after(bn, bd, s_v[l], x.num, x.den, x.id)) {
@@ -1096,7 +1096,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
 
 int tkc_launch_batch(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv, DevTopk tk,
                      BatchWork w, int64_t* stats, const int32_t* list, int32_t list_count,
-                     int32_t start_pos, int32_t max_batches, bool lb_mode, bool no_cut,
+                     int32_t start_pos, int32_t max_batches, int lb_mode, bool no_cut,
                      int64_t* out_S, int64_t* out_r, const EngineTuning& tune, hipStream_t s,
                      int* grid_out) {
     int W = tune.batch_width;
@@ -1125,7 +1125,7 @@ int tkc_launch_batch(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv
     a.stats = stats; a.list = list; a.list_count = list_count;
     a.start_pos = start_pos;
     a.max_batches = max_batches > 0 ? max_batches : 0x7fffffff;
-    a.lb_mode = lb_mode ? 1 : 0;
+    a.lb_mode = lb_mode;
     a.no_cut = no_cut ? 1 : 0;
     a.until_x = (max_batches == -1) ? 1 : 0;
     if (max_batches == -1) a.max_batches = 0x7fffffff;

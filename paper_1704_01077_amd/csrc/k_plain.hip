@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
         int64_t mvis = 0, bytes = 0;
         for (;;) {
             if (nf == 0) { status = 1; break; }
-            if (!a.lb_mode) {
+            if (cut_allowed(a.lb_mode, D)) {
                 int64_t bn, bd;
                 cut_bound(SD, nD, U, D, av, ov, &bn, &bd);
                 if (lex_after(bn, bd, v, x.num, x.den, x.id)) { status = 2; break; }
@@ -397,7 +397,7 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
 
 int tkc_launch_plain(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv, DevTopk tk,
                      PlainWork w, int64_t* stats, const int32_t* list, int32_t list_count,
-                     bool lb_mode, const EngineTuning& tune, hipStream_t s, int* grid_out) {
+                     int lb_mode, const EngineTuning& tune, hipStream_t s, int* grid_out) {
     if (!w.bar || !w.vis || !w.fb || !w.ql || !w.qh || !w.qg || !w.ctr || !stats) return -2;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return -1;
@@ -413,7 +413,7 @@ int tkc_launch_plain(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv
     PlainArgs a{};
     a.g = g; a.rc = rc; a.ov = ov; a.bv = bv; a.tk = tk; a.w = w;
     a.stats = stats; a.list = list; a.list_count = list_count;
-    a.lb_mode = lb_mode ? 1 : 0;
+    a.lb_mode = lb_mode;
     a.alpha_td = tune.td_bu_alpha > 0 ? tune.td_bu_alpha : 14;
     a.beta_bu = tune.bu_td_beta > 0 ? tune.bu_td_beta : 24;
     a.bar = w.bar;

@@ -181,7 +181,7 @@ extern "C" int tkc_server_add_graph(tkc_server* s, tkc_graph* g, int32_t* graph_
 extern "C" int tkc_server_submit(tkc_server* s, int32_t graph_id, int32_t k, int32_t variant, uint64_t* ticket) {
     if (!s || !ticket) return tkc_fail(TKC_EINVAL, "NULL argument");
     if (k < 1) return tkc_fail(TKC_EINVAL, "k must be >= 1");
-    if (variant < TKC_AUTO || variant > TKC_NB_BOUND) return tkc_fail(TKC_EINVAL, "unknown variant");
+    if (variant < TKC_AUTO || variant > TKC_NB_CUTLB) return tkc_fail(TKC_EINVAL, "unknown variant");
     std::lock_guard<std::mutex> lk(s->mu);
     if (graph_id < 0 || graph_id >= (int32_t)s->graphs.size()) return tkc_fail(TKC_EINVAL, "unknown graph id");
     tkc_graph* g = s->graphs[graph_id];
@@ -191,7 +191,7 @@ extern "C" int tkc_server_submit(tkc_server* s, int32_t graph_id, int32_t k, int
     rq->k = k;
     rq->variant = variant;
     rq->t_submit = now_ms();
-    bool lb = (variant == TKC_DEG_BOUND || variant == TKC_NB_BOUND || variant == TKC_AUTO);
+    bool lb = tkc_lb_level(variant) != 0 || variant == TKC_AUTO;
     rq->need = tkc_ws_bytes(tkc_shape_for(tkc_effective_tuning(s->ctx->tune, g), g, std::min(k, g->n), lb));
     if (rq->need > s->budget) return tkc_fail(TKC_EBUSY, "request needs %zu bytes, budget is %zu", rq->need, s->budget);
     s->queue.push_back(rq);

@@ -25,11 +25,13 @@ TKC_EBUSY = -5
 TKC_ECANCELED = -6
 
 TKC_AUTO, TKC_DEG_CUT, TKC_NB_CUT, TKC_DEG_BOUND, TKC_NB_BOUND = 0, 1, 2, 3, 4
+TKC_DEG_CUTLB, TKC_NB_CUTLB = 5, 6
 TKC_PLAIN, TKC_BATCHED, TKC_HYBRID, TKC_MODE_AUTO = 0, 1, 2, 3
 TKC_DIRECTED, TKC_VALIDATE, TKC_DEVICE_PTRS, TKC_REVERSE = 1, 2, 4, 8
 
 VARIANTS = {"auto": TKC_AUTO, "degcut": TKC_DEG_CUT, "nbcut": TKC_NB_CUT,
-            "degbound": TKC_DEG_BOUND, "nbbound": TKC_NB_BOUND}
+            "degbound": TKC_DEG_BOUND, "nbbound": TKC_NB_BOUND,
+            "degcutlb": TKC_DEG_CUTLB, "nbcutlb": TKC_NB_CUTLB}
 MODES = {"plain": TKC_PLAIN, "batched": TKC_BATCHED, "hybrid": TKC_HYBRID, "auto": TKC_MODE_AUTO}
 
 EXPORTS = [

@@ -129,6 +129,16 @@ def test_full_grid2000_topk(ctx):
     check_topk(g, 10, ids, S, r, f)
 
 
+# Cut and level-based updates combined: the same answer on every workload
+@pytest.mark.parametrize("name", ["ba1m", "rmat20", "grid2000"])
+def test_full_cutlb_topk(ctx, name):
+    g = workload(name)
+    dg = dev(ctx, name)
+    ids, S, r, f, st = tkc.topk_closeness(dg, 10, "nbcutlb", "batched")
+    check_topk(g, 10, ids, S, r, f)
+    assert st["variant_used"] == tkc.TKC_NB_CUTLB
+
+
 @pytest.mark.parametrize("name", ["ba1m", "rmat20", "grid2000"])
 def test_full_sums(ctx, name):
     g = workload(name)

@@ -230,7 +230,7 @@ def test_lb_update_parity(ctx, name):
 
 # ------------------------------------------------------------- top-k parity
 @pytest.mark.parametrize("name", SMALL)
-@pytest.mark.parametrize("variant", ["degcut", "nbcut", "degbound", "nbbound", "auto"])
+@pytest.mark.parametrize("variant", ["degcut", "nbcut", "degbound", "nbbound", "degcutlb", "nbcutlb", "auto"])
 @pytest.mark.parametrize("mode", ["plain", "batched", "hybrid"])
 @pytest.mark.parametrize("k", [1, 10, 100])
 def test_topk_parity(ctx, name, variant, mode, k):
@@ -241,12 +241,12 @@ def test_topk_parity(ctx, name, variant, mode, k):
     assert np.array_equal(ids, wids), (ids[:10], wids[:10])
     assert np.array_equal(S, wS) and np.array_equal(r, wr)
     assert np.array_equal(f, wf)
-    assert st["bfs_exact"] >= min(k, g.n) or variant in ("degbound", "nbbound", "auto")
+    assert st["bfs_exact"] >= min(k, g.n) or variant in ("degbound", "nbbound", "degcutlb", "nbcutlb", "auto")
 
 
 @pytest.mark.parametrize("name", ["ba20k", "grid150", "rmat13"])
 @pytest.mark.parametrize("mode", ["batched", "hybrid"])
-@pytest.mark.parametrize("variant", ["nbcut", "degcut", "nbbound"])
+@pytest.mark.parametrize("variant", ["nbcut", "degcut", "nbbound", "nbcutlb", "degcutlb"])
 def test_topk_parity_medium(ctx, name, mode, variant):
     for k in (1, 10, 100):
         dg = upload(ctx, name)
