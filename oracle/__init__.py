@@ -44,6 +44,8 @@ def _L():
         lib.oracle_check_csr.argtypes = [c.c_int32, c.c_int64, i32p, c.c_int, c.c_int, i32p, i32p]
         lib.oracle_sums.argtypes = [c.c_int32, c.c_int64, i32p, c.c_int, c.c_void_p, c.c_int64,
                                     i64p, i64p, c.c_int]
+        lib.oracle_harmonic.argtypes = [c.c_int32, c.c_int64, i32p, c.c_int, c.c_void_p, c.c_int64,
+                                         np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS"), c.c_int]
         lib.oracle_threads.restype = c.c_int
         lib.oracle_arcs.argtypes = [c.c_int32, c.c_int64, i32p, c.c_int]
         lib.oracle_arcs.restype = c.c_int64
@@ -101,6 +103,31 @@ def sums(n, edges, directed, sources=None, nthreads=0):
     if rc:
         raise ValueError("bad edge list")
     return S[:cnt], r[:cnt]
+
+
+def harmonic(n, edges, directed, sources=None, nthreads=0):
+    """Harmonic centrality per source (Sect. 2 with f(d) = 1/d): the binary64
+    sum over d = 1, 2, ... of n_d / d, added in increasing d (oracle.c)."""
+    e = _edges(edges)
+    if sources is None:
+        cnt = n
+        src_ptr = None
+    else:
+        src = np.ascontiguousarray(sources, dtype=np.int32)
+        cnt = src.size
+        src_ptr = src.ctypes.data_as(ctypes.c_void_p)
+    h = np.zeros(max(1, cnt), dtype=np.float64)
+    rc = _L().oracle_harmonic(n, e.size // 2, e, int(directed), src_ptr, cnt, h, nthreads)
+    if rc:
+        raise ValueError("bad edge list")
+    return h[:cnt]
+
+
+def harmonic_topk(h, k):
+    """The first min(k, n) vertices: larger h first, an exact tie to the smaller id."""
+    h = np.asarray(h, dtype=np.float64)
+    order = np.lexsort((np.arange(h.size), -h))
+    return order[:max(0, min(k, h.size))].astype(np.int32)
 
 
 def arcs(n, edges, directed) -> int:

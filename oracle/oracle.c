@@ -36,6 +36,8 @@
  *  - oracle_lb_source: the level-based bound of Sect. 7 (Eq. 4, Lemma 7.2,
  *                    Alg. 5; directed Eq. 5, same-SCC rule of Sect. 8.3).
  *  - oracle_alpha_omega: reachability bounds of Sect. 8.4 (Alg. 6).
+ *  - oracle_harmonic: harmonic centrality, the measure of Sect. 2 with
+ *                    f(d) = 1/d that Sect. 9.1 also ranks.
  * Readings taken where the text is silent or garbled are listed at each
  * function.
  */
@@ -152,6 +154,64 @@ int oracle_sums(int32_t n, int64_t ne, const int32_t *ed, int directed,
         for (int64_t i = 0; i < cnt; i++) {
             int32_t s = src ? src[i] : (int32_t)i;
             S[i] = bfs_sum(&A, s, dist, queue, &r[i]);
+        }
+        free(dist); free(queue);
+    }
+    adj_free(&A);
+    return 0;
+}
+
+/* ------------------------------------ harmonic centrality (Sect. 2, 9.1) */
+/* h(v) = sum over the vertices w != v that v reaches of 1/d(v,w): the
+ * centrality of the form sum f(d(v,w)) with f(d) = 1/d, f(inf) = 0.
+ * Larger is more central; an exact tie goes to the smaller id.
+ * Reading (the paper fixes no precision): h is the IEEE binary64 value of
+ *     sum over d = 1, 2, ..., ecc(v) of  (double)n_d / (double)d,
+ * n_d the number of vertices at distance exactly d, each quotient rounded
+ * to nearest and the terms added in increasing d, rounding to nearest after
+ * each addition.  It differs from the exact rational by at most ecc(v)
+ * units in the last place. */
+static double bfs_harmonic(const oadj *A, int32_t s, int32_t *dist, int32_t *queue) {
+    int64_t head = 0, tail = 0;
+    dist[s] = 0; queue[tail++] = s;
+    while (head < tail) {
+        int32_t u = queue[head++];
+        for (int64_t q = A->off[u]; q < A->off[u + 1]; q++) {
+            int32_t w = A->nbr[q];
+            if (dist[w] < 0) { dist[w] = dist[u] + 1; queue[tail++] = w; }
+        }
+    }
+    /* a FIFO search emits the vertices in nondecreasing distance: the queue
+     * is the levels one after the other */
+    double h = 0.0;
+    int64_t q = 1;
+    while (q < tail) {
+        int32_t d = dist[queue[q]];
+        int64_t nd = 0;
+        while (q < tail && dist[queue[q]] == d) { nd++; q++; }
+        h += (double)nd / (double)d;
+    }
+    for (int64_t i = 0; i < tail; i++) dist[queue[i]] = -1;
+    return h;
+}
+
+int oracle_harmonic(int32_t n, int64_t ne, const int32_t *ed, int directed,
+                    const int32_t *src, int64_t ns, double *h, int nthreads) {
+    oadj A;
+    if (adj_build(n, ne, ed, directed, 0, &A)) return -1;
+    int64_t cnt = src ? ns : n;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    #pragma omp parallel
+    {
+        int32_t *dist = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+        int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+        for (int32_t i = 0; i < n; i++) dist[i] = -1;
+        #pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < cnt; i++) {
+            int32_t s = src ? src[i] : (int32_t)i;
+            h[i] = bfs_harmonic(&A, s, dist, queue);
         }
         free(dist); free(queue);
     }
