@@ -46,6 +46,8 @@ def _L():
                                     i64p, i64p, c.c_int]
         lib.oracle_harmonic.argtypes = [c.c_int32, c.c_int64, i32p, c.c_int, c.c_void_p, c.c_int64,
                                          np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS"), c.c_int]
+        lib.oracle_nb_harmonic.argtypes = [c.c_int32, c.c_int64, i32p, c.c_int, i64p,
+                                            np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")]
         lib.oracle_threads.restype = c.c_int
         lib.oracle_arcs.argtypes = [c.c_int32, c.c_int64, i32p, c.c_int]
         lib.oracle_arcs.restype = c.c_int64
@@ -121,6 +123,36 @@ def harmonic(n, edges, directed, sources=None, nthreads=0):
     if rc:
         raise ValueError("bad edge list")
     return h[:cnt]
+
+
+def nb_harmonic(n, edges, directed, omega=None):
+    """Walk-count upper bound on the harmonic centrality (oracle.c); omega
+    defaults to the reachability upper bounds of Sect. 8.4."""
+    e = _edges(edges)
+    if omega is None:
+        omega = reach_bounds(n, edges, directed)[1]
+    o = np.ascontiguousarray(omega, dtype=np.int64)
+    ub = np.zeros(max(1, n), dtype=np.float64)
+    if _L().oracle_nb_harmonic(n, e.size // 2, e, int(directed), o, ub):
+        raise ValueError("bad edge list")
+    return ub[:n]
+
+
+def deg_harmonic(n, edges, directed, omega=None):
+    """Degree upper bound on the harmonic centrality: the out-neighbours at
+    distance 1, every other vertex v may reach at distance >= 2."""
+    e = _edges(edges).reshape(-1, 2)
+    if omega is None:
+        omega = reach_bounds(n, edges, directed)[1]
+    deg = np.zeros(n, dtype=np.int64)
+    np.add.at(deg, e[:, 0], 1)
+    if not directed:
+        np.add.at(deg, e[:, 1], 1)
+    out = np.zeros(n, dtype=np.float64)
+    for v in range(n):
+        if omega[v] > 1:
+            out[v] = float(deg[v]) + float(omega[v] - 1 - deg[v]) / 2.0
+    return out
 
 
 def harmonic_topk(h, k):

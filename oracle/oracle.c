@@ -582,6 +582,61 @@ int oracle_nb(int32_t n, int64_t ne, const int32_t *ed, int directed,
     return 0;
 }
 
+/* Upper bound on the harmonic centrality of every vertex from the walk
+ * counts of Sect. 5 (the same gamma_k as oracle_nb): h(s) is largest when
+ * the vertices s reaches sit as close as the counts allow, so level k takes
+ * min(gamma_k(s), omega(s) - placed) of them, placed starting at 1 (s
+ * itself), until omega(s) vertices are placed or gamma_k(s) = 0.  omega(s)
+ * >= r(s) (Sect. 8.4), so the fill never undercounts.  The bound is the
+ * binary64 sum of placed_k / k in increasing k, as for h itself; on a tree
+ * the counts are exact and the bound equals h bit for bit. */
+int oracle_nb_harmonic(int32_t n, int64_t ne, const int32_t *ed, int directed,
+                       const int64_t *omega, double *ub) {
+    oadj A;
+    if (adj_build(n, ne, ed, directed, 0, &A)) return -1;
+    int64_t *g1 = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+    int64_t *g2 = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+    int64_t *gk = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+    int64_t *placed = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+    char *done = (char *)malloc((size_t)(n ? n : 1));
+    int32_t ndone = 0;
+    for (int32_t s = 0; s < n; s++) {
+        int64_t d = A.off[s + 1] - A.off[s];
+        g2[s] = 1; g1[s] = d;
+        ub[s] = 0.0; placed[s] = 1; done[s] = 0;
+        if (omega[s] <= 1 || d == 0) { done[s] = 1; ndone++; continue; }
+        int64_t take = d < omega[s] - 1 ? d : omega[s] - 1;
+        ub[s] += (double)take / 1.0;
+        placed[s] += take;
+        if (placed[s] >= omega[s]) { done[s] = 1; ndone++; }
+    }
+    for (int64_t k = 2; ndone < n; k++) {
+        for (int32_t s = 0; s < n; s++) {
+            int64_t acc = 0;
+            for (int64_t q = A.off[s]; q < A.off[s + 1]; q++) acc = sat_add(acc, g1[A.nbr[q]]);
+            if (!directed && acc < NB_INF) {
+                int64_t d = A.off[s + 1] - A.off[s];
+                u128 sub = (k == 2) ? (u128)d : (u128)(uint64_t)(d - 1) * (uint64_t)g2[s];
+                acc = (u128)acc >= sub ? (int64_t)((u128)acc - sub) : 0;
+            }
+            gk[s] = acc;
+        }
+        for (int32_t s = 0; s < n; s++) {
+            g2[s] = g1[s]; g1[s] = gk[s];
+            if (done[s]) continue;
+            if (gk[s] == 0) { done[s] = 1; ndone++; continue; }
+            int64_t room = omega[s] - placed[s];
+            int64_t take = gk[s] < room ? gk[s] : room;
+            ub[s] += (double)take / (double)k;
+            placed[s] += take;
+            if (placed[s] >= omega[s]) { done[s] = 1; ndone++; }
+        }
+    }
+    free(g1); free(g2); free(gk); free(placed); free(done);
+    adj_free(&A);
+    return 0;
+}
+
 /* ---------------------------------------------------- BFSCut bound (Sect. 6) */
 /*
  * Full BFS from v; after the vertices at distance <= D are all known

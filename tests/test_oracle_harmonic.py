@@ -128,3 +128,65 @@ def test_sources_subset_matches_all():
     h = oracle.harmonic(n, e, True)
     src = np.array([0, 7, 299, 150], np.int32)
     assert np.array_equal(oracle.harmonic(n, e, True, sources=src), h[src])
+
+
+# ------------------------------------------------ upper bounds (Sect. 5, 8.4)
+def random_tree(n, rng):
+    return E([(i, int(rng.integers(0, i))) for i in range(1, n)])
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_nb_bound_exact_on_trees(seed):
+    """On a tree the walk counts are the level sizes, so the bound is h
+    itself, bit for bit (the same terms in the same order)."""
+    rng = np.random.default_rng(4000 + seed)
+    n = int(rng.integers(1, 60))
+    e = random_tree(n, rng)
+    h = oracle.harmonic(n, e, False)
+    ub = oracle.nb_harmonic(n, e, False)
+    assert np.array_equal(ub, h)
+
+
+def test_nb_bound_forest_with_isolated_vertices():
+    rng = np.random.default_rng(77)
+    e1 = random_tree(30, rng)
+    e2 = random_tree(20, rng) + 30
+    e = np.concatenate([e1, e2])
+    n = 55   # vertices 50..54 isolated
+    h = oracle.harmonic(n, e, False)
+    ub = oracle.nb_harmonic(n, e, False)
+    assert np.array_equal(ub, h)
+    assert np.all(ub[50:] == 0.0)
+
+
+@pytest.mark.parametrize("directed", [False, True])
+@pytest.mark.parametrize("seed", range(40))
+def test_bounds_above_h(directed, seed):
+    """Both upper bounds hold on random graphs (connected or not), with
+    alpha / omega from the reachability bounds for directed ones."""
+    rng = np.random.default_rng(5000 + seed + (1000 if directed else 0))
+    n = int(rng.integers(2, 40))
+    p = float(rng.uniform(0.02, 0.3))
+    pairs = {(u, w) for u in range(n) for w in range(n)
+             if u != w and rng.random() < p and (directed or u < w)}
+    e = E(sorted(pairs))
+    # exact h from Floyd-Warshall levels, as Fractions
+    for v, lv in enumerate(fw_levels(n, e, directed)):
+        exact = sum((Fraction(c, d) for d, c in lv.items()), Fraction(0))
+        ub_nb = oracle.nb_harmonic(n, e, directed)[v]
+        ub_deg = oracle.deg_harmonic(n, e, directed)[v]
+        tol = 1e-12 * max(1.0, float(exact))
+        assert ub_nb >= float(exact) - tol, (v, ub_nb, exact)
+        assert ub_deg >= float(exact) - tol, (v, ub_deg, exact)
+
+
+def test_deg_bound_closed_forms():
+    # star: the centre's bound is exact (n-1); a leaf sees 1 at distance 1
+    # and n-2 at distance 2, also exact
+    n = 9
+    e = E([(0, i) for i in range(1, n)])
+    ub = oracle.deg_harmonic(n, e, False)
+    assert ub[0] == n - 1 and np.all(ub[1:] == 1 + (n - 2) / 2)
+    # complete graph: n-1 everywhere
+    e = E([(i, j) for i in range(6) for j in range(i + 1, 6)])
+    assert np.all(oracle.deg_harmonic(6, e, False) == 5.0)
