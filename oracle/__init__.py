@@ -139,15 +139,18 @@ def nb_harmonic(n, edges, directed, omega=None):
 
 
 def deg_harmonic(n, edges, directed, omega=None):
-    """Degree upper bound on the harmonic centrality: the out-neighbours at
-    distance 1, every other vertex v may reach at distance >= 2."""
-    e = _edges(edges).reshape(-1, 2)
+    """Degree upper bound on the harmonic centrality: the distinct
+    out-neighbours at distance 1, every other vertex v may reach at
+    distance >= 2 (self-loops and repeated arcs count once, as in the
+    adjacency oracle.c builds)."""
+    e = _edges(edges).reshape(-1, 2).astype(np.int64)
+    e = e[e[:, 0] != e[:, 1]]
+    if not directed:
+        e = np.concatenate([e, e[:, ::-1]])
+    e = np.unique(e[:, 0] * max(n, 1) + e[:, 1])
     if omega is None:
         omega = reach_bounds(n, edges, directed)[1]
-    deg = np.zeros(n, dtype=np.int64)
-    np.add.at(deg, e[:, 0], 1)
-    if not directed:
-        np.add.at(deg, e[:, 1], 1)
+    deg = np.bincount((e // max(n, 1)).astype(np.int64), minlength=n)
     out = np.zeros(n, dtype=np.float64)
     for v in range(n):
         if omega[v] > 1:

@@ -190,3 +190,13 @@ def test_deg_bound_closed_forms():
     # complete graph: n-1 everywhere
     e = E([(i, j) for i in range(6) for j in range(i + 1, 6)])
     assert np.all(oracle.deg_harmonic(6, e, False) == 5.0)
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_repeated_arcs_and_self_loops_count_once(directed):
+    """The measure is on the simple graph: repeats and self-loops change
+    neither h nor its bounds."""
+    clean = E([(0, 1), (1, 2), (2, 3), (3, 0), (0, 4)])
+    noisy = E([(0, 1), (0, 1), (1, 2), (2, 2), (2, 3), (3, 0), (0, 4), (0, 4), (4, 4)])
+    for f in (oracle.harmonic, oracle.nb_harmonic, oracle.deg_harmonic):
+        assert np.array_equal(f(6, noisy, directed), f(6, clean, directed)), f.__name__
