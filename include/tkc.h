@@ -179,6 +179,26 @@ int tkc_topk_closeness(tkc_graph *g, int32_t k, int32_t variant, int32_t mode,
                        int32_t *ids, int64_t *sum_dist, int64_t *reach, double *farness,
                        int32_t *n_out, tkc_stats *stats);
 
+/* Top-k harmonic centrality: h(v) = sum of 1/d(v,w) over the vertices w
+ * that v reaches (the measure of Sect. 2 with f(d) = 1/d, ranked in Sect.
+ * 9.1).  h is the binary64 value of the terms n_d / d added in increasing d
+ * (n_d = vertices at distance d), exactly as the library computes it; the
+ * order is larger h first, an exact tie to the smaller id.  variant:
+ * TKC_AUTO (= TKC_NB_CUT), TKC_DEG_CUT or TKC_NB_CUT with upper bounds in
+ * place of the farness lower bounds (degree: the out-neighbours at distance
+ * 1, every other reachable vertex at distance 2; walk counts: levels filled
+ * as close as the counts of Sect. 5 allow); other variants give
+ * TKC_EINVAL.  mode: TKC_PLAIN or TKC_BATCHED (TKC_HYBRID and
+ * TKC_MODE_AUTO run batched).  *n_out = min(k, n) results in order: ids
+ * and harmonic values.  stats may be NULL. */
+int tkc_topk_harmonic(tkc_graph *g, int32_t k, int32_t variant, int32_t mode,
+                      int32_t *ids, double *harmonic, int32_t *n_out, tkc_stats *stats);
+/* The harmonic upper bounds a harmonic query starts from (variant
+ * TKC_DEG_CUT or TKC_NB_CUT), each already raised by the relative margin
+ * 1e-9 the search applies to every bound, and the processing order
+ * (largest bound first, ties by id; may be NULL).  Host arrays of n. */
+int tkc_graph_harmonic_bounds(tkc_graph *g, int32_t variant, double *ub, int32_t *order);
+
 /* Autotuner: times the query (k, variant) on g under candidate knob
  * settings, one knob at a time (batch width, mode, workgroups per CU, the
  * pull threshold beta, batch alpha), keeping each improvement, until the settings are exhausted or the

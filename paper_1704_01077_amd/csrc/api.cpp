@@ -76,6 +76,7 @@ static size_t ws_items(Workspace& ws, const WsShape& sh, std::vector<WsItem>& it
         {(void**)&ws.mask, 64, false}, {(void**)&ws.parent, 4 * n, false},
         {(void**)&ws.csize, 8 * n + 8, false}, {(void**)&ws.gbuf, 24 * n, false},
         {(void**)&ws.nbsum, 8 * n, false}, {(void**)&ws.nbvis, 8 * n, false},
+        {(void**)&ws.nbhub, 8 * n, false},
         {(void**)&ws.nbflags, n, false}, {(void**)&ws.small, 4096, false},
         {(void**)&ws.nbpart, 8 * (size_t)sh.nchunks + 8, false},
         {(void**)&ws.tstate, 4096, false}, {(void**)&ws.ring, sizeof(XRec) * TKC_XRING, false},
@@ -557,7 +558,7 @@ extern "C" int tkc_graph_reach_info(const tkc_graph* g, int32_t* path, double* m
 }
 
 // step 2 + 3: bounds into ws.lnum / ws.lden, order into ws.ord / ws.key
-int tkc_step_bounds(tkc_ctx* c, tkc_graph* g, Workspace& ws, bool nb, int32_t* rounds) {
+int tkc_step_bounds(tkc_ctx* c, tkc_graph* g, Workspace& ws, bool nb, int32_t* rounds, bool harm) {
     hipStream_t s = c->stream;
     DevGraph dg = g->view();
     int32_t n = g->n;
@@ -565,11 +566,18 @@ int tkc_step_bounds(tkc_ctx* c, tkc_graph* g, Workspace& ws, bool nb, int32_t* r
     if (nb) {
         int32_t* nfin_dev = (int32_t*)ws.small;
         int r = tkc_launch_nb(dg, ws.alpha, ws.omega, ws.gbuf, ws.nbsum, ws.nbvis, ws.nbflags, ws.lnum, ws.lden,
-                              ws.nbpart, nfin_dev, (int32_t*)c->pinned, s);
+                              ws.nbpart, nfin_dev, (int32_t*)c->pinned, s, harm ? ws.nbhub : nullptr);
         if (r < 0) return tkc_fail(TKC_EDEVICE, "NB bound kernels failed");
         if (rounds) *rounds = r;
-        if (tkc_launch_nb_keys(n, ws.lnum, ws.lden, ws.key, ws.ord, s))
+        if (harm) {
+            if (tkc_launch_harm_bounds(dg, ws.omega, ws.nbhub, ws.lnum, ws.lden, ws.key, ws.ord, s))
+                return tkc_fail(TKC_EDEVICE, "harmonic bound kernel failed");
+        } else if (tkc_launch_nb_keys(n, ws.lnum, ws.lden, ws.key, ws.ord, s)) {
             return tkc_fail(TKC_EDEVICE, "key kernel failed");
+        }
+    } else if (harm) {
+        if (tkc_launch_harm_bounds(dg, ws.omega, nullptr, ws.lnum, ws.lden, ws.key, ws.ord, s))
+            return tkc_fail(TKC_EDEVICE, "harmonic bound kernel failed");
     } else {
         if (tkc_launch_deg_bounds(dg, ws.omega, ws.lnum, ws.lden, ws.key, ws.ord, s))
             return tkc_fail(TKC_EDEVICE, "degree bound kernel failed");
@@ -690,6 +698,18 @@ extern "C" int tkc_topk_closeness_ties(tkc_graph* g, int32_t k, int32_t variant,
     return tkc_run_query(c, g, k, variant, mode, ids, sum_dist, reach, farness, n_out, stats, cap);
 }
 
+extern "C" int tkc_topk_harmonic(tkc_graph* g, int32_t k, int32_t variant, int32_t mode, int32_t* ids,
+                                 double* harmonic, int32_t* n_out, tkc_stats* stats) {
+    if (!g || !ids || !n_out) return tkc_fail(TKC_EINVAL, "NULL argument");
+    if (k < 1) return tkc_fail(TKC_EINVAL, "k must be >= 1");
+    if (variant != TKC_AUTO && variant != TKC_DEG_CUT && variant != TKC_NB_CUT)
+        return tkc_fail(TKC_EINVAL, "harmonic centrality runs TKC_AUTO, TKC_DEG_CUT or TKC_NB_CUT, not %d", variant);
+    if (mode < TKC_PLAIN || mode > TKC_MODE_AUTO) return tkc_fail(TKC_EINVAL, "unknown mode %d", mode);
+    tkc_ctx* c = g->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    return tkc_run_query(c, g, k, variant, mode, ids, nullptr, nullptr, harmonic, n_out, stats, 0, true);
+}
+
 // Runs one query under knobs t (on the graph's context, whose own knobs are
 // restored afterwards) and returns its wall time.
 static int autotune_trial(tkc_graph* g, int32_t k, int32_t variant, const EngineTuning& t,
@@ -771,7 +791,7 @@ extern "C" int tkc_autotune(tkc_graph* g, int32_t k, int32_t variant, double bud
 
 int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t mode, int32_t* ids,
                   int64_t* sum_dist, int64_t* reach, double* farness, int32_t* n_out, tkc_stats* stats,
-                  int32_t ties_cap) {
+                  int32_t ties_cap, bool harm) {
     const bool ties = ties_cap > 0;
     Workspace& ws = c->ws;
     hipStream_t s = c->stream;
@@ -787,12 +807,14 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
         const EngineTuning keep = c->tune;
         c->tune = tkc_effective_tuning(keep, g);
         c->tune.slice_batches = keep.slice_batches;
-        rc = tkc_run_query(c, g, k, variant, c->tune.mode, ids, sum_dist, reach, farness, n_out, stats, ties_cap);
+        rc = tkc_run_query(c, g, k, variant, c->tune.mode, ids, sum_dist, reach, farness, n_out, stats, ties_cap,
+                           harm);
         c->tune = keep;
         return rc;
     }
-    // AUTO: high-diameter graphs favour level-based updates (Sect. 9.1)
-    if (variant == TKC_AUTO) variant = tkc_auto_variant(c, g);
+    // AUTO: high-diameter graphs favour level-based updates (Sect. 9.1);
+    // harmonic centrality runs the Cut variants only
+    if (variant == TKC_AUTO) variant = harm ? TKC_NB_CUT : tkc_auto_variant(c, g);
     const int lbl = tkc_lb_level(variant);
     const bool lb = lbl != 0;
     const bool nb = tkc_is_nb(variant);
@@ -804,16 +826,16 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
     if (rc) return rc;
     int32_t rounds = 0;
     double t1;
-    if (tkc_prep_cached(c, g, nb, &rounds)) {
+    if (!harm && tkc_prep_cached(c, g, nb, &rounds)) {
         t1 = now_ms();
     } else {
         rc = tkc_step_reach(c, g, ws);
         if (rc) return rc;
         HIPCHK(hipStreamSynchronize(s));
         t1 = now_ms();
-        rc = tkc_step_bounds(c, g, ws, nb, &rounds);
+        rc = tkc_step_bounds(c, g, ws, nb, &rounds, harm);
         if (rc) return rc;
-        if (g->cache_prep) {
+        if (g->cache_prep && !harm) {
             rc = tkc_prep_store(c, g, nb, rounds);
             if (rc) return rc;
         }
@@ -828,8 +850,11 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
 
     DevGraph dg = g->view();
     DevReach rcv{ws.alpha, ws.omega, g->directed ? ws.scc : nullptr};
-    OrderView ov{ws.ord, ws.key, n, nb};
+    // harmonic bounds order from the largest down for both variants, so the
+    // keys bound the value and the stop rule applies
+    OrderView ov{ws.ord, ws.key, n, nb || harm};
     BoundsView bv{ws.lnum, ws.lden};
+    bv.harm = harm ? 1 : 0;
     int64_t* st_plain = ws.stats;
     int64_t* st_batch = ws.stats + ST_COUNT;
     int64_t* st_swarm = ws.stats + 2 * ST_COUNT;
@@ -837,7 +862,8 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
     double ms_eng[3] = {0, 0, 0};
     int32_t nl_eng[3] = {0, 0, 0};
     int grid = 0;
-    if (lb && mode == TKC_HYBRID) mode = TKC_BATCHED;
+    // the per-workgroup engine has no level-based or harmonic path
+    if ((lb || harm) && mode == TKC_HYBRID) mode = TKC_BATCHED;
     if (mode == TKC_PLAIN) {
         EngineTimer tm(c, &ms_eng[0], &nl_eng[0]);
         if (tkc_launch_plain(dg, rcv, ov, bv, tk, plain_view(ws), st_plain, nullptr, 0, lbl, c->tune, s, &grid))
@@ -991,6 +1017,14 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
     }
     for (int32_t i = 0; i < cnt; i++) {
         ids[i] = hI[i];
+        if (harm) {
+            // decode harm_enc: the value's bit pattern is HARM_TOP - S
+            const int64_t bits = (int64_t)0x7FF0000000000000LL - hS[i];
+            double h;
+            memcpy(&h, &bits, 8);
+            if (farness) farness[i] = h;
+            continue;
+        }
         if (sum_dist) sum_dist[i] = hS[i];
         if (reach) reach[i] = hR[i];
         if (farness)
@@ -1065,6 +1099,29 @@ extern "C" int tkc_graph_reach(tkc_graph* g, int64_t* alpha, int64_t* omega, int
     if (scc && g->directed)
         HIPCHK(hipMemcpyAsync(scc, c->ws.scc, 4 * (size_t)g->n, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    return TKC_OK;
+}
+
+extern "C" int tkc_graph_harmonic_bounds(tkc_graph* g, int32_t variant, double* ub, int32_t* order) {
+    if (!g || !ub) return tkc_fail(TKC_EINVAL, "NULL argument");
+    if (variant != TKC_DEG_CUT && variant != TKC_NB_CUT) return tkc_fail(TKC_EINVAL, "bad variant");
+    tkc_ctx* c = g->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    int rc = tkc_ws_reserve(c, c->ws, tkc_shape_for(c->tune, g, 1, false));
+    if (rc) return rc;
+    rc = tkc_step_reach(c, g, c->ws);
+    if (rc) return rc;
+    rc = tkc_step_bounds(c, g, c->ws, variant == TKC_NB_CUT, nullptr, true);
+    if (rc) return rc;
+    const size_t n = g->n;
+    std::vector<int64_t> f(n);
+    HIPCHK(hipMemcpyAsync(f.data(), c->ws.lnum, 8 * n, hipMemcpyDeviceToHost, c->stream));
+    if (order) HIPCHK(hipMemcpyAsync(order, c->ws.ord, 4 * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t v = 0; v < n; v++) {
+        const int64_t bits = (int64_t)0x7FF0000000000000LL - f[v];
+        memcpy(&ub[v], &bits, 8);
+    }
     return TKC_OK;
 }
 

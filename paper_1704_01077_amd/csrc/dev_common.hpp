@@ -306,6 +306,31 @@ TKC_DEV void cut_bound(int64_t SD, int64_t nD, int64_t U, int64_t D, int64_t alp
     *bden = bd;
 }
 
+// ------------------------------------------- harmonic centrality (Sect. 2)
+// h(v) = sum of 1/d(v,w) over the vertices v reaches, evaluated in binary64
+// as the terms n_d / d added in increasing d.  Larger is better, so the
+// engines, the top k and the order keys carry it as the farness-like
+// integer F = HARM_TOP - bits(h) with denominator 1: the bit pattern of a
+// non-negative double grows with its value, so F orders vertices exactly as
+// h does, reversed, and every (value, id) comparison above applies as is.
+#define HARM_TOP ((int64_t)0x7FF0000000000000LL)
+TKC_DEV int64_t harm_enc(double h) { return HARM_TOP - (int64_t)__double_as_longlong(h); }
+// Relative margin on every upper bound: covers the rounding of the bound's
+// own binary64 terms and that of the final value (ecc terms, far below it).
+#define HARM_MARGIN 1e-9
+// BFSCut bound for harmonic centrality: after levels 0..D (nD vertices,
+// partial value H) with at most U vertices at level D+1 and at most omega
+// reachable, h(v) <= H + a/(D+1) + b/(D+2), a = min(U, rem), b = rem - a,
+// rem = omega - nD: the unseen vertices placed as close as allowed.
+TKC_DEV void harm_cut_bound(double H, int64_t nD, int64_t U, int64_t D, int64_t omega, int64_t* bnum,
+                            int64_t* bden) {
+    const int64_t rem = omega > nD ? omega - nD : 0;
+    const int64_t a = U < rem ? U : rem;
+    const double ub = H + (double)a / (double)(D + 1) + (double)(rem - a) / (double)(D + 2);
+    *bnum = harm_enc(ub * (1.0 + HARM_MARGIN));
+    *bden = 1;
+}
+
 // key of a lower bound for the processing order: the top 32 bits of the
 // IEEE double num/den (monotone in the value; +inf sorts last).  Its value
 // read back never exceeds the true bound by more than the double rounding.
@@ -328,4 +353,19 @@ TKC_DEV bool key_stops(uint32_t key, XVal x) {
     if (kv == __builtin_inf()) return true;
     double xv = (double)x.num / (double)x.den;
     return kv > xv * (1.0 + 1e-9);
+}
+// Harmonic order keys: the complement of the top 32 bits of the (margined)
+// upper bound's bit pattern, so ascending keys run from the largest bound
+// down at 2^-20 relative resolution.
+TKC_DEV uint32_t harm_key(double ub) {
+    return ~(uint32_t)((uint64_t)__double_as_longlong(ub) >> 32);
+}
+// Stop test on a harmonic key: the largest bound the key can stand for
+// (the top of its bucket) is already below x, and so is every later one.
+TKC_DEV bool key_stops_h(uint32_t key, XVal x) {
+    if (x.den == 0) return false;
+    const uint64_t top = ((uint64_t)(uint32_t)(~key) + 1) << 32;
+    const double ub_hi = __longlong_as_double((long long)top);
+    const double xh = __longlong_as_double((long long)(HARM_TOP - x.num));
+    return ub_hi < xh;
 }

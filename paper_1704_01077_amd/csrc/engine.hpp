@@ -80,6 +80,8 @@ struct OrderView {
 struct BoundsView {
     int64_t* num;            // current lower bound num/den (den 0 = +inf)
     int64_t* den;
+    int32_t harm = 0;        // harmonic centrality: bounds, cuts and results
+                             // carry harm_enc of an upper bound / value
 };
 
 struct EngineTuning {
@@ -110,9 +112,15 @@ int tkc_launch_degrees(const DevGraph& g, hipStream_t s);
 int tkc_launch_cc(const DevGraph& g, int32_t* parent, int64_t* size, int64_t* alpha, int64_t* omega,
                   uint8_t* in_giant, int32_t* sample_host, hipStream_t s);
 // partial holds nchunks uint64
+// hub (n doubles, may be null): also the walk-count upper bound on the
+// harmonic centrality
 int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega, int64_t* gbuf, int64_t* sum,
                   int64_t* vis, uint8_t* flags, int64_t* num, int64_t* den, uint64_t* partial,
-                  int32_t* nfin_dev, int32_t* nfin_host, hipStream_t s);
+                  int32_t* nfin_dev, int32_t* nfin_host, hipStream_t s, double* hub = nullptr);
+// harmonic centrality bounds and order keys: from hub (walk counts) when
+// given, else the degree bound
+int tkc_launch_harm_bounds(const DevGraph& g, const int64_t* omega, const double* hub, int64_t* num,
+                           int64_t* den, uint32_t* key, int32_t* val, hipStream_t s);
 int tkc_launch_deg_bounds(const DevGraph& g, const int64_t* omega, int64_t* num, int64_t* den,
                           uint32_t* key, int32_t* val, hipStream_t s);
 int tkc_launch_nb_keys(int32_t n, const int64_t* num, const int64_t* den, uint32_t* key,

@@ -34,6 +34,7 @@ struct Workspace {
     int32_t* parent;
     int64_t* csize;
     int64_t *gbuf, *nbsum, *nbvis;
+    double* nbhub;
     uint64_t* nbpart;
     uint8_t* nbflags;
     void* small;
@@ -135,14 +136,15 @@ static inline bool tkc_is_nb(int32_t variant) {
 }
 int tkc_ws_reserve(tkc_ctx* ctx, Workspace& ws, const WsShape& sh);
 // ties_cap > 0: all-ties mode, output arrays of ties_cap entries
+// harm: harmonic centrality; farness then receives the values h
 int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t mode, int32_t* ids,
                   int64_t* sum_dist, int64_t* reach, double* farness, int32_t* n_out, tkc_stats* stats,
-                  int32_t ties_cap = 0);
+                  int32_t ties_cap = 0, bool harm = false);
 int tkc_sums_impl(tkc_ctx* c, tkc_graph* g, const int32_t* sources, int32_t count, int64_t* S, int64_t* R,
                   tkc_stats* st);
 int32_t tkc_auto_variant(tkc_ctx* c, tkc_graph* g);
 int tkc_step_reach(tkc_ctx* c, tkc_graph* g, Workspace& ws);
-int tkc_step_bounds(tkc_ctx* c, tkc_graph* g, Workspace& ws, bool nb, int32_t* rounds);
+int tkc_step_bounds(tkc_ctx* c, tkc_graph* g, Workspace& ws, bool nb, int32_t* rounds, bool harm = false);
 // copy a graph's cached reachability/bounds/order into c's workspace; false
 // when the graph has no cache for this bound kind
 bool tkc_prep_cached(tkc_ctx* c, tkc_graph* g, bool nb, int32_t* rounds);

@@ -342,6 +342,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
     // replicated per-lane control state
     __shared__ int32_t s_v[MAXW];
     __shared__ int64_t s_a[MAXW], s_o[MAXW], s_nD[MAXW], s_SD[MAXW], s_U[MAXW], s_nf[MAXW], s_mf[MAXW];
+    __shared__ double s_H[MAXW];   // harmonic centrality so far (levels 1..D)
     __shared__ int32_t s_st[MAXW];      // 0 unused, 1 active, 2 exact, 3 cut
     __shared__ int32_t s_maxD[MAXW];
     __shared__ uint64_t s_act[NW];
@@ -383,7 +384,8 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 if (valid && !a.no_cut) {
                     if (order_mode) {
                         uint32_t key = a.ov.key[i];
-                        st = a.ov.key_is_bound ? key_stops(key, x) : (key == 0xffffffffu && x.den != 0);
+                        st = a.bv.harm ? key_stops_h(key, x)
+                                       : (a.ov.key_is_bound ? key_stops(key, x) : (key == 0xffffffffu && x.den != 0));
                     }
                     if (!st) sk = lex_after(a.bv.num[v], a.bv.den[v], v, x.num, x.den, x.id);
                 }
@@ -414,7 +416,8 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                         int l = __ffsll((long long)m) - 1;
                         m &= m - 1;
                         int32_t vv = order_mode ? a.ov.ord[pos + l] : a.list[pos + l];
-                        topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, 0, 1, vv);
+                        if (a.bv.harm) topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, harm_enc(0.0), 2, vv);
+                        else topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, 0, 1, vv);
                     }
                 }
                 r1 += __popcll(mone);
@@ -452,7 +455,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 s_v[l] = v;
                 s_a[l] = a.rc.alpha[v];
                 s_o[l] = a.rc.omega[v];
-                s_nD[l] = 1; s_SD[l] = 0;
+                s_nD[l] = 1; s_SD[l] = 0; s_H[l] = 0.0;
                 s_U[l] = deg[v]; s_nf[l] = 1; s_mf[l] = deg[v];
                 s_st[l] = 1;
                 s_maxD[l] = 0;
@@ -530,7 +533,8 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                         s_maxD[l] = (int32_t)(D - 1);
                     } else if (cut_allowed(a.lb_mode, D) && !a.no_cut) {
                         int64_t bn, bd;
-                        cut_bound(s_SD[l], s_nD[l], s_U[l], D, s_a[l], s_o[l], &bn, &bd);
+                        if (a.bv.harm) harm_cut_bound(s_H[l], s_nD[l], s_U[l], D, s_o[l], &bn, &bd);
+                        else cut_bound(s_SD[l], s_nD[l], s_U[l], D, s_a[l], s_o[l], &bn, &bd);
                         if (lex_after(bn, bd, s_v[l], x.num, x.den, x.id)) {
                             s_st[l] = 3;
                             s_maxD[l] = (int32_t)D;
@@ -953,6 +957,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                     int64_t d = ld_rlx(&ctr[C_DEG(p, l)]);
                     s_nD[l] += c;
                     s_SD[l] += (D + 1) * c;
+                    if (a.bv.harm) s_H[l] += (double)c / (double)(D + 1);
                     s_U[l] = dir ? d : d - c;
                     s_nf[l] = c;
                     s_mf[l] = d;
@@ -1005,8 +1010,12 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 if (s_maxD[l] > md) md = s_maxD[l];
                 if (s_st[l] == 2) {
                     ex++;
-                    if (!a.no_cut)
+                    if (a.no_cut) {
+                    } else if (a.bv.harm) {
+                        topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, harm_enc(s_H[l]), 2, s_v[l]);
+                    } else {
                         topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, s_SD[l], s_nD[l], s_v[l]);
+                    }
                 } else if (s_st[l] == 3) cu++;
             }
             stats[ST_STARTED] += nsel;

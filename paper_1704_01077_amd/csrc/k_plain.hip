@@ -150,7 +150,8 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
         const XVal x = read_x(a.tk.st, a.tk.ring);
         if (!a.list) {
             uint32_t key = a.ov.key[pos];
-            bool stop = a.ov.key_is_bound ? key_stops(key, x) : (key == 0xffffffffu && x.den != 0);
+            bool stop = a.bv.harm ? key_stops_h(key, x)
+                                  : (a.ov.key_is_bound ? key_stops(key, x) : (key == 0xffffffffu && x.den != 0));
             if (stop) {
                 if (boss) stats[ST_STOP] = 1;
                 break;
@@ -165,7 +166,8 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
             if (boss) {
                 stats[ST_STARTED]++;
                 stats[ST_EXACT]++;
-                topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, 0, 1, v);
+                if (a.bv.harm) topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, harm_enc(0.0), 2, v);
+                else topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, 0, 1, v);
             }
             grid_barrier(a.bar, gridDim.x);
             continue;
@@ -186,6 +188,7 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
         grid_barrier(a.bar, gridDim.x);
 
         int64_t D = 0, nD = 1, SD = 0;
+        double H = 0.0;   // harmonic centrality so far (levels 1..D)
         int64_t U = dv, mf = dv, nf = 1, mdisc = dv;
         // frontier segments [st[c], en[c]) of the light, heavy and chunk queues
         int64_t st[3] = {0, 0, 0}, en[3] = {0, 0, 0};
@@ -198,7 +201,8 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
             if (nf == 0) { status = 1; break; }
             if (cut_allowed(a.lb_mode, D)) {
                 int64_t bn, bd;
-                cut_bound(SD, nD, U, D, av, ov, &bn, &bd);
+                if (a.bv.harm) harm_cut_bound(H, nD, U, D, ov, &bn, &bd);
+                else cut_bound(SD, nD, U, D, av, ov, &bn, &bd);
                 if (lex_after(bn, bd, v, x.num, x.den, x.id)) { status = 2; break; }
             }
             // direction (Beamer): pull when the frontier's arcs outweigh the
@@ -343,6 +347,7 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
             D++;
             nD += cnt;
             SD += D * cnt;
+            if (a.bv.harm) H += (double)cnt / (double)D;
             U = dir ? dsum : dsum - cnt;
             mf = dsum;
             nf = cnt;
@@ -385,7 +390,8 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
             if (maxD > stats[ST_MAXLEVEL]) stats[ST_MAXLEVEL] = maxD;
             if (status == 1) {
                 stats[ST_EXACT]++;
-                topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, SD, nD, v);
+                if (a.bv.harm) topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, harm_enc(H), 2, v);
+                else topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, SD, nD, v);
             } else {
                 stats[ST_CUT]++;
             }

@@ -140,7 +140,17 @@ struct NBState {
     uint8_t* flags;   // bit0 finished, bit1 alpha reached
     int64_t* num;
     int64_t* den;
+    double* hub;      // harmonic upper bound (null: closeness only)
 };
+// Harmonic centrality from the same counts: level k takes min(gamma_k,
+// omega - placed) vertices (placed = the visited count, s included), the
+// closest placement the counts allow, and adds that many times 1/k.  Called
+// before nb_advance, while s is unfinished (so placed < omega).
+TKC_DEV void nb_harm(double* hub, int32_t s, int64_t k, int64_t gk, int64_t o, int64_t pv) {
+    const int64_t room = o - pv;
+    const int64_t take = gk < room ? gk : room;
+    if (take > 0) hub[s] += (double)take / (double)k;
+}
 TKC_DEV void rat_keep_min(int64_t* num, int64_t* den, int64_t cn, int64_t cd) {
     if (*den == 0 || rat_cmp(cn, cd, *num, *den) < 0) { *num = cn; *den = cd; }
 }
@@ -183,8 +193,12 @@ __global__ void k_nb_init(int32_t n, const int32_t* __restrict__ deg, const int6
         int64_t a = alpha[s], o = omega[s];
         int64_t pv = 1, ps = 0, num = 0, den = 0;
         uint8_t fl = 0;
+        if (st.hub) st.hub[s] = 0.0;
         if (o <= 1) { fl = 1; fin = true; }
-        else fin = nb_advance(1, d, a, o, pv, ps, fl, num, den);
+        else {
+            if (st.hub) nb_harm(st.hub, s, 1, d, o, pv);
+            fin = nb_advance(1, d, a, o, pv, ps, fl, num, den);
+        }
         st.sum[s] = ps; st.vis[s] = pv; st.flags[s] = fl; st.num[s] = num; st.den[s] = den;
     }
     int tot;
@@ -211,6 +225,7 @@ TKC_DEV void nb_finish_vertex(int32_t s, uint64_t acc, int64_t k, int32_t d, con
     *fin_now = false;
     if (fl & 1) return;
     int64_t pv = st.vis[s], ps = st.sum[s], num = st.num[s], den = st.den[s];
+    if (st.hub) nb_harm(st.hub, s, k, val, omega[s], pv);
     *fin_now = nb_advance(k, val, alpha[s], omega[s], pv, ps, fl, num, den);
     st.vis[s] = pv; st.sum[s] = ps; st.flags[s] = fl; st.num[s] = num; st.den[s] = den;
 }
@@ -305,6 +320,33 @@ __global__ void k_nb_keys(int32_t n, const int64_t* __restrict__ num, const int6
     val[v] = v;
 }
 
+// harmonic centrality: bounds and keys carry harm_enc of the upper bound
+// (with its margin), so the order runs from the largest bound down and the
+// skip and stop tests compare with x as for closeness
+__global__ void k_harm_deg_bounds(int32_t n, const int32_t* __restrict__ deg, const int64_t* __restrict__ omega,
+                                  int64_t* num, int64_t* den, uint32_t* key, int32_t* val) {
+    int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int64_t o = omega[v], d = deg[v];
+    // the out-neighbours at distance 1, every other reachable vertex at >= 2
+    const double ub = o > 1 ? (double)d + (double)(o - 1 - d) / 2.0 : 0.0;
+    const double ubm = ub * (1.0 + HARM_MARGIN);
+    num[v] = harm_enc(ubm);
+    den[v] = 1;
+    key[v] = harm_key(ubm);
+    val[v] = v;
+}
+__global__ void k_harm_nb_keys(int32_t n, const double* __restrict__ hub, int64_t* num, int64_t* den,
+                               uint32_t* key, int32_t* val) {
+    int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const double ubm = hub[v] * (1.0 + HARM_MARGIN);
+    num[v] = harm_enc(ubm);
+    den[v] = 1;
+    key[v] = harm_key(ubm);
+    val[v] = v;
+}
+
 // ------------------------------------------------------------ host side
 static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
@@ -363,12 +405,12 @@ int tkc_launch_cc(const DevGraph& g, int32_t* parent, int64_t* size, int64_t* al
 // NB bound: returns the number of rounds, -1 on error.  gbuf holds 3*n int64.
 int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega, int64_t* gbuf, int64_t* sum,
                   int64_t* vis, uint8_t* flags, int64_t* num, int64_t* den, uint64_t* partial,
-                  int32_t* nfin_dev, int32_t* nfin_host, hipStream_t s) {
+                  int32_t* nfin_dev, int32_t* nfin_host, hipStream_t s, double* hub) {
     int32_t n = g.n;
     int nl = nblk(n, 256);
     int nc = nblk((int64_t)g.nchunks * 64, 256);
     int nhb = nblk(g.nheavy, 256);
-    NBState st{sum, vis, flags, num, den};
+    NBState st{sum, vis, flags, num, den, hub};
     int64_t* buf[3] = {gbuf, gbuf + n, gbuf + 2 * (int64_t)n};
     hipMemsetAsync(nfin_dev, 0, sizeof(int32_t), s);
     // gamma_0 -> buf[0], gamma_1 -> buf[1]
@@ -414,6 +456,15 @@ int tkc_launch_deg_bounds(const DevGraph& g, const int64_t* omega, int64_t* num,
                           uint32_t* key, int32_t* val, hipStream_t s) {
     hipLaunchKernelGGL(k_deg_bounds, dim3(nblk(g.n, 256)), dim3(256), 0, s, g.n, g.deg, omega, num,
                        den, key, val);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+int tkc_launch_harm_bounds(const DevGraph& g, const int64_t* omega, const double* hub, int64_t* num,
+                           int64_t* den, uint32_t* key, int32_t* val, hipStream_t s) {
+    if (hub)
+        hipLaunchKernelGGL(k_harm_nb_keys, dim3(nblk(g.n, 256)), dim3(256), 0, s, g.n, hub, num, den, key, val);
+    else
+        hipLaunchKernelGGL(k_harm_deg_bounds, dim3(nblk(g.n, 256)), dim3(256), 0, s, g.n, g.deg, omega, num, den,
+                           key, val);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 int tkc_launch_nb_keys(int32_t n, const int64_t* num, const int64_t* den, uint32_t* key, int32_t* val,

@@ -36,7 +36,7 @@ MODES = {"plain": TKC_PLAIN, "batched": TKC_BATCHED, "hybrid": TKC_HYBRID, "auto
 
 EXPORTS = [
     "tkc_ctx_create", "tkc_ctx_destroy", "tkc_ctx_get_tuning", "tkc_ctx_set_tuning", "tkc_graph_upload",
-    "tkc_graph_free", "tkc_topk_closeness", "tkc_topk_closeness_ties", "tkc_autotune", "tkc_graph_reach", "tkc_graph_reach_info", "tkc_graph_bounds", "tkc_graph_lb_update",
+    "tkc_graph_free", "tkc_topk_closeness", "tkc_topk_closeness_ties", "tkc_autotune", "tkc_graph_reach", "tkc_graph_reach_info", "tkc_graph_bounds", "tkc_topk_harmonic", "tkc_graph_harmonic_bounds", "tkc_graph_lb_update",
     "tkc_graph_sums", "tkc_server_create", "tkc_server_add_graph", "tkc_server_submit",
     "tkc_server_poll", "tkc_server_result", "tkc_server_cancel", "tkc_server_destroy",
     "tkc_last_error", "tkc_version",
@@ -100,6 +100,8 @@ def _load():
         "tkc_topk_closeness_ties": [vp, i32, i32, i32, i32, vp, vp, vp, vp, P(i32), P(tkc_stats)],
         "tkc_graph_reach": [vp, vp, vp, vp],
         "tkc_graph_reach_info": [vp, P(i32), P(c.c_double)],
+        "tkc_topk_harmonic": [vp, i32, i32, i32, vp, vp, P(i32), P(tkc_stats)],
+        "tkc_graph_harmonic_bounds": [vp, i32, vp, vp],
         "tkc_graph_bounds": [vp, i32, vp, vp, vp],
         "tkc_graph_lb_update": [vp, vp, i32, vp, vp],
         "tkc_graph_sums": [vp, vp, i32, vp, vp],
@@ -348,6 +350,13 @@ class Graph:
         """(path, ms): 0 not computed yet, 1 device, 2 host fallback."""
         return tkc_graph_reach_info(self.h)
 
+    def harmonic_bounds(self, variant):
+        """(upper bounds with the search's margin, processing order)."""
+        ub = np.zeros(self.n, np.float64)
+        order = np.zeros(self.n, np.int32)
+        tkc_graph_harmonic_bounds(self.h, VARIANTS.get(variant, variant), ub, order)
+        return ub, order
+
     def bounds(self, variant):
         num = np.zeros(self.n, np.int64)
         den = np.zeros(self.n, np.int64)
@@ -423,6 +432,28 @@ def topk_closeness(g: Graph, k: int, variant="auto", mode="hybrid"):
     n_out, st = tkc_topk_closeness(g.h, int(k), VARIANTS.get(variant, variant), MODES.get(mode, mode),
                                    ids, S, R, F)
     return ids[:n_out], S[:n_out], R[:n_out], F[:n_out], st.as_dict()
+
+
+def tkc_topk_harmonic(g, k, variant, mode, ids, harmonic):
+    n_out = ctypes.c_int32(0)
+    st = tkc_stats()
+    _check(lib.tkc_topk_harmonic(g, k, variant, mode, _ptr(ids), _ptr(harmonic), ctypes.byref(n_out),
+                                 ctypes.byref(st)))
+    return n_out.value, st
+
+
+def tkc_graph_harmonic_bounds(g, variant, ub, order=None):
+    _check(lib.tkc_graph_harmonic_bounds(g, variant, _ptr(ub), _ptr(order)))
+
+
+def topk_harmonic(g: Graph, k: int, variant="auto", mode="batched"):
+    """(ids int32, harmonic float64, stats) of the top min(k, n) by harmonic
+    centrality, larger first, ties to the smaller id."""
+    cap = max(1, min(int(k), g.n) if k > 0 else 1)
+    ids = np.zeros(cap, np.int32)
+    h = np.zeros(cap, np.float64)
+    n_out, st = tkc_topk_harmonic(g.h, int(k), VARIANTS.get(variant, variant), MODES.get(mode, mode), ids, h)
+    return ids[:n_out], h[:n_out], st.as_dict()
 
 
 def topk_closeness_ties(g: Graph, k: int, variant="auto", mode="hybrid", cap=None):
