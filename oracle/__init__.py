@@ -48,6 +48,9 @@ def _L():
                                          np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS"), c.c_int]
         lib.oracle_nb_harmonic.argtypes = [c.c_int32, c.c_int64, i32p, c.c_int, i64p,
                                             np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")]
+        lib.oracle_lb_harmonic.argtypes = [c.c_int32, c.c_int64, i32p, c.c_int, c.c_int32, c.c_void_p,
+                                            np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")]
+        lib.oracle_lb_harmonic.restype = c.c_int64
         lib.oracle_threads.restype = c.c_int
         lib.oracle_arcs.argtypes = [c.c_int32, c.c_int64, i32p, c.c_int]
         lib.oracle_arcs.restype = c.c_int64
@@ -156,6 +159,21 @@ def deg_harmonic(n, edges, directed, omega=None):
         if omega[v] > 1:
             out[v] = float(deg[v]) + float(omega[v] - 1 - deg[v]) / 2.0
     return out
+
+
+def lb_harmonic(n, edges, directed, s, scc_ids=None):
+    """Level-based upper bound on the harmonic centrality from a complete
+    search at s (oracle.c); -1 where it does not apply.  Returns (r(s), ub)."""
+    e = _edges(edges)
+    out = np.zeros(max(1, n), dtype=np.float64)
+    if scc_ids is not None:
+        sc = np.ascontiguousarray(scc_ids, dtype=np.int32)
+        ptr = sc.ctypes.data_as(ctypes.c_void_p)
+    else:
+        sc = None
+        ptr = None
+    r = _L().oracle_lb_harmonic(n, e.size // 2, e, int(directed), int(s), ptr, out)
+    return int(r), out[:n]
 
 
 def harmonic_topk(h, k):

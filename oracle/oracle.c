@@ -795,3 +795,52 @@ int64_t oracle_lb_source(int32_t n, int64_t ne, const int32_t *ed, int directed,
     free(gam); free(lev); free(dist); free(queue); adj_free(&A);
     return tail;
 }
+
+/* Level-based upper bound on the harmonic centrality from one complete
+ * search at s (Sect. 7's argument with f(d) = 1/d): a vertex x at level i
+ * and w at level l satisfy d(w,x) >= |i - l| (undirected; directed and in
+ * the SCC of s, d(w,x) >= i - l, Sect. 8.3), and d(w,x) >= 2 for every x
+ * but w's deg(w) out-neighbours, which sit at exactly 1.  So
+ *   h(w) <= sum over x != w of 1 / max(2, t(x)) + deg(w) / 2,
+ * t = |i - l| or i - l.  w reaches exactly what s reaches (same component,
+ * or same SCC), so the sum runs over the vertices s reached.
+ * Binary64 reading (the device computes the same): per level l, the terms
+ * n_i / max(2, t) added in increasing i, then 1/2 (w itself) subtracted;
+ * the bound is that plus 0.5 * deg(w).  ub[v] = -1 where it does not apply
+ * (v = s, not reached, or another SCC).  Returns r(s). */
+int64_t oracle_lb_harmonic(int32_t n, int64_t ne, const int32_t *ed, int directed, int32_t s,
+                           const int32_t *scc, double *ub) {
+    oadj A;
+    if (adj_build(n, ne, ed, directed, 0, &A)) return -1;
+    int32_t *dist = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    for (int32_t i = 0; i < n; i++) dist[i] = -1;
+    int64_t head = 0, tail = 0;
+    dist[s] = 0; queue[tail++] = s;
+    while (head < tail) {
+        int32_t u = queue[head++];
+        for (int64_t q = A.off[u]; q < A.off[u + 1]; q++)
+            if (dist[A.nbr[q]] < 0) { dist[A.nbr[q]] = dist[u] + 1; queue[tail++] = A.nbr[q]; }
+    }
+    int32_t maxD = dist[queue[tail - 1]];
+    int64_t *cnt = (int64_t *)calloc((size_t)maxD + 1, sizeof(int64_t));
+    for (int64_t q = 0; q < tail; q++) cnt[dist[queue[q]]]++;
+    double *lev = (double *)calloc((size_t)maxD + 1, sizeof(double));
+    for (int32_t l = 0; l <= maxD; l++) {
+        double x = 0.0;
+        for (int32_t i = 0; i <= maxD; i++) {
+            int64_t t = directed ? (int64_t)i - l : (i > l ? (int64_t)i - l : (int64_t)l - i);
+            x += (double)cnt[i] / (double)(t < 2 ? 2 : t);
+        }
+        lev[l] = x - 0.5;
+    }
+    for (int32_t v = 0; v < n; v++) ub[v] = -1.0;
+    for (int64_t q = 1; q < tail; q++) {
+        int32_t v = queue[q];
+        if (directed && scc && scc[v] != scc[s]) continue;
+        int64_t d = A.off[v + 1] - A.off[v];
+        ub[v] = lev[dist[v]] + 0.5 * (double)d;
+    }
+    free(cnt); free(lev); free(dist); free(queue); adj_free(&A);
+    return tail;
+}

@@ -200,3 +200,45 @@ def test_repeated_arcs_and_self_loops_count_once(directed):
     noisy = E([(0, 1), (0, 1), (1, 2), (2, 2), (2, 3), (3, 0), (0, 4), (0, 4), (4, 4)])
     for f in (oracle.harmonic, oracle.nb_harmonic, oracle.deg_harmonic):
         assert np.array_equal(f(6, noisy, directed), f(6, clean, directed)), f.__name__
+
+
+# ------------------------------------------- level-based bound (Sect. 7, 8.3)
+def test_lb_exact_on_path_and_star():
+    """Paths (from an end) and stars (from a leaf): the level structure pins
+    every distance, so the bound is h itself up to rounding."""
+    n = 40
+    e = E([(i, i + 1) for i in range(n - 1)])
+    h = oracle.harmonic(n, e, False)
+    r, ub = oracle.lb_harmonic(n, e, False, 0)
+    assert r == n and ub[0] == -1.0
+    for w in range(1, n):
+        assert close(ub[w], H(w) + H(n - 1 - w), 2 * n)
+    n = 12
+    e = E([(0, i) for i in range(1, n)])
+    r, ub = oracle.lb_harmonic(n, e, False, 3)
+    assert ub[0] == n - 1                       # the centre: n-1 neighbours
+    for w in range(1, n):
+        if w != 3:
+            assert ub[w] == n / 2               # a leaf: 1 + (n-2)/2
+
+
+@pytest.mark.parametrize("directed", [False, True])
+@pytest.mark.parametrize("seed", range(40))
+def test_lb_above_h(directed, seed):
+    """Every applicable bound (same component, or same SCC) stays above the
+    exact Floyd-Warshall value, from every source."""
+    rng = np.random.default_rng(7000 + seed + (1000 if directed else 0))
+    n = int(rng.integers(2, 30))
+    p = float(rng.uniform(0.05, 0.4))
+    pairs = {(u, w) for u in range(n) for w in range(n)
+             if u != w and rng.random() < p and (directed or u < w)}
+    e = E(sorted(pairs))
+    exact = [sum((Fraction(c, d) for d, c in lv.items()), Fraction(0)) for lv in fw_levels(n, e, directed)]
+    scc = oracle.scc(n, e)[1] if directed else None
+    for s in range(n):
+        r, ub = oracle.lb_harmonic(n, e, directed, s, scc)
+        for w in range(n):
+            if ub[w] >= 0:
+                assert ub[w] >= float(exact[w]) - 1e-12 * max(1.0, float(exact[w])), (s, w)
+                if directed:
+                    assert scc[w] == scc[s]
