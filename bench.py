@@ -181,6 +181,47 @@ def cpu_baseline(g, seconds: float):
             "wall_s": wall, "sources": count, "all_sources_extrapolated_s": full_s}
 
 
+def reach_bench(args):
+    """Reachability bounds of one workload (Sect. 8.4, Alg. 6), computed once
+    per graph: the device path, then the host fallback forced on a second
+    upload of the same graph; both must agree.  Prints one JSON line."""
+    import torch
+    import graphgen
+    from paper_1704_01077_amd import tkc
+    torch.cuda.init()
+    g = graphgen.workload(args.workload)
+    ctx = tkc.Context(0)
+    out = {"metric": "reachability bounds (SCC + Alg. 6) wall time", "unit": "ms", "higher_is_better": False,
+           "config": {"workload": WORKLOADS.get(args.workload, args.workload), "n": g.n}}
+    res = {}
+    for path in ("device", "host"):
+        if path == "host":
+            os.environ["TKC_REACH"] = "host"
+        try:
+            dg = tkc.Graph.from_graphgen(ctx, g)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            a, o, sc = dg.reach()
+            wall = (time.perf_counter() - t) * 1e3
+            used, ms = dg.reach_info()
+            res[path] = (a, o, sc)
+            out[path] = {"wall_ms": round(wall, 3), "library_ms": round(ms, 3),
+                         "path_used": {1: "device", 2: "host"}.get(used, used)}
+            dg.free()
+        finally:
+            os.environ.pop("TKC_REACH", None)
+        print("bench: reach %s %.1f ms" % (path, wall), file=sys.stderr, flush=True)
+    a1, o1, s1 = res["device"]
+    a2, o2, s2 = res["host"]
+    same = bool(np.array_equal(a1, a2) and np.array_equal(o1, o2))
+    if s1 is not None:
+        same = same and len(set(zip(s1.tolist(), s2.tolist()))) == len(set(s2.tolist()))
+        out["components"] = int(len(set(s2.tolist())))
+    out["same_result"] = same
+    out["value"] = out["device"]["library_ms"]
+    print(json.dumps(out))
+
+
 def serve_bench(args):
     """Serving mix: a resident pool of seeded graphs (BA, R-MAT, king-move
     lattices; n log-uniform in [1e3, 1e6], average degree 8-16), top-k
@@ -302,6 +343,8 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration)")
     ap.add_argument("--serve", action="store_true", help="run the serving-mix benchmark instead")
+    ap.add_argument("--reach-only", action="store_true",
+                    help="time the reachability bounds of --workload (device and host paths) instead")
     ap.add_argument("--serve-graphs", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-sat", type=int, default=400, help="requests of the saturation run")
@@ -333,6 +376,9 @@ def main():
         sys.exit(2)
     if args.serve:
         serve_bench(args)
+        return
+    if args.reach_only:
+        reach_bench(args)
         return
 
     import torch

@@ -184,13 +184,14 @@ int tkc_topk_closeness(tkc_graph *g, int32_t k, int32_t variant, int32_t mode,
  * 9.1).  h is the binary64 value of the terms n_d / d added in increasing d
  * (n_d = vertices at distance d), exactly as the library computes it; the
  * order is larger h first, an exact tie to the smaller id.  variant:
- * TKC_AUTO (= TKC_NB_CUT), TKC_DEG_CUT or TKC_NB_CUT with upper bounds in
- * place of the farness lower bounds (degree: the out-neighbours at distance
- * 1, every other reachable vertex at distance 2; walk counts: levels filled
- * as close as the counts of Sect. 5 allow); other variants give
- * TKC_EINVAL.  mode: TKC_PLAIN or TKC_BATCHED (TKC_HYBRID and
- * TKC_MODE_AUTO run batched).  *n_out = min(k, n) results in order: ids
- * and harmonic values.  stats may be NULL. */
+ * any of them, with upper bounds in place of the farness lower bounds
+ * (degree: the out-neighbours at distance 1, every other reachable vertex
+ * at distance 2; walk counts: levels filled as close as the counts of
+ * Sect. 5 allow; level-based: every vertex at least max(2, level gap)
+ * away from w but its out-neighbours, see tkc_graph_harmonic_lb_update).
+ * mode: TKC_PLAIN or TKC_BATCHED (TKC_HYBRID runs batched; TKC_MODE_AUTO
+ * as for closeness).  *n_out = min(k, n) results in order: ids and
+ * harmonic values.  stats may be NULL. */
 int tkc_topk_harmonic(tkc_graph *g, int32_t k, int32_t variant, int32_t mode,
                       int32_t *ids, double *harmonic, int32_t *n_out, tkc_stats *stats);
 /* The harmonic upper bounds a harmonic query starts from (variant
@@ -198,6 +199,15 @@ int tkc_topk_harmonic(tkc_graph *g, int32_t k, int32_t variant, int32_t mode,
  * 1e-9 the search applies to every bound, and the processing order
  * (largest bound first, ties by id; may be NULL).  Host arrays of n. */
 int tkc_graph_harmonic_bounds(tkc_graph *g, int32_t variant, double *ub, int32_t *order);
+/* Level-based update of harmonic upper bounds (Sect. 7's argument with
+ * f(d) = 1/d): after a complete search from s, a vertex w that s reaches
+ * (same SCC of s for directed graphs) has h(w) <= the sum over the other
+ * vertices s reaches of 1/max(2, level gap) (gap |i - l|, directed i - l)
+ * plus 1/2 per out-neighbour of w; the binary64 value is the per-level sum
+ * in increasing level, minus w's own 1/2, plus 0.5 * deg(w).  Each bound is
+ * raised by the 1e-9 margin and ub[w] becomes the least of its old value
+ * and those bounds.  ub: host array of n finite values >= 0, in place. */
+int tkc_graph_harmonic_lb_update(tkc_graph *g, const int32_t *sources, int32_t count, double *ub);
 
 /* Autotuner: times the query (k, variant) on g under candidate knob
  * settings, one knob at a time (batch width, mode, workgroups per CU, the

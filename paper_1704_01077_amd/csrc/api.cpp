@@ -702,8 +702,7 @@ extern "C" int tkc_topk_harmonic(tkc_graph* g, int32_t k, int32_t variant, int32
                                  double* harmonic, int32_t* n_out, tkc_stats* stats) {
     if (!g || !ids || !n_out) return tkc_fail(TKC_EINVAL, "NULL argument");
     if (k < 1) return tkc_fail(TKC_EINVAL, "k must be >= 1");
-    if (variant != TKC_AUTO && variant != TKC_DEG_CUT && variant != TKC_NB_CUT)
-        return tkc_fail(TKC_EINVAL, "harmonic centrality runs TKC_AUTO, TKC_DEG_CUT or TKC_NB_CUT, not %d", variant);
+    if (variant < TKC_AUTO || variant > TKC_NB_CUTLB) return tkc_fail(TKC_EINVAL, "unknown variant %d", variant);
     if (mode < TKC_PLAIN || mode > TKC_MODE_AUTO) return tkc_fail(TKC_EINVAL, "unknown mode %d", mode);
     tkc_ctx* c = g->ctx;
     HIPCHK(hipSetDevice(c->device));
@@ -812,9 +811,8 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
         c->tune = keep;
         return rc;
     }
-    // AUTO: high-diameter graphs favour level-based updates (Sect. 9.1);
-    // harmonic centrality runs the Cut variants only
-    if (variant == TKC_AUTO) variant = harm ? TKC_NB_CUT : tkc_auto_variant(c, g);
+    // AUTO: high-diameter graphs favour level-based updates (Sect. 9.1)
+    if (variant == TKC_AUTO) variant = tkc_auto_variant(c, g);
     const int lbl = tkc_lb_level(variant);
     const bool lb = lbl != 0;
     const bool nb = tkc_is_nb(variant);
@@ -1104,14 +1102,14 @@ extern "C" int tkc_graph_reach(tkc_graph* g, int64_t* alpha, int64_t* omega, int
 
 extern "C" int tkc_graph_harmonic_bounds(tkc_graph* g, int32_t variant, double* ub, int32_t* order) {
     if (!g || !ub) return tkc_fail(TKC_EINVAL, "NULL argument");
-    if (variant != TKC_DEG_CUT && variant != TKC_NB_CUT) return tkc_fail(TKC_EINVAL, "bad variant");
+    if (variant < TKC_DEG_CUT || variant > TKC_NB_CUTLB) return tkc_fail(TKC_EINVAL, "bad variant");
     tkc_ctx* c = g->ctx;
     HIPCHK(hipSetDevice(c->device));
     int rc = tkc_ws_reserve(c, c->ws, tkc_shape_for(c->tune, g, 1, false));
     if (rc) return rc;
     rc = tkc_step_reach(c, g, c->ws);
     if (rc) return rc;
-    rc = tkc_step_bounds(c, g, c->ws, variant == TKC_NB_CUT, nullptr, true);
+    rc = tkc_step_bounds(c, g, c->ws, tkc_is_nb(variant), nullptr, true);
     if (rc) return rc;
     const size_t n = g->n;
     std::vector<int64_t> f(n);
@@ -1228,6 +1226,55 @@ extern "C" int tkc_graph_lb_update(tkc_graph* g, const int32_t* sources, int32_t
     HIPCHK(hipMemcpyAsync(num, ws.lnum, 8 * (size_t)g->n, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(den, ws.lden, 8 * (size_t)g->n, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    return TKC_OK;
+}
+
+extern "C" int tkc_graph_harmonic_lb_update(tkc_graph* g, const int32_t* sources, int32_t count, double* ub) {
+    if (!g || !sources || !ub || count < 0) return tkc_fail(TKC_EINVAL, "bad argument");
+    for (int32_t i = 0; i < count; i++)
+        if (sources[i] < 0 || sources[i] >= g->n) return tkc_fail(TKC_EINVAL, "source %d out of range", sources[i]);
+    for (int32_t v = 0; v < g->n; v++)
+        if (!(ub[v] >= 0.0) || ub[v] == INFINITY) return tkc_fail(TKC_EINVAL, "bound %d is not finite and >= 0", v);
+    tkc_ctx* c = g->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    Workspace& ws = c->ws;
+    int rc = tkc_ws_reserve(c, ws, tkc_shape_for(c->tune, g, 1, true));
+    if (rc) return rc;
+    rc = tkc_step_reach(c, g, ws);
+    if (rc) return rc;
+    const size_t n = g->n;
+    std::vector<int64_t> f(n), one(n, 1);
+    for (size_t v = 0; v < n; v++) {
+        int64_t bits;
+        memcpy(&bits, &ub[v], 8);
+        f[v] = (int64_t)0x7FF0000000000000LL - bits;
+    }
+    HIPCHK(hipMemcpyAsync(ws.lnum, f.data(), 8 * n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ws.lden, one.data(), 8 * n, hipMemcpyHostToDevice, s));
+    DevTopk tk = topk_view(ws);
+    if (tkc_launch_topk_init(tk, 1, s)) return tkc_fail(TKC_EDEVICE, "top-k init failed");
+    HIPCHK(hipMemsetAsync(ws.stats, 0, 8 * ST_COUNT, s));
+    DevReach rcv{ws.alpha, ws.omega, g->directed ? ws.scc : nullptr};
+    OrderView ov{ws.ord, ws.key, 0, false};
+    BoundsView bv{ws.lnum, ws.lden};
+    bv.harm = 1;
+    int grid = 0;
+    for (int32_t off = 0; off < count; off += g->n) {
+        int32_t cnt = std::min(count - off, g->n);
+        HIPCHK(hipMemcpyAsync(ws.s_deferred, sources + off, 4 * (size_t)cnt, hipMemcpyHostToDevice, s));
+        std::lock_guard<std::mutex> lk(tkc_coop_mutex());
+        if (tkc_launch_batch(g->view(), rcv, ov, bv, tk, batch_view(ws), ws.stats, ws.s_deferred, cnt, 0, 0,
+                             1, true, ws.b_outS, ws.b_outR, c->tune, s, &grid))
+            return tkc_fail(TKC_EDEVICE, "batched engine launch failed");
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    HIPCHK(hipMemcpyAsync(f.data(), ws.lnum, 8 * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (size_t v = 0; v < n; v++) {
+        const int64_t bits = (int64_t)0x7FF0000000000000LL - f[v];
+        memcpy(&ub[v], &bits, 8);
+    }
     return TKC_OK;
 }
 

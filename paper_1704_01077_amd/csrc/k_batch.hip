@@ -1035,7 +1035,47 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             // every level's counts and levels fit the tables (same value in
             // every workgroup: D is replicated)
             const bool lbok = D < a.w.lcap;
-            if (lbok) {
+            if (lbok && a.bv.harm) {
+                // harmonic centrality: per exact lane and level l the sum
+                // over levels i of n_i / max(2, gap) minus w's own 1/2, in
+                // increasing i (entries spread over the whole grid)
+                const int64_t L1 = D + 1;
+                for (int64_t q = gtid; q < (int64_t)nsel * L1; q += nthreads) {
+                    const int l = (int)(q / L1);
+                    const int64_t lv = q % L1;
+                    if (s_st[l] != 2 || lv > s_maxD[l]) continue;
+                    double x = 0.0;
+                    for (int64_t i = 0; i <= s_maxD[l]; i++) {
+                        const int64_t t = dir ? i - lv : (i > lv ? i - lv : lv - i);
+                        x += (double)a.w.hist[i * W + l] / (double)(t < 2 ? 2 : t);
+                    }
+                    a.w.levtab[lv * W + l] = __double_as_longlong(x - 0.5);
+                }
+                grid_barrier(a.bar, gridDim.x);
+                // every vertex takes the least bound over the lanes that
+                // reached it, its out-neighbours at exactly 1
+                for (int64_t w = gtid; w < n; w += nthreads) {
+                    double best = 0.0;
+                    bool any = false;
+#pragma unroll
+                    for (int j = 0; j < NW; j++) {
+                        uint64_t m = vis[w * NW + j];
+                        while (m) {
+                            int l = j * 64 + __ffsll((long long)m) - 1;
+                            m &= m - 1;
+                            if (l >= nsel || s_st[l] != 2 || s_v[l] == w) continue;
+                            if (dir && a.rc.scc[w] != a.rc.scc[s_v[l]]) continue;
+                            const int64_t lv = a.w.lvl[w * W + l];
+                            const double b = __longlong_as_double(a.w.levtab[lv * W + l]) + 0.5 * (double)deg[w];
+                            if (!any || b < best) { best = b; any = true; }
+                        }
+                    }
+                    if (any) {
+                        const int64_t f = harm_enc(best * (1.0 + HARM_MARGIN));
+                        if (rat_cmp(f, 1, a.bv.num[w], a.bv.den[w]) > 0) { a.bv.num[w] = f; a.bv.den[w] = 1; }
+                    }
+                }
+            } else if (lbok) {
                 if (blockIdx.x == 0 && tid < nsel && s_st[tid] == 2) {
                     int l = tid;
                     int64_t maxD = s_maxD[l];

@@ -357,7 +357,29 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
             if (a.lb_mode && boss) a.w.levcnt[D] = cnt;
         }
         const int64_t maxD = D - (status == 1 ? 1 : 0);
-        if (a.lb_mode && status == 1) {
+        if (a.lb_mode && status == 1 && a.bv.harm) {
+            // harmonic centrality: per level l the sum over levels i of
+            // n_i / max(2, gap) minus w's own 1/2, in increasing i; then
+            // every reached vertex adds its out-neighbours' 1/2 each
+            for (int64_t lv = gtid; lv <= maxD; lv += nthreads) {
+                double xs = 0.0;
+                for (int64_t i = 0; i <= maxD; i++) {
+                    const int64_t t = dir ? i - lv : (i > lv ? i - lv : lv - i);
+                    xs += (double)a.w.levcnt[i] / (double)(t < 2 ? 2 : t);
+                }
+                a.w.levtab[lv] = __double_as_longlong(xs - 0.5);
+            }
+            grid_barrier(a.bar, gridDim.x);
+            const int32_t sc = dir ? a.rc.scc[v] : 0;
+            for (int64_t i = gtid; i < en[0] + en[1]; i += nthreads) {
+                int32_t w = i < en[0] ? a.w.ql[i] : a.w.qh[i - en[0]];
+                if (w == v) continue;
+                if (dir && a.rc.scc[w] != sc) continue;
+                const double b = __longlong_as_double(a.w.levtab[a.w.lvl[w]]) + 0.5 * (double)deg[w];
+                const int64_t f = harm_enc(b * (1.0 + HARM_MARGIN));
+                if (rat_cmp(f, 1, a.bv.num[w], a.bv.den[w]) > 0) { a.bv.num[w] = f; a.bv.den[w] = 1; }
+            }
+        } else if (a.lb_mode && status == 1) {
             // level-based update of every reached vertex (Sect. 7)
             if (boss) {
                 a.w.levcnt[D] = 0;

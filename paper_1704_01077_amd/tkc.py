@@ -36,7 +36,7 @@ MODES = {"plain": TKC_PLAIN, "batched": TKC_BATCHED, "hybrid": TKC_HYBRID, "auto
 
 EXPORTS = [
     "tkc_ctx_create", "tkc_ctx_destroy", "tkc_ctx_get_tuning", "tkc_ctx_set_tuning", "tkc_graph_upload",
-    "tkc_graph_free", "tkc_topk_closeness", "tkc_topk_closeness_ties", "tkc_autotune", "tkc_graph_reach", "tkc_graph_reach_info", "tkc_graph_bounds", "tkc_topk_harmonic", "tkc_graph_harmonic_bounds", "tkc_graph_lb_update",
+    "tkc_graph_free", "tkc_topk_closeness", "tkc_topk_closeness_ties", "tkc_autotune", "tkc_graph_reach", "tkc_graph_reach_info", "tkc_graph_bounds", "tkc_topk_harmonic", "tkc_graph_harmonic_bounds", "tkc_graph_harmonic_lb_update", "tkc_graph_lb_update",
     "tkc_graph_sums", "tkc_server_create", "tkc_server_add_graph", "tkc_server_submit",
     "tkc_server_poll", "tkc_server_result", "tkc_server_cancel", "tkc_server_destroy",
     "tkc_last_error", "tkc_version",
@@ -102,6 +102,7 @@ def _load():
         "tkc_graph_reach_info": [vp, P(i32), P(c.c_double)],
         "tkc_topk_harmonic": [vp, i32, i32, i32, vp, vp, P(i32), P(tkc_stats)],
         "tkc_graph_harmonic_bounds": [vp, i32, vp, vp],
+        "tkc_graph_harmonic_lb_update": [vp, vp, i32, vp],
         "tkc_graph_bounds": [vp, i32, vp, vp, vp],
         "tkc_graph_lb_update": [vp, vp, i32, vp, vp],
         "tkc_graph_sums": [vp, vp, i32, vp, vp],
@@ -357,6 +358,11 @@ class Graph:
         tkc_graph_harmonic_bounds(self.h, VARIANTS.get(variant, variant), ub, order)
         return ub, order
 
+    def harmonic_lb_update(self, sources, ub):
+        ub = np.ascontiguousarray(ub, dtype=np.float64).copy()
+        tkc_graph_harmonic_lb_update(self.h, np.ascontiguousarray(sources, dtype=np.int32), ub)
+        return ub
+
     def bounds(self, variant):
         num = np.zeros(self.n, np.int64)
         den = np.zeros(self.n, np.int64)
@@ -444,6 +450,10 @@ def tkc_topk_harmonic(g, k, variant, mode, ids, harmonic):
 
 def tkc_graph_harmonic_bounds(g, variant, ub, order=None):
     _check(lib.tkc_graph_harmonic_bounds(g, variant, _ptr(ub), _ptr(order)))
+
+
+def tkc_graph_harmonic_lb_update(g, sources, ub):
+    _check(lib.tkc_graph_harmonic_lb_update(g, _ptr(sources), len(sources), _ptr(ub)))
 
 
 def topk_harmonic(g: Graph, k: int, variant="auto", mode="batched"):

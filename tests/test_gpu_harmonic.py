@@ -80,7 +80,7 @@ def graph(name):
         return _g(name, 50, np.zeros((0, 2), np.int32), False)
     if name == "sinks":
         return _g(name, 40, np.zeros((0, 2), np.int32), True)
-    if name in ("ba1m", "rmat20"):
+    if name in ("ba1m", "rmat20", "grid2000"):
         return graphgen.workload(name)
     raise KeyError(name)
 
@@ -92,7 +92,7 @@ _DEV = {}
 
 def dev(ctx, name):
     if name not in _DEV:
-        _DEV[name] = tkc.Graph.from_graphgen(ctx, graph(name), validate=name not in ("ba1m", "rmat20"))
+        _DEV[name] = tkc.Graph.from_graphgen(ctx, graph(name), validate=name not in ("ba1m", "rmat20", "grid2000"))
     return _DEV[name]
 
 
@@ -103,7 +103,7 @@ def truth(name):
 
 
 @pytest.mark.parametrize("name", SMALL)
-@pytest.mark.parametrize("variant", ["degcut", "nbcut", "auto"])
+@pytest.mark.parametrize("variant", ["degcut", "nbcut", "degbound", "nbbound", "degcutlb", "nbcutlb", "auto"])
 @pytest.mark.parametrize("mode", ["plain", "batched", "hybrid"])
 @pytest.mark.parametrize("k", [1, 10, 100])
 def test_harmonic_topk_parity(ctx, name, variant, mode, k):
@@ -117,7 +117,7 @@ def test_harmonic_topk_parity(ctx, name, variant, mode, k):
 
 
 @pytest.mark.parametrize("name", ["ba20k", "grid150", "rmat13", "king40"])
-@pytest.mark.parametrize("variant", ["degcut", "nbcut"])
+@pytest.mark.parametrize("variant", ["degcut", "nbcut", "nbbound", "nbcutlb"])
 @pytest.mark.parametrize("mode", ["plain", "batched"])
 def test_harmonic_topk_medium(ctx, name, variant, mode):
     h = truth(name)
@@ -161,12 +161,31 @@ def test_harmonic_bounds_parity(ctx, name):
         assert np.all(np.diff(ub[order]) <= ub[order][:-1] * 2.0 ** -19)
 
 
-def test_harmonic_rejects_level_variants(ctx):
+def test_harmonic_rejects_unknown_variant(ctx):
     dg = dev(ctx, "ba2k")
-    for variant in ("degbound", "nbbound", "nbcutlb"):
-        with pytest.raises(tkc.TkcError) as e:
-            tkc.topk_harmonic(dg, 10, variant, "batched")
-        assert e.value.code == tkc.TKC_EINVAL
+    with pytest.raises(tkc.TkcError) as e:
+        tkc.topk_harmonic(dg, 10, 7, "batched")
+    assert e.value.code == tkc.TKC_EINVAL
+
+
+@pytest.mark.parametrize("name", ["ba2k", "gnp_u", "forest", "grid60", "gnp_d", "rmat11", "dpath", "star"])
+def test_harmonic_lb_update_parity(ctx, name):
+    """The level-based update of a few complete searches, bit for bit: the
+    least of the old bound and the oracle's bounds (raised by the margin)."""
+    g = graph(name)
+    dg = dev(ctx, name)
+    ub0, _ = dg.harmonic_bounds("nbcut")
+    rng = np.random.default_rng(3)
+    src = np.unique(rng.integers(0, g.n, size=5)).astype(np.int32)
+    got = dg.harmonic_lb_update(src, ub0)
+    scc = oracle.scc(g.n, g.edges)[1] if g.directed else None
+    want = ub0.copy()
+    for s_ in src.tolist():
+        _, b = oracle.lb_harmonic(g.n, g.edges, g.directed, s_, scc)
+        ok = b >= 0
+        want[ok] = np.minimum(want[ok], b[ok] * MARGIN)
+    assert np.array_equal(got, want), np.flatnonzero(got != want)[:5]
+    assert np.all(got >= truth(name))
 
 
 def test_harmonic_and_closeness_interleave(ctx):
@@ -185,11 +204,11 @@ def test_harmonic_and_closeness_interleave(ctx):
 
 # full size: every returned value from the oracle one source at a time, the
 # order, and sampled outsiders (random plus the highest-degree vertices)
-@pytest.mark.parametrize("name", ["ba1m", "rmat20"])
+@pytest.mark.parametrize("name", ["ba1m", "rmat20", "grid2000"])
 def test_harmonic_full(ctx, name):
     g = graph(name)
     dg = dev(ctx, name)
-    ids, hv, st = tkc.topk_harmonic(dg, 10, "nbcut", "batched")
+    ids, hv, st = tkc.topk_harmonic(dg, 10, "auto", "batched")
     assert len(ids) == 10 and len(set(ids.tolist())) == 10
     assert np.array_equal(hv, oracle.harmonic(g.n, g.edges, g.directed, sources=ids))
     for i in range(1, 10):
@@ -203,6 +222,9 @@ def test_harmonic_full(ctx, name):
     ho = oracle.harmonic(g.n, g.edges, g.directed, sources=out)
     for v, x in zip(out.tolist(), ho.tolist()):
         assert x < hv[-1] or (x == hv[-1] and v > ids[-1]), (v, x)
+    if name == "grid2000":
+        assert st["variant_used"] == tkc.TKC_NB_BOUND
+        return
     ids2, hv2, _ = tkc.topk_harmonic(dg, 10, "nbcut", "plain")
     assert np.array_equal(ids2, ids) and np.array_equal(hv2, hv)
     ids3, hv3, _ = tkc.topk_harmonic(dg, 10, "degcut", "batched")
