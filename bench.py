@@ -222,6 +222,41 @@ def reach_bench(args):
     print(json.dumps(out))
 
 
+def harmonic_bench(args):
+    """Top-k harmonic centrality (Sect. 2 with f(d) = 1/d) on --workload:
+    --warmup untimed queries, then --steps timed ones.  Prints one JSON line."""
+    import torch
+    import graphgen
+    from paper_1704_01077_amd import tkc
+    torch.cuda.init()
+    g = graphgen.workload(args.workload)
+    ctx = tkc.Context(0)
+    dg = tkc.Graph.from_graphgen(ctx, g)
+    mode = "batched" if args.mode == "hybrid" else args.mode
+    for _ in range(args.warmup):
+        tkc.topk_harmonic(dg, args.k, args.variant, mode)
+    torch.cuda.synchronize()
+    walls = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        ids, h, st = tkc.topk_harmonic(dg, args.k, args.variant, mode)
+        torch.cuda.synchronize()
+        walls.append((time.perf_counter() - t0) * 1e3)
+    walls = np.array(walls)
+    out = {"metric": "top-k harmonic centrality wall time", "value": round(float(walls.mean()), 4), "unit": "ms",
+           "higher_is_better": False, "steps": args.steps, "warmup": args.warmup, "dtype": "f64",
+           "config": {"workload": WORKLOADS.get(args.workload, args.workload), "k": args.k,
+                      "variant": args.variant, "variant_used": st["variant_used"], "mode": mode},
+           "wall_ms_p50": round(float(np.percentile(walls, 50)), 4),
+           "wall_ms_p99": round(float(np.percentile(walls, 99)), 4),
+           "m_vis": st["m_vis"],
+           "phase_ms": {"reach": st["ms_reach"], "bounds": st["ms_bounds"], "traverse": st["ms_traverse"]},
+           "searches": {"started": st["bfs_started"], "exact": st["bfs_exact"], "cut": st["bfs_cut"],
+                        "skipped": st["skipped"], "max_level": st["max_level"]},
+           "top": [[int(i), float(x)] for i, x in zip(ids[:3], h[:3])]}
+    print(json.dumps(out))
+
+
 def serve_bench(args):
     """Serving mix: a resident pool of seeded graphs (BA, R-MAT, king-move
     lattices; n log-uniform in [1e3, 1e6], average degree 8-16), top-k
@@ -343,6 +378,8 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration)")
     ap.add_argument("--serve", action="store_true", help="run the serving-mix benchmark instead")
+    ap.add_argument("--harmonic", action="store_true",
+                    help="time top-k harmonic centrality on --workload instead")
     ap.add_argument("--reach-only", action="store_true",
                     help="time the reachability bounds of --workload (device and host paths) instead")
     ap.add_argument("--serve-graphs", type=int, default=64)
@@ -379,6 +416,9 @@ def main():
         return
     if args.reach_only:
         reach_bench(args)
+        return
+    if args.harmonic:
+        harmonic_bench(args)
         return
 
     import torch

@@ -23,6 +23,7 @@ struct DevGraph {
     const int32_t* hcb;
     const int32_t* ch_beg;
     const int32_t* ch_end;
+    const int32_t* ch_vtx;   // owner of each chunk
     int32_t nchunks;
     // in-arc chunks of the vertices with more than HEAVY_DEG in-arcs (pull
     // steps; the same table as above for undirected graphs)

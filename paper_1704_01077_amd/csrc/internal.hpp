@@ -115,7 +115,7 @@ struct tkc_graph {
         DevGraph g;
         g.n = n; g.m = m; g.directed = directed;
         g.rp = rp; g.ci = ci; g.rrp = rrp; g.rci = rci; g.deg = deg;
-        g.heavy = heavy; g.nheavy = nheavy; g.hcb = hcb; g.ch_beg = ch_beg; g.ch_end = ch_end;
+        g.heavy = heavy; g.nheavy = nheavy; g.hcb = hcb; g.ch_beg = ch_beg; g.ch_end = ch_end; g.ch_vtx = ch_vtx;
         g.nchunks = nchunks;
         g.rch_vtx = rch_vtx; g.rch_beg = rch_beg; g.rch_end = rch_end; g.rnchunks = rnchunks;
         g.bch_vtx = bch_vtx; g.bch_beg = bch_beg; g.bch_end = bch_end; g.bnchunks = bnchunks;

@@ -57,6 +57,52 @@ __device__ __forceinline__ int64_t wave_max_i64(int64_t v) {
     return v;
 }
 
+// Reductions and appends to one global address are aggregated per block
+// (grid-strided over at most RB blocks): same-address atomics serialise,
+// so one per wave over a million vertices costs a few hundred microseconds.
+#define RB 1024
+static inline int rblk(int64_t n) {
+    const int b = nblk(n);
+    return b < 1 ? 1 : (b < RB ? b : RB);
+}
+__device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v, unsigned long long* sh) {
+    v = wave_max_u64(v);
+    if (lane_id() == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    unsigned long long r = sh[0];
+    for (int w = 1; w < SB / 64; w++) r = sh[w] > r ? sh[w] : r;
+    __syncthreads();
+    return r;
+}
+__device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t* sh) {
+    v = wave_sum_i64(v);
+    if (lane_id() == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int64_t r = 0;
+    for (int w = 0; w < SB / 64; w++) r += sh[w];
+    __syncthreads();
+    return r;
+}
+// block-wide append of the threads whose pred holds: one atomic per call
+__device__ __forceinline__ int32_t block_append_base(bool pred, int32_t* cnt, int32_t* sh, int32_t* rank) {
+    const uint64_t m = __ballot(pred);
+    const int wv = threadIdx.x >> 6;
+    if (lane_id() == 0) sh[wv] = __popcll(m);
+    __syncthreads();
+    int32_t pre = 0, tot = 0;
+    for (int w = 0; w < SB / 64; w++) {
+        pre += w < wv ? sh[w] : 0;
+        tot += sh[w];
+    }
+    if (threadIdx.x == 0) sh[SB / 64] = tot ? atomicAdd(cnt, tot) : 0;
+    __syncthreads();
+    const uint64_t below = lane_id() ? (~0ull >> (64 - lane_id())) : 0ull;
+    *rank = pre + __popcll(m & below);
+    const int32_t base = sh[SB / 64];
+    __syncthreads();
+    return base;
+}
+
 // ------------------------------------------------------------------ scan
 // exclusive scan of n int32 in place (three passes)
 __global__ void __launch_bounds__(SCAN_T) k_scan_blocks(int32_t* a, int64_t n, int32_t* bsum) {
@@ -136,20 +182,18 @@ __global__ void k_scc_init(int32_t n, const int32_t* rp, const int32_t* rrp, int
 }
 
 // a vertex without remaining in-arcs or out-arcs is a component of its own
-__global__ void k_scc_trim(int32_t n, int32_t* scc, const int32_t* in_rem, const int32_t* out_rem, int32_t* list,
-                           int32_t* cnt) {
-    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool take = v < n && scc[v] < 0 && (in_rem[v] <= 0 || out_rem[v] <= 0);
-    const uint64_t m = __ballot(take);
-    if (!m) return;
-    int32_t b = 0;
-    const int leader = __ffsll((long long)__ballot(1)) - 1;
-    if (lane_id() == leader) b = atomicAdd(cnt, __popcll(m));
-    b = __shfl(b, leader, 64);
-    if (take) {
-        scc[v] = v;
-        const uint64_t below = lane_id() ? (~0ull >> (64 - lane_id())) : 0ull;
-        list[b + __popcll(m & below)] = v;
+__global__ void __launch_bounds__(SB) k_scc_trim(int32_t n, int32_t* scc, const int32_t* in_rem,
+                                                 const int32_t* out_rem, int32_t* list, int32_t* cnt) {
+    __shared__ int32_t sh[SB / 64 + 1];
+    for (int64_t b0 = (int64_t)blockIdx.x * SB; b0 < n; b0 += (int64_t)gridDim.x * SB) {
+        const int64_t v = b0 + threadIdx.x;
+        const bool take = v < n && scc[v] < 0 && (in_rem[v] <= 0 || out_rem[v] <= 0);
+        int32_t rank;
+        const int32_t base = block_append_base(take, cnt, sh, &rank);
+        if (take) {
+            scc[v] = (int32_t)v;
+            list[base + rank] = (int32_t)v;
+        }
     }
 }
 // removed vertices take their arcs away from their neighbours' counts
@@ -165,31 +209,60 @@ __global__ void k_scc_trim_update(const int32_t* list, int32_t cnt, const int32_
 }
 
 // pivot: the unassigned vertex with the largest (in+1)(out+1), smallest id on ties
-__global__ void k_scc_pivot(int32_t n, const int32_t* scc, const int32_t* in_rem, const int32_t* out_rem,
-                            unsigned long long* best) {
-    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(SB) k_scc_pivot(int32_t n, const int32_t* scc, const int32_t* in_rem,
+                                                  const int32_t* out_rem, unsigned long long* best) {
+    __shared__ unsigned long long sh[SB / 64];
     unsigned long long key = 0;
-    if (v < n && scc[v] < 0) {
+    for (int64_t v = (int64_t)blockIdx.x * SB + threadIdx.x; v < n; v += (int64_t)gridDim.x * SB) {
+        if (scc[v] >= 0) continue;
         uint64_t p = (uint64_t)(in_rem[v] + 1) * (uint64_t)(out_rem[v] + 1);
         if (p > 0x7fffffffull) p = 0x7fffffffull;
-        key = ((unsigned long long)p << 32) | (0xffffffffull - (uint32_t)v);
+        const unsigned long long k = ((unsigned long long)p << 32) | (0xffffffffull - (uint32_t)v);
+        key = k > key ? k : key;
     }
-    key = wave_max_u64(key);
-    if (lane_id() == 0 && key) atomicMax(best, key);
+    key = block_max_u64(key, sh);
+    if (threadIdx.x == 0 && key) atomicMax(best, key);
 }
 
-// one level of a search over unassigned vertices (one wave per frontier
-// vertex); a vertex found first is given the next level number
-__global__ void k_scc_bfs(const int32_t* fr, int32_t fcnt, const int32_t* rp, const int32_t* ci, const int32_t* scc,
-                          uint32_t* mark, uint32_t bit, int32_t* lev, int32_t nl) {
-    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
-    for (int64_t i = gw; i < fcnt; i += nw) {
-        const int32_t u = fr[i];
-        for (int32_t e = rp[u] + lane_id(); e < rp[u + 1]; e += 64) {
-            const int32_t w = ci[e];
-            if (scc[w] < 0 && !(mark[w] & bit) && !(atomicOr(&mark[w], bit) & bit)) lev[w] = nl;
+// the same level as a pull: an unassigned vertex not yet found looks for a
+// predecessor found at level nl - 1 (its own thread, first hit ends it);
+// used when the frontier is a large part of the graph
+__global__ void k_scc_pull(int32_t n, const int32_t* prp, const int32_t* pci, const int32_t* scc, uint32_t* mark,
+                           uint32_t bit, int32_t* lev, int32_t nl) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        if (scc[v] >= 0 || (mark[v] & bit)) continue;
+        for (int32_t e = prp[v]; e < prp[v + 1]; e++) {
+            if (__hip_atomic_load(&lev[pci[e]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nl - 1) {
+                mark[v] |= bit;
+                __hip_atomic_store(&lev[v], nl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
         }
+    }
+}
+// out-degrees (in the search's direction) of the frontier entries, zero
+// past its end: an exclusive scan of these spreads its arcs evenly
+__global__ void k_front_deg(int32_t n, const int32_t* fr, const int32_t* fcnt_dev, const int32_t* arp, int32_t* deg) {
+    const int32_t fcnt = *fcnt_dev;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        deg[i] = i < fcnt ? arp[fr[i] + 1] - arp[fr[i]] : 0;
+}
+// one level of a push over the frontier's arcs, one thread per arc: arc j
+// belongs to the last entry whose prefix pre[] is <= j
+__global__ void k_scc_push(const int32_t* fr, const int32_t* pre, int32_t fcnt, int64_t farcs, const int32_t* arp,
+                           const int32_t* aci, const int32_t* scc, uint32_t* mark, uint32_t bit, int32_t* lev,
+                           int32_t nl) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < farcs;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        int32_t lo = 0, hi = fcnt - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (pre[mid] <= j) lo = mid;
+            else hi = mid - 1;
+        }
+        const int32_t u = fr[lo];
+        const int32_t w = aci[arp[u] + (int32_t)(j - pre[lo])];
+        if (scc[w] < 0 && !(mark[w] & bit) && !(atomicOr(&mark[w], bit) & bit)) lev[w] = nl;
     }
 }
 // the vertices of level nl, in id order: flags, then (after a scan) scatter
@@ -201,11 +274,13 @@ __global__ void k_lev_scatter(int32_t n, const int32_t* lev, int32_t nl, const i
     const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v < n && lev[v] == nl) out[pos[v]] = v;
 }
-__global__ void k_scc_seed(int32_t* list, uint32_t* mark, int32_t* lev, int32_t pivot, uint32_t bit) {
+__global__ void k_scc_seed(int32_t* list, uint32_t* mark, int32_t* lev, int32_t pivot, uint32_t bit,
+                           int32_t* fcnt_dev) {
     if (threadIdx.x == 0) {
         list[0] = pivot;
         mark[pivot] |= bit;
         lev[pivot] = 0;
+        *fcnt_dev = 1;
     }
 }
 __global__ void k_scc_assign_fb(int32_t n, int32_t* scc, uint32_t* mark, int32_t pivot) {
@@ -235,12 +310,17 @@ __global__ void k_scc_recount(int32_t n, const int32_t* rp, const int32_t* ci, c
 }
 
 // colouring: every unassigned vertex takes the largest id that reaches it
-__global__ void k_col_init(int32_t n, const int32_t* scc, int32_t* color, int32_t* unassigned) {
-    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool un = v < n && scc[v] < 0;
-    if (v < n) color[v] = un ? v : -1;
-    const uint64_t m = __ballot(un);
-    if (m && lane_id() == __ffsll((long long)__ballot(1)) - 1) atomicAdd(unassigned, __popcll(m));
+__global__ void __launch_bounds__(SB) k_col_init(int32_t n, const int32_t* scc, int32_t* color,
+                                                 int32_t* unassigned) {
+    __shared__ int64_t sh[SB / 64];
+    int64_t c = 0;
+    for (int64_t v = (int64_t)blockIdx.x * SB + threadIdx.x; v < n; v += (int64_t)gridDim.x * SB) {
+        const bool un = scc[v] < 0;
+        color[v] = un ? (int32_t)v : -1;
+        c += un;
+    }
+    c = block_sum_i64(c, sh);
+    if (threadIdx.x == 0 && c) atomicAdd(unassigned, (int32_t)c);
 }
 __global__ void k_col_prop(int32_t n, const int32_t* rrp, const int32_t* rci, const int32_t* scc, int32_t* color,
                            int32_t* changed) {
@@ -292,33 +372,43 @@ __global__ void k_comp_of(int32_t n, const int32_t* scc, const int32_t* cid, int
     const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v < n) comp[v] = cid[scc[v]];
 }
-__global__ void k_comp_stats(int32_t n, const int32_t* comp, int32_t pivot, int32_t* wt, int32_t* minid) {
-    // the pivot's component holds most vertices: one atomic per wave for it
-    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(SB) k_comp_stats(int32_t n, const int32_t* comp, int32_t pivot, int32_t* wt,
+                                                   int32_t* minid) {
+    // the pivot's component holds most vertices: one atomic per block for it
+    __shared__ int64_t sh[SB / 64];
+    __shared__ unsigned long long shm[SB / 64];
     const int32_t hot = pivot >= 0 ? comp[pivot] : -1;
-    const bool in = v < n;
-    const int32_t c = in ? comp[v] : -1;
-    const bool h = in && c == hot;
-    const uint64_t m = __ballot(h);
-    if (m) {
-        const int32_t mn = -wave_max_i32(h ? -v : INT32_MIN);
-        if (lane_id() == __ffsll((long long)m) - 1) {
-            atomicAdd(&wt[hot], __popcll(m));
-            atomicMin(&minid[hot], mn);
+    int64_t hc = 0;
+    unsigned long long hm = 0;   // 0xffffffff - smallest id of the hot component seen
+    for (int64_t v = (int64_t)blockIdx.x * SB + threadIdx.x; v < n; v += (int64_t)gridDim.x * SB) {
+        const int32_t c = comp[v];
+        if (c == hot) {
+            hc++;
+            const unsigned long long k = 0xffffffffull - (uint32_t)v;
+            hm = k > hm ? k : hm;
+        } else {
+            atomicAdd(&wt[c], 1);
+            atomicMin(&minid[c], (int32_t)v);
         }
     }
-    if (in && !h) {
-        atomicAdd(&wt[c], 1);
-        atomicMin(&minid[c], v);
+    hc = block_sum_i64(hc, sh);
+    hm = block_max_u64(hm, shm);
+    if (threadIdx.x == 0 && hc) {
+        atomicAdd(&wt[hot], (int32_t)hc);
+        atomicMin(&minid[hot], (int32_t)(0xffffffffull - hm));
     }
 }
 // the largest component, ties to the one holding the smallest vertex id
-__global__ void k_comp_big(int32_t nc, const int32_t* wt, const int32_t* minid, unsigned long long* best) {
-    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(SB) k_comp_big(int32_t nc, const int32_t* wt, const int32_t* minid,
+                                                 unsigned long long* best) {
+    __shared__ unsigned long long sh[SB / 64];
     unsigned long long key = 0;
-    if (c < nc) key = ((unsigned long long)(uint32_t)wt[c] << 32) | (0xffffffffull - (uint32_t)minid[c]);
-    key = wave_max_u64(key);
-    if (lane_id() == 0 && key) atomicMax(best, key);
+    for (int64_t c = (int64_t)blockIdx.x * SB + threadIdx.x; c < nc; c += (int64_t)gridDim.x * SB) {
+        const unsigned long long k = ((unsigned long long)(uint32_t)wt[c] << 32) | (0xffffffffull - (uint32_t)minid[c]);
+        key = k > key ? k : key;
+    }
+    key = block_max_u64(key, sh);
+    if (threadIdx.x == 0 && key) atomicMax(best, key);
 }
 
 __global__ void k_set_big(const int32_t* comp, int32_t bmin, int32_t* tob, int32_t* frb, int32_t* out) {
@@ -331,34 +421,79 @@ __global__ void k_set_big(const int32_t* comp, int32_t bmin, int32_t* tob, int32
 }
 
 // --------------------------------------------------------------- the DAG
+// arcs leaving each vertex's component: a thread per light vertex, a wave
+// per heavy one (more than HEAVY_DEG out-arcs)
 __global__ void k_dag_count(int32_t n, const int32_t* rp, const int32_t* ci, const int32_t* comp, int32_t* cnt) {
-    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
-    for (int64_t u = gw; u < n; u += nw) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+        if (rp[u + 1] - rp[u] > HEAVY_DEG) continue;
         const int32_t cu = comp[u];
         int32_t c = 0;
-        for (int32_t e = rp[u] + lane_id(); e < rp[u + 1]; e += 64) c += comp[ci[e]] != cu;
-        c = wave_sum_i32(c);
-        if (lane_id() == 0) cnt[u] = c;
+        for (int32_t e = rp[u]; e < rp[u + 1]; e++) c += comp[ci[e]] != cu;
+        cnt[u] = c;
     }
+}
+// heavy vertices: one wave per chunk of CHUNK_ARCS arcs, then each heavy
+// vertex sums its chunks and notes where they start
+__global__ void k_dag_chunk_count(int32_t nchunks, const int32_t* ch_beg, const int32_t* ch_end,
+                                  const int32_t* ch_vtx, const int32_t* ci, const int32_t* comp, int32_t* ccnt) {
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    for (int64_t c = gw; c < nchunks; c += nw) {
+        const int32_t cu = comp[ch_vtx[c]];
+        int32_t k = 0;
+        for (int32_t e = ch_beg[c] + lane_id(); e < ch_end[c]; e += 64) k += comp[ci[e]] != cu;
+        k = wave_sum_i32(k);
+        if (lane_id() == 0) ccnt[c] = k;
+    }
+}
+__global__ void k_dag_heavy_sum(int32_t nheavy, const int32_t* heavy, const int32_t* hcb, const int32_t* ccnt,
+                                int32_t* cnt, int32_t* cfirst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nheavy) return;
+    int32_t k = 0;
+    for (int32_t c = hcb[i]; c < hcb[i + 1]; c++) {
+        k += ccnt[c];
+        cfirst[c] = hcb[i];
+    }
+    cnt[heavy[i]] = k;
 }
 __global__ void k_dag_pairs(int32_t n, const int32_t* rp, const int32_t* ci, const int32_t* comp, const int32_t* off,
                             uint32_t* key, int32_t* val) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+        if (rp[u + 1] - rp[u] > HEAVY_DEG) continue;
+        const int32_t cu = comp[u];
+        int32_t o = off[u];
+        for (int32_t e = rp[u]; e < rp[u + 1]; e++) {
+            const int32_t cw = comp[ci[e]];
+            if (cw != cu) {
+                key[o] = (uint32_t)cw;   // first pass: by target
+                val[o] = cu;
+                o++;
+            }
+        }
+    }
+}
+// chunk c writes from off[owner] + (its owner's arcs in earlier chunks),
+// cpre[] being the exclusive scan of the chunk counts
+__global__ void k_dag_chunk_pairs(int32_t nchunks, const int32_t* ch_beg, const int32_t* ch_end,
+                                  const int32_t* ch_vtx, const int32_t* ci, const int32_t* comp, const int32_t* off,
+                                  const int32_t* cpre, const int32_t* cfirst, uint32_t* key, int32_t* val) {
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
     const uint64_t below = lane_id() ? (~0ull >> (64 - lane_id())) : 0ull;
-    for (int64_t u = gw; u < n; u += nw) {
+    for (int64_t c = gw; c < nchunks; c += nw) {
+        const int32_t u = ch_vtx[c];
         const int32_t cu = comp[u];
-        int32_t o = off[u];
-        for (int32_t e0 = rp[u]; e0 < rp[u + 1]; e0 += 64) {
+        int32_t o = off[u] + cpre[c] - cpre[cfirst[c]];
+        for (int32_t e0 = ch_beg[c]; e0 < ch_end[c]; e0 += 64) {
             const int32_t e = e0 + lane_id();
             int32_t cw = cu;
-            if (e < rp[u + 1]) cw = comp[ci[e]];
+            if (e < ch_end[c]) cw = comp[ci[e]];
             const bool x = cw != cu;
             const uint64_t m = __ballot(x);
             if (x) {
                 const int32_t p = o + __popcll(m & below);
-                key[p] = (uint32_t)cw;   // first pass: by target
+                key[p] = (uint32_t)cw;
                 val[p] = cu;
             }
             o += __popcll(m);
@@ -432,17 +567,21 @@ __global__ void k_dag_relax(int32_t U, const int32_t* asrc, const int32_t* adst,
     if (__ballot(ch) && lane_id() == 0) *changed = 1;
 }
 // |reach of C~| and the largest height (one atomic per wave each)
-__global__ void k_dag_reach_big(int32_t nc, const int32_t* wt, const int32_t* frb, const int32_t* hgt,
-                                unsigned long long* rb, int32_t* hmax) {
-    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool ok = c < nc;
-    const int64_t w = ok && frb[c] ? wt[c] : 0;
-    const int32_t h = ok ? hgt[c] : 0;
-    const int64_t ws = wave_sum_i64(w);
-    const int32_t hm = wave_max_i32(h);
-    if (lane_id() == 0) {
-        if (ws) atomicAdd(rb, (unsigned long long)ws);
-        atomicMax(hmax, hm);
+__global__ void __launch_bounds__(SB) k_dag_reach_big(int32_t nc, const int32_t* wt, const int32_t* frb,
+                                                      const int32_t* hgt, unsigned long long* rb, int32_t* hmax) {
+    __shared__ int64_t sh[SB / 64];
+    __shared__ unsigned long long shm[SB / 64];
+    int64_t w = 0;
+    unsigned long long h = 0;
+    for (int64_t c = (int64_t)blockIdx.x * SB + threadIdx.x; c < nc; c += (int64_t)gridDim.x * SB) {
+        if (frb[c]) w += wt[c];
+        h = (unsigned long long)hgt[c] > h ? (unsigned long long)hgt[c] : h;
+    }
+    w = block_sum_i64(w, sh);
+    h = block_max_u64(h, shm);
+    if (threadIdx.x == 0) {
+        if (w) atomicAdd(rb, (unsigned long long)w);
+        atomicMax(hmax, (int32_t)h);
     }
 }
 // sort keys: components and arcs by decreasing height (of the source)
@@ -607,6 +746,7 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
     int32_t* adst = nullptr;
     int32_t* hsrc = nullptr;
     int32_t* hdst = nullptr;
+    int32_t *ccnt = nullptr, *cfirst = nullptr;   // heavy-vertex chunks
     int32_t* bsum = nullptr;
     int32_t* hist = nullptr;
     int32_t* small = nullptr;
@@ -645,6 +785,8 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
         adst = sc.take<int32_t>(m);
         hsrc = sc.take<int32_t>(m);
         hdst = sc.take<int32_t>(m);
+        ccnt = sc.take<int32_t>((int64_t)g.nchunks + 1);
+        cfirst = sc.take<int32_t>((int64_t)g.nchunks + 1);
         bsum = sc.take<int32_t>(words_scan);
         hist = sc.take<int32_t>(hist_words);
         small = sc.take<int32_t>(256);
@@ -685,7 +827,7 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
         auto trim = [&](int max_rounds) -> int {
             for (int r = 0; r < max_rounds; r++) {
                 if (hipMemsetAsync(small, 0, 4, s) != hipSuccess) return -1;
-                hipLaunchKernelGGL(k_scc_trim, dim3(gb), dim3(SB), 0, s, n, scc, in_rem, out_rem, list, small);
+                hipLaunchKernelGGL(k_scc_trim, dim3(rblk(n)), dim3(SB), 0, s, n, scc, in_rem, out_rem, list, small);
                 const int32_t c = read_i32(small, pin, s);
                 if (c < 0) return -1;
                 if (c == 0) break;
@@ -698,7 +840,7 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
         phase("trim", rounds, 0);
         // ---- forward / backward search from the pivot
         DEV_OK(hipMemsetAsync(big_key, 0, 8, s));
-        hipLaunchKernelGGL(k_scc_pivot, dim3(gb), dim3(SB), 0, s, n, scc, in_rem, out_rem, big_key);
+        hipLaunchKernelGGL(k_scc_pivot, dim3(rblk(n)), dim3(SB), 0, s, n, scc, in_rem, out_rem, big_key);
         DEV_OK(hipMemcpyAsync(pin, big_key, 8, hipMemcpyDeviceToHost, s));
         DEV_OK(hipStreamSynchronize(s));
         if (*(unsigned long long*)pin != 0) {
@@ -709,17 +851,35 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
                 const int32_t* arp = dir == 0 ? g.rp : g.rrp;
                 const int32_t* aci = dir == 0 ? g.ci : g.rci;
                 DEV_OK(hipMemsetAsync(lev, 0xff, 4 * (size_t)n, s));
-                hipLaunchKernelGGL(k_scc_seed, dim3(1), dim3(64), 0, s, list, mark, lev, pivot, bit);
-                int32_t fcnt = 1;
+                hipLaunchKernelGGL(k_scc_seed, dim3(1), dim3(64), 0, s, list, mark, lev, pivot, bit, small);
+                // frontier size (small[0]), its arcs (small[2]) and their
+                // prefix by entry (next[]), read back once per level
+                auto frontier = [&]() -> int {
+                    hipLaunchKernelGGL(k_front_deg, dim3(rblk(n)), dim3(SB), 0, s, n, list, small, arp, next);
+                    if (scan(next, n, bsum, small + 2, s)) return -1;
+                    if (hipMemcpyAsync(pin, small, 16, hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
+                    if (hipStreamSynchronize(s) != hipSuccess) return -1;
+                    return 0;
+                };
+                STEP_OK(frontier());
+                int32_t fcnt = pin[0];
+                int64_t farcs = pin[2];
                 for (int32_t nl = 1; fcnt > 0; nl++) {
                     if (++rounds > RBUDGET) { fail(1); goto done; }
-                    hipLaunchKernelGGL(k_scc_bfs, dim3(wblk(fcnt)), dim3(SB), 0, s, list, fcnt, arp, aci, scc, mark,
-                                       bit, lev, nl);
+                    // a frontier holding a large share of the arcs: pull
+                    // over the predecessors instead (direction optimising)
+                    if ((int64_t)fcnt * 16 > n || farcs * 8 > m)
+                        hipLaunchKernelGGL(k_scc_pull, dim3(nblk(n)), dim3(SB), 0, s, n, dir == 0 ? g.rrp : g.rp,
+                                           dir == 0 ? g.rci : g.ci, scc, mark, bit, lev, nl);
+                    else if (farcs > 0)
+                        hipLaunchKernelGGL(k_scc_push, dim3(std::min(nblk(farcs), 8192)), dim3(SB), 0, s, list, next,
+                                           fcnt, farcs, arp, aci, scc, mark, bit, lev, nl);
                     hipLaunchKernelGGL(k_lev_flag, dim3(gb), dim3(SB), 0, s, n, lev, nl, cid);
                     STEP_OK(scan(cid, n, bsum, small, s));
                     hipLaunchKernelGGL(k_lev_scatter, dim3(gb), dim3(SB), 0, s, n, lev, nl, cid, list);
-                    fcnt = read_i32(small, pin, s);
-                    if (fcnt < 0) { fail(-1); goto done; }
+                    STEP_OK(frontier());
+                    fcnt = pin[0];
+                    farcs = pin[2];
                 }
             }
             phase("fw-bw", rounds, pivot);
@@ -732,7 +892,7 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
         // ---- colouring until every vertex has a component
         for (int it = 0;; it++) {
             DEV_OK(hipMemsetAsync(small + 1, 0, 4, s));
-            hipLaunchKernelGGL(k_col_init, dim3(gb), dim3(SB), 0, s, n, scc, color, small + 1);
+            hipLaunchKernelGGL(k_col_init, dim3(rblk(n)), dim3(SB), 0, s, n, scc, color, small + 1);
             const int32_t un = read_i32(small + 1, pin, s);
             if (un < 0) { fail(-1); goto done; }
             phase("col-init", it, un);
@@ -770,18 +930,28 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
         hipLaunchKernelGGL(k_comp_of, dim3(gb), dim3(SB), 0, s, n, scc, cid, comp);
         DEV_OK(hipMemsetAsync(wt, 0, 4 * (size_t)nc, s));
         DEV_OK(hipMemsetAsync(minid, 0x7f, 4 * (size_t)nc, s));
-        hipLaunchKernelGGL(k_comp_stats, dim3(gb), dim3(SB), 0, s, n, comp, pivot, wt, minid);
+        hipLaunchKernelGGL(k_comp_stats, dim3(rblk(n)), dim3(SB), 0, s, n, comp, pivot, wt, minid);
         DEV_OK(hipMemsetAsync(big_key, 0, 8, s));
-        hipLaunchKernelGGL(k_comp_big, dim3(nblk(nc)), dim3(SB), 0, s, nc, wt, minid, big_key);
+        hipLaunchKernelGGL(k_comp_big, dim3(rblk(nc)), dim3(SB), 0, s, nc, wt, minid, big_key);
         phase("ids", nc, 0);
         // ---- DAG arcs, sorted by (source, target) and deduplicated
-        hipLaunchKernelGGL(k_dag_count, dim3(wblk(n)), dim3(SB), 0, s, n, g.rp, g.ci, comp, cnt);
+        hipLaunchKernelGGL(k_dag_count, dim3(nblk(n)), dim3(SB), 0, s, n, g.rp, g.ci, comp, cnt);
+        if (g.nheavy) {
+            hipLaunchKernelGGL(k_dag_chunk_count, dim3(wblk(g.nchunks)), dim3(SB), 0, s, g.nchunks, g.ch_beg, g.ch_end,
+                               g.ch_vtx, g.ci, comp, ccnt);
+            hipLaunchKernelGGL(k_dag_heavy_sum, dim3(nblk(g.nheavy)), dim3(SB), 0, s, g.nheavy, g.heavy, g.hcb, ccnt,
+                               cnt, cfirst);
+            STEP_OK(scan(ccnt, g.nchunks, bsum, small + 10, s));
+        }
         STEP_OK(scan(cnt, n, bsum, small + 4, s));
         const int32_t E = read_i32(small + 4, pin, s);
         if (E < 0) { fail(-1); goto done; }
         int32_t U = 0;
         if (E > 0) {
-            hipLaunchKernelGGL(k_dag_pairs, dim3(wblk(n)), dim3(SB), 0, s, n, g.rp, g.ci, comp, cnt, key, val);
+            hipLaunchKernelGGL(k_dag_pairs, dim3(nblk(n)), dim3(SB), 0, s, n, g.rp, g.ci, comp, cnt, key, val);
+            if (g.nheavy)
+                hipLaunchKernelGGL(k_dag_chunk_pairs, dim3(wblk(g.nchunks)), dim3(SB), 0, s, g.nchunks, g.ch_beg,
+                                   g.ch_end, g.ch_vtx, g.ci, comp, cnt, ccnt, cfirst, key, val);
             // by target, then (stable) by source
             STEP_OK(tkc_sort_pairs(key, val, tkey, tval, E, hist, smask, pin_mask, s));
             DEV_OK(hipMemcpyAsync(tkey, val, 4 * (size_t)E, hipMemcpyDeviceToDevice, s));
@@ -817,7 +987,7 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
         }
         DEV_OK(hipMemsetAsync(rb, 0, 8, s));
         DEV_OK(hipMemsetAsync(small + 7, 0, 4, s));
-        hipLaunchKernelGGL(k_dag_reach_big, dim3(nblk(nc)), dim3(SB), 0, s, nc, wt, frb, hgt, rb, small + 7);
+        hipLaunchKernelGGL(k_dag_reach_big, dim3(rblk(nc)), dim3(SB), 0, s, nc, wt, frb, hgt, rb, small + 7);
         const int32_t hmax = read_i32(small + 7, pin, s);
         if (hmax < 0) { fail(-1); goto done; }
         if (hmax > RBUDGET) { fail(1); goto done; }
