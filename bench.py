@@ -36,12 +36,20 @@ WORKLOADS = {
 }
 
 
-def kernel_source_hash() -> str:
+# the sources each profiled kernel is compiled from (its file and the
+# headers it includes)
+KERNEL_SOURCES = {
+    "k_batch": ["k_batch.hip", "dev_common.hpp", "engine.hpp"],
+    "k_swarm": ["k_swarm.hip", "dev_common.hpp", "engine.hpp"],
+    "k_plain": ["k_plain.hip", "dev_common.hpp", "engine.hpp"],
+}
+
+
+def kernel_source_hash(kernel: str) -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1704_01077_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in KERNEL_SOURCES.get(kernel, sorted(x for x in os.listdir(csrc) if x.endswith((".hip", ".hpp")))):
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -55,7 +63,7 @@ def load_traffic(kernel: str, workload: str, mode: str, width: int):
     try:
         d = json.load(open(path))
         rec = d.get(workload, {}).get(kernel)
-        if not rec or rec.get("source_hash") != kernel_source_hash():
+        if not rec or rec.get("source_hash") != kernel_source_hash(kernel):
             return None
         if rec.get("mode") != mode or rec.get("batch_width") != width:
             return None
@@ -129,7 +137,7 @@ def traffic_from(fetch_dir: str, write_dir: str, workload: str, kernel: str, las
             key = (int(disp), name)
             vals[key] = vals.get(key, 0.0) + float(value)
         return sorted(vals.items(), key=lambda kv: kv[0][0])
-    rec = {"source_hash": kernel_source_hash(), "copy_bytes": copy_bytes, "mode": mode, "batch_width": width}
+    rec = {"source_hash": kernel_source_hash(kernel), "copy_bytes": copy_bytes, "mode": mode, "batch_width": width}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         disp = per_dispatch(d, counter)
         copies = [v for (i, name), v in disp if "copy" in name.lower()]
