@@ -240,7 +240,7 @@ def harmonic_bench(args):
     g = graphgen.workload(args.workload)
     ctx = tkc.Context(0)
     dg = tkc.Graph.from_graphgen(ctx, g)
-    mode = "batched" if args.mode == "hybrid" else args.mode
+    mode = args.mode
     for _ in range(args.warmup):
         tkc.topk_harmonic(dg, args.k, args.variant, mode)
     torch.cuda.synchronize()
@@ -254,7 +254,8 @@ def harmonic_bench(args):
     out = {"metric": "top-k harmonic centrality wall time", "value": round(float(walls.mean()), 4), "unit": "ms",
            "higher_is_better": False, "steps": args.steps, "warmup": args.warmup, "dtype": "f64",
            "config": {"workload": WORKLOADS.get(args.workload, args.workload), "k": args.k,
-                      "variant": args.variant, "variant_used": st["variant_used"], "mode": mode},
+                      "variant": args.variant, "variant_used": st["variant_used"], "mode": mode,
+                      "mode_used": MODE_NAMES.get(st["mode_used"], st["mode_used"])},
            "wall_ms_p50": round(float(np.percentile(walls, 50)), 4),
            "wall_ms_p99": round(float(np.percentile(walls, 99)), 4),
            "m_vis": st["m_vis"],

@@ -189,9 +189,8 @@ int tkc_topk_closeness(tkc_graph *g, int32_t k, int32_t variant, int32_t mode,
  * at distance 2; walk counts: levels filled as close as the counts of
  * Sect. 5 allow; level-based: every vertex at least max(2, level gap)
  * away from w but its out-neighbours, see tkc_graph_harmonic_lb_update).
- * mode: TKC_PLAIN or TKC_BATCHED (TKC_HYBRID runs batched; TKC_MODE_AUTO
- * as for closeness).  *n_out = min(k, n) results in order: ids and
- * harmonic values.  stats may be NULL. */
+ * mode: any, as for closeness.  *n_out = min(k, n) results in order: ids
+ * and harmonic values.  stats may be NULL. */
 int tkc_topk_harmonic(tkc_graph *g, int32_t k, int32_t variant, int32_t mode,
                       int32_t *ids, double *harmonic, int32_t *n_out, tkc_stats *stats);
 /* The harmonic upper bounds a harmonic query starts from (variant

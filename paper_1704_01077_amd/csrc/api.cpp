@@ -860,8 +860,8 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
     double ms_eng[3] = {0, 0, 0};
     int32_t nl_eng[3] = {0, 0, 0};
     int grid = 0;
-    // the per-workgroup engine has no level-based or harmonic path
-    if ((lb || harm) && mode == TKC_HYBRID) mode = TKC_BATCHED;
+    // the per-workgroup engine has no level-based path
+    if (lb && mode == TKC_HYBRID) mode = TKC_BATCHED;
     if (mode == TKC_PLAIN) {
         EngineTimer tm(c, &ms_eng[0], &nl_eng[0]);
         if (tkc_launch_plain(dg, rcv, ov, bv, tk, plain_view(ws), st_plain, nullptr, 0, lbl, c->tune, s, &grid))

@@ -93,13 +93,15 @@ __global__ void __launch_bounds__(SB) k_swarm(SwarmArgs a) {
             if (p >= 0 && p < count) {
                 int32_t v = a.ov.ord[p];
                 uint32_t key = a.ov.key[p];
-                bool stop = a.ov.key_is_bound ? key_stops(key, x) : (key == 0xffffffffu && x.den != 0);
+                bool stop = a.bv.harm ? key_stops_h(key, x)
+                                      : (a.ov.key_is_bound ? key_stops(key, x) : (key == 0xffffffffu && x.den != 0));
                 if (stop) { for_rlx(a.w.stop, 1); s_dec = 1; }
                 else if (lex_after(a.bv.num[v], a.bv.den[v], v, x.num, x.den, x.id)) { s_dec = 2; st_skip++; }
                 else if (a.rc.omega[v] <= 1) {
                     s_dec = 3;
                     st_started++; st_exact++;
-                    topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, 0, 1, v);
+                    if (a.bv.harm) topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, harm_enc(0.0), 2, v);
+                    else topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, 0, 1, v);
                 }
             } else {
                 s_dec = 1;
@@ -123,6 +125,7 @@ __global__ void __launch_bounds__(SB) k_swarm(SwarmArgs a) {
         }
         __syncthreads();
         int64_t D = 0, nD = 1, SD = 0, U = dv, nf = 1;
+        double H = 0.0;   // harmonic centrality so far (levels 1..D)
         int32_t ls = 0, le = 1;
         int status = 0;   // 1 exact, 2 cut, 3 deferred
         int64_t mvis = 0;
@@ -137,7 +140,8 @@ __global__ void __launch_bounds__(SB) k_swarm(SwarmArgs a) {
             __syncthreads();
             {
                 int64_t bn, bd;
-                cut_bound(SD, nD, U, D, av, ov, &bn, &bd);
+                if (a.bv.harm) harm_cut_bound(H, nD, U, D, ov, &bn, &bd);
+                else cut_bound(SD, nD, U, D, av, ov, &bn, &bd);
                 if (lex_after(bn, bd, v, s_x[0], s_x[1], (int32_t)s_x[2])) { status = 2; break; }
             }
             if (s_closed) { status = 3; break; }
@@ -192,6 +196,7 @@ __global__ void __launch_bounds__(SB) k_swarm(SwarmArgs a) {
             D++;
             nD += cnt;
             SD += D * cnt;
+            if (a.bv.harm) H += (double)cnt / (double)D;
             U = dir ? dsum : dsum - cnt;
             nf = cnt;
             ls = le;
@@ -214,7 +219,8 @@ __global__ void __launch_bounds__(SB) k_swarm(SwarmArgs a) {
             if (md > st_maxl) st_maxl = md;
             if (status == 1) {
                 st_exact++;
-                topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, SD, nD, v);
+                if (a.bv.harm) topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, harm_enc(H), 2, v);
+                else topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, SD, nD, v);
             } else if (status == 2) {
                 st_cut++;
             } else {

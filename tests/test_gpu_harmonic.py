@@ -229,3 +229,6 @@ def test_harmonic_full(ctx, name):
     assert np.array_equal(ids2, ids) and np.array_equal(hv2, hv)
     ids3, hv3, _ = tkc.topk_harmonic(dg, 10, "degcut", "batched")
     assert np.array_equal(ids3, ids) and np.array_equal(hv3, hv)
+    ids4, hv4, st4 = tkc.topk_harmonic(dg, 10, "nbcut", "hybrid")
+    assert np.array_equal(ids4, ids) and np.array_equal(hv4, hv)
+    assert st4["mode_used"] == tkc.TKC_HYBRID
