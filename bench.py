@@ -369,8 +369,8 @@ def serve_bench(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--variant", default="auto")
     ap.add_argument("--mode", default="hybrid",

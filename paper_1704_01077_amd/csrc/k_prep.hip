@@ -246,7 +246,13 @@ __global__ void k_nb_round(int32_t n, const int32_t* __restrict__ rp, const int3
             int32_t e = rp[s], end = rp[s + 1];
             for (; e + 4 <= end; e += 4) {
                 uint64_t a0 = g1[ci[e]], a1 = g1[ci[e + 1]], a2 = g1[ci[e + 2]], a3 = g1[ci[e + 3]];
-                acc += a0 + a1 + a2 + a3;           // 4 x 2^62 fits in 64 unsigned bits
+                // every term is at most 2^62: clamp the pairs before adding
+                // so no partial sum passes 2^64 (acc + 2 clamped pairs <
+                // 2^62 + 2^63)
+                uint64_t s01 = a0 + a1, s23 = a2 + a3;
+                if (s01 > (uint64_t)NB_INF) s01 = NB_INF;
+                if (s23 > (uint64_t)NB_INF) s23 = NB_INF;
+                acc += s01 + s23;
                 if (acc > (uint64_t)NB_INF) acc = NB_INF;
             }
             for (; e < end; e++) {
