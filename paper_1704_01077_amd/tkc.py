@@ -316,7 +316,8 @@ class Graph:
         row_ptr = _as_i32(row_ptr)
         col_idx = _as_i32(col_idx)
         flags = (TKC_DIRECTED if rrow_ptr is not None else 0) | (TKC_VALIDATE if validate else 0)
-        if device_ptrs:
+        # device tensors (torch on the GPU) are copied device to device
+        if device_ptrs or getattr(row_ptr, "is_cuda", False):
             flags |= TKC_DEVICE_PTRS
         if reverse:
             flags |= TKC_REVERSE
@@ -327,6 +328,12 @@ class Graph:
         self.directed = rrow_ptr is not None
         self._keep = (row_ptr, col_idx, rrow_ptr, rcol_idx)
         self.h = tkc_graph_upload(ctx.h, self.n, self.m, row_ptr, col_idx, rrow_ptr, rcol_idx, flags)
+
+    @classmethod
+    def from_csr(cls, ctx, row_ptr, col_idx, rrow_ptr=None, rcol_idx=None, validate=False, reverse=False):
+        """From int32 CSR arrays (numpy, or torch tensors on the host or the
+        GPU); the reverse CSR is given iff the graph is directed."""
+        return cls(ctx, len(row_ptr) - 1, row_ptr, col_idx, rrow_ptr, rcol_idx, validate=validate, reverse=reverse)
 
     @classmethod
     def from_graphgen(cls, ctx, g, validate=False, reverse=False):

@@ -382,6 +382,12 @@ def test_device_pointer_upload(ctx):
     wids, wS, wr, wf = expect("gnp_d", 10)
     assert np.array_equal(ids, wids) and np.array_equal(S, wS)
     dg.free()
+    # from_csr: device tensors are detected, host tensors and arrays copied
+    for arrs in (t, [x.cpu() for x in t], [g.row_ptr, g.col_idx, g.rrow_ptr, g.rcol_idx]):
+        dg = tkc.Graph.from_csr(ctx, *arrs, validate=True)
+        ids, S, r, f, st = tkc.topk_closeness(dg, 10, "nbcut", "batched")
+        assert np.array_equal(ids, wids) and np.array_equal(S, wS)
+        dg.free()
 
 
 def test_repeatable(ctx):
