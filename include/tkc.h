@@ -159,9 +159,12 @@ int tkc_ctx_set_tuning(tkc_ctx *ctx, const tkc_tuning *t);
 /* Copy a graph to device memory.  row_ptr[n+1], col_idx[m_arcs] give the
  * out-arcs; rrow_ptr/rcol_idx give the in-arcs and are required iff
  * TKC_DIRECTED (NULL otherwise).  Undirected graphs hold each edge in both
- * rows.  The graph must be simple (no self-loops, no repeated arcs, rows
- * need not be sorted); TKC_VALIDATE checks it (and symmetry / that the
- * reverse CSR is the transpose) and returns TKC_EINVAL with a message.
+ * rows.  Every upload checks that row_ptr starts at 0, never decreases and
+ * ends at m_arcs, and that every vertex id is in [0, n) (TKC_EINVAL
+ * otherwise: the kernels index with them).  The graph must also be simple
+ * (no self-loops, no repeated arcs, rows need not be sorted); TKC_VALIDATE
+ * checks that too, and symmetry / that the reverse CSR is the transpose,
+ * and returns TKC_EINVAL with a message.
  * n >= 1.  Errors: TKC_EINVAL, TKC_ENOMEM, TKC_EDEVICE. */
 int tkc_graph_upload(tkc_ctx *ctx, int32_t n, int64_t m_arcs,
                      const int32_t *row_ptr, const int32_t *col_idx,

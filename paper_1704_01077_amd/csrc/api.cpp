@@ -257,6 +257,19 @@ static int validate_csr(int32_t n, int64_t m, const int32_t* rp, const int32_t* 
     return TKC_OK;
 }
 
+// the checks every upload runs (memory safety of the kernels): row_ptr starts
+// at 0, never decreases and ends at m; every vertex id is in [0, n)
+static int check_csr_bounds(int32_t n, int64_t m, const int32_t* rp, const int32_t* ci, const char* what) {
+    if (rp[0] != 0) return tkc_fail(TKC_EINVAL, "%s: row_ptr[0] must be 0", what);
+    if ((int64_t)rp[n] != m) return tkc_fail(TKC_EINVAL, "%s: row_ptr[n] != m_arcs", what);
+    for (int32_t u = 0; u < n; u++)
+        if (rp[u + 1] < rp[u]) return tkc_fail(TKC_EINVAL, "%s: row_ptr not monotone at %d", what, u);
+    bool bad = false;
+    for (int64_t e = 0; e < m; e++) bad |= (uint32_t)ci[e] >= (uint32_t)n;
+    if (bad) return tkc_fail(TKC_EINVAL, "%s: vertex id out of range", what);
+    return TKC_OK;
+}
+
 // true when (rp2, ci2) is the transpose of (rp, ci)
 static bool is_transpose(int32_t n, int64_t m, const int32_t* rp, const int32_t* ci, const int32_t* rp2,
                          const int32_t* ci2) {
@@ -297,7 +310,8 @@ extern "C" int tkc_graph_upload(tkc_ctx* c, int32_t n, int64_t m, const int32_t*
     if (!directed && (rrow_ptr || rcol_idx))
         return tkc_fail(TKC_EINVAL, "reverse CSR given for an undirected graph");
     HIPCHK(hipSetDevice(c->device));
-    // host copies (the directed reachability bounds run on the host)
+    // host copies: the checks below, the heavy-vertex tables, and (directed)
+    // the host fallback of the reachability bounds
     std::vector<int32_t> hrp(n + 1), hci(m), hrrp, hrci;
     const hipMemcpyKind k = (flags & TKC_DEVICE_PTRS) ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
     HIPCHK(hipMemcpy(hrp.data(), row_ptr, 4 * (size_t)(n + 1), k));
@@ -308,7 +322,11 @@ extern "C" int tkc_graph_upload(tkc_ctx* c, int32_t n, int64_t m, const int32_t*
         HIPCHK(hipMemcpy(hrrp.data(), rrow_ptr, 4 * (size_t)(n + 1), k));
         if (m) HIPCHK(hipMemcpy(hrci.data(), rcol_idx, 4 * (size_t)m, k));
     }
-    if ((int64_t)hrp[n] != m) return tkc_fail(TKC_EINVAL, "row_ptr[n] != m_arcs");
+    {
+        int rc = check_csr_bounds(n, m, hrp.data(), hci.data(), "out-arcs");
+        if (!rc && directed) rc = check_csr_bounds(n, m, hrrp.data(), hrci.data(), "in-arcs");
+        if (rc) return rc;
+    }
     if (flags & TKC_VALIDATE) {
         int rc = validate_csr(n, m, hrp.data(), hci.data(), "out-arcs");
         if (rc) return rc;

@@ -370,6 +370,32 @@ def test_error_codes(ctx):
     with pytest.raises(tkc.TkcError) as e:
         tkc.tkc_graph_upload(ctx.h, g.n, g.arcs, g.row_ptr, g.col_idx, None, None, tkc.TKC_DIRECTED)
     assert e.value.code == tkc.TKC_EINVAL
+    # checked on every upload, validate or not: ids out of range, row
+    # pointers that decrease or do not end at m, n < 1, m out of range
+    for v in (-1, g.n):
+        bad = g.col_idx.copy()
+        bad[-1] = v
+        with pytest.raises(tkc.TkcError) as e:
+            tkc.Graph(ctx, g.n, g.row_ptr, bad)
+        assert e.value.code == tkc.TKC_EINVAL
+    rp = g.row_ptr.copy()
+    rp[7], rp[8] = rp[8], rp[7]
+    with pytest.raises(tkc.TkcError) as e:
+        tkc.Graph(ctx, g.n, rp, g.col_idx)
+    assert e.value.code == tkc.TKC_EINVAL
+    with pytest.raises(tkc.TkcError) as e:
+        tkc.tkc_graph_upload(ctx.h, g.n, g.arcs - 1, g.row_ptr, g.col_idx, None, None, 0)
+    assert e.value.code == tkc.TKC_EINVAL
+    for nn, mm in ((0, 0), (g.n, -1), (g.n, 1 << 31)):
+        with pytest.raises(tkc.TkcError) as e:
+            tkc.tkc_graph_upload(ctx.h, nn, mm, g.row_ptr, g.col_idx, None, None, 0)
+        assert e.value.code == tkc.TKC_EINVAL
+    d = graph("gnp_d")
+    badr = d.rcol_idx.copy()
+    badr[0] = d.n + 3
+    with pytest.raises(tkc.TkcError) as e:
+        tkc.Graph(ctx, d.n, d.row_ptr, d.col_idx, d.rrow_ptr, badr)
+    assert e.value.code == tkc.TKC_EINVAL
 
 
 def test_device_pointer_upload(ctx):
