@@ -701,8 +701,8 @@ int32_t read_i32(const int32_t* dev, int32_t* pin, hipStream_t s) {
 
 }  // namespace
 
-// Returns 0 on success, 1 when a round budget ran out (use the host), -1 on
-// a device error.  pinned: at least 256 bytes of pinned host memory.
+// Returns 0 on success, 1 when a round budget ran out or the scratch arena
+// does not fit (use the host), -1 on a device error.  pinned: at least 256 bytes of pinned host memory.
 int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, int32_t* scc_topo, void* pinned,
                            hipStream_t s) {
     const int32_t n = g.n;
@@ -794,8 +794,9 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
     };
     const size_t bytes = layout(nullptr);
     if (hipMalloc(&sc.base, bytes) != hipSuccess) {
+        // no room for the scratch arena: the host path needs none
         hipGetLastError();
-        return -1;
+        return 1;
     }
     layout((char*)sc.base);
     unsigned long long* big_key = (unsigned long long*)(small + 64);
