@@ -795,7 +795,7 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
     const size_t bytes = layout(nullptr);
     if (hipMalloc(&sc.base, bytes) != hipSuccess) {
         // no room for the scratch arena: the host path needs none
-        hipGetLastError();
+        (void)hipGetLastError();
         return 1;
     }
     layout((char*)sc.base);
@@ -812,7 +812,7 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
     double tph = wall_ms();
     auto phase = [&](const char* what, int64_t a, int64_t b) {
         if (!tr) return;
-        hipStreamSynchronize(s);
+        (void)hipStreamSynchronize(s);
         const double t = wall_ms();
         fprintf(stderr, "reach %-10s %9.3f ms  %lld %lld\n", what, t - tph, (long long)a, (long long)b);
         tph = t;
@@ -1042,7 +1042,7 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
 done:
 #undef DEV_OK
 #undef STEP_OK
-    hipStreamSynchronize(s);
-    hipFree(sc.base);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(sc.base);
     return rc;
 }
