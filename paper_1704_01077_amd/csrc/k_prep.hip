@@ -322,7 +322,12 @@ __global__ void k_nb_keys(int32_t n, const int64_t* __restrict__ num, const int6
                           uint32_t* key, int32_t* val) {
     int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
-    key[v] = order_key(num[v], den[v]);
+    // 24 bits (12 of mantissa, 2^-12 relative) order the candidates as well
+    // as 32 and save the sort two of its 4-bit passes; truncating further
+    // keeps every key a lower bound of its vertex's bound, so the stop test
+    // stays valid (+inf keeps its all-ones key)
+    const uint32_t k = order_key(num[v], den[v]);
+    key[v] = k == 0xffffffffu ? k : (k & 0xffffff00u);
     val[v] = v;
 }
 
