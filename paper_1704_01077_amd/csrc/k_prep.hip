@@ -64,13 +64,47 @@ __global__ void k_cc_link_one(int32_t n, const int32_t* __restrict__ rp, const i
     int32_t q = rp[u] + which;
     if (q < rp[u + 1]) uf_union(parent, u, ci[q]);
 }
-// full path compression; snapshot of membership in the component rooted at giant
-__global__ void k_cc_compress(int32_t n, int32_t* parent, int32_t giant, uint8_t* in_giant) {
+// full path compression; with in_giant, a snapshot of membership in the
+// component rooted at *giant
+__global__ void k_cc_compress(int32_t n, int32_t* parent, const int32_t* giant, uint8_t* in_giant) {
     int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     int32_t r = uf_find_coherent(parent, v);
     parent[v] = r;
-    if (in_giant) in_giant[v] = (r == giant);
+    if (in_giant) in_giant[v] = (r == *giant);
+}
+// the most frequent root among the samples, ties to the smallest: one block
+// of 1024 threads, each counting the copies of its own sample (every
+// thread reads the same LDS word at the same step: broadcasts)
+__global__ void __launch_bounds__(1024) k_cc_mode(int32_t ns, const int32_t* smp, int32_t* out) {
+    __shared__ int32_t a[1024];
+    __shared__ unsigned long long best[1024 / 64];
+    const int t = threadIdx.x;
+    a[t] = t < ns ? smp[t] : -1;
+    __syncthreads();
+    unsigned long long key = 0;
+    if (t < ns) {
+        const int32_t mine = a[t];
+        int32_t c = 0;
+        for (int j = 0; j < ns; j++) c += a[j] == mine;
+        key = ((unsigned long long)c << 32) | (0xffffffffull - (uint32_t)mine);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(key, o, 64);
+        key = y > key ? y : key;
+    }
+    if (lane_id() == 0) best[t >> 6] = key;
+    __syncthreads();
+    if (t == 0) {
+        unsigned long long m = 0;
+        for (int w = 0; w < 1024 / 64; w++) m = best[w] > m ? best[w] : m;
+        *out = (int32_t)(0xffffffffull - (m & 0xffffffffull));
+    }
+}
+// the dominant component may since have been linked under a smaller root
+__global__ void k_cc_giant_root(const int32_t* parent, const int32_t* giant, int32_t* root) {
+    if (threadIdx.x == 0) *root = parent[*giant];
 }
 __global__ void k_cc_sample(int32_t n, int32_t ns, const int32_t* parent, int32_t* out) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -96,9 +130,10 @@ __global__ void k_cc_link_rest(int32_t n, const int32_t* __restrict__ rp, const 
 }
 // sizes: vertices outside the dominant component count into their root,
 // the dominant component's size is n minus all of those
-__global__ void k_cc_count(int32_t n, const int32_t* __restrict__ parent, int32_t giant, int64_t* size,
+__global__ void k_cc_count(int32_t n, const int32_t* __restrict__ parent, const int32_t* giant_dev, int64_t* size,
                            int64_t* outside) {
     __shared__ int64_t part[4];
+    const int32_t giant = *giant_dev;
     int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     int64_t mine = 0;
     if (v < n) {
@@ -113,10 +148,11 @@ __global__ void k_cc_count(int32_t n, const int32_t* __restrict__ parent, int32_
         if (t) fadd_rlx(outside, t);
     }
 }
-__global__ void k_cc_assign(int32_t n, const int32_t* parent, const int64_t* size, int32_t giant,
+__global__ void k_cc_assign(int32_t n, const int32_t* parent, const int64_t* size, const int32_t* giant_dev,
                             const int64_t* outside, int64_t* alpha, int64_t* omega) {
     int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
+    const int32_t giant = *giant_dev;
     int32_t r = parent[v];
     int64_t s = (r == giant) ? (int64_t)n - *outside : size[r];
     alpha[v] = s;
@@ -369,6 +405,7 @@ int tkc_launch_degrees(const DevGraph& g, hipStream_t s) {
 
 int tkc_launch_cc(const DevGraph& g, int32_t* parent, int64_t* size, int64_t* alpha, int64_t* omega,
                   uint8_t* in_giant, int32_t* sample_host, hipStream_t s) {
+    (void)sample_host;   // the dominant component is found on the device
     int32_t n = g.n;
     const int32_t* heavy = g.heavy;
     const int32_t nheavy = g.nheavy;
@@ -377,39 +414,32 @@ int tkc_launch_cc(const DevGraph& g, int32_t* parent, int64_t* size, int64_t* al
     hipLaunchKernelGGL(k_cc_init, dim3(nl), dim3(256), 0, s, n, parent);
     for (int32_t which = 0; which < first; which++) {
         hipLaunchKernelGGL(k_cc_link_one, dim3(nl), dim3(256), 0, s, n, g.rp, g.ci, which, parent);
-        hipLaunchKernelGGL(k_cc_compress, dim3(nl), dim3(256), 0, s, n, parent, -1, (uint8_t*)nullptr);
+        hipLaunchKernelGGL(k_cc_compress, dim3(nl), dim3(256), 0, s, n, parent, (const int32_t*)nullptr,
+                           (uint8_t*)nullptr);
     }
-    // dominant component: most frequent root among evenly spaced samples
+    // dominant component: most frequent root among evenly spaced samples,
+    // found on the device (no host round trip).  The samples and their mode
+    // live in `size` until the counting below; the final root, in the first
+    // four bytes of in_giant once the membership snapshot is spent (the
+    // workspace gives every buffer at least 256 bytes).
     const int NS = 1024;
     int ns = n < NS ? n : NS;
-    int32_t* sample_dev = (int32_t*)size;   // free until the counting below
+    int32_t* sample_dev = (int32_t*)size;
+    int32_t* giant_sample = sample_dev + ns;
+    int32_t* giant_root = (int32_t*)in_giant;
     hipLaunchKernelGGL(k_cc_sample, dim3(nblk(ns, 256)), dim3(256), 0, s, n, ns, parent, sample_dev);
-    if (hipMemcpyAsync(sample_host, sample_dev, 4 * (size_t)ns, hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
-    if (hipStreamSynchronize(s) != hipSuccess) return -1;
-    // mode of the sample (ties: smallest root)
-    int32_t giant = sample_host[0];
-    {
-        std::sort(sample_host, sample_host + ns);
-        int best = 0;
-        for (int i = 0; i < ns;) {
-            int j = i;
-            while (j < ns && sample_host[j] == sample_host[i]) j++;
-            if (j - i > best) { best = j - i; giant = sample_host[i]; }
-            i = j;
-        }
-    }
-    hipLaunchKernelGGL(k_cc_compress, dim3(nl), dim3(256), 0, s, n, parent, giant, in_giant);
+    hipLaunchKernelGGL(k_cc_mode, dim3(1), dim3(1024), 0, s, ns, sample_dev, giant_sample);
+    hipLaunchKernelGGL(k_cc_compress, dim3(nl), dim3(256), 0, s, n, parent, (const int32_t*)giant_sample, in_giant);
     int nh = nblk((int64_t)nheavy * 64, 256);
     hipLaunchKernelGGL(k_cc_link_rest, dim3(nl + nh), dim3(256), 0, s, n, g.rp, g.ci, g.deg, heavy, nheavy,
                        nl, first, in_giant, parent);
-    hipLaunchKernelGGL(k_cc_compress, dim3(nl), dim3(256), 0, s, n, parent, -1, (uint8_t*)nullptr);
-    // the dominant component may have been linked under a smaller root
-    if (hipMemcpyAsync(sample_host, parent + giant, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
-    if (hipStreamSynchronize(s) != hipSuccess) return -1;
-    giant = sample_host[0];
+    hipLaunchKernelGGL(k_cc_compress, dim3(nl), dim3(256), 0, s, n, parent, (const int32_t*)nullptr,
+                       (uint8_t*)nullptr);
+    hipLaunchKernelGGL(k_cc_giant_root, dim3(1), dim3(64), 0, s, parent, (const int32_t*)giant_sample, giant_root);
     if (hipMemsetAsync(size, 0, sizeof(int64_t) * ((size_t)n + 1), s) != hipSuccess) return -1;
-    hipLaunchKernelGGL(k_cc_count, dim3(nl), dim3(256), 0, s, n, parent, giant, size, size + n);
-    hipLaunchKernelGGL(k_cc_assign, dim3(nl), dim3(256), 0, s, n, parent, size, giant, size + n, alpha, omega);
+    hipLaunchKernelGGL(k_cc_count, dim3(nl), dim3(256), 0, s, n, parent, (const int32_t*)giant_root, size, size + n);
+    hipLaunchKernelGGL(k_cc_assign, dim3(nl), dim3(256), 0, s, n, parent, size, (const int32_t*)giant_root, size + n,
+                       alpha, omega);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
