@@ -462,12 +462,9 @@ int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega,
     int64_t k = 2;
     const int64_t kmax = (int64_t)n + 2;
     for (;;) {
-        if (hipMemcpyAsync(nfin_host, nfin_dev, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
-            return -1;
-        if (hipStreamSynchronize(s) != hipSuccess) return -1;
-        done = *nfin_host;
-        if (done >= n || k > kmax) break;
-        // several rounds per host check: a finished graph makes extra rounds no-ops
+        // two rounds per host check (the first pair without one: the
+        // initial level rarely finishes every vertex); once every vertex
+        // has finished, further rounds change no bound
         for (int rep = 0; rep < 2 && k <= kmax; rep++, k++) {
             int64_t* g1 = buf[(k - 1) % 3];
             int64_t* g2 = buf[(k - 2) % 3];
@@ -489,6 +486,11 @@ int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega,
             }
         }
         if (hipGetLastError() != hipSuccess) return -1;
+        if (hipMemcpyAsync(nfin_host, nfin_dev, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+            return -1;
+        if (hipStreamSynchronize(s) != hipSuccess) return -1;
+        done = *nfin_host;
+        if (done >= n || k > kmax) break;
     }
     return (int)(k - 2);
 }
