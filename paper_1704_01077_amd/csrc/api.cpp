@@ -174,6 +174,7 @@ extern "C" int tkc_ctx_create(int device, void* hip_stream, tkc_ctx** out) {
     }
     hipEventCreate(&c->ev0);
     hipEventCreate(&c->ev1);
+    for (auto& e : c->evq) hipEventCreate(&e);
     hipHostMalloc((void**)&c->pinned, 4096, hipHostMallocDefault);
     *out = c;
     return TKC_OK;
@@ -188,6 +189,7 @@ extern "C" int tkc_ctx_destroy(tkc_ctx* c) {
     if (c->pinned) hipHostFree(c->pinned);
     hipEventDestroy(c->ev0);
     hipEventDestroy(c->ev1);
+    for (auto& e : c->evq) hipEventDestroy(e);
     if (c->own_stream) hipStreamDestroy(c->stream);
     delete c;
     return TKC_OK;
@@ -841,14 +843,13 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
     }
     if (rc) return rc;
     int32_t rounds = 0;
-    double t1;
+    HIPCHK(hipEventRecord(c->evq[0], s));
     if (!harm && tkc_prep_cached(c, g, nb, &rounds)) {
-        t1 = now_ms();
+        HIPCHK(hipEventRecord(c->evq[1], s));
     } else {
         rc = tkc_step_reach(c, g, ws);
         if (rc) return rc;
-        HIPCHK(hipStreamSynchronize(s));
-        t1 = now_ms();
+        HIPCHK(hipEventRecord(c->evq[1], s));
         rc = tkc_step_bounds(c, g, ws, nb, &rounds, harm);
         if (rc) return rc;
         if (g->cache_prep && !harm) {
@@ -861,8 +862,7 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
     if (tkc_launch_topk_init(tk, k, s, ties ? &tb : nullptr)) return tkc_fail(TKC_EDEVICE, "top-k init failed");
     HIPCHK(hipMemsetAsync(ws.stats, 0, 8 * 4 * ST_COUNT, s));
     HIPCHK(hipMemsetAsync(ws.p_vis, 0, 4 * (((size_t)n + 31) / 32), s));
-    HIPCHK(hipStreamSynchronize(s));
-    double t2 = now_ms();
+    HIPCHK(hipEventRecord(c->evq[2], s));
 
     DevGraph dg = g->view();
     DevReach rcv{ws.alpha, ws.omega, g->directed ? ws.scc : nullptr};
@@ -978,8 +978,7 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
             }
         }
     }
-    HIPCHK(hipStreamSynchronize(s));
-    double t3 = now_ms();
+    HIPCHK(hipEventRecord(c->evq[3], s));
     // readback
     int64_t hstat[4][ST_COUNT];
     HIPCHK(hipMemcpyAsync(hstat, ws.stats, sizeof(hstat), hipMemcpyDeviceToHost, s));
@@ -1063,9 +1062,12 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
         st.variant_used = variant;
         st.mode_used = mode;
         st.nb_rounds = rounds;
-        st.ms_reach = t1 - t0;
-        st.ms_bounds = t2 - t1;
-        st.ms_traverse = t3 - t2;
+        // phases from the stream's marks (the readback synchronised it)
+        float ph[3] = {0.f, 0.f, 0.f};
+        for (int i = 0; i < 3; i++) HIPCHK(hipEventElapsedTime(&ph[i], c->evq[i], c->evq[i + 1]));
+        st.ms_reach = ph[0];
+        st.ms_bounds = ph[1];
+        st.ms_traverse = ph[2];
         st.ms_total = t4 - t0;
         int best = 0;
         for (int e = 1; e < 3; e++)

@@ -68,6 +68,9 @@ struct tkc_ctx {
     EngineTuning tune;
     Workspace ws;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // query phase marks on the stream: start, reachability done, bounds and
+    // top-k set-up done, searches done (phase times without host waits)
+    hipEvent_t evq[4] = {nullptr, nullptr, nullptr, nullptr};
     void* pinned = nullptr;   // 4 KiB of pinned host memory for small readbacks
 };
 
