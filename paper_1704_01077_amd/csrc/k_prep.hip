@@ -242,10 +242,12 @@ __global__ void k_nb_init(int32_t n, const int32_t* __restrict__ deg, const int6
     if (lane_id() == 0 && tot) fadd_rlx(nfin, tot);
 }
 
+// adv = false only writes the count (the vertex's state was advanced at this
+// level already, by a tail round over the open vertices)
 template <bool DIRECTED>
 TKC_DEV void nb_finish_vertex(int32_t s, uint64_t acc, int64_t k, int32_t d, const int64_t* g2,
                               int64_t* gk, const int64_t* alpha, const int64_t* omega, NBState st,
-                              bool* fin_now) {
+                              bool adv, bool* fin_now) {
     int64_t val;
     if (acc >= (uint64_t)NB_INF) val = NB_INF;
     else {
@@ -257,8 +259,9 @@ TKC_DEV void nb_finish_vertex(int32_t s, uint64_t acc, int64_t k, int32_t d, con
         }
     }
     gk[s] = val;
-    uint8_t fl = st.flags[s];
     *fin_now = false;
+    if (!adv) return;
+    uint8_t fl = st.flags[s];
     if (fl & 1) return;
     int64_t pv = st.vis[s], ps = st.sum[s], num = st.num[s], den = st.den[s];
     if (st.hub) nb_harm(st.hub, s, k, val, omega[s], pv);
@@ -272,7 +275,8 @@ __global__ void k_nb_round(int32_t n, const int32_t* __restrict__ rp, const int3
                            const int32_t* __restrict__ ch_end, int32_t nchunks, int32_t nlight_blocks,
                            int64_t k, const int64_t* __restrict__ g1, const int64_t* __restrict__ g2,
                            int64_t* __restrict__ gk, const int64_t* __restrict__ alpha,
-                           const int64_t* __restrict__ omega, NBState st, uint64_t* partial, int32_t* nfin) {
+                           const int64_t* __restrict__ omega, NBState st, uint64_t* partial, int32_t* nfin,
+                           int32_t adv) {
     if ((int32_t)blockIdx.x < nlight_blocks) {
         // light vertices: one thread each, finished in place
         bool fin = false;
@@ -295,7 +299,7 @@ __global__ void k_nb_round(int32_t n, const int32_t* __restrict__ rp, const int3
                 acc += (uint64_t)g1[ci[e]];
                 if (acc > (uint64_t)NB_INF) acc = NB_INF;
             }
-            nb_finish_vertex<DIRECTED>(s, acc, k, deg[s], g2, gk, alpha, omega, st, &fin);
+            nb_finish_vertex<DIRECTED>(s, acc, k, deg[s], g2, gk, alpha, omega, st, adv != 0, &fin);
         }
         int tot;
         wave_rank(fin, &tot);
@@ -323,7 +327,7 @@ __global__ void k_nb_heavy(int32_t nheavy, const int32_t* __restrict__ heavy, co
                            const uint64_t* __restrict__ partial, const int32_t* __restrict__ deg, int64_t k,
                            const int64_t* __restrict__ g2, int64_t* __restrict__ gk,
                            const int64_t* __restrict__ alpha, const int64_t* __restrict__ omega, NBState st,
-                           int32_t* nfin) {
+                           int32_t* nfin, int32_t adv) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     bool fin = false;
     if (i < nheavy) {
@@ -333,11 +337,56 @@ __global__ void k_nb_heavy(int32_t nheavy, const int32_t* __restrict__ heavy, co
             if (acc > (uint64_t)NB_INF) acc = NB_INF;
         }
         int32_t s = heavy[i];
-        nb_finish_vertex<DIRECTED>(s, acc, k, deg[s], g2, gk, alpha, omega, st, &fin);
+        nb_finish_vertex<DIRECTED>(s, acc, k, deg[s], g2, gk, alpha, omega, st, adv != 0, &fin);
     }
     int tot;
     wave_rank(fin, &tot);
     if (lane_id() == 0 && tot) fadd_rlx(nfin, tot);
+}
+
+// The open (unfinished) vertices, in no particular order: the tail round
+// treats each on its own, so the order changes no result.  At most cap are
+// written; *cnt counts them all.
+__global__ void k_nb_collect(int32_t n, const uint8_t* __restrict__ flags, int32_t cap, int32_t* list,
+                             int32_t* cnt) {
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool open = s < n && !(flags[s] & 1);
+    int tot;
+    const int r = wave_rank(open, &tot);
+    int base = 0;
+    if (lane_id() == 0 && tot) base = fadd_rlx(cnt, tot);
+    base = __shfl(base, 0, 64);
+    if (open && base + r < cap) list[base + r] = s;
+}
+// A round over the listed vertices alone (one wave each): the same
+// saturating sum as the full round (min(sum, 2^62) in any order), then the
+// same finish.  Only the listed vertices' counts at level k are written.
+template <bool DIRECTED>
+__global__ void k_nb_tail(const int32_t* __restrict__ cnt, int32_t cap, const int32_t* __restrict__ list,
+                          const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                          const int32_t* __restrict__ deg, int64_t k, const int64_t* __restrict__ g1,
+                          const int64_t* __restrict__ g2, int64_t* __restrict__ gk,
+                          const int64_t* __restrict__ alpha, const int64_t* __restrict__ omega, NBState st,
+                          int32_t* nfin) {
+    const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int32_t m = *cnt < cap ? *cnt : cap;
+    if (w >= m) return;   // wave-uniform
+    const int32_t s = list[w];
+    uint64_t acc = 0;
+    for (int32_t e = rp[s] + lane_id(); e < rp[s + 1]; e += 64) {
+        acc += (uint64_t)g1[ci[e]];
+        if (acc > (uint64_t)NB_INF) acc = NB_INF;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        acc += __shfl_xor(acc, o, 64);
+        if (acc > (uint64_t)NB_INF) acc = NB_INF;
+    }
+    if (lane_id() == 0) {
+        bool fin = false;
+        nb_finish_vertex<DIRECTED>(s, acc, k, deg[s], g2, gk, alpha, omega, st, true, &fin);
+        if (fin) fadd_rlx(nfin, 1);
+    }
 }
 
 // ------------------------------------------------------ order keys (Sect. 4)
@@ -443,7 +492,12 @@ int tkc_launch_cc(const DevGraph& g, int32_t* parent, int64_t* size, int64_t* al
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// NB bound: returns the number of rounds, -1 on error.  gbuf holds 3*n int64.
+// open vertices below which a round first treats them alone
+#define NB_TAIL_DIV 64
+
+// NB bound: returns the number of rounds, -1 on error.  gbuf holds 3*n int64;
+// partial holds the heavy chunks' partial sums and also at least
+// n / NB_TAIL_DIV int32; nfin_dev holds two int32.
 int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega, int64_t* gbuf, int64_t* sum,
                   int64_t* vis, uint8_t* flags, int64_t* num, int64_t* den, uint64_t* partial,
                   int32_t* nfin_dev, int32_t* nfin_host, hipStream_t s, double* hub) {
@@ -461,36 +515,77 @@ int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega,
     int32_t done = 0;
     int64_t k = 2;
     const int64_t kmax = (int64_t)n + 2;
-    for (;;) {
-        // two rounds per host check (the first pair without one: the
+    // a full round at level k (adv = 0: counts only, no vertex advances)
+    auto round = [&](int64_t lv, int32_t adv) {
+        int64_t* g1 = buf[(lv - 1) % 3];
+        int64_t* g2 = buf[(lv - 2) % 3];
+        int64_t* gk = buf[lv % 3];
+        if (g.directed) {
+            hipLaunchKernelGGL(k_nb_round<true>, dim3(nl + nc), dim3(256), 0, s, n, g.rp, g.ci, g.deg, g.ch_beg,
+                               g.ch_end, g.nchunks, nl, lv, g1, g2, gk, alpha, omega, st, partial, nfin_dev, adv);
+            if (g.nheavy)
+                hipLaunchKernelGGL(k_nb_heavy<true>, dim3(nhb), dim3(256), 0, s, g.nheavy, g.heavy, g.hcb, partial,
+                                   g.deg, lv, g2, gk, alpha, omega, st, nfin_dev, adv);
+        } else {
+            hipLaunchKernelGGL(k_nb_round<false>, dim3(nl + nc), dim3(256), 0, s, n, g.rp, g.ci, g.deg, g.ch_beg,
+                               g.ch_end, g.nchunks, nl, lv, g1, g2, gk, alpha, omega, st, partial, nfin_dev, adv);
+            if (g.nheavy)
+                hipLaunchKernelGGL(k_nb_heavy<false>, dim3(nhb), dim3(256), 0, s, g.nheavy, g.heavy, g.hcb,
+                                   partial, g.deg, lv, g2, gk, alpha, omega, st, nfin_dev, adv);
+        }
+    };
+    auto check = [&]() -> bool {
+        if (hipGetLastError() != hipSuccess) return false;
+        if (hipMemcpyAsync(nfin_host, nfin_dev, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+            return false;
+        if (hipStreamSynchronize(s) != hipSuccess) return false;
+        done = *nfin_host;
+        return true;
+    };
+    // tail rounds: once at most n / NB_TAIL_DIV vertices are open, a round
+    // first treats them alone (their list sits in `partial`, which the
+    // tail round does not use); if some stay open, a full round at the
+    // same level then supplies every other vertex's count, and the next
+    // try waits until four times fewer are open
+    const int32_t tail_cap = n / NB_TAIL_DIV;
+    int32_t tail_at = tail_cap;
+    int32_t* tail_list = (int32_t*)partial;
+    int32_t* tail_cnt = nfin_dev + 1;
+    bool checked = false;
+    while (k <= kmax) {
+        const int32_t open = n - done;
+        if (checked && open <= tail_at) {
+            if (hipMemsetAsync(tail_cnt, 0, sizeof(int32_t), s) != hipSuccess) return -1;
+            hipLaunchKernelGGL(k_nb_collect, dim3(nl), dim3(256), 0, s, n, (const uint8_t*)flags, tail_cap,
+                               tail_list, tail_cnt);
+            const int nt = nblk((int64_t)open * 64, 256);
+            const int64_t* g1 = buf[(k - 1) % 3];
+            const int64_t* g2 = buf[(k - 2) % 3];
+            int64_t* gk = buf[k % 3];
+            if (g.directed)
+                hipLaunchKernelGGL(k_nb_tail<true>, dim3(nt), dim3(256), 0, s, (const int32_t*)tail_cnt, tail_cap,
+                                   (const int32_t*)tail_list, g.rp, g.ci, g.deg, k, g1, g2, gk, alpha, omega, st,
+                                   nfin_dev);
+            else
+                hipLaunchKernelGGL(k_nb_tail<false>, dim3(nt), dim3(256), 0, s, (const int32_t*)tail_cnt, tail_cap,
+                                   (const int32_t*)tail_list, g.rp, g.ci, g.deg, k, g1, g2, gk, alpha, omega, st,
+                                   nfin_dev);
+            if (!check()) return -1;
+            if (done < n) {
+                round(k, 0);
+                tail_at = (n - done) / 4;
+            }
+            k++;
+            if (done >= n) break;
+            continue;
+        }
+        // two full rounds per host check (the first pair without one: the
         // initial level rarely finishes every vertex); once every vertex
         // has finished, further rounds change no bound
-        for (int rep = 0; rep < 2 && k <= kmax; rep++, k++) {
-            int64_t* g1 = buf[(k - 1) % 3];
-            int64_t* g2 = buf[(k - 2) % 3];
-            int64_t* gk = buf[k % 3];
-            if (g.directed) {
-                hipLaunchKernelGGL(k_nb_round<true>, dim3(nl + nc), dim3(256), 0, s, n, g.rp, g.ci, g.deg,
-                                   g.ch_beg, g.ch_end, g.nchunks, nl, k, g1, g2, gk, alpha, omega, st, partial,
-                                   nfin_dev);
-                if (g.nheavy)
-                    hipLaunchKernelGGL(k_nb_heavy<true>, dim3(nhb), dim3(256), 0, s, g.nheavy, g.heavy, g.hcb,
-                                       partial, g.deg, k, g2, gk, alpha, omega, st, nfin_dev);
-            } else {
-                hipLaunchKernelGGL(k_nb_round<false>, dim3(nl + nc), dim3(256), 0, s, n, g.rp, g.ci, g.deg,
-                                   g.ch_beg, g.ch_end, g.nchunks, nl, k, g1, g2, gk, alpha, omega, st, partial,
-                                   nfin_dev);
-                if (g.nheavy)
-                    hipLaunchKernelGGL(k_nb_heavy<false>, dim3(nhb), dim3(256), 0, s, g.nheavy, g.heavy, g.hcb,
-                                       partial, g.deg, k, g2, gk, alpha, omega, st, nfin_dev);
-            }
-        }
-        if (hipGetLastError() != hipSuccess) return -1;
-        if (hipMemcpyAsync(nfin_host, nfin_dev, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
-            return -1;
-        if (hipStreamSynchronize(s) != hipSuccess) return -1;
-        done = *nfin_host;
-        if (done >= n || k > kmax) break;
+        for (int rep = 0; rep < 2 && k <= kmax; rep++, k++) round(k, 1);
+        if (!check()) return -1;
+        checked = true;
+        if (done >= n) break;
     }
     return (int)(k - 2);
 }

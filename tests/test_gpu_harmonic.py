@@ -48,6 +48,9 @@ def graph(name):
         return graphgen.workload("ba2k")
     if name == "ba20k":
         return graphgen.ba_graph(20000, 5, 7)
+    if name == "ba_path":     # BA with a hanging path: open vertices linger for many levels
+        b = graphgen.ba(3000, 3, 17)
+        return _g(name, 3030, np.concatenate([b, [(2999 + i, 3000 + i) for i in range(30)]]), False)
     if name == "grid60":
         return graphgen.grid_graph(60, 0.05, 3, seed=5)
     if name == "grid150":
@@ -85,7 +88,7 @@ def graph(name):
     raise KeyError(name)
 
 
-SMALL = ["ba2k", "grid60", "king40", "rmat11", "gnp_u", "gnp_d", "forest", "cycle", "complete", "star",
+SMALL = ["ba2k", "ba_path", "grid60", "king40", "rmat11", "gnp_u", "gnp_d", "forest", "cycle", "complete", "star",
          "dpath", "single", "edgeless", "sinks"]
 _DEV = {}
 
@@ -141,7 +144,8 @@ def test_harmonic_batch_widths(ctx, width):
         ctx.tune(**keep)
 
 
-@pytest.mark.parametrize("name", ["ba2k", "gnp_u", "gnp_d", "forest", "rmat11", "dpath", "star", "sinks"])
+@pytest.mark.parametrize("name", ["ba2k", "ba_path", "grid60", "gnp_u", "gnp_d", "forest", "rmat11", "dpath",
+                                  "star", "sinks"])
 def test_harmonic_bounds_parity(ctx, name):
     """Walk-count bounds bit for bit (the same terms in the same order as the
     oracle's), degree bounds likewise, both above h, and the order."""

@@ -48,6 +48,9 @@ def graph(name):
         return graphgen.ba_graph(20000, 5, 7)
     if name == "ba3k_m2":
         return graphgen.ba_graph(3000, 2, 11)
+    if name == "ba_path":     # BA with a hanging path: open vertices linger for many levels
+        b = graphgen.ba(3000, 3, 17)
+        return _g(name, 3030, np.concatenate([b, [(2999 + i, 3000 + i) for i in range(30)]]), False)
     if name == "grid60":
         return graphgen.grid_graph(60, 0.05, 3, seed=5)
     if name == "grid150":
@@ -119,7 +122,7 @@ def expect(name, k):
     return ids, S[ids], r[ids], far
 
 
-SMALL = ["ba2k", "ba3k_m2", "grid60", "king40", "rmat11", "gnp_u", "gnp_d", "forest", "cycle", "complete",
+SMALL = ["ba2k", "ba3k_m2", "ba_path", "grid60", "king40", "rmat11", "gnp_u", "gnp_d", "forest", "cycle", "complete",
          "star", "dpath", "ties", "reduction", "single", "edgeless", "sinks"]
 
 
@@ -154,8 +157,10 @@ def rat_equal(n1, d1, n2, d2):
     return bool(np.all(n1[fin] * d2[fin] == n2[fin] * d1[fin]))
 
 
-@pytest.mark.parametrize("name", ["ba2k", "ba20k", "grid60", "king40", "rmat11", "rmat13", "gnp_u", "gnp_d",
-                                  "forest", "cycle", "star", "dpath", "reduction", "sinks", "single"])
+# the NB rounds' tail (a round over the few open vertices alone) succeeds on
+# grid60 and gnp_u, fails and falls back to full rounds on gnp_d and ba_path
+@pytest.mark.parametrize("name", ["ba2k", "ba20k", "ba_path", "grid60", "king40", "rmat11", "rmat13", "gnp_u",
+                                  "gnp_d", "forest", "cycle", "star", "dpath", "reduction", "sinks", "single"])
 def test_nb_bound_parity(ctx, name):
     g = graph(name)
     dg = upload(ctx, name)
