@@ -77,7 +77,7 @@ static size_t ws_items(Workspace& ws, const WsShape& sh, std::vector<WsItem>& it
         {(void**)&ws.csize, 8 * n + 8, false}, {(void**)&ws.gbuf, 24 * n, false},
         {(void**)&ws.nbsum, 8 * n, false}, {(void**)&ws.nbvis, 8 * n, false},
         {(void**)&ws.nbhub, 8 * n, false},
-        {(void**)&ws.nbflags, n, false}, {(void**)&ws.small, 4096, false},
+        {(void**)&ws.nbflags, n, false}, {(void**)&ws.small, 8192, false},
         // NB: heavy chunks' partial sums, or the tail rounds' list (n / 64 int32)
         {(void**)&ws.nbpart, std::max(8 * (size_t)sh.nchunks, 4 * (n / 64)) + 8, false},
         {(void**)&ws.tstate, 4096, false}, {(void**)&ws.ring, sizeof(XRec) * TKC_XRING, false},

@@ -178,6 +178,35 @@ struct NBState {
     int64_t* den;
     double* hub;      // harmonic upper bound (null: closeness only)
 };
+// Finish counts: one add per workgroup, into NB_NCTR counters 128 B apart.
+// Adds to one address are done one after another at the cache; with one
+// add per wave on a single counter, a round in which most waves finish a
+// vertex queued ~16K adds there and took twice as long.  k_nb_total sums
+// the counters for the host check.
+#define NB_NCTR 32
+#define NB_CTR_WORDS 32
+#define NB_TOTAL_WORD (NB_NCTR * NB_CTR_WORDS)
+#define NB_TAILCNT_WORD (NB_TOTAL_WORD + 32)
+// every thread of the block calls it; lds holds one int per wave
+TKC_DEV void nb_count(bool fin, int32_t* nfin, int32_t* lds) {
+    int tot;
+    wave_rank(fin, &tot);
+    if (lane_id() == 0) lds[threadIdx.x >> 6] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int i = 0; i < (int)((blockDim.x + 63) >> 6); i++) t += lds[i];
+        if (t) fadd_rlx(nfin + (blockIdx.x % NB_NCTR) * NB_CTR_WORDS, t);
+    }
+}
+// one wave: the counters' sum into nfin[NB_TOTAL_WORD]
+__global__ void k_nb_total(int32_t* nfin) {
+    int32_t v = lane_id() < NB_NCTR ? nfin[lane_id() * NB_CTR_WORDS] : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane_id() == 0) nfin[NB_TOTAL_WORD] = v;
+}
+
 // Harmonic centrality from the same counts: level k takes min(gamma_k,
 // omega - placed) vertices (placed = the visited count, s included), the
 // closest placement the counts allow, and adds that many times 1/k.  Called
@@ -237,9 +266,8 @@ __global__ void k_nb_init(int32_t n, const int32_t* __restrict__ deg, const int6
         }
         st.sum[s] = ps; st.vis[s] = pv; st.flags[s] = fl; st.num[s] = num; st.den[s] = den;
     }
-    int tot;
-    wave_rank(fin, &tot);
-    if (lane_id() == 0 && tot) fadd_rlx(nfin, tot);
+    __shared__ int32_t lds[16];
+    nb_count(fin, nfin, lds);
 }
 
 // adv = false only writes the count (the vertex's state was advanced at this
@@ -301,9 +329,8 @@ __global__ void k_nb_round(int32_t n, const int32_t* __restrict__ rp, const int3
             }
             nb_finish_vertex<DIRECTED>(s, acc, k, deg[s], g2, gk, alpha, omega, st, adv != 0, &fin);
         }
-        int tot;
-        wave_rank(fin, &tot);
-        if (lane_id() == 0 && tot) fadd_rlx(nfin, tot);
+        __shared__ int32_t lds[16];
+        nb_count(fin, nfin, lds);   // the branch is uniform over the workgroup
     } else {
         // arcs of heavy vertices: one wave per chunk, saturating partial sum
         int32_t c = ((blockIdx.x - nlight_blocks) * blockDim.x + threadIdx.x) >> 6;
@@ -339,24 +366,36 @@ __global__ void k_nb_heavy(int32_t nheavy, const int32_t* __restrict__ heavy, co
         int32_t s = heavy[i];
         nb_finish_vertex<DIRECTED>(s, acc, k, deg[s], g2, gk, alpha, omega, st, adv != 0, &fin);
     }
-    int tot;
-    wave_rank(fin, &tot);
-    if (lane_id() == 0 && tot) fadd_rlx(nfin, tot);
+    __shared__ int32_t lds[16];
+    nb_count(fin, nfin, lds);
 }
 
 // The open (unfinished) vertices, in no particular order: the tail round
 // treats each on its own, so the order changes no result.  At most cap are
-// written; *cnt counts them all.
+// written; *cnt counts them all.  One add per workgroup of 1024 threads.
 __global__ void k_nb_collect(int32_t n, const uint8_t* __restrict__ flags, int32_t cap, int32_t* list,
                              int32_t* cnt) {
+    __shared__ int32_t wbase[16];
+    __shared__ int32_t bbase;
     const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     const bool open = s < n && !(flags[s] & 1);
     int tot;
     const int r = wave_rank(open, &tot);
-    int base = 0;
-    if (lane_id() == 0 && tot) base = fadd_rlx(cnt, tot);
-    base = __shfl(base, 0, 64);
-    if (open && base + r < cap) list[base + r] = s;
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) wbase[w] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int i = 0; i < (int)((blockDim.x + 63) >> 6); i++) {
+            const int x = wbase[i];
+            wbase[i] = t;
+            t += x;
+        }
+        bbase = t ? fadd_rlx(cnt, t) : 0;
+    }
+    __syncthreads();
+    const int32_t pos = bbase + wbase[w] + r;
+    if (open && pos < cap) list[pos] = s;
 }
 // A round over the listed vertices alone (one wave each): the same
 // saturating sum as the full round (min(sum, 2^62) in any order), then the
@@ -370,23 +409,24 @@ __global__ void k_nb_tail(const int32_t* __restrict__ cnt, int32_t cap, const in
                           int32_t* nfin) {
     const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const int32_t m = *cnt < cap ? *cnt : cap;
-    if (w >= m) return;   // wave-uniform
-    const int32_t s = list[w];
-    uint64_t acc = 0;
-    for (int32_t e = rp[s] + lane_id(); e < rp[s + 1]; e += 64) {
-        acc += (uint64_t)g1[ci[e]];
-        if (acc > (uint64_t)NB_INF) acc = NB_INF;
-    }
+    bool fin = false;
+    if (w < m) {   // wave-uniform
+        const int32_t s = list[w];
+        uint64_t acc = 0;
+        for (int32_t e = rp[s] + lane_id(); e < rp[s + 1]; e += 64) {
+            acc += (uint64_t)g1[ci[e]];
+            if (acc > (uint64_t)NB_INF) acc = NB_INF;
+        }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        acc += __shfl_xor(acc, o, 64);
-        if (acc > (uint64_t)NB_INF) acc = NB_INF;
+        for (int o = 32; o > 0; o >>= 1) {
+            acc += __shfl_xor(acc, o, 64);
+            if (acc > (uint64_t)NB_INF) acc = NB_INF;
+        }
+        if (lane_id() == 0)
+            nb_finish_vertex<DIRECTED>(s, acc, k, deg[s], g2, gk, alpha, omega, st, true, &fin);
     }
-    if (lane_id() == 0) {
-        bool fin = false;
-        nb_finish_vertex<DIRECTED>(s, acc, k, deg[s], g2, gk, alpha, omega, st, true, &fin);
-        if (fin) fadd_rlx(nfin, 1);
-    }
+    __shared__ int32_t lds[16];
+    nb_count(fin, nfin, lds);
 }
 
 // ------------------------------------------------------ order keys (Sect. 4)
@@ -497,7 +537,8 @@ int tkc_launch_cc(const DevGraph& g, int32_t* parent, int64_t* size, int64_t* al
 
 // NB bound: returns the number of rounds, -1 on error.  gbuf holds 3*n int64;
 // partial holds the heavy chunks' partial sums and also at least
-// n / NB_TAIL_DIV int32; nfin_dev holds two int32.
+// n / NB_TAIL_DIV int32; nfin_dev holds NB_TAILCNT_WORD + 1 int32 (the
+// finish counters, their total, the tail list's count).
 int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega, int64_t* gbuf, int64_t* sum,
                   int64_t* vis, uint8_t* flags, int64_t* num, int64_t* den, uint64_t* partial,
                   int32_t* nfin_dev, int32_t* nfin_host, hipStream_t s, double* hub) {
@@ -507,7 +548,7 @@ int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega,
     int nhb = nblk(g.nheavy, 256);
     NBState st{sum, vis, flags, num, den, hub};
     int64_t* buf[3] = {gbuf, gbuf + n, gbuf + 2 * (int64_t)n};
-    hipMemsetAsync(nfin_dev, 0, sizeof(int32_t), s);
+    hipMemsetAsync(nfin_dev, 0, sizeof(int32_t) * NB_TOTAL_WORD, s);
     // gamma_0 -> buf[0], gamma_1 -> buf[1]
     hipLaunchKernelGGL(k_nb_init, dim3(nl), dim3(256), 0, s, n, g.deg, alpha, omega, buf[0], buf[1],
                        st, nfin_dev);
@@ -535,8 +576,10 @@ int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega,
         }
     };
     auto check = [&]() -> bool {
+        hipLaunchKernelGGL(k_nb_total, dim3(1), dim3(64), 0, s, nfin_dev);
         if (hipGetLastError() != hipSuccess) return false;
-        if (hipMemcpyAsync(nfin_host, nfin_dev, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+        if (hipMemcpyAsync(nfin_host, nfin_dev + NB_TOTAL_WORD, sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
+            hipSuccess)
             return false;
         if (hipStreamSynchronize(s) != hipSuccess) return false;
         done = *nfin_host;
@@ -550,14 +593,14 @@ int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega,
     const int32_t tail_cap = n / NB_TAIL_DIV;
     int32_t tail_at = tail_cap;
     int32_t* tail_list = (int32_t*)partial;
-    int32_t* tail_cnt = nfin_dev + 1;
+    int32_t* tail_cnt = nfin_dev + NB_TAILCNT_WORD;
     bool checked = false;
     while (k <= kmax) {
         const int32_t open = n - done;
         if (checked && open <= tail_at) {
             if (hipMemsetAsync(tail_cnt, 0, sizeof(int32_t), s) != hipSuccess) return -1;
-            hipLaunchKernelGGL(k_nb_collect, dim3(nl), dim3(256), 0, s, n, (const uint8_t*)flags, tail_cap,
-                               tail_list, tail_cnt);
+            hipLaunchKernelGGL(k_nb_collect, dim3(nblk(n, 1024)), dim3(1024), 0, s, n, (const uint8_t*)flags,
+                               tail_cap, tail_list, tail_cnt);
             const int nt = nblk((int64_t)open * 64, 256);
             const int64_t* g1 = buf[(k - 1) % 3];
             const int64_t* g2 = buf[(k - 2) % 3];
