@@ -80,12 +80,13 @@ static size_t ws_items(Workspace& ws, const WsShape& sh, std::vector<WsItem>& it
         {(void**)&ws.nbflags, n, false}, {(void**)&ws.small, 8192, false},
         // NB: heavy chunks' partial sums, or the tail rounds' list (n / 64 int32)
         {(void**)&ws.nbpart, std::max(8 * (size_t)sh.nchunks, 4 * (n / 64)) + 8, false},
-        {(void**)&ws.tstate, 4096, false}, {(void**)&ws.ring, sizeof(XRec) * TKC_XRING, false},
+        // read back together: keep stats .. tI adjacent and in this order
+        {(void**)&ws.stats, 8 * 4 * ST_COUNT, false}, {(void**)&ws.tstate, 4096, false},
         {(void**)&ws.tS, 8 * (size_t)sh.kcap, false}, {(void**)&ws.tR, 8 * (size_t)sh.kcap, false},
         {(void**)&ws.tI, 4 * (size_t)sh.kcap, false},
+        {(void**)&ws.ring, sizeof(XRec) * TKC_XRING, false},
         {(void**)&ws.tieS, sh.ties ? 8 * n : 8, false}, {(void**)&ws.tieR, sh.ties ? 8 * n : 8, false},
         {(void**)&ws.tieI, sh.ties ? 4 * n : 4, false},
-        {(void**)&ws.stats, 8 * 4 * ST_COUNT, false},
         {(void**)&ws.bar, 4 * tkc_bar_words(4096), true},
         // plain engine
         {(void**)&ws.p_vis, 4 * words, true}, {(void**)&ws.p_fb, 12 * words, true},
@@ -146,6 +147,18 @@ int tkc_ws_reserve(tkc_ctx* ctx, Workspace& ws, const WsShape& sh) {
         if (it.zero) HIPCHK(hipMemsetAsync(ws.base + off, 0, it.bytes, ctx->stream));
         off += align_up(it.bytes);
     }
+    const size_t span = (size_t)(((char*)ws.tI + 4 * (size_t)sh.kcap) - (char*)ws.stats);
+    if (ws.pin_bytes < span) {
+        if (ws.pin) hipHostFree(ws.pin);
+        ws.pin = nullptr;
+        ws.pin_bytes = 0;
+        if (hipHostMalloc((void**)&ws.pin, span, hipHostMallocDefault) != hipSuccess) {
+            hipGetLastError();
+            ws.pin = nullptr;
+            return tkc_fail(TKC_ENOMEM, "pinned host allocation of %zu bytes failed", span);
+        }
+        ws.pin_bytes = span;
+    }
     if (getenv("TKC_TRACE") && !ws.trace) {
         if (hipMalloc((void**)&ws.trace, 8 * (8 + 16 * 4096)) != hipSuccess) ws.trace = nullptr;
     }
@@ -187,6 +200,7 @@ extern "C" int tkc_ctx_destroy(tkc_ctx* c) {
     hipStreamSynchronize(c->stream);
     if (c->ws.base) hipFree(c->ws.base);
     if (c->ws.trace) hipFree(c->ws.trace);
+    if (c->ws.pin) hipHostFree(c->ws.pin);
     if (c->pinned) hipHostFree(c->pinned);
     hipEventDestroy(c->ev0);
     hipEventDestroy(c->ev1);
@@ -678,19 +692,50 @@ struct EngineTimer {
     EngineTimer(tkc_ctx* c_, double* a, int32_t* l) : c(c_), acc(a), launches(l), lk(tkc_coop_mutex()) {
         hipEventRecord(c->ev0, c->stream);
     }
-    void done() {
+    // ends the timed launch; `more` queues copies to pinned memory that the
+    // same host wait completes
+    template <typename F>
+    int done(F more) {
         hipEventRecord(c->ev1, c->stream);
-        hipEventSynchronize(c->ev1);
+        const int rc = more();
+        if (hipStreamSynchronize(c->stream) != hipSuccess)
+            return tkc_fail(TKC_EDEVICE, "engine launch failed: %s", hipGetErrorString(hipGetLastError()));
         float ms = 0.f;
         hipEventElapsedTime(&ms, c->ev0, c->ev1);
         *acc += ms;
         (*launches)++;
+        return rc;
+    }
+    int done() {
+        return done([] { return (int)TKC_OK; });
     }
 };
 
-static int read_stats(tkc_ctx* c, const int64_t* dev, int64_t* host) {
-    HIPCHK(hipMemcpyAsync(host, dev, 8 * ST_COUNT, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+// where a device address inside the read-back span sits in the pinned copy
+template <typename T>
+static T* pin_at(Workspace& ws, const void* dev) {
+    return (T*)(ws.pin + ((const char*)dev - (const char*)ws.stats));
+}
+// queue the copy of one engine's counters into the pinned span
+static int queue_stats(tkc_ctx* c, const int64_t* dev) {
+    HIPCHK(hipMemcpyAsync(pin_at<int64_t>(c->ws, dev), dev, 8 * ST_COUNT, hipMemcpyDeviceToHost, c->stream));
+    return TKC_OK;
+}
+// queue the copy of the whole result span (counters, top-k state, the k
+// results): one copy while the capacity is modest, else one per part
+static int queue_readback(tkc_ctx* c, int32_t k) {
+    Workspace& ws = c->ws;
+    hipStream_t s = c->stream;
+    if (ws.shape.kcap <= 4096) {
+        const size_t span = (size_t)(((char*)ws.tI + 4 * (size_t)k) - (char*)ws.stats);
+        HIPCHK(hipMemcpyAsync(ws.pin, ws.stats, span, hipMemcpyDeviceToHost, s));
+        return TKC_OK;
+    }
+    const size_t head = (size_t)(((char*)ws.tstate + sizeof(TopkState)) - (char*)ws.stats);
+    HIPCHK(hipMemcpyAsync(ws.pin, ws.stats, head, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(pin_at<int64_t>(ws, ws.tS), ws.tS, 8 * (size_t)k, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(pin_at<int64_t>(ws, ws.tR), ws.tR, 8 * (size_t)k, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(pin_at<int32_t>(ws, ws.tI), ws.tI, 4 * (size_t)k, hipMemcpyDeviceToHost, s));
     return TKC_OK;
 }
 
@@ -872,6 +917,9 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
     OrderView ov{ws.ord, ws.key, n, nb || harm};
     BoundsView bv{ws.lnum, ws.lden};
     bv.harm = harm ? 1 : 0;
+    // the results' copy, queued inside the last engine's host wait
+    bool rb_ready = false;
+    auto readback = [&] { return queue_readback(c, k); };
     int64_t* st_plain = ws.stats;
     int64_t* st_batch = ws.stats + ST_COUNT;
     int64_t* st_swarm = ws.stats + 2 * ST_COUNT;
@@ -885,7 +933,8 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
         EngineTimer tm(c, &ms_eng[0], &nl_eng[0]);
         if (tkc_launch_plain(dg, rcv, ov, bv, tk, plain_view(ws), st_plain, nullptr, 0, lbl, c->tune, s, &grid))
             return tkc_fail(TKC_EDEVICE, "plain engine launch failed: %s", hipGetErrorString(hipGetLastError()));
-        tm.done();
+        if ((rc = tm.done(readback))) return rc;
+        rb_ready = true;
     } else if (mode == TKC_BATCHED) {
         trace_reset(c);
         // one launch, or slices of slice_batches batches (the cursor, stop
@@ -899,12 +948,16 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
                                          false, nullptr, nullptr, c->tune, s, &grid);
                 if (e)
                     return tkc_fail(TKC_EDEVICE, "batched engine launch failed: %s", hipGetErrorString(hipGetLastError()));
-                tm.done();
+                if (!slice) {
+                    if ((rc = tm.done(readback))) return rc;
+                    rb_ready = true;
+                } else if ((rc = tm.done([&] { return queue_stats(c, st_batch); }))) {
+                    return rc;
+                }
             }
             if (!slice) break;
             int64_t hs[ST_COUNT];
-            rc = read_stats(c, st_batch, hs);
-            if (rc) return rc;
+            memcpy(hs, pin_at<int64_t>(ws, st_batch), sizeof(hs));
             if (hs[ST_STOP] || hs[ST_CURSOR] >= n) break;
             pos = (int32_t)hs[ST_CURSOR];
         }
@@ -923,11 +976,10 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
             if (tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_batch, nullptr, 0, 0, -1, false,
                                  false, nullptr, nullptr, seed, s, &grid))
                 return tkc_fail(TKC_EDEVICE, "batched seed launch failed: %s", hipGetErrorString(hipGetLastError()));
-            tm.done();
+            if ((rc = tm.done([&] { return queue_stats(c, st_batch); }))) return rc;
         }
+        memcpy(hs, pin_at<int64_t>(ws, st_batch), sizeof(hs));
         trace_dump(c, "seed");
-        rc = read_stats(c, st_batch, hs);
-        if (rc) return rc;
         int32_t cursor = (int32_t)hs[ST_CURSOR];
         bool stopped = hs[ST_STOP] != 0;
         if (!stopped && cursor < n) {
@@ -943,15 +995,19 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
             sw.qcap = ws.shape.qcap;
             sw.defer_cap = c->tune.batch_width;
             HIPCHK(hipMemsetAsync(small + 4, 0, 3 * sizeof(int32_t), s));
+            int32_t* pin = (int32_t*)c->pinned;
             {
+                // the swarm's exit state, and the results in case nothing follows
                 EngineTimer tm(c, &ms_eng[2], &nl_eng[2]);
                 if (tkc_launch_swarm(dg, rcv, ov, bv, tk, sw, st_swarm, cursor, c->tune, s))
                     return tkc_fail(TKC_EDEVICE, "per-workgroup engine launch failed");
-                tm.done();
+                if ((rc = tm.done([&] {
+                         HIPCHK(hipMemcpyAsync(pin, small + 4, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                         return readback();
+                     })))
+                    return rc;
+                rb_ready = true;
             }
-            int32_t* pin = (int32_t*)c->pinned;
-            HIPCHK(hipMemcpyAsync(pin, small + 4, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
             const int32_t ndef = pin[0], fetched = pin[1], sw_stop = pin[2];
             if (c->ws.trace)
                 fprintf(stderr, "trace hybrid: seed cursor %d, swarm deferred %d, fetched %d, stop bits %d\n",
@@ -962,7 +1018,7 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
                 if (tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_tail, ws.s_deferred, ndef, 0, 0,
                                      false, false, nullptr, nullptr, c->tune, s, &grid))
                     return tkc_fail(TKC_EDEVICE, "batched tail launch failed");
-                tm.done();
+                if ((rc = tm.done(readback))) return rc;
                 trace_dump(c, "tail");
             }
             // every position the cursor handed out was searched, skipped or
@@ -974,23 +1030,32 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
                 if (tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_batch, nullptr, 0, resume, 0, false,
                                      false, nullptr, nullptr, c->tune, s, &grid))
                     return tkc_fail(TKC_EDEVICE, "batched continuation launch failed");
-                tm.done();
+                if ((rc = tm.done(readback))) return rc;
                 trace_dump(c, "rest");
             }
         }
     }
-    HIPCHK(hipEventRecord(c->evq[3], s));
-    // readback
+    // the searches end with the last engine's end mark when its host wait
+    // already took the results, else here
+    hipEvent_t trav_end = c->ev1;
+    if (!rb_ready) {
+        trav_end = c->evq[3];
+        HIPCHK(hipEventRecord(trav_end, s));
+    }
+    // readback (already in pinned memory when the last engine's wait copied it)
+    if (!rb_ready) {
+        if ((rc = readback())) return rc;
+        HIPCHK(hipStreamSynchronize(s));
+    }
     int64_t hstat[4][ST_COUNT];
-    HIPCHK(hipMemcpyAsync(hstat, ws.stats, sizeof(hstat), hipMemcpyDeviceToHost, s));
+    memcpy(hstat, pin_at<int64_t>(ws, ws.stats), sizeof(hstat));
     TopkState hst;
-    HIPCHK(hipMemcpyAsync(&hst, ws.tstate, sizeof(hst), hipMemcpyDeviceToHost, s));
-    std::vector<int64_t> hS(k), hR(k);
-    std::vector<int32_t> hI(k);
-    HIPCHK(hipMemcpyAsync(hS.data(), ws.tS, 8 * (size_t)k, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hR.data(), ws.tR, 8 * (size_t)k, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hI.data(), ws.tI, 4 * (size_t)k, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    memcpy(&hst, pin_at<TopkState>(ws, ws.tstate), sizeof(hst));
+    const int64_t* pS = pin_at<int64_t>(ws, ws.tS);
+    const int64_t* pR = pin_at<int64_t>(ws, ws.tR);
+    const int32_t* pI = pin_at<int32_t>(ws, ws.tI);
+    std::vector<int64_t> hS(pS, pS + k), hR(pR, pR + k);
+    std::vector<int32_t> hI(pI, pI + k);
     int32_t cnt = std::min(hst.cnt, k);
     if (cnt != k)
         return tkc_fail(TKC_EDEVICE, "internal error: %d results for k = %d", cnt, k);
@@ -1065,7 +1130,8 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
         st.nb_rounds = rounds;
         // phases from the stream's marks (the readback synchronised it)
         float ph[3] = {0.f, 0.f, 0.f};
-        for (int i = 0; i < 3; i++) HIPCHK(hipEventElapsedTime(&ph[i], c->evq[i], c->evq[i + 1]));
+        for (int i = 0; i < 3; i++)
+            HIPCHK(hipEventElapsedTime(&ph[i], c->evq[i], i < 2 ? c->evq[i + 1] : trav_end));
         st.ms_reach = ph[0];
         st.ms_bounds = ph[1];
         st.ms_traverse = ph[2];

@@ -23,6 +23,10 @@ struct WsShape {
 struct Workspace {
     char* base = nullptr;
     size_t bytes = 0;
+    // pinned host copy of the span from `stats` to the end of `tI` (the
+    // query's results and counters, read back with one copy)
+    char* pin = nullptr;
+    size_t pin_bytes = 0;
     WsShape shape;
     int64_t *alpha, *omega;
     int32_t* scc;
