@@ -74,7 +74,7 @@ static size_t ws_items(Workspace& ws, const WsShape& sh, std::vector<WsItem>& it
         {(void**)&ws.tval, 4 * n, false},
         {(void**)&ws.hist, 4 * (size_t)tkc_sort_hist_words(sh.n), false},
         {(void**)&ws.mask, 64, false}, {(void**)&ws.parent, 4 * n, false},
-        {(void**)&ws.csize, 8 * n + 8, false}, {(void**)&ws.gbuf, 24 * n, false},
+        {(void**)&ws.csize, 8 * n + 16, false}, {(void**)&ws.gbuf, 24 * n, false},
         {(void**)&ws.nbsum, 8 * n, false}, {(void**)&ws.nbvis, 8 * n, false},
         {(void**)&ws.nbhub, 8 * n, false},
         {(void**)&ws.nbflags, n, false}, {(void**)&ws.small, 8192, false},
@@ -976,7 +976,12 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
             if (tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_batch, nullptr, 0, 0, -1, false,
                                  false, nullptr, nullptr, seed, s, &grid))
                 return tkc_fail(TKC_EDEVICE, "batched seed launch failed: %s", hipGetErrorString(hipGetLastError()));
-            if ((rc = tm.done([&] { return queue_stats(c, st_batch); }))) return rc;
+            // the swarm's exit counters are cleared behind the seed, before the wait
+            if ((rc = tm.done([&] {
+                     HIPCHK(hipMemsetAsync((int32_t*)ws.small + 4, 0, 3 * sizeof(int32_t), s));
+                     return queue_stats(c, st_batch);
+                 })))
+                return rc;
         }
         memcpy(hs, pin_at<int64_t>(ws, st_batch), sizeof(hs));
         trace_dump(c, "seed");
@@ -994,7 +999,6 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
             sw.nblocks = ws.shape.swarm_blocks;
             sw.qcap = ws.shape.qcap;
             sw.defer_cap = c->tune.batch_width;
-            HIPCHK(hipMemsetAsync(small + 4, 0, 3 * sizeof(int32_t), s));
             int32_t* pin = (int32_t*)c->pinned;
             {
                 // the swarm's exit state, and the results in case nothing follows

@@ -73,20 +73,26 @@ __global__ void k_cc_compress(int32_t n, int32_t* parent, const int32_t* giant, 
     parent[v] = r;
     if (in_giant) in_giant[v] = (r == *giant);
 }
-// the most frequent root among the samples, ties to the smallest: one block
-// of 1024 threads, each counting the copies of its own sample (every
-// thread reads the same LDS word at the same step: broadcasts)
-__global__ void __launch_bounds__(1024) k_cc_mode(int32_t ns, const int32_t* smp, int32_t* out) {
-    __shared__ int32_t a[1024];
+// the most frequent root among ns evenly spaced samples of the (compressed)
+// parents, ties to the smallest: one block of 1024 threads, each counting
+// the copies of its own sample (every thread reads the same LDS words at
+// the same step: broadcasts, four at a time; padding never matches a root)
+__global__ void __launch_bounds__(1024) k_cc_mode(int32_t n, int32_t ns, const int32_t* __restrict__ parent,
+                                                  int32_t* out) {
+    __shared__ __align__(16) int32_t a[1024];
     __shared__ unsigned long long best[1024 / 64];
     const int t = threadIdx.x;
-    a[t] = t < ns ? smp[t] : -1;
+    a[t] = t < ns ? parent[(int64_t)t * n / ns] : -1;
     __syncthreads();
     unsigned long long key = 0;
     if (t < ns) {
         const int32_t mine = a[t];
+        const int4* a4 = (const int4*)a;
         int32_t c = 0;
-        for (int j = 0; j < ns; j++) c += a[j] == mine;
+        for (int j = 0; j < 1024 / 4; j++) {
+            const int4 q = a4[j];
+            c += (q.x == mine) + (q.y == mine) + (q.z == mine) + (q.w == mine);
+        }
         key = ((unsigned long long)c << 32) | (0xffffffffull - (uint32_t)mine);
     }
 #pragma unroll
@@ -101,14 +107,6 @@ __global__ void __launch_bounds__(1024) k_cc_mode(int32_t ns, const int32_t* smp
         for (int w = 0; w < 1024 / 64; w++) m = best[w] > m ? best[w] : m;
         *out = (int32_t)(0xffffffffull - (m & 0xffffffffull));
     }
-}
-// the dominant component may since have been linked under a smaller root
-__global__ void k_cc_giant_root(const int32_t* parent, const int32_t* giant, int32_t* root) {
-    if (threadIdx.x == 0) *root = parent[*giant];
-}
-__global__ void k_cc_sample(int32_t n, int32_t ns, const int32_t* parent, int32_t* out) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < ns) out[i] = parent[(int64_t)i * n / ns];
 }
 // phase 2: vertices outside the dominant component link their other
 // neighbours (light: one thread each; heavy: one wave each)
@@ -130,10 +128,12 @@ __global__ void k_cc_link_rest(int32_t n, const int32_t* __restrict__ rp, const 
 }
 // sizes: vertices outside the dominant component count into their root,
 // the dominant component's size is n minus all of those
+// (the dominant component's root: the final root of its sampled root,
+// which later links may have put under a smaller one)
 __global__ void k_cc_count(int32_t n, const int32_t* __restrict__ parent, const int32_t* giant_dev, int64_t* size,
                            int64_t* outside) {
     __shared__ int64_t part[4];
-    const int32_t giant = *giant_dev;
+    const int32_t giant = parent[*giant_dev];
     int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     int64_t mine = 0;
     if (v < n) {
@@ -152,7 +152,7 @@ __global__ void k_cc_assign(int32_t n, const int32_t* parent, const int64_t* siz
                             const int64_t* outside, int64_t* alpha, int64_t* omega) {
     int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
-    const int32_t giant = *giant_dev;
+    const int32_t giant = parent[*giant_dev];
     int32_t r = parent[v];
     int64_t s = (r == giant) ? (int64_t)n - *outside : size[r];
     alpha[v] = s;
@@ -492,6 +492,7 @@ int tkc_launch_degrees(const DevGraph& g, hipStream_t s) {
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Components (undirected reachability): size holds n + 2 int64, in_giant n bytes.
 int tkc_launch_cc(const DevGraph& g, int32_t* parent, int64_t* size, int64_t* alpha, int64_t* omega,
                   uint8_t* in_giant, int32_t* sample_host, hipStream_t s) {
     (void)sample_host;   // the dominant component is found on the device
@@ -507,28 +508,23 @@ int tkc_launch_cc(const DevGraph& g, int32_t* parent, int64_t* size, int64_t* al
                            (uint8_t*)nullptr);
     }
     // dominant component: most frequent root among evenly spaced samples,
-    // found on the device (no host round trip).  The samples and their mode
-    // live in `size` until the counting below; the final root, in the first
-    // four bytes of in_giant once the membership snapshot is spent (the
-    // workspace gives every buffer at least 256 bytes).
+    // found on the device (no host round trip); it sits in size[n + 1],
+    // past what the counting below clears
     const int NS = 1024;
     int ns = n < NS ? n : NS;
-    int32_t* sample_dev = (int32_t*)size;
-    int32_t* giant_sample = sample_dev + ns;
-    int32_t* giant_root = (int32_t*)in_giant;
-    hipLaunchKernelGGL(k_cc_sample, dim3(nblk(ns, 256)), dim3(256), 0, s, n, ns, parent, sample_dev);
-    hipLaunchKernelGGL(k_cc_mode, dim3(1), dim3(1024), 0, s, ns, sample_dev, giant_sample);
+    int32_t* giant_sample = (int32_t*)(size + n + 1);
+    hipLaunchKernelGGL(k_cc_mode, dim3(1), dim3(1024), 0, s, n, ns, (const int32_t*)parent, giant_sample);
     hipLaunchKernelGGL(k_cc_compress, dim3(nl), dim3(256), 0, s, n, parent, (const int32_t*)giant_sample, in_giant);
     int nh = nblk((int64_t)nheavy * 64, 256);
     hipLaunchKernelGGL(k_cc_link_rest, dim3(nl + nh), dim3(256), 0, s, n, g.rp, g.ci, g.deg, heavy, nheavy,
                        nl, first, in_giant, parent);
     hipLaunchKernelGGL(k_cc_compress, dim3(nl), dim3(256), 0, s, n, parent, (const int32_t*)nullptr,
                        (uint8_t*)nullptr);
-    hipLaunchKernelGGL(k_cc_giant_root, dim3(1), dim3(64), 0, s, parent, (const int32_t*)giant_sample, giant_root);
     if (hipMemsetAsync(size, 0, sizeof(int64_t) * ((size_t)n + 1), s) != hipSuccess) return -1;
-    hipLaunchKernelGGL(k_cc_count, dim3(nl), dim3(256), 0, s, n, parent, (const int32_t*)giant_root, size, size + n);
-    hipLaunchKernelGGL(k_cc_assign, dim3(nl), dim3(256), 0, s, n, parent, size, (const int32_t*)giant_root, size + n,
-                       alpha, omega);
+    hipLaunchKernelGGL(k_cc_count, dim3(nl), dim3(256), 0, s, n, parent, (const int32_t*)giant_sample, size,
+                       size + n);
+    hipLaunchKernelGGL(k_cc_assign, dim3(nl), dim3(256), 0, s, n, parent, size, (const int32_t*)giant_sample,
+                       size + n, alpha, omega);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
