@@ -74,13 +74,14 @@ __global__ void k_cc_compress(int32_t n, int32_t* parent, const int32_t* giant, 
     if (in_giant) in_giant[v] = (r == *giant);
 }
 // the most frequent root among ns evenly spaced samples of the (compressed)
-// parents, ties to the smallest: one block of 1024 threads, each counting
+// parents, ties to the smallest: one block of CC_NS threads, each counting
 // the copies of its own sample (every thread reads the same LDS words at
 // the same step: broadcasts, four at a time; padding never matches a root)
-__global__ void __launch_bounds__(1024) k_cc_mode(int32_t n, int32_t ns, const int32_t* __restrict__ parent,
-                                                  int32_t* out) {
-    __shared__ __align__(16) int32_t a[1024];
-    __shared__ unsigned long long best[1024 / 64];
+#define CC_NS 256
+__global__ void __launch_bounds__(CC_NS) k_cc_mode(int32_t n, int32_t ns, const int32_t* __restrict__ parent,
+                                                   int32_t* out) {
+    __shared__ __align__(16) int32_t a[CC_NS];
+    __shared__ unsigned long long best[CC_NS / 64];
     const int t = threadIdx.x;
     a[t] = t < ns ? parent[(int64_t)t * n / ns] : -1;
     __syncthreads();
@@ -89,7 +90,7 @@ __global__ void __launch_bounds__(1024) k_cc_mode(int32_t n, int32_t ns, const i
         const int32_t mine = a[t];
         const int4* a4 = (const int4*)a;
         int32_t c = 0;
-        for (int j = 0; j < 1024 / 4; j++) {
+        for (int j = 0; j < CC_NS / 4; j++) {
             const int4 q = a4[j];
             c += (q.x == mine) + (q.y == mine) + (q.z == mine) + (q.w == mine);
         }
@@ -104,7 +105,7 @@ __global__ void __launch_bounds__(1024) k_cc_mode(int32_t n, int32_t ns, const i
     __syncthreads();
     if (t == 0) {
         unsigned long long m = 0;
-        for (int w = 0; w < 1024 / 64; w++) m = best[w] > m ? best[w] : m;
+        for (int w = 0; w < CC_NS / 64; w++) m = best[w] > m ? best[w] : m;
         *out = (int32_t)(0xffffffffull - (m & 0xffffffffull));
     }
 }
@@ -510,10 +511,9 @@ int tkc_launch_cc(const DevGraph& g, int32_t* parent, int64_t* size, int64_t* al
     // dominant component: most frequent root among evenly spaced samples,
     // found on the device (no host round trip); it sits in size[n + 1],
     // past what the counting below clears
-    const int NS = 1024;
-    int ns = n < NS ? n : NS;
+    int ns = n < CC_NS ? n : CC_NS;
     int32_t* giant_sample = (int32_t*)(size + n + 1);
-    hipLaunchKernelGGL(k_cc_mode, dim3(1), dim3(1024), 0, s, n, ns, (const int32_t*)parent, giant_sample);
+    hipLaunchKernelGGL(k_cc_mode, dim3(1), dim3(CC_NS), 0, s, n, ns, (const int32_t*)parent, giant_sample);
     hipLaunchKernelGGL(k_cc_compress, dim3(nl), dim3(256), 0, s, n, parent, (const int32_t*)giant_sample, in_giant);
     int nh = nblk((int64_t)nheavy * 64, 256);
     hipLaunchKernelGGL(k_cc_link_rest, dim3(nl + nh), dim3(256), 0, s, n, g.rp, g.ci, g.deg, heavy, nheavy,

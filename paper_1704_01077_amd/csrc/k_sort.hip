@@ -15,8 +15,20 @@ static inline int rs_tiles(int32_t n) { return (n + RS_TILE - 1) / RS_TILE; }
 __global__ void k_rs_mask(const uint32_t* __restrict__ keys, int32_t n, uint32_t* mask) {
     // mask[0] = OR of keys, mask[1] = AND of keys
     uint32_t o = 0, a = 0xffffffffu;
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        uint32_t k = keys[i];
+    const int32_t t0 = blockIdx.x * blockDim.x + threadIdx.x, step = gridDim.x * blockDim.x;
+    int32_t head = 0;
+    if (((uintptr_t)keys & 15u) == 0) {
+        // 16-byte loads, independent across the loop
+        const uint4* k4 = (const uint4*)keys;
+        head = n & ~3;
+        for (int32_t i = t0; i < head / 4; i += step) {
+            const uint4 q = k4[i];
+            o |= q.x | q.y | q.z | q.w;
+            a &= q.x & q.y & q.z & q.w;
+        }
+    }
+    for (int32_t i = head + t0; i < n; i += step) {
+        const uint32_t k = keys[i];
         o |= k; a &= k;
     }
 #pragma unroll
@@ -170,10 +182,11 @@ int64_t tkc_sort_hist_words(int32_t n) { return (int64_t)RS_DIG * rs_tiles(n > 0
 int tkc_sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* tmp_keys, int32_t* tmp_vals, int32_t n,
                    int32_t* hist, uint32_t* mask_dev, uint32_t* mask_host, hipStream_t s) {
     if (n <= 1) return 0;
-    uint32_t init[2] = {0u, 0xffffffffu};
-    if (hipMemcpyAsync(mask_dev, init, sizeof(init), hipMemcpyHostToDevice, s) != hipSuccess) return -1;
+    // OR of all keys from 0, AND from all ones (fills: no host staging)
+    if (hipMemsetD32Async((hipDeviceptr_t)mask_dev, 0u, 1, s) != hipSuccess) return -1;
+    if (hipMemsetD32Async((hipDeviceptr_t)(mask_dev + 1), 0xffffffffu, 1, s) != hipSuccess) return -1;
     int gb = rs_tiles(n);
-    if (gb > 256) gb = 256;
+    if (gb > 256) gb = 256;   // one pair of adds to the mask per workgroup
     hipLaunchKernelGGL(k_rs_mask, dim3(gb), dim3(256), 0, s, keys, n, mask_dev);
     if (hipMemcpyAsync(mask_host, mask_dev, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
         return -1;
