@@ -21,7 +21,20 @@
 #include "dev_common.hpp"
 #include "engine.hpp"
 
-#define SB 256
+#include <stdlib.h>
+
+// workgroup size: big enough that one search keeps many arcs in flight
+// (the searches left after the seed batch are few and large on complex
+// networks); TKC_SWARM_SB=256 or 1024 picks one for experiments
+#define SB_DEFAULT 1024
+static int swarm_sb() {
+    static const int v = [] {
+        const char* e = getenv("TKC_SWARM_SB");
+        const int x = e ? atoi(e) : SB_DEFAULT;
+        return x == 256 ? 256 : (x == 1024 ? 1024 : SB_DEFAULT);
+    }();
+    return v;
+}
 
 struct SwarmArgs {
     DevGraph g;
@@ -37,6 +50,7 @@ struct SwarmArgs {
 };
 
 // exclusive scan of one int per thread over the workgroup; returns the total
+template <int SB>
 TKC_DEV int32_t block_excl_scan(int32_t v, int32_t* out, int32_t* wsum) {
     int32_t x = v;
 #pragma unroll
@@ -58,6 +72,7 @@ TKC_DEV int32_t block_excl_scan(int32_t v, int32_t* out, int32_t* wsum) {
     return tot;
 }
 
+template <int SB>
 __global__ void __launch_bounds__(SB) k_swarm(SwarmArgs a) {
     __shared__ int32_t s_pos;
     __shared__ int32_t s_pre[SB + 1];
@@ -156,7 +171,7 @@ __global__ void __launch_bounds__(SB) k_swarm(SwarmArgs a) {
                     d = rp[u + 1] - b;
                 }
                 int32_t pre;
-                int32_t tot = block_excl_scan(d, &pre, s_wsum);
+                int32_t tot = block_excl_scan<SB>(d, &pre, s_wsum);
                 s_pre[tid] = pre;
                 s_beg[tid] = b;
                 if (tid == 0) s_pre[SB] = tot;
@@ -254,8 +269,14 @@ int tkc_swarm_max_blocks(int block) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return -1;
     int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_swarm, SB, 0) != hipSuccess) return -1;
-    if (occ > 8) occ = 8;
+    const int sb = swarm_sb();
+    if (sb == 1024) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_swarm<1024>, 1024, 0) != hipSuccess) return -1;
+        if (occ > 2) occ = 2;
+    } else {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_swarm<256>, 256, 0) != hipSuccess) return -1;
+        if (occ > 8) occ = 8;
+    }
     return prop.multiProcessorCount * (occ > 0 ? occ : 1);
 }
 
@@ -269,6 +290,9 @@ int tkc_launch_swarm(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv
     a.start_pos = start_pos;
     a.words = (int32_t)(((int64_t)g.n + 31) / 32);
     a.defer_cap = w.defer_cap > 0 ? w.defer_cap : 0x7fffffff;
-    hipLaunchKernelGGL(k_swarm, dim3(w.nblocks), dim3(SB), 0, s, a);
+    if (swarm_sb() == 1024)
+        hipLaunchKernelGGL(k_swarm<1024>, dim3(w.nblocks), dim3(1024), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_swarm<256>, dim3(w.nblocks), dim3(256), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
