@@ -1,6 +1,8 @@
 // Preprocessing kernels: out-degrees, connected components (r(v) of an
 // undirected graph), the neighbourhood-based lower bound of Sect. 5 and the
 // keys of the processing order (Sect. 4, computeBounds).
+#include <stdlib.h>
+
 #include <algorithm>
 
 #include "dev_common.hpp"
@@ -298,7 +300,9 @@ TKC_DEV void nb_finish_vertex(int32_t s, uint64_t acc, int64_t k, int32_t d, con
     st.vis[s] = pv; st.sum[s] = ps; st.flags[s] = fl; st.num[s] = num; st.den[s] = den;
 }
 
-template <bool DIRECTED>
+// LPV lanes share one light vertex (its arcs strided over them), so a wave
+// waits on the longest of 64 / LPV rows rather than of 64
+template <bool DIRECTED, int LPV>
 __global__ void k_nb_round(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                            const int32_t* __restrict__ deg, const int32_t* __restrict__ ch_beg,
                            const int32_t* __restrict__ ch_end, int32_t nchunks, int32_t nlight_blocks,
@@ -306,7 +310,40 @@ __global__ void k_nb_round(int32_t n, const int32_t* __restrict__ rp, const int3
                            int64_t* __restrict__ gk, const int64_t* __restrict__ alpha,
                            const int64_t* __restrict__ omega, NBState st, uint64_t* partial, int32_t* nfin,
                            int32_t adv) {
-    if ((int32_t)blockIdx.x < nlight_blocks) {
+    if ((int32_t)blockIdx.x < nlight_blocks && LPV > 1) {
+        // light vertices: LPV lanes each, finished in place by the first
+        const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const int32_t s = (int32_t)(gt / LPV);
+        const int sub = (int)(gt & (LPV - 1));
+        const bool mine = s < n && deg[s] <= HEAVY_DEG;   // the same on the LPV lanes of s
+        uint64_t acc = 0;
+        if (mine) {
+            int32_t e = rp[s] + sub;
+            const int32_t end = rp[s + 1];
+            for (; e + LPV < end; e += 2 * LPV) {
+                // both terms at most 2^62: their sum fits, then clamp
+                uint64_t s01 = (uint64_t)g1[ci[e]] + (uint64_t)g1[ci[e + LPV]];
+                if (s01 > (uint64_t)NB_INF) s01 = NB_INF;
+                acc += s01;
+                if (acc > (uint64_t)NB_INF) acc = NB_INF;
+            }
+            if (e < end) {
+                acc += (uint64_t)g1[ci[e]];
+                if (acc > (uint64_t)NB_INF) acc = NB_INF;
+            }
+        }
+        // the LPV partial sums (xor partners stay inside the group of s)
+#pragma unroll
+        for (int o = 1; o < LPV; o <<= 1) {
+            acc += __shfl_xor(acc, o, 64);
+            if (acc > (uint64_t)NB_INF) acc = NB_INF;
+        }
+        bool fin = false;
+        if (mine && sub == 0)
+            nb_finish_vertex<DIRECTED>(s, acc, k, deg[s], g2, gk, alpha, omega, st, adv != 0, &fin);
+        __shared__ int32_t lds[16];
+        nb_count(fin, nfin, lds);   // the branch is uniform over the workgroup
+    } else if ((int32_t)blockIdx.x < nlight_blocks) {
         // light vertices: one thread each, finished in place
         bool fin = false;
         int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -531,6 +568,27 @@ int tkc_launch_cc(const DevGraph& g, int32_t* parent, int64_t* size, int64_t* al
 // open vertices below which a round first treats them alone
 #define NB_TAIL_DIV 64
 
+// lanes per light vertex in a full round; TKC_NB_LPV = 1, 2, 4 or 8 picks
+// one for experiments
+#define NB_LPV_DEFAULT 4
+static int nb_lpv() {
+    static const int v = [] {
+        const char* e = getenv("TKC_NB_LPV");
+        const int x = e ? atoi(e) : NB_LPV_DEFAULT;
+        return (x == 1 || x == 2 || x == 4 || x == 8) ? x : NB_LPV_DEFAULT;
+    }();
+    return v;
+}
+template <bool DIRECTED, typename... A>
+static void launch_nb_round(int lpv, dim3 grid, hipStream_t s, A... args) {
+    switch (lpv) {
+        case 1: hipLaunchKernelGGL((k_nb_round<DIRECTED, 1>), grid, dim3(256), 0, s, args...); break;
+        case 2: hipLaunchKernelGGL((k_nb_round<DIRECTED, 2>), grid, dim3(256), 0, s, args...); break;
+        case 8: hipLaunchKernelGGL((k_nb_round<DIRECTED, 8>), grid, dim3(256), 0, s, args...); break;
+        default: hipLaunchKernelGGL((k_nb_round<DIRECTED, 4>), grid, dim3(256), 0, s, args...); break;
+    }
+}
+
 // NB bound: returns the number of rounds, -1 on error.  gbuf holds 3*n int64;
 // partial holds the heavy chunks' partial sums and also at least
 // n / NB_TAIL_DIV int32; nfin_dev holds NB_TAILCNT_WORD + 1 int32 (the
@@ -553,19 +611,21 @@ int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega,
     int64_t k = 2;
     const int64_t kmax = (int64_t)n + 2;
     // a full round at level k (adv = 0: counts only, no vertex advances)
+    const int lpv = nb_lpv();
+    const int nlr = nblk((int64_t)n * lpv, 256);
     auto round = [&](int64_t lv, int32_t adv) {
         int64_t* g1 = buf[(lv - 1) % 3];
         int64_t* g2 = buf[(lv - 2) % 3];
         int64_t* gk = buf[lv % 3];
         if (g.directed) {
-            hipLaunchKernelGGL(k_nb_round<true>, dim3(nl + nc), dim3(256), 0, s, n, g.rp, g.ci, g.deg, g.ch_beg,
-                               g.ch_end, g.nchunks, nl, lv, g1, g2, gk, alpha, omega, st, partial, nfin_dev, adv);
+            launch_nb_round<true>(lpv, dim3(nlr + nc), s, n, g.rp, g.ci, g.deg, g.ch_beg, g.ch_end, g.nchunks, nlr,
+                                  lv, g1, g2, gk, alpha, omega, st, partial, nfin_dev, adv);
             if (g.nheavy)
                 hipLaunchKernelGGL(k_nb_heavy<true>, dim3(nhb), dim3(256), 0, s, g.nheavy, g.heavy, g.hcb, partial,
                                    g.deg, lv, g2, gk, alpha, omega, st, nfin_dev, adv);
         } else {
-            hipLaunchKernelGGL(k_nb_round<false>, dim3(nl + nc), dim3(256), 0, s, n, g.rp, g.ci, g.deg, g.ch_beg,
-                               g.ch_end, g.nchunks, nl, lv, g1, g2, gk, alpha, omega, st, partial, nfin_dev, adv);
+            launch_nb_round<false>(lpv, dim3(nlr + nc), s, n, g.rp, g.ci, g.deg, g.ch_beg, g.ch_end, g.nchunks, nlr,
+                                   lv, g1, g2, gk, alpha, omega, st, partial, nfin_dev, adv);
             if (g.nheavy)
                 hipLaunchKernelGGL(k_nb_heavy<false>, dim3(nhb), dim3(256), 0, s, g.nheavy, g.heavy, g.hcb,
                                    partial, g.deg, lv, g2, gk, alpha, omega, st, nfin_dev, adv);
