@@ -104,6 +104,13 @@ __global__ void __launch_bounds__(1024) k_rs_scan(int32_t* a, int32_t len) {
     for (int32_t i = lo; i < hi; i++) { int32_t t = a[i]; a[i] = run; run += t; }
 }
 
+// Up to RS_FUSE_TILES tiles, each scatter workgroup finds its own 16 offsets
+// in the count table (thread t sums digit t / 16 over the t % 16-th
+// sixteenth of the tiles: the counts of earlier tiles and of all tiles),
+// which saves the scan launch; above that, off holds the scanned table.
+#define RS_FUSE_TILES 512
+static_assert(RS_THREADS == RS_DIG * 16, "one digit per 16 threads");
+template <bool FUSED>
 __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint32_t* __restrict__ keys,
                                                             const int32_t* __restrict__ vals, int32_t n,
                                                             int shift, const int32_t* __restrict__ off,
@@ -112,6 +119,33 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint32_t* __res
     __shared__ int32_t cs[RS_DIG * RS_THREADS];   // [digit][thread]
     __shared__ int32_t wtot[RS_THREADS / 64];
     __shared__ int32_t dstart[RS_DIG];
+    __shared__ int32_t s_off[RS_DIG], s_bef[RS_DIG], s_all[RS_DIG];
+    if (FUSED) {
+        const int d = threadIdx.x >> 4, r = threadIdx.x & 15;
+        const int32_t per = (tiles + 15) / 16;
+        const int32_t t0 = r * per, t1 = t0 + per < tiles ? t0 + per : tiles;
+        const int32_t* row = off + (int64_t)d * tiles;
+        int32_t bef = 0, all = 0;
+#pragma unroll 8
+        for (int32_t t = t0; t < t1; t++) {
+            const int32_t c = row[t];
+            all += c;
+            bef += t < (int32_t)blockIdx.x ? c : 0;
+        }
+        // the 16 threads of a digit are 16 consecutive lanes of one wave
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            bef += __shfl_xor(bef, o, 64);
+            all += __shfl_xor(all, o, 64);
+        }
+        if (r == 0) { s_bef[d] = bef; s_all[d] = all; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int32_t run = 0;
+            for (int q = 0; q < RS_DIG; q++) { s_off[q] = run + s_bef[q]; run += s_all[q]; }
+        }
+        __syncthreads();
+    }
     int32_t base = blockIdx.x * RS_TILE + threadIdx.x * RS_ITEMS;
     uint32_t k[RS_ITEMS];
     int32_t v[RS_ITEMS];
@@ -170,7 +204,7 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint32_t* __res
             }
             pre = cs[d * RS_THREADS + threadIdx.x];
             st = dstart[d];
-            int32_t pos = off[d * tiles + blockIdx.x] + (pre - st) + rank;
+            int32_t pos = (FUSED ? s_off[d] : off[d * tiles + blockIdx.x]) + (pre - st) + rank;
             okeys[pos] = k[j];
             ovals[pos] = v[j];
         }
@@ -198,9 +232,14 @@ int tkc_sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* tmp_keys, int32_t* t
     for (int shift = 0; shift < 32; shift += 4) {
         if (((vary >> shift) & 15u) == 0) continue;
         hipLaunchKernelGGL(k_rs_count, dim3(tiles), dim3(RS_THREADS), 0, s, ka, n, shift, hist, tiles);
-        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, s, hist, RS_DIG * tiles);
-        hipLaunchKernelGGL(k_rs_scatter, dim3(tiles), dim3(RS_THREADS), 0, s, ka, va, n, shift, hist,
-                           tiles, kb, vb);
+        if (tiles <= RS_FUSE_TILES) {
+            hipLaunchKernelGGL(k_rs_scatter<true>, dim3(tiles), dim3(RS_THREADS), 0, s, ka, va, n, shift,
+                               (const int32_t*)hist, tiles, kb, vb);
+        } else {
+            hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, s, hist, RS_DIG * tiles);
+            hipLaunchKernelGGL(k_rs_scatter<false>, dim3(tiles), dim3(RS_THREADS), 0, s, ka, va, n, shift,
+                               (const int32_t*)hist, tiles, kb, vb);
+        }
         uint32_t* tk = ka; ka = kb; kb = tk;
         int32_t* tv = va; va = vb; vb = tv;
     }
