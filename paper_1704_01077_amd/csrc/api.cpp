@@ -189,6 +189,7 @@ extern "C" int tkc_ctx_create(int device, void* hip_stream, tkc_ctx** out) {
     hipEventCreate(&c->ev0);
     hipEventCreate(&c->ev1);
     for (auto& e : c->evq) hipEventCreate(&e);
+    hipEventCreate(&c->evm);
     hipHostMalloc((void**)&c->pinned, 4096, hipHostMallocDefault);
     *out = c;
     return TKC_OK;
@@ -205,6 +206,7 @@ extern "C" int tkc_ctx_destroy(tkc_ctx* c) {
     hipEventDestroy(c->ev0);
     hipEventDestroy(c->ev1);
     for (auto& e : c->evq) hipEventDestroy(e);
+    hipEventDestroy(c->evm);
     if (c->own_stream) hipStreamDestroy(c->stream);
     delete c;
     return TKC_OK;
@@ -969,49 +971,56 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
         // continues batched from its cursor
         int64_t hs[ST_COUNT];
         trace_reset(c);
+        int32_t* small = (int32_t*)ws.small;
+        int32_t* pin = (int32_t*)c->pinned;
+        SwarmWork sw{};
+        sw.vis = ws.s_vis;
+        sw.queue = ws.s_queue;
+        sw.deferred = ws.s_deferred;
+        sw.ndeferred = small + 4;
+        sw.cursor = small + 5;
+        sw.stop = small + 6;
+        sw.nblocks = ws.shape.swarm_blocks;
+        sw.qcap = ws.shape.qcap;
+        sw.defer_cap = c->tune.batch_width;
+        // the seed's cursor and stop flag reach the swarm on the device: no
+        // host wait between the two launches
+        sw.seed = st_batch;
         {
+            const double before = ms_eng[1];
             EngineTimer tm(c, &ms_eng[1], &nl_eng[1]);
             EngineTuning seed = c->tune;
             seed.lanes_cap = seed.seed_lanes;
             if (tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_batch, nullptr, 0, 0, -1, false,
                                  false, nullptr, nullptr, seed, s, &grid))
                 return tkc_fail(TKC_EDEVICE, "batched seed launch failed: %s", hipGetErrorString(hipGetLastError()));
-            // the swarm's exit counters are cleared behind the seed, before the wait
+            HIPCHK(hipEventRecord(c->evm, s));
+            HIPCHK(hipMemsetAsync(small + 4, 0, 3 * sizeof(int32_t), s));
+            if (tkc_launch_swarm(dg, rcv, ov, bv, tk, sw, st_swarm, 0, c->tune, s))
+                return tkc_fail(TKC_EDEVICE, "per-workgroup engine launch failed");
+            // the seed's counters, the swarm's exit state, and the results in
+            // case nothing follows
             if ((rc = tm.done([&] {
-                     HIPCHK(hipMemsetAsync((int32_t*)ws.small + 4, 0, 3 * sizeof(int32_t), s));
-                     return queue_stats(c, st_batch);
+                     HIPCHK(hipMemcpyAsync(pin, small + 4, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                     if (int r = queue_stats(c, st_batch)) return r;
+                     return readback();
                  })))
                 return rc;
+            rb_ready = true;
+            // split the timed span at the mark between the launches
+            float seed_ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&seed_ms, c->ev0, c->evm));
+            const double span = ms_eng[1] - before;
+            const double seed_part = std::min(span, (double)seed_ms);
+            ms_eng[1] = before + seed_part;
+            ms_eng[2] += span - seed_part;
+            nl_eng[2]++;
         }
         memcpy(hs, pin_at<int64_t>(ws, st_batch), sizeof(hs));
         trace_dump(c, "seed");
-        int32_t cursor = (int32_t)hs[ST_CURSOR];
-        bool stopped = hs[ST_STOP] != 0;
+        const int32_t cursor = (int32_t)hs[ST_CURSOR];
+        const bool stopped = hs[ST_STOP] != 0;
         if (!stopped && cursor < n) {
-            SwarmWork sw{};
-            sw.vis = ws.s_vis;
-            sw.queue = ws.s_queue;
-            sw.deferred = ws.s_deferred;
-            int32_t* small = (int32_t*)ws.small;
-            sw.ndeferred = small + 4;
-            sw.cursor = small + 5;
-            sw.stop = small + 6;
-            sw.nblocks = ws.shape.swarm_blocks;
-            sw.qcap = ws.shape.qcap;
-            sw.defer_cap = c->tune.batch_width;
-            int32_t* pin = (int32_t*)c->pinned;
-            {
-                // the swarm's exit state, and the results in case nothing follows
-                EngineTimer tm(c, &ms_eng[2], &nl_eng[2]);
-                if (tkc_launch_swarm(dg, rcv, ov, bv, tk, sw, st_swarm, cursor, c->tune, s))
-                    return tkc_fail(TKC_EDEVICE, "per-workgroup engine launch failed");
-                if ((rc = tm.done([&] {
-                         HIPCHK(hipMemcpyAsync(pin, small + 4, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-                         return readback();
-                     })))
-                    return rc;
-                rb_ready = true;
-            }
             const int32_t ndef = pin[0], fetched = pin[1], sw_stop = pin[2];
             if (c->ws.trace)
                 fprintf(stderr, "trace hybrid: seed cursor %d, swarm deferred %d, fetched %d, stop bits %d\n",

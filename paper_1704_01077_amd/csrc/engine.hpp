@@ -208,6 +208,9 @@ struct SwarmWork {
     int32_t nblocks;
     int32_t qcap;
     int32_t defer_cap;   // deferrals after which the engine closes itself
+    // counters of the batch launched just before (its cursor is the start
+    // position, its stop flag ends the engine at once), or null: start_pos
+    const int64_t* seed;
 };
 int tkc_launch_swarm(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv, DevTopk tk,
                      SwarmWork w, int64_t* stats, int32_t start_pos, const EngineTuning& tune,

@@ -75,6 +75,8 @@ struct tkc_ctx {
     // query phase marks on the stream: start, reachability done, bounds and
     // top-k set-up done, searches done (phase times without host waits)
     hipEvent_t evq[4] = {nullptr, nullptr, nullptr, nullptr};
+    // between two launches timed as one span (the seed batch and the swarm)
+    hipEvent_t evm = nullptr;
     void* pinned = nullptr;   // 4 KiB of pinned host memory for small readbacks
 };
 

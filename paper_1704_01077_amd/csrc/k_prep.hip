@@ -631,13 +631,30 @@ int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega,
                                    partial, g.deg, lv, g2, gk, alpha, omega, st, nfin_dev, adv);
         }
     };
-    auto check = [&]() -> bool {
+    // the finish count after the rounds queued so far; with `ahead`, round k
+    // is queued behind the count's copy, so the GPU works while the host
+    // waits for the copy alone (a round after every vertex has finished
+    // changes no bound)
+    hipEvent_t ev_copy = nullptr;
+    if (hipEventCreateWithFlags(&ev_copy, hipEventDisableTiming) != hipSuccess) return -1;
+    struct EventGuard {
+        hipEvent_t e;
+        ~EventGuard() { hipEventDestroy(e); }
+    } ev_guard{ev_copy};
+    auto check = [&](bool ahead) -> bool {
         hipLaunchKernelGGL(k_nb_total, dim3(1), dim3(64), 0, s, nfin_dev);
         if (hipGetLastError() != hipSuccess) return false;
         if (hipMemcpyAsync(nfin_host, nfin_dev + NB_TOTAL_WORD, sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
             hipSuccess)
             return false;
-        if (hipStreamSynchronize(s) != hipSuccess) return false;
+        if (ahead) {
+            if (hipEventRecord(ev_copy, s) != hipSuccess) return false;
+            round(k, 1);
+            k++;
+            if (hipEventSynchronize(ev_copy) != hipSuccess) return false;
+        } else if (hipStreamSynchronize(s) != hipSuccess) {
+            return false;
+        }
         done = *nfin_host;
         return true;
     };
@@ -651,9 +668,11 @@ int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega,
     int32_t* tail_list = (int32_t*)partial;
     int32_t* tail_cnt = nfin_dev + NB_TAILCNT_WORD;
     bool checked = false;
+    int ahead = 0;   // rounds of the current pair already queued by a check
     while (k <= kmax) {
-        const int32_t open = n - done;
+        const int32_t open = n - done;   // may count some that a queued round finished
         if (checked && open <= tail_at) {
+            ahead = 0;
             if (hipMemsetAsync(tail_cnt, 0, sizeof(int32_t), s) != hipSuccess) return -1;
             hipLaunchKernelGGL(k_nb_collect, dim3(nblk(n, 1024)), dim3(1024), 0, s, n, (const uint8_t*)flags,
                                tail_cap, tail_list, tail_cnt);
@@ -669,7 +688,7 @@ int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega,
                 hipLaunchKernelGGL(k_nb_tail<false>, dim3(nt), dim3(256), 0, s, (const int32_t*)tail_cnt, tail_cap,
                                    (const int32_t*)tail_list, g.rp, g.ci, g.deg, k, g1, g2, gk, alpha, omega, st,
                                    nfin_dev);
-            if (!check()) return -1;
+            if (!check(false)) return -1;
             if (done < n) {
                 round(k, 0);
                 tail_at = (n - done) / 4;
@@ -679,10 +698,13 @@ int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega,
             continue;
         }
         // two full rounds per host check (the first pair without one: the
-        // initial level rarely finishes every vertex); once every vertex
+        // initial level rarely finishes every vertex, so the first check
+        // also queues the next round ahead of its wait); once every vertex
         // has finished, further rounds change no bound
-        for (int rep = 0; rep < 2 && k <= kmax; rep++, k++) round(k, 1);
-        if (!check()) return -1;
+        for (int rep = ahead; rep < 2 && k <= kmax; rep++, k++) round(k, 1);
+        const bool spec = !checked && k <= kmax;
+        if (!check(spec)) return -1;
+        ahead = spec ? 1 : 0;
         checked = true;
         if (done >= n) break;
     }

@@ -96,11 +96,18 @@ __global__ void __launch_bounds__(SB) k_swarm(SwarmArgs a) {
     const int32_t count = a.ov.count;
     int64_t st_mvis = 0, st_started = 0, st_exact = 0, st_cut = 0, st_skip = 0, st_def = 0;
     int64_t st_maxl = 0, st_bytes = 0;
+    // the preceding batch (same stream, finished) hands over where it stopped
+    int32_t start_pos = a.start_pos;
+    bool seed_stopped = false;
+    if (a.w.seed) {
+        start_pos = (int32_t)a.w.seed[ST_CURSOR];
+        seed_stopped = a.w.seed[ST_STOP] != 0;
+    }
 
     for (;;) {
         if (tid == 0) {
             int32_t p = -1;
-            if (ld_rlx(a.w.stop) == 0) p = a.start_pos + fadd_rlx(a.w.cursor, 1);
+            if (!seed_stopped && ld_rlx(a.w.stop) == 0) p = start_pos + fadd_rlx(a.w.cursor, 1);
             s_pos = p;
             XVal x = read_x(a.tk.st, a.tk.ring);
             s_x[0] = x.num; s_x[1] = x.den; s_x[2] = x.id;
