@@ -74,7 +74,7 @@ static size_t ws_items(Workspace& ws, const WsShape& sh, std::vector<WsItem>& it
         {(void**)&ws.tval, 4 * n, false},
         {(void**)&ws.hist, 4 * (size_t)tkc_sort_hist_words(sh.n), false},
         {(void**)&ws.mask, 64, false}, {(void**)&ws.parent, 4 * n, false},
-        {(void**)&ws.csize, 8 * n + 16, false}, {(void**)&ws.gbuf, 24 * n, false},
+        {(void**)&ws.csize, 8 * n + 16, false}, {(void**)&ws.gbuf, 32 * n, false},
         {(void**)&ws.nbsum, 8 * n, false}, {(void**)&ws.nbvis, 8 * n, false},
         {(void**)&ws.nbhub, 8 * n, false},
         {(void**)&ws.nbflags, n, false}, {(void**)&ws.small, 8192, false},

@@ -180,7 +180,12 @@ struct NBState {
     int64_t* num;
     int64_t* den;
     double* hub;      // harmonic upper bound (null: closeness only)
+    // 32-bit copy of the level being written, min(count, NB_C32) (null: none);
+    // the next round gathers it and re-reads a row exactly from the 64-bit
+    // counts when it meets NB_C32
+    int32_t* c32;
 };
+#define NB_C32 0x7fffffff
 // Finish counts: one add per workgroup, into NB_NCTR counters 128 B apart.
 // Adds to one address are done one after another at the cache; with one
 // add per wave on a single counter, a round in which most waves finish a
@@ -290,6 +295,7 @@ TKC_DEV void nb_finish_vertex(int32_t s, uint64_t acc, int64_t k, int32_t d, con
         }
     }
     gk[s] = val;
+    if (st.c32) st.c32[s] = val >= (int64_t)NB_C32 ? NB_C32 : (int32_t)val;
     *fin_now = false;
     if (!adv) return;
     uint8_t fl = st.flags[s];
@@ -302,11 +308,15 @@ TKC_DEV void nb_finish_vertex(int32_t s, uint64_t acc, int64_t k, int32_t d, con
 
 // LPV lanes share one light vertex (its arcs strided over them), so a wave
 // waits on the longest of 64 / LPV rows rather than of 64
-template <bool DIRECTED, int LPV>
+// G: the type of the previous level's counts as gathered (the first round
+// reads gamma_1, the out-degrees, from the int32 degree array: half the
+// bytes per gather)
+template <bool DIRECTED, int LPV, typename G>
 __global__ void k_nb_round(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                            const int32_t* __restrict__ deg, const int32_t* __restrict__ ch_beg,
                            const int32_t* __restrict__ ch_end, int32_t nchunks, int32_t nlight_blocks,
-                           int64_t k, const int64_t* __restrict__ g1, const int64_t* __restrict__ g2,
+                           int64_t k, const G* __restrict__ g1, const int64_t* __restrict__ g1x,
+                           const int64_t* __restrict__ g2,
                            int64_t* __restrict__ gk, const int64_t* __restrict__ alpha,
                            const int64_t* __restrict__ omega, NBState st, uint64_t* partial, int32_t* nfin,
                            int32_t adv) {
@@ -317,19 +327,37 @@ __global__ void k_nb_round(int32_t n, const int32_t* __restrict__ rp, const int3
         const int sub = (int)(gt & (LPV - 1));
         const bool mine = s < n && deg[s] <= HEAVY_DEG;   // the same on the LPV lanes of s
         uint64_t acc = 0;
+        bool redo = false;
         if (mine) {
             int32_t e = rp[s] + sub;
             const int32_t end = rp[s + 1];
             for (; e + LPV < end; e += 2 * LPV) {
                 // both terms at most 2^62: their sum fits, then clamp
-                uint64_t s01 = (uint64_t)g1[ci[e]] + (uint64_t)g1[ci[e + LPV]];
+                const G v0 = g1[ci[e]], v1 = g1[ci[e + LPV]];
+                if (sizeof(G) == 4) redo |= (v0 == (G)NB_C32) | (v1 == (G)NB_C32);
+                uint64_t s01 = (uint64_t)v0 + (uint64_t)v1;
                 if (s01 > (uint64_t)NB_INF) s01 = NB_INF;
                 acc += s01;
                 if (acc > (uint64_t)NB_INF) acc = NB_INF;
             }
             if (e < end) {
-                acc += (uint64_t)g1[ci[e]];
+                const G v0 = g1[ci[e]];
+                if (sizeof(G) == 4) redo |= v0 == (G)NB_C32;
+                acc += (uint64_t)v0;
                 if (acc > (uint64_t)NB_INF) acc = NB_INF;
+            }
+        }
+        if (sizeof(G) == 4) {
+            // a capped count in the row: the vertex's LPV lanes sum it again
+            // from the exact 64-bit counts
+#pragma unroll
+            for (int o = 1; o < LPV; o <<= 1) redo |= __shfl_xor((int)redo, o, 64) != 0;
+            if (mine && redo) {
+                acc = 0;
+                for (int32_t e = rp[s] + sub; e < rp[s + 1]; e += LPV) {
+                    acc += (uint64_t)g1x[ci[e]];
+                    if (acc > (uint64_t)NB_INF) acc = NB_INF;
+                }
             }
         }
         // the LPV partial sums (xor partners stay inside the group of s)
@@ -374,9 +402,20 @@ __global__ void k_nb_round(int32_t n, const int32_t* __restrict__ rp, const int3
         int32_t c = ((blockIdx.x - nlight_blocks) * blockDim.x + threadIdx.x) >> 6;
         if (c >= nchunks) return;   // wave-uniform
         uint64_t acc = 0;
+        bool redo = false;
         for (int32_t e = ch_beg[c] + lane_id(); e < ch_end[c]; e += 64) {
-            acc += (uint64_t)g1[ci[e]];
+            const G v = g1[ci[e]];
+            if (sizeof(G) == 4) redo |= v == (G)NB_C32;
+            acc += (uint64_t)v;
             if (acc > (uint64_t)NB_INF) acc = NB_INF;
+        }
+        if (sizeof(G) == 4 && __any(redo)) {
+            // a capped count in the chunk: sum it again from the exact counts
+            acc = 0;
+            for (int32_t e = ch_beg[c] + lane_id(); e < ch_end[c]; e += 64) {
+                acc += (uint64_t)g1x[ci[e]];
+                if (acc > (uint64_t)NB_INF) acc = NB_INF;
+            }
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -579,17 +618,30 @@ static int nb_lpv() {
     }();
     return v;
 }
-template <bool DIRECTED, typename... A>
+// experiment switch: TKC_NB_C32=0 gathers the 64-bit counts only
+static bool nb_c32() {
+    static const bool v = [] {
+        const char* e = getenv("TKC_NB_C32");
+        return !(e && atoi(e) == 0);
+    }();
+    return v;
+}
+template <bool DIRECTED, typename G, typename... A>
 static void launch_nb_round(int lpv, dim3 grid, hipStream_t s, A... args) {
     switch (lpv) {
-        case 1: hipLaunchKernelGGL((k_nb_round<DIRECTED, 1>), grid, dim3(256), 0, s, args...); break;
-        case 2: hipLaunchKernelGGL((k_nb_round<DIRECTED, 2>), grid, dim3(256), 0, s, args...); break;
-        case 8: hipLaunchKernelGGL((k_nb_round<DIRECTED, 8>), grid, dim3(256), 0, s, args...); break;
-        default: hipLaunchKernelGGL((k_nb_round<DIRECTED, 4>), grid, dim3(256), 0, s, args...); break;
+        case 1:
+            // one lane per vertex has no capped-count fallback: 64-bit only
+            if constexpr (sizeof(G) == 8)
+                hipLaunchKernelGGL((k_nb_round<DIRECTED, 1, G>), grid, dim3(256), 0, s, args...);
+            break;
+        case 2: hipLaunchKernelGGL((k_nb_round<DIRECTED, 2, G>), grid, dim3(256), 0, s, args...); break;
+        case 8: hipLaunchKernelGGL((k_nb_round<DIRECTED, 8, G>), grid, dim3(256), 0, s, args...); break;
+        default: hipLaunchKernelGGL((k_nb_round<DIRECTED, 4, G>), grid, dim3(256), 0, s, args...); break;
     }
 }
 
-// NB bound: returns the number of rounds, -1 on error.  gbuf holds 3*n int64;
+// NB bound: returns the number of rounds, -1 on error.  gbuf holds 3*n int64
+// and then 2*n int32;
 // partial holds the heavy chunks' partial sums and also at least
 // n / NB_TAIL_DIV int32; nfin_dev holds NB_TAILCNT_WORD + 1 int32 (the
 // finish counters, their total, the tail list's count).
@@ -600,7 +652,7 @@ int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega,
     int nl = nblk(n, 256);
     int nc = nblk((int64_t)g.nchunks * 64, 256);
     int nhb = nblk(g.nheavy, 256);
-    NBState st{sum, vis, flags, num, den, hub};
+    NBState st{sum, vis, flags, num, den, hub, nullptr};
     int64_t* buf[3] = {gbuf, gbuf + n, gbuf + 2 * (int64_t)n};
     hipMemsetAsync(nfin_dev, 0, sizeof(int32_t) * NB_TOTAL_WORD, s);
     // gamma_0 -> buf[0], gamma_1 -> buf[1]
@@ -613,22 +665,42 @@ int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega,
     // a full round at level k (adv = 0: counts only, no vertex advances)
     const int lpv = nb_lpv();
     const int nlr = nblk((int64_t)n * lpv, 256);
+    // 32-bit copies of two consecutive levels follow the three 64-bit buffers
+    int32_t* c32[2] = {(int32_t*)(gbuf + 3 * (int64_t)n), (int32_t*)(gbuf + 3 * (int64_t)n) + n};
+    const bool use32 = lpv > 1 && nb_c32();
     auto round = [&](int64_t lv, int32_t adv) {
         int64_t* g1 = buf[(lv - 1) % 3];
         int64_t* g2 = buf[(lv - 2) % 3];
         int64_t* gk = buf[lv % 3];
-        if (g.directed) {
-            launch_nb_round<true>(lpv, dim3(nlr + nc), s, n, g.rp, g.ci, g.deg, g.ch_beg, g.ch_end, g.nchunks, nlr,
-                                  lv, g1, g2, gk, alpha, omega, st, partial, nfin_dev, adv);
-            if (g.nheavy)
-                hipLaunchKernelGGL(k_nb_heavy<true>, dim3(nhb), dim3(256), 0, s, g.nheavy, g.heavy, g.hcb, partial,
-                                   g.deg, lv, g2, gk, alpha, omega, st, nfin_dev, adv);
+        NBState rs = st;
+        if (use32) {
+            // gamma_1 is the out-degree (k_nb_init stores the same values)
+            rs.c32 = c32[lv & 1];
+            const int32_t* g1c = lv == 2 ? g.deg : c32[(lv - 1) & 1];
+            if (g.directed)
+                launch_nb_round<true, int32_t>(lpv, dim3(nlr + nc), s, n, g.rp, g.ci, g.deg, g.ch_beg, g.ch_end,
+                                               g.nchunks, nlr, lv, g1c, (const int64_t*)g1, (const int64_t*)g2, gk,
+                                               alpha, omega, rs, partial, nfin_dev, adv);
+            else
+                launch_nb_round<false, int32_t>(lpv, dim3(nlr + nc), s, n, g.rp, g.ci, g.deg, g.ch_beg, g.ch_end,
+                                                g.nchunks, nlr, lv, g1c, (const int64_t*)g1, (const int64_t*)g2, gk,
+                                                alpha, omega, rs, partial, nfin_dev, adv);
+        } else if (g.directed) {
+            launch_nb_round<true, int64_t>(lpv, dim3(nlr + nc), s, n, g.rp, g.ci, g.deg, g.ch_beg, g.ch_end,
+                                           g.nchunks, nlr, lv, (const int64_t*)g1, (const int64_t*)g1,
+                                           (const int64_t*)g2, gk, alpha, omega, rs, partial, nfin_dev, adv);
         } else {
-            launch_nb_round<false>(lpv, dim3(nlr + nc), s, n, g.rp, g.ci, g.deg, g.ch_beg, g.ch_end, g.nchunks, nlr,
-                                   lv, g1, g2, gk, alpha, omega, st, partial, nfin_dev, adv);
-            if (g.nheavy)
+            launch_nb_round<false, int64_t>(lpv, dim3(nlr + nc), s, n, g.rp, g.ci, g.deg, g.ch_beg, g.ch_end,
+                                            g.nchunks, nlr, lv, (const int64_t*)g1, (const int64_t*)g1,
+                                            (const int64_t*)g2, gk, alpha, omega, rs, partial, nfin_dev, adv);
+        }
+        if (g.nheavy) {
+            if (g.directed)
+                hipLaunchKernelGGL(k_nb_heavy<true>, dim3(nhb), dim3(256), 0, s, g.nheavy, g.heavy, g.hcb, partial,
+                                   g.deg, lv, (const int64_t*)g2, gk, alpha, omega, rs, nfin_dev, adv);
+            else
                 hipLaunchKernelGGL(k_nb_heavy<false>, dim3(nhb), dim3(256), 0, s, g.nheavy, g.heavy, g.hcb,
-                                   partial, g.deg, lv, g2, gk, alpha, omega, st, nfin_dev, adv);
+                                   partial, g.deg, lv, (const int64_t*)g2, gk, alpha, omega, rs, nfin_dev, adv);
         }
     };
     // the finish count after the rounds queued so far; with `ahead`, round k
