@@ -110,6 +110,7 @@ __global__ void __launch_bounds__(1024) k_rs_scan(int32_t* a, int32_t len) {
 // which saves the scan launch; above that, off holds the scanned table.
 #define RS_FUSE_TILES 512
 static_assert(RS_THREADS == RS_DIG * 16, "one digit per 16 threads");
+static_assert(RS_DIG * RS_THREADS >= 2 * RS_TILE, "the count table's LDS holds a staged tile");
 template <bool FUSED>
 __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint32_t* __restrict__ keys,
                                                             const int32_t* __restrict__ vals, int32_t n,
@@ -190,24 +191,44 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint32_t* __res
     __syncthreads();
     if (threadIdx.x < RS_DIG) dstart[threadIdx.x] = cs[threadIdx.x * RS_THREADS];
     __syncthreads();
+    if (!FUSED && threadIdx.x < RS_DIG) s_off[threadIdx.x] = off[threadIdx.x * tiles + blockIdx.x];
+    // each item's place in the tile's stable order by digit
     int32_t seen[RS_DIG];
 #pragma unroll
     for (int d = 0; d < RS_DIG; d++) seen[d] = 0;
+    int32_t lp[RS_ITEMS];
 #pragma unroll
     for (int j = 0; j < RS_ITEMS; j++) {
         uint32_t d = dg[j];
+        lp[j] = -1;
         if (d < RS_DIG) {
-            int32_t rank = 0, pre = 0, st = 0;
+            int32_t rank = 0;
 #pragma unroll
             for (int e = 0; e < RS_DIG; e++) {
                 if ((uint32_t)e == d) { rank = seen[e]; seen[e]++; }
             }
-            pre = cs[d * RS_THREADS + threadIdx.x];
-            st = dstart[d];
-            int32_t pos = (FUSED ? s_off[d] : off[d * tiles + blockIdx.x]) + (pre - st) + rank;
-            okeys[pos] = k[j];
-            ovals[pos] = v[j];
+            lp[j] = cs[d * RS_THREADS + threadIdx.x] + rank;
         }
+    }
+    // the tile in that order in LDS (cs is free once every place is read),
+    // then written out in order: consecutive threads store consecutive
+    // positions of a digit's run
+    __syncthreads();
+    uint32_t* sk = (uint32_t*)cs;
+    int32_t* sv = cs + RS_TILE;
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; j++) {
+        if (lp[j] >= 0) { sk[lp[j]] = k[j]; sv[lp[j]] = v[j]; }
+    }
+    __syncthreads();
+    const int32_t rem = n - (int32_t)blockIdx.x * RS_TILE;
+    const int32_t cnt = rem < RS_TILE ? rem : RS_TILE;
+    for (int32_t q = threadIdx.x; q < cnt; q += RS_THREADS) {
+        const uint32_t key = sk[q];
+        const uint32_t d = (key >> shift) & 15u;
+        const int32_t pos = s_off[d] + (q - dstart[d]);
+        okeys[pos] = key;
+        ovals[pos] = sv[q];
     }
 }
 
