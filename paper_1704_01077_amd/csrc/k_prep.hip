@@ -68,9 +68,13 @@ __global__ void k_cc_link_one(int32_t n, const int32_t* __restrict__ rp, const i
 }
 // full path compression; with in_giant, a snapshot of membership in the
 // component rooted at *giant
-__global__ void k_cc_compress(int32_t n, int32_t* parent, const int32_t* giant, uint8_t* in_giant) {
+// (zero, when given, has its n + 1 counters cleared for the counting pass)
+__global__ void k_cc_compress(int32_t n, int32_t* parent, const int32_t* giant, uint8_t* in_giant,
+                              int64_t* zero) {
     int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (zero && v == 0) zero[n] = 0;
     if (v >= n) return;
+    if (zero) zero[v] = 0;
     int32_t r = uf_find_coherent(parent, v);
     parent[v] = r;
     if (in_giant) in_giant[v] = (r == *giant);
@@ -207,12 +211,16 @@ TKC_DEV void nb_count(bool fin, int32_t* nfin, int32_t* lds) {
         if (t) fadd_rlx(nfin + (blockIdx.x % NB_NCTR) * NB_CTR_WORDS, t);
     }
 }
-// one wave: the counters' sum into nfin[NB_TOTAL_WORD]
+// one wave: the counters' sum into nfin[NB_TOTAL_WORD]; it also clears the
+// tail list's count, which a collect after the check starts from
 __global__ void k_nb_total(int32_t* nfin) {
     int32_t v = lane_id() < NB_NCTR ? nfin[lane_id() * NB_CTR_WORDS] : 0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (lane_id() == 0) nfin[NB_TOTAL_WORD] = v;
+    if (lane_id() == 0) {
+        nfin[NB_TOTAL_WORD] = v;
+        nfin[NB_TAILCNT_WORD] = 0;
+    }
 }
 
 // Harmonic centrality from the same counts: level k takes min(gamma_k,
@@ -582,7 +590,7 @@ int tkc_launch_cc(const DevGraph& g, int32_t* parent, int64_t* size, int64_t* al
     for (int32_t which = 0; which < first; which++) {
         hipLaunchKernelGGL(k_cc_link_one, dim3(nl), dim3(256), 0, s, n, g.rp, g.ci, which, parent);
         hipLaunchKernelGGL(k_cc_compress, dim3(nl), dim3(256), 0, s, n, parent, (const int32_t*)nullptr,
-                           (uint8_t*)nullptr);
+                           (uint8_t*)nullptr, (int64_t*)nullptr);
     }
     // dominant component: most frequent root among evenly spaced samples,
     // found on the device (no host round trip); it sits in size[n + 1],
@@ -590,13 +598,14 @@ int tkc_launch_cc(const DevGraph& g, int32_t* parent, int64_t* size, int64_t* al
     int ns = n < CC_NS ? n : CC_NS;
     int32_t* giant_sample = (int32_t*)(size + n + 1);
     hipLaunchKernelGGL(k_cc_mode, dim3(1), dim3(CC_NS), 0, s, n, ns, (const int32_t*)parent, giant_sample);
-    hipLaunchKernelGGL(k_cc_compress, dim3(nl), dim3(256), 0, s, n, parent, (const int32_t*)giant_sample, in_giant);
+    hipLaunchKernelGGL(k_cc_compress, dim3(nl), dim3(256), 0, s, n, parent, (const int32_t*)giant_sample, in_giant,
+                       (int64_t*)nullptr);
     int nh = nblk((int64_t)nheavy * 64, 256);
     hipLaunchKernelGGL(k_cc_link_rest, dim3(nl + nh), dim3(256), 0, s, n, g.rp, g.ci, g.deg, heavy, nheavy,
                        nl, first, in_giant, parent);
+    // the last compression also clears the component counters
     hipLaunchKernelGGL(k_cc_compress, dim3(nl), dim3(256), 0, s, n, parent, (const int32_t*)nullptr,
-                       (uint8_t*)nullptr);
-    if (hipMemsetAsync(size, 0, sizeof(int64_t) * ((size_t)n + 1), s) != hipSuccess) return -1;
+                       (uint8_t*)nullptr, size);
     hipLaunchKernelGGL(k_cc_count, dim3(nl), dim3(256), 0, s, n, parent, (const int32_t*)giant_sample, size,
                        size + n);
     hipLaunchKernelGGL(k_cc_assign, dim3(nl), dim3(256), 0, s, n, parent, size, (const int32_t*)giant_sample,
@@ -745,7 +754,7 @@ int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega,
         const int32_t open = n - done;   // may count some that a queued round finished
         if (checked && open <= tail_at) {
             ahead = 0;
-            if (hipMemsetAsync(tail_cnt, 0, sizeof(int32_t), s) != hipSuccess) return -1;
+            // tail_cnt was cleared by the check's k_nb_total
             hipLaunchKernelGGL(k_nb_collect, dim3(nblk(n, 1024)), dim3(1024), 0, s, n, (const uint8_t*)flags,
                                tail_cap, tail_list, tail_cnt);
             const int nt = nblk((int64_t)open * 64, 256);
