@@ -109,12 +109,14 @@ static inline int tkc_grid_for(int cus, int per, int32_t n) {
 
 // k_prep.hip
 int tkc_launch_degrees(const DevGraph& g, hipStream_t s);
-// size holds n+1 int64; in_giant n bytes; sample_host 1024 pinned int32
+// size holds n+2 int64; in_giant n bytes; sample_host is unused (the
+// dominant component is found on the device)
 int tkc_launch_cc(const DevGraph& g, int32_t* parent, int64_t* size, int64_t* alpha, int64_t* omega,
                   uint8_t* in_giant, int32_t* sample_host, hipStream_t s);
-// partial holds nchunks uint64
-// hub (n doubles, may be null): also the walk-count upper bound on the
-// harmonic centrality
+// gbuf holds 3n int64 and then 2n int32; partial holds nchunks uint64 and
+// at least n/64 int32; nfin_dev the finish counters (1,057 int32).  Returns
+// the number of rounds, -1 on error.  hub (n doubles, may be null): also
+// the walk-count upper bound on the harmonic centrality
 int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega, int64_t* gbuf, int64_t* sum,
                   int64_t* vis, uint8_t* flags, int64_t* num, int64_t* den, uint64_t* partial,
                   int32_t* nfin_dev, int32_t* nfin_host, hipStream_t s, double* hub = nullptr);
