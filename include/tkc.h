@@ -105,8 +105,11 @@ typedef struct {
     int32_t batch_width;    /* lanes per batch (W)                         */
     int32_t variant_used;
     int32_t mode_used;
-    int32_t nb_rounds;      /* walk-count rounds of the NB bound           */
+    int32_t nb_rounds;      /* walk-count levels the NB bound computed
+                               (full rounds and tail rounds over the open
+                               vertices; 0 when the bounds were cached)    */
     int32_t pad_;
+    /* phase times: HIP events on the context's stream                     */
     double ms_reach;        /* reachability (r or alpha/omega)             */
     double ms_bounds;       /* initial bounds and ordering                 */
     double ms_traverse;     /* searches (all engines)                      */
