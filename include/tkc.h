@@ -107,7 +107,8 @@ typedef struct {
     int32_t mode_used;
     int32_t nb_rounds;      /* walk-count levels the NB bound computed
                                (full rounds and tail rounds over the open
-                               vertices; 0 when the bounds were cached)    */
+                               vertices; with cached bounds, the count of
+                               the run that computed them)                 */
     int32_t pad_;
     /* phase times: HIP events on the context's stream                     */
     double ms_reach;        /* reachability (r or alpha/omega)             */
