@@ -409,21 +409,12 @@ __global__ void k_nb_round(int32_t n, const int32_t* __restrict__ rp, const int3
         // arcs of heavy vertices: one wave per chunk, saturating partial sum
         int32_t c = ((blockIdx.x - nlight_blocks) * blockDim.x + threadIdx.x) >> 6;
         if (c >= nchunks) return;   // wave-uniform
+        // (the exact 64-bit counts: a 512-arc chunk meets a capped count
+        // far more often than a light row)
         uint64_t acc = 0;
-        bool redo = false;
         for (int32_t e = ch_beg[c] + lane_id(); e < ch_end[c]; e += 64) {
-            const G v = g1[ci[e]];
-            if (sizeof(G) == 4) redo |= v == (G)NB_C32;
-            acc += (uint64_t)v;
+            acc += (uint64_t)g1x[ci[e]];
             if (acc > (uint64_t)NB_INF) acc = NB_INF;
-        }
-        if (sizeof(G) == 4 && __any(redo)) {
-            // a capped count in the chunk: sum it again from the exact counts
-            acc = 0;
-            for (int32_t e = ch_beg[c] + lane_id(); e < ch_end[c]; e += 64) {
-                acc += (uint64_t)g1x[ci[e]];
-                if (acc > (uint64_t)NB_INF) acc = NB_INF;
-            }
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
