@@ -631,6 +631,8 @@ static void launch_nb_round(int lpv, dim3 grid, hipStream_t s, A... args) {
     switch (lpv) {
         case 1:
             // one lane per vertex has no capped-count fallback: 64-bit only
+            // (the caller takes the 32-bit copy only with lpv > 1, and the
+            // grid is sized for lpv, so no other width may stand in)
             if constexpr (sizeof(G) == 8)
                 hipLaunchKernelGGL((k_nb_round<DIRECTED, 1, G>), grid, dim3(256), 0, s, args...);
             break;
