@@ -212,6 +212,15 @@ def workload(name: str) -> Graph:
         return rmat_graph(20, 16, 3)
     if name == "grid2000":      # 2000^2 grid, 5% deleted, 1,000 shortcuts, LCC
         return grid_graph(2000, 0.05, 1000, 4)
+    # medium tier: the same shapes at sizes whose all-sources answer takes
+    # minutes of CPU, large enough to hold hubs of in-degree > 1024 and
+    # walk counts beyond 2^31
+    if name == "ba128k":        # undirected BA, n=2^17, m=5, seed 6
+        return ba_graph(1 << 17, 5, 6)
+    if name == "rmat16":        # directed R-MAT scale 16, edge factor 16, seed 7
+        return rmat_graph(16, 16, 7)
+    if name == "grid500":       # 500^2 grid, 5% deleted, 63 shortcuts, seed 8, LCC
+        return grid_graph(500, 0.05, 63, 8)
     raise KeyError(name)
 
 

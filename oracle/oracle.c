@@ -119,19 +119,34 @@ int oracle_check_csr(int32_t n, int64_t ne, const int32_t *ed, int directed, int
 }
 
 /* ------------------------------------------------- textbook BFS (Sect. 1) */
-/* one BFS from s: returns S(s), writes r(s); dist[] must be all -1 on entry
- * and is restored to all -1 on exit; queue holds n entries. */
-static int64_t bfs_sum(const oadj *A, int32_t s, int32_t *dist, int32_t *queue, int64_t *r_out) {
-    int64_t head = 0, tail = 0, S = 0;
-    dist[s] = 0; queue[tail++] = s;
+/* One FIFO breadth-first search from s: returns S(s) and writes r(s).
+ * The queue holds the vertices in the order they are found, so it is the
+ * levels one after the other: queue[0] = s is level 0, and while level d is
+ * being expanded every vertex appended belongs to level d + 1.  S adds d
+ * once per vertex of level d.  seen[] is a bitmap of n bits, all clear on
+ * entry and cleared again on exit; queue holds n entries.  The two
+ * prefetches only warm the cache for rows a few entries ahead in the queue
+ * and change nothing computed. */
+static int64_t bfs_sum(const oadj *A, int32_t s, uint64_t *seen, int32_t *queue, int64_t *r_out) {
+    int64_t head = 0, tail = 0, S = 0, d = 0;
+    seen[s >> 6] |= 1ull << (s & 63);
+    queue[tail++] = s;
     while (head < tail) {
-        int32_t u = queue[head++];
-        for (int64_t q = A->off[u]; q < A->off[u + 1]; q++) {
-            int32_t w = A->nbr[q];
-            if (dist[w] < 0) { dist[w] = dist[u] + 1; S += dist[w]; queue[tail++] = w; }
+        int64_t level_end = tail;   /* queue[head, level_end) is level d */
+        while (head < level_end) {
+            if (head + 16 < tail) __builtin_prefetch(&A->off[queue[head + 16]]);
+            if (head + 6 < tail) __builtin_prefetch(&A->nbr[A->off[queue[head + 6]]]);
+            int32_t u = queue[head++];
+            for (int64_t q = A->off[u]; q < A->off[u + 1]; q++) {
+                int32_t w = A->nbr[q];
+                uint64_t bit = 1ull << (w & 63);
+                if (!(seen[w >> 6] & bit)) { seen[w >> 6] |= bit; queue[tail++] = w; }
+            }
         }
+        d++;
+        S += d * (tail - level_end);   /* the vertices just appended are at distance d */
     }
-    for (int64_t q = 0; q < tail; q++) dist[queue[q]] = -1;
+    for (int64_t q = 0; q < tail; q++) seen[queue[q] >> 6] = 0;
     *r_out = tail;
     return S;
 }
@@ -147,15 +162,14 @@ int oracle_sums(int32_t n, int64_t ne, const int32_t *ed, int directed,
 #endif
     #pragma omp parallel
     {
-        int32_t *dist = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+        uint64_t *seen = (uint64_t *)calloc(((size_t)n + 63) / 64 + 1, sizeof(uint64_t));
         int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
-        for (int32_t i = 0; i < n; i++) dist[i] = -1;
         #pragma omp for schedule(dynamic, 16)
         for (int64_t i = 0; i < cnt; i++) {
             int32_t s = src ? src[i] : (int32_t)i;
-            S[i] = bfs_sum(&A, s, dist, queue, &r[i]);
+            S[i] = bfs_sum(&A, s, seen, queue, &r[i]);
         }
-        free(dist); free(queue);
+        free(seen); free(queue);
     }
     adj_free(&A);
     return 0;
@@ -386,11 +400,19 @@ int32_t oracle_scc(int32_t n, int64_t ne, const int32_t *ed, int32_t *comp) {
 }
 
 /*
- * Alg. 6.  Readings: the line "W not reachable from C~" refers to the
- * successor Y being examined; the biggest SCC C~ is the largest component,
- * ties going to the one that holds the smallest vertex id; every omega is
- * capped at n after it is formed (r <= n always holds, and the double
- * counting allowed by the algorithm can otherwise exceed n).
+ * Alg. 6 (Sect. 8.4): alpha(C) = w(C) + the largest alpha of C's successors,
+ * omega(C) = w(C) + the sum of their omegas, taken sinks first, with the
+ * largest SCC's reach counted exactly.  For a component that reaches the
+ * largest SCC, omega sums only the successors that the largest SCC does not
+ * reach and then adds the largest SCC's reach once.
+ * Readings: the pseudocode's reachability test inside the successor loop
+ * names a variable that is never bound; it is read as a test on the
+ * successor being examined.  The largest SCC's ties go to the component
+ * holding the smallest vertex id.  The successors' omegas are taken as
+ * computed (a successor that itself reaches the largest SCC already holds
+ * that SCC's reach, so it can be counted twice; the bound stays valid), and
+ * every omega is capped at n after it is formed, since r <= n always holds.
+ * tests/golden/alg6_*.txt work three small digraphs out by hand.
  */
 int oracle_alpha_omega(int32_t n, int64_t ne, const int32_t *ed, int64_t *alpha, int64_t *omega,
                        int32_t *scc_out) {
