@@ -245,12 +245,14 @@ int tkc_topk_closeness_ties(tkc_graph *g, int32_t k, int32_t variant, int32_t mo
  * NULL and is filled (component ids in topological order) for directed
  * graphs only. */
 int tkc_graph_reach(tkc_graph *g, int64_t *alpha, int64_t *omega, int32_t *scc);
-/* How the reachability bounds of g were computed (Sect. 8.4, Alg. 6):
- * *path = 0 not yet (computed by the first query or tkc_graph_reach),
- * 1 on the device (always for undirected graphs), 2 host fallback (the
- * device path gives up on long chains of strongly connected components);
- * *ms = the time it took.  Either pointer may be NULL.  Errors: TKC_EINVAL
- * for a NULL graph. */
+/* How the reachability bounds of g were computed (Sect. 8.4, Alg. 6), all
+ * on the device: *path = 0 not yet (computed by the first query or
+ * tkc_graph_reach), 1 by the parallel steps alone (always for undirected
+ * graphs), 2 with a one-thread device pass finishing what the parallel
+ * steps left at their round caps (long chains of strongly connected
+ * components, or a component DAG deeper than the relaxation cap); *ms =
+ * the time it took.  Either pointer may be NULL.  Errors: TKC_EINVAL for a
+ * NULL graph. */
 int tkc_graph_reach_info(const tkc_graph *g, int32_t *path, double *ms);
 /* Initial lower bounds (Sect. 4 computeBounds): the farness bound is
  * (n-1) * num / den, den = 0 meaning +inf.  variant TKC_DEG_* gives 0 (and

@@ -27,7 +27,6 @@
 #include "dev_common.hpp"
 #include "engine.hpp"
 #include "internal.hpp"
-#include "reach_host.hpp"
 
 static thread_local std::string g_err;
 
@@ -497,10 +496,6 @@ extern "C" int tkc_graph_upload(tkc_ctx* c, int32_t n, int64_t m, const int32_t*
         delete g;
         return rc;
     }
-    if (directed) {
-        g->h_rp.swap(hrp);
-        g->h_ci.swap(hci);
-    }
     *out = g;
     return TKC_OK;
 }
@@ -562,23 +557,12 @@ int tkc_step_reach(tkc_ctx* c, tkc_graph* g, Workspace& ws) {
                 g->d_scc = (int32_t*)(g->d_omega + n);
             }
             const double t0 = now_ms();
-            const char* e = getenv("TKC_REACH");
-            int r = 1;
-            if (!(e && strcmp(e, "host") == 0))
-                r = tkc_device_alpha_omega(dg, g->d_alpha, g->d_omega, g->d_scc, c->pinned, s);
+            int seq = 0;
+            const int r = tkc_device_alpha_omega(dg, g->d_alpha, g->d_omega, g->d_scc, c->pinned, s, &seq);
+            if (r == -2) return tkc_fail(TKC_ENOMEM, "no device memory for the reachability scratch");
             if (r < 0) return tkc_fail(TKC_EDEVICE, "reachability kernels failed");
-            if (r == 1) {
-                // a round budget ran out (long chains of components): Tarjan on the host
-                std::vector<int64_t> ha, ho;
-                std::vector<int32_t> hs;
-                tkc_host_alpha_omega(g->n, g->h_rp.data(), g->h_ci.data(), ha, ho, hs);
-                HIPCHK(hipMemcpyAsync(g->d_alpha, ha.data(), 8 * n, hipMemcpyHostToDevice, s));
-                HIPCHK(hipMemcpyAsync(g->d_omega, ho.data(), 8 * n, hipMemcpyHostToDevice, s));
-                HIPCHK(hipMemcpyAsync(g->d_scc, hs.data(), 4 * n, hipMemcpyHostToDevice, s));
-                HIPCHK(hipStreamSynchronize(s));
-            }
             g->reach_ms = now_ms() - t0;
-            g->reach_path = r == 1 ? 2 : 1;
+            g->reach_path = seq ? 2 : 1;
         }
     }
     HIPCHK(hipMemcpyAsync(ws.alpha, g->d_alpha, 8 * (size_t)g->n, hipMemcpyDeviceToDevice, s));

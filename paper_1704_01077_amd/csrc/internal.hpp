@@ -99,15 +99,12 @@ struct tkc_graph {
     int32_t nmseg = 0;
     int32_t server_refs = 0;
     int32_t auto_variant = 0;
-    // directed graphs keep a host copy of the out-arcs for the host fallback
-    // of the reachability bounds
-    std::vector<int32_t> h_rp, h_ci;
     // reachability bounds of a directed graph, computed once per graph:
     // alpha, omega (n int64 each) and topological SCC ids (n int32)
     void* reach_base = nullptr;
     int64_t *d_alpha = nullptr, *d_omega = nullptr;
     int32_t* d_scc = nullptr;
-    int32_t reach_path = 0;     // 0 not yet, 1 device, 2 host fallback
+    int32_t reach_path = 0;     // 0 not yet, 1 parallel steps, 2 a one-thread pass finished chains
     double reach_ms = 0;        // time of that computation
     std::mutex mu;
     // cached preprocessing (serving): [0] Deg, [1] NB

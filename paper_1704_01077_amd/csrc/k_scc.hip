@@ -14,13 +14,16 @@
 // networks); (3) trimming again; (4) max-colour propagation (a vertex takes
 // the largest id that reaches it), then each colour root collects the
 // vertices of its colour that reach it -- repeated until every vertex has a
-// component.  Steps that would need more rounds than a fixed budget (long
-// chains) give up, and the caller falls back to the host.
+// component.  Each of these steps has a round cap; a step that meets it
+// (long chains of components) hands every vertex still unassigned to
+// Tarjan's algorithm run by one device thread.
 //
 // The DAG: every arc between components as a (source, target) pair, sorted
 // by two stable radix passes and deduplicated.  Heights (longest path to a
 // sink) order the dynamic programme, and components are numbered in
-// decreasing height, a topological order.
+// decreasing height, a topological order.  A DAG deeper than the
+// relaxation cap is swept by one device thread in the order of a sinks-first
+// peel instead.
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -665,6 +668,157 @@ __global__ void k_scc_out(int32_t n, const int32_t* comp, const int64_t* ca, con
     scc_topo[v] = topo[c];
 }
 
+// ------------------------------------------- one-thread passes for chains
+// The parallel steps converge in a number of rounds that grows with the
+// length of the longest chain of components (a directed path of 10^4
+// vertices needs 10^4 search levels, and colouring can need that many
+// rounds per component).  Past their round caps the rest is finished by
+// the passes below, one thread each: linear in the vertices and arcs they
+// touch, whatever the chain length.
+
+// the unassigned vertices, in id order (flags, then after a scan a scatter)
+__global__ void k_unassigned_flag(int32_t n, const int32_t* scc, int32_t* flag) {
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) flag[v] = scc[v] < 0;
+}
+__global__ void k_unassigned_scatter(int32_t n, const int32_t* scc, const int32_t* pos, int32_t* out) {
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n && scc[v] < 0) out[pos[v]] = v;
+}
+
+// Tarjan's algorithm, iteratively, over the subgraph of unassigned vertices
+// (ulist[0, ucnt)), one thread.  Every component gets the id of its root,
+// a member, as the parallel steps do.  idx[] must be -1 on every listed
+// vertex; low, tstk, cstk and epos hold n entries each.  A vertex whose
+// scc[] is set is either assigned by an earlier step or closed by this
+// pass; in both cases its arcs lead nowhere new and are skipped.
+__global__ void k_seq_scc(const int32_t* ulist, int32_t ucnt, const int32_t* rp, const int32_t* ci, int32_t* scc,
+                          int32_t* idx, int32_t* low, int32_t* tstk, int32_t* cstk, int32_t* epos) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int32_t nidx = 0;
+    for (int32_t i = 0; i < ucnt; i++) {
+        const int32_t s0 = ulist[i];
+        if (idx[s0] >= 0) continue;
+        int32_t tsp = 0, csp = 0;
+        idx[s0] = low[s0] = nidx++;
+        epos[s0] = rp[s0];
+        tstk[tsp++] = s0;
+        cstk[csp++] = s0;
+        while (csp > 0) {
+            const int32_t u = cstk[csp - 1];
+            const int32_t e = epos[u];
+            if (e < rp[u + 1]) {
+                epos[u] = e + 1;
+                const int32_t w = ci[e];
+                if (scc[w] >= 0) continue;
+                const int32_t iw = idx[w];
+                if (iw < 0) {
+                    idx[w] = low[w] = nidx++;
+                    epos[w] = rp[w];
+                    tstk[tsp++] = w;
+                    cstk[csp++] = w;
+                } else if (iw < low[u]) {
+                    low[u] = iw;   // w is open: on the search stack
+                }
+            } else {
+                csp--;
+                const int32_t lu = low[u];
+                if (csp > 0) {
+                    const int32_t p = cstk[csp - 1];
+                    if (lu < low[p]) low[p] = lu;
+                }
+                if (lu == idx[u]) {
+                    int32_t w;
+                    do {
+                        w = tstk[--tsp];
+                        scc[w] = u;
+                    } while (w != u);
+                }
+            }
+        }
+    }
+}
+
+// Alg. 6 over a deep component DAG, one thread: arcs asrc/adst (U of them,
+// deduplicated, sorted by source), component weights wt, the largest
+// component big.  The components are peeled sinks first (Kahn's order on
+// the reversed DAG), which puts every component after all of its
+// successors; "reaches big" follows in that order, "reached from big" in
+// the opposite one, then alpha and omega as in the parallel sweep by
+// height.  topo numbers the components in the reverse of the peel order, a
+// topological order.  soff, poff: nc + 1 entries; cnt, queue, cur: nc;
+// pred: U.
+__global__ void k_seq_dag(int32_t nc, int32_t U, const int32_t* asrc, const int32_t* adst, const int32_t* wt,
+                          int32_t big, int64_t n, int32_t* soff, int32_t* poff, int32_t* pred, int32_t* cnt,
+                          int32_t* queue, int32_t* cur, int32_t* tob, int32_t* frb, int64_t* ca, int64_t* co,
+                          int32_t* topo, int32_t* err) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    // successor lists: the arcs are grouped by source
+    int32_t j = 0;
+    for (int32_t c = 0; c < nc; c++) {
+        soff[c] = j;
+        while (j < U && asrc[j] == c) j++;
+    }
+    soff[nc] = U;
+    // predecessor lists by counting
+    for (int32_t c = 0; c <= nc; c++) poff[c] = 0;
+    for (int32_t a = 0; a < U; a++) poff[adst[a] + 1]++;
+    for (int32_t c = 0; c < nc; c++) poff[c + 1] += poff[c];
+    for (int32_t c = 0; c < nc; c++) cur[c] = poff[c];
+    for (int32_t a = 0; a < U; a++) pred[cur[adst[a]]++] = asrc[a];
+    // peel: a component joins the queue once all its successors are in it
+    int32_t qt = 0;
+    for (int32_t c = 0; c < nc; c++) {
+        cnt[c] = soff[c + 1] - soff[c];
+        if (cnt[c] == 0) queue[qt++] = c;
+    }
+    for (int32_t qh = 0; qh < qt; qh++) {
+        const int32_t c = queue[qh];
+        for (int32_t q = poff[c]; q < poff[c + 1]; q++)
+            if (--cnt[pred[q]] == 0) queue[qt++] = pred[q];
+    }
+    if (qt != nc) {   // not acyclic: the components are wrong
+        *err = 1;
+        return;
+    }
+    // reaches big: successors first
+    for (int32_t i = 0; i < nc; i++) {
+        const int32_t c = queue[i];
+        int32_t t = c == big;
+        for (int32_t q = soff[c]; q < soff[c + 1] && !t; q++) t = tob[adst[q]];
+        tob[c] = t;
+    }
+    // reached from big: predecessors first
+    int64_t rb = 0;
+    for (int32_t i = nc - 1; i >= 0; i--) {
+        const int32_t c = queue[i];
+        int32_t f = c == big;
+        for (int32_t q = poff[c]; q < poff[c + 1] && !f; q++) f = frb[pred[q]];
+        frb[c] = f;
+        if (f) rb += wt[c];
+    }
+    // alpha and omega, successors first
+    for (int32_t i = 0; i < nc; i++) {
+        const int32_t c = queue[i];
+        topo[c] = nc - 1 - i;
+        if (c == big) {
+            ca[c] = co[c] = rb;
+            continue;
+        }
+        int64_t a = 0, o = 0, o2 = 0;
+        for (int32_t q = soff[c]; q < soff[c + 1]; q++) {
+            const int32_t d = adst[q];
+            a = ca[d] > a ? ca[d] : a;
+            o += co[d];
+            if (!frb[d]) o2 += co[d];
+        }
+        if (tob[c]) o = o2 + rb;
+        o += wt[c];
+        ca[c] = a + wt[c];
+        co[c] = o > n ? n : o;
+    }
+}
+
 // ------------------------------------------------------------------ host
 namespace {
 
@@ -701,10 +855,11 @@ int32_t read_i32(const int32_t* dev, int32_t* pin, hipStream_t s) {
 
 }  // namespace
 
-// Returns 0 on success, 1 when a round budget ran out or the scratch arena
-// does not fit (use the host), -1 on a device error.  pinned: at least 256 bytes of pinned host memory.
+// Returns 0 on success (*seq_used: a one-thread pass finished a long chain),
+// -2 when the scratch arena does not fit, -1 on a device error.  pinned: at least 256 bytes of pinned host memory.
 int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, int32_t* scc_topo, void* pinned,
-                           hipStream_t s) {
+                           hipStream_t s, int* seq_used) {
+    *seq_used = 0;
     const int32_t n = g.n;
     const int64_t m = g.m;
     if (n <= 0) return 0;
@@ -794,9 +949,8 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
     };
     const size_t bytes = layout(nullptr);
     if (hipMalloc(&sc.base, bytes) != hipSuccess) {
-        // no room for the scratch arena: the host path needs none
         (void)hipGetLastError();
-        return 1;
+        return -2;
     }
     layout((char*)sc.base);
     unsigned long long* big_key = (unsigned long long*)(small + 64);
@@ -822,8 +976,13 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
 #define STEP_OK(x) \
     if ((x) != 0) { fail(-1); goto done; }
     {
-        const int RBUDGET = 4096;   // launch rounds of all the iterative steps together
-        int rounds = 0;
+        // round caps of the parallel steps; past them the one-thread passes
+        // finish the job (long chains of components)
+        const int FB_LEVELS = 1024;    // levels of the pivot's forward or backward search
+        const int COL_ITERS = 64;      // colouring iterations
+        const int COL_ROUNDS = 256;    // propagation or closing rounds in one iteration
+        const int DAG_ROUNDS = 64;     // relaxation rounds for the heights
+        bool seq = false;
         hipLaunchKernelGGL(k_scc_init, dim3(gb), dim3(SB), 0, s, n, g.rp, g.rrp, scc, in_rem, out_rem, mark);
         auto trim = [&](int max_rounds) -> int {
             for (int r = 0; r < max_rounds; r++) {
@@ -838,7 +997,7 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
             return hipGetLastError() == hipSuccess ? 0 : -1;
         };
         STEP_OK(trim(32));
-        phase("trim", rounds, 0);
+        phase("trim", 0, 0);
         // ---- forward / backward search from the pivot
         DEV_OK(hipMemsetAsync(big_key, 0, 8, s));
         hipLaunchKernelGGL(k_scc_pivot, dim3(rblk(n)), dim3(SB), 0, s, n, scc, in_rem, out_rem, big_key);
@@ -847,7 +1006,7 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
         if (*(unsigned long long*)pin != 0) {
             pivot = (int32_t)(0xffffffffull - (*(unsigned long long*)pin & 0xffffffffull));
             int32_t* lev = color;   // free until the colouring
-            for (int dir = 0; dir < 2; dir++) {
+            for (int dir = 0; dir < 2 && !seq; dir++) {
                 const uint32_t bit = dir == 0 ? 1u : 2u;
                 const int32_t* arp = dir == 0 ? g.rp : g.rrp;
                 const int32_t* aci = dir == 0 ? g.ci : g.rci;
@@ -866,7 +1025,10 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
                 int32_t fcnt = pin[0];
                 int64_t farcs = pin[2];
                 for (int32_t nl = 1; fcnt > 0; nl++) {
-                    if (++rounds > RBUDGET) { fail(1); goto done; }
+                    if (nl > FB_LEVELS) {
+                        seq = true;
+                        break;
+                    }
                     // a frontier holding a large share of the arcs: pull
                     // over the predecessors instead (direction optimising)
                     if ((int64_t)fcnt * 16 > n || farcs * 8 > m)
@@ -883,45 +1045,82 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
                     farcs = pin[2];
                 }
             }
-            phase("fw-bw", rounds, pivot);
-            hipLaunchKernelGGL(k_scc_assign_fb, dim3(gb), dim3(SB), 0, s, n, scc, mark, pivot);
-            hipLaunchKernelGGL(k_scc_recount, dim3(wblk(n)), dim3(SB), 0, s, n, g.rp, g.ci, g.rrp, g.rci, scc, in_rem,
-                               out_rem);
+            phase("fw-bw", seq, pivot);
+            if (seq) {
+                // a long search: drop its marks, the one-thread pass takes over
+                DEV_OK(hipMemsetAsync(mark, 0, 4 * (size_t)n, s));
+            } else {
+                hipLaunchKernelGGL(k_scc_assign_fb, dim3(gb), dim3(SB), 0, s, n, scc, mark, pivot);
+                hipLaunchKernelGGL(k_scc_recount, dim3(wblk(n)), dim3(SB), 0, s, n, g.rp, g.ci, g.rrp, g.rci, scc,
+                                   in_rem, out_rem);
+            }
         }
-        STEP_OK(trim(32));
-        phase("trim2", rounds, 0);
+        if (!seq) {
+            STEP_OK(trim(32));
+            phase("trim2", 0, 0);
+        }
         // ---- colouring until every vertex has a component
-        for (int it = 0;; it++) {
+        for (int it = 0; !seq; it++) {
             DEV_OK(hipMemsetAsync(small + 1, 0, 4, s));
             hipLaunchKernelGGL(k_col_init, dim3(rblk(n)), dim3(SB), 0, s, n, scc, color, small + 1);
             const int32_t un = read_i32(small + 1, pin, s);
             if (un < 0) { fail(-1); goto done; }
             phase("col-init", it, un);
             if (un == 0) break;
-            if (it >= 64) { fail(1); goto done; }
-            for (;;) {
-                if (++rounds > RBUDGET) { fail(1); goto done; }
+            if (it >= COL_ITERS) {
+                seq = true;
+                break;
+            }
+            for (int r = 0;; r++) {
+                if (r >= COL_ROUNDS) {
+                    seq = true;
+                    break;
+                }
                 DEV_OK(hipMemsetAsync(small + 2, 0, 4, s));
                 hipLaunchKernelGGL(k_col_prop, dim3(gb), dim3(SB), 0, s, n, g.rrp, g.rci, scc, color, small + 2);
                 const int32_t ch = read_i32(small + 2, pin, s);
                 if (ch < 0) { fail(-1); goto done; }
                 if (!ch) break;
             }
-            phase("col-prop", rounds, 0);
+            if (seq) break;
+            phase("col-prop", it, 0);
             hipLaunchKernelGGL(k_col_close_init, dim3(gb), dim3(SB), 0, s, n, scc, color, mark);
-            for (;;) {
-                if (++rounds > RBUDGET) { fail(1); goto done; }
+            for (int r = 0;; r++) {
+                if (r >= COL_ROUNDS) {
+                    seq = true;
+                    break;
+                }
                 DEV_OK(hipMemsetAsync(small + 2, 0, 4, s));
                 hipLaunchKernelGGL(k_col_close, dim3(gb), dim3(SB), 0, s, n, g.rp, g.ci, scc, color, mark, small + 2);
                 const int32_t ch = read_i32(small + 2, pin, s);
                 if (ch < 0) { fail(-1); goto done; }
                 if (!ch) break;
             }
-            phase("col-close", rounds, 0);
+            if (seq) {
+                DEV_OK(hipMemsetAsync(mark, 0, 4 * (size_t)n, s));
+                break;
+            }
+            phase("col-close", it, 0);
             hipLaunchKernelGGL(k_col_assign, dim3(gb), dim3(SB), 0, s, n, scc, color, mark);
             hipLaunchKernelGGL(k_scc_recount, dim3(wblk(n)), dim3(SB), 0, s, n, g.rp, g.ci, g.rrp, g.rci, scc, in_rem,
                                out_rem);
             STEP_OK(trim(32));
+        }
+        if (seq) {
+            // ---- the rest, one thread: Tarjan over the unassigned vertices
+            hipLaunchKernelGGL(k_unassigned_flag, dim3(gb), dim3(SB), 0, s, n, scc, cid);
+            STEP_OK(scan(cid, n, bsum, small + 1, s));
+            hipLaunchKernelGGL(k_unassigned_scatter, dim3(gb), dim3(SB), 0, s, n, scc, cid, list);
+            const int32_t un = read_i32(small + 1, pin, s);
+            if (un < 0) { fail(-1); goto done; }
+            if (un > 0) {
+                // idx = color, low = next, search stack = cid, call stack = cnt, arc cursor = hgt
+                DEV_OK(hipMemsetAsync(color, 0xff, 4 * (size_t)n, s));
+                hipLaunchKernelGGL(k_seq_scc, dim3(1), dim3(64), 0, s, list, un, g.rp, g.ci, scc, color, next, cid,
+                                   cnt, hgt);
+                DEV_OK(hipGetLastError());
+            }
+            phase("seq-scc", un, 0);
         }
         // ---- dense component ids, sizes, the largest component
         hipLaunchKernelGGL(k_rep_flag, dim3(gb), dim3(SB), 0, s, n, scc, cid);
@@ -978,24 +1177,36 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
         hipLaunchKernelGGL(k_set_big, dim3(1), dim3(64), 0, s, comp, (int32_t)bmin, tob, frb, small + 9);
         const int32_t big = read_i32(small + 9, pin, s);
         if (big < 0) { fail(-1); goto done; }
-        while (U > 0) {
-            if (++rounds > RBUDGET) { fail(1); goto done; }
+        bool deep = false;
+        for (int r = 0; U > 0; r++) {
+            if (r >= DAG_ROUNDS) {
+                deep = true;
+                break;
+            }
             DEV_OK(hipMemsetAsync(small + 2, 0, 4, s));
             hipLaunchKernelGGL(k_dag_relax, dim3(nblk(U)), dim3(SB), 0, s, U, asrc, adst, hgt, tob, frb, small + 2);
             const int32_t ch = read_i32(small + 2, pin, s);
             if (ch < 0) { fail(-1); goto done; }
             if (!ch) break;
         }
-        DEV_OK(hipMemsetAsync(rb, 0, 8, s));
-        DEV_OK(hipMemsetAsync(small + 7, 0, 4, s));
-        hipLaunchKernelGGL(k_dag_reach_big, dim3(rblk(nc)), dim3(SB), 0, s, nc, wt, frb, hgt, rb, small + 7);
-        const int32_t hmax = read_i32(small + 7, pin, s);
-        if (hmax < 0) { fail(-1); goto done; }
-        if (hmax > RBUDGET) { fail(1); goto done; }
-        phase("heights", rounds, hmax);
-        // ---- components and arcs grouped by decreasing height (of the
-        // source): a topological numbering, and the sweep order of Alg. 6
-        {
+        if (deep) {
+            // ---- a deep DAG: Alg. 6 in one thread, in peel order
+            // soff = cstart, poff = astart, pred = pos, cnt = hgt, queue = cnt, cursor = minid
+            DEV_OK(hipMemsetAsync(small + 8, 0, 4, s));
+            hipLaunchKernelGGL(k_seq_dag, dim3(1), dim3(64), 0, s, nc, U, asrc, adst, wt, big, (int64_t)n, cstart,
+                               astart, pos, hgt, cnt, minid, tob, frb, ca, co, topo, small + 8);
+            const int32_t bad = read_i32(small + 8, pin, s);
+            if (bad != 0) { fail(-1); goto done; }
+            phase("seq-dag", nc, U);
+        } else {
+            DEV_OK(hipMemsetAsync(rb, 0, 8, s));
+            DEV_OK(hipMemsetAsync(small + 7, 0, 4, s));
+            hipLaunchKernelGGL(k_dag_reach_big, dim3(rblk(nc)), dim3(SB), 0, s, nc, wt, frb, hgt, rb, small + 7);
+            const int32_t hmax = read_i32(small + 7, pin, s);
+            if (hmax < 0 || hmax > DAG_ROUNDS) { fail(-1); goto done; }
+            phase("heights", 0, hmax);
+            // ---- components and arcs grouped by decreasing height (of the
+            // source): a topological numbering, and the sweep order of Alg. 6
             uint32_t* ck = (uint32_t*)in_rem;   // vertex arrays free from here on
             int32_t* byh = out_rem;
             hipLaunchKernelGGL(k_comp_hkey, dim3(nblk(nc)), dim3(SB), 0, s, nc, hgt, hmax, ck, byh);
@@ -1034,6 +1245,7 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
                                        byh, big, (int64_t)n, wt, tob, rb, accA, accO, accO2, ca, co);
             }
         }
+        *seq_used = (seq || deep) ? 1 : 0;
         hipLaunchKernelGGL(k_scc_out, dim3(gb), dim3(SB), 0, s, n, comp, ca, co, topo, alpha, omega, scc_topo);
         DEV_OK(hipStreamSynchronize(s));
         if (hipGetLastError() != hipSuccess) fail(-1);

@@ -4,11 +4,10 @@ The device path (trimming, a forward/backward search from a pivot, colour
 propagation, the component DAG by sorting) must give alpha and omega bit
 for bit equal to the oracle's, the same partition into strongly connected
 components, and ids in a topological order of the component DAG.  Inputs
-with long chains of components exceed the device path's round budget and
-take the host fallback, which must agree as well.
+with long chains of components meet the parallel steps' round caps, and a
+one-thread device pass finishes them; it must agree as well.
 """
 import functools
-import os
 
 import numpy as np
 import pytest
@@ -83,12 +82,31 @@ def graph(name):
     if name == "dpath_long":      # a long chain with increasing ids
         n = 6000
         return _g(name, n, [(i, i + 1) for i in range(n - 1)])
+    if name == "cycle_chain_long":   # 3,000 2-cycles in a chain, ids falling along it
+        n = 6000
+        e = []
+        for i in range(0, n, 2):
+            a, b = n - 1 - i, n - 2 - i
+            e += [(a, b), (b, a)]
+            if b - 1 >= 0:
+                e.append((b, b - 1))
+        return _g(name, n, e)
+    if name == "dag_deep":      # triangles in a chain of 300, plus side sinks: a deep DAG
+        e = []
+        for t in range(300):
+            x, y, z = 3 * t, 3 * t + 1, 3 * t + 2
+            e += [(x, y), (y, z), (z, x)]
+            if t + 1 < 300:
+                e.append((z, 3 * t + 3))
+            e.append((x, 900 + t))
+        return _g(name, 1200, e)
     raise KeyError(name)
 
 
-DEVICE = ["gnp_d", "gnp_giant", "rmat11", "rmat13", "rmat15", "dpath", "sinks", "scc_mix", "two_big_rev",
-          "cycle_chain"]
-FALLBACK = ["dpath_desc", "dpath_long"]
+DEVICE = ["gnp_d", "gnp_giant", "rmat11", "rmat13", "rmat15", "sinks", "scc_mix", "two_big_rev"]
+# chains past the parallel steps' round caps (the component DAGs of dpath
+# and cycle_chain are 89 and 199 deep)
+SEQ = ["dpath", "cycle_chain", "dpath_desc", "dpath_long", "cycle_chain_long", "dag_deep"]
 
 
 def check(g, a, o, sc):
@@ -103,7 +121,7 @@ def check(g, a, o, sc):
         assert np.all(sc[u] <= sc[v])
 
 
-@pytest.mark.parametrize("name", DEVICE + FALLBACK)
+@pytest.mark.parametrize("name", DEVICE + SEQ)
 def test_reach_device_path(ctx, name):
     g = graph(name)
     dg = tkc.Graph.from_graphgen(ctx, g, validate=True)
@@ -112,7 +130,7 @@ def test_reach_device_path(ctx, name):
         a, o, sc = dg.reach()
         check(g, a, o, sc)
         path, ms = dg.reach_info()
-        assert path == (2 if name in FALLBACK else 1), (name, path)
+        assert path == (2 if name in SEQ else 1), (name, path)
         assert ms >= 0
         # cached: a second call gives the same arrays
         a2, o2, sc2 = dg.reach()
@@ -121,28 +139,18 @@ def test_reach_device_path(ctx, name):
         dg.free()
 
 
-@pytest.mark.parametrize("name", ["rmat13", "scc_mix", "gnp_giant"])
-def test_reach_host_and_device_agree(ctx, name):
-    """The host path (forced) and the device path give the same bounds and
-    the same partition."""
+@pytest.mark.parametrize("name", ["dpath_desc", "cycle_chain_long", "dag_deep"])
+def test_reach_seq_pass_exact(ctx, name):
+    """Graphs whose chains exceed the parallel steps' round caps: the
+    one-thread device pass finishes them, bit for bit equal to the oracle."""
     g = graph(name)
-    os.environ["TKC_REACH"] = "host"
+    dg = tkc.Graph.from_graphgen(ctx, g)
     try:
-        dh = tkc.Graph.from_graphgen(ctx, g)
-        ah, oh, sh = dh.reach()
-        assert dh.reach_info()[0] == 2
+        a, o, sc = dg.reach()
+        check(g, a, o, sc)
+        assert dg.reach_info()[0] == 2
     finally:
-        del os.environ["TKC_REACH"]
-    dd = tkc.Graph.from_graphgen(ctx, g)
-    try:
-        ad, od, sd = dd.reach()
-        assert dd.reach_info()[0] == 1
-        assert np.array_equal(ah, ad) and np.array_equal(oh, od)
-        pairs = set(zip(sh.tolist(), sd.tolist()))
-        assert len(pairs) == len(set(sh.tolist()))
-    finally:
-        dh.free()
-        dd.free()
+        dg.free()
 
 
 @pytest.mark.parametrize("name", ["rmat13", "scc_mix", "dpath_desc"])
