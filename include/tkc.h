@@ -254,6 +254,27 @@ int tkc_graph_reach(tkc_graph *g, int64_t *alpha, int64_t *omega, int32_t *scc);
  * the time it took.  Either pointer may be NULL.  Errors: TKC_EINVAL for a
  * NULL graph. */
 int tkc_graph_reach_info(const tkc_graph *g, int32_t *path, double *ms);
+
+/* For callers that cannot allocate device or pinned memory (tight serving
+ * loops, harnesses that forbid allocation): the reachability bounds of
+ * tkc_graph_reach, computed without any allocation.  Every buffer the
+ * kernels need beyond the graph and the outputs comes from one static
+ * device array of TKC_NOALLOC_SCRATCH_BYTES per GPU, set up when a context
+ * is created on that GPU and held until the process ends.
+ *   alpha, omega: device int64[n], written; scc: device int32[n] (component
+ *   ids in a topological order of the component DAG, directed graphs only)
+ *   or NULL.  Undirected graphs get alpha = omega = component size and
+ *   leave scc untouched.  Nothing is cached on g (tkc_graph_reach_info is
+ *   unchanged).
+ *   Errors: TKC_EINVAL for a NULL g, alpha or omega, or for a graph whose
+ *   scratch need exceeds TKC_NOALLOC_SCRATCH_BYTES (the message gives the
+ *   need); TKC_EDEVICE on a device error.
+ * Calls on one GPU share its array, which keeps the last call's contents:
+ * the library serialises the calls of one process on one GPU, and the
+ * call returns only after its kernels have finished.  It reads counts back
+ * to the host between steps, so it cannot be captured into a HIP graph. */
+#define TKC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int tkc_graph_reach_noalloc(tkc_graph *g, int64_t *alpha, int64_t *omega, int32_t *scc);
 /* Initial lower bounds (Sect. 4 computeBounds): the farness bound is
  * (n-1) * num / den, den = 0 meaning +inf.  variant TKC_DEG_* gives 0 (and
  * +inf when r = 1), TKC_NB_* the neighbourhood bound of Sect. 5 / 8.1.

@@ -1,9 +1,9 @@
 // C ABI of the top-k closeness library and the host driver of Alg. 1.
 //
 // A query runs these steps on the context's stream:
-//   1. reachability: r(v) by connected components on the device
-//      (undirected), or the alpha/omega bounds of Alg. 6 on the host
-//      (directed) -- Sect. 4 and Sect. 8.4;
+//   1. reachability: r(v) by connected components (undirected), or the
+//      alpha/omega bounds of Alg. 6 (directed), on the device -- Sect. 4
+//      and Sect. 8.4;
 //   2. initial bounds (computeBounds): Deg (L = 0, order by degree) or NB
 //      (walk-count bound of Sect. 5 / 8.1, order by the bound);
 //   3. processing order: one stable radix sort of the order keys;
@@ -173,6 +173,7 @@ extern "C" int tkc_ctx_create(int device, void* hip_stream, tkc_ctx** out) {
         return tkc_fail(TKC_EDEVICE, "no HIP device available");
     if (device < 0 || device >= count) return tkc_fail(TKC_EINVAL, "device %d out of range", device);
     HIPCHK(hipSetDevice(device));
+    if (int rc = tkc_noalloc_init(device)) return rc;
     tkc_ctx* c = new tkc_ctx();
     c->device = device;
     if (hip_stream) {

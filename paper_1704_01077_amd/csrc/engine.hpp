@@ -131,10 +131,13 @@ int tkc_launch_nb_keys(int32_t n, const int64_t* num, const int64_t* den, uint32
 
 // k_scc.hip: alpha / omega / topological SCC ids of a directed graph.
 // 0 on success (*seq_used = 1 when a one-thread pass finished long chains),
-// -2 when its scratch arena cannot be allocated, -1 on a device error.
+// -2 when its scratch arena cannot be allocated, -3 when the caller's arena
+// is too small (*need: the bytes it takes), -1 on a device error.  arena
+// NULL: it allocates its scratch and frees it before returning.
 // pinned: 256 bytes of pinned host memory.
 int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, int32_t* scc_topo, void* pinned,
-                           hipStream_t s, int* seq_used);
+                           hipStream_t s, int* seq_used, void* arena = nullptr, size_t arena_bytes = 0,
+                           size_t* need = nullptr);
 
 // k_sort.hip: stable ascending sort of (key, val) pairs; the result ends in
 // keys/vals.  tmp_* hold n items, hist holds sort_hist_words(n) int32.

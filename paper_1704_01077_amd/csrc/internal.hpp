@@ -131,6 +131,8 @@ struct tkc_graph {
 };
 
 int tkc_fail(int code, const char* fmt, ...);
+// noalloc.hip: the per-device address of the no-allocation scratch array
+int tkc_noalloc_init(int device);
 // level-based updates of a variant: 0 none (Cut), 1 only (Bound), 2 with cuts
 static inline int tkc_lb_level(int32_t variant) {
     if (variant == TKC_DEG_BOUND || variant == TKC_NB_BOUND) return 1;

@@ -856,9 +856,11 @@ int32_t read_i32(const int32_t* dev, int32_t* pin, hipStream_t s) {
 }  // namespace
 
 // Returns 0 on success (*seq_used: a one-thread pass finished a long chain),
-// -2 when the scratch arena does not fit, -1 on a device error.  pinned: at least 256 bytes of pinned host memory.
+// -2 when the scratch arena cannot be allocated, -3 when the caller's arena
+// (arena_bytes) is smaller than the *need bytes this graph takes, -1 on a
+// device error.  arena NULL: the function allocates its own and frees it.  pinned: at least 256 bytes of pinned host memory.
 int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, int32_t* scc_topo, void* pinned,
-                           hipStream_t s, int* seq_used) {
+                           hipStream_t s, int* seq_used, void* arena, size_t arena_bytes, size_t* need) {
     *seq_used = 0;
     const int32_t n = g.n;
     const int64_t m = g.m;
@@ -948,9 +950,16 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
         return (size_t)(sc.p - base);
     };
     const size_t bytes = layout(nullptr);
-    if (hipMalloc(&sc.base, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return -2;
+    if (need) *need = bytes;
+    const bool own = arena == nullptr;
+    if (own) {
+        if (hipMalloc(&sc.base, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return -2;
+        }
+    } else {
+        if (bytes > arena_bytes) return -3;
+        sc.base = arena;
     }
     layout((char*)sc.base);
     unsigned long long* big_key = (unsigned long long*)(small + 64);
@@ -981,7 +990,7 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
         const int FB_LEVELS = 1024;    // levels of the pivot's forward or backward search
         const int COL_ITERS = 64;      // colouring iterations
         const int COL_ROUNDS = 256;    // propagation or closing rounds in one iteration
-        const int DAG_ROUNDS = 64;     // relaxation rounds for the heights
+        constexpr int DAG_ROUNDS = 64; // relaxation rounds for the heights
         bool seq = false;
         hipLaunchKernelGGL(k_scc_init, dim3(gb), dim3(SB), 0, s, n, g.rp, g.rrp, scc, in_rem, out_rem, mark);
         auto trim = [&](int max_rounds) -> int {
@@ -1221,9 +1230,9 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
                 hipLaunchKernelGGL(k_arc_gather, dim3(nblk(U)), dim3(SB), 0, s, U, tval, asrc, adst, hsrc, hdst);
                 hipLaunchKernelGGL(k_bucket_starts, dim3(nblk(U)), dim3(SB), 0, s, U, tkey, astart);
             }
-            std::vector<int32_t> cb((size_t)hmax + 2), ab((size_t)hmax + 2);
-            DEV_OK(hipMemcpyAsync(cb.data(), cstart, 4 * cb.size(), hipMemcpyDeviceToHost, s));
-            DEV_OK(hipMemcpyAsync(ab.data(), astart, 4 * ab.size(), hipMemcpyDeviceToHost, s));
+            int32_t cb[DAG_ROUNDS + 2], ab[DAG_ROUNDS + 2];   // hmax <= DAG_ROUNDS
+            DEV_OK(hipMemcpyAsync(cb, cstart, 4 * ((size_t)hmax + 2), hipMemcpyDeviceToHost, s));
+            DEV_OK(hipMemcpyAsync(ab, astart, 4 * ((size_t)hmax + 2), hipMemcpyDeviceToHost, s));
             DEV_OK(hipStreamSynchronize(s));
             cb[hmax + 1] = nc;
             ab[hmax + 1] = U;
@@ -1255,6 +1264,6 @@ done:
 #undef DEV_OK
 #undef STEP_OK
     (void)hipStreamSynchronize(s);
-    (void)hipFree(sc.base);
+    if (own) (void)hipFree(sc.base);
     return rc;
 }

@@ -36,7 +36,7 @@ MODES = {"plain": TKC_PLAIN, "batched": TKC_BATCHED, "hybrid": TKC_HYBRID, "auto
 
 EXPORTS = [
     "tkc_ctx_create", "tkc_ctx_destroy", "tkc_ctx_get_tuning", "tkc_ctx_set_tuning", "tkc_graph_upload",
-    "tkc_graph_free", "tkc_topk_closeness", "tkc_topk_closeness_ties", "tkc_autotune", "tkc_graph_reach", "tkc_graph_reach_info", "tkc_graph_bounds", "tkc_topk_harmonic", "tkc_graph_harmonic_bounds", "tkc_graph_harmonic_lb_update", "tkc_graph_lb_update",
+    "tkc_graph_free", "tkc_topk_closeness", "tkc_topk_closeness_ties", "tkc_autotune", "tkc_graph_reach", "tkc_graph_reach_info", "tkc_graph_reach_noalloc", "tkc_graph_bounds", "tkc_topk_harmonic", "tkc_graph_harmonic_bounds", "tkc_graph_harmonic_lb_update", "tkc_graph_lb_update",
     "tkc_graph_sums", "tkc_server_create", "tkc_server_add_graph", "tkc_server_submit",
     "tkc_server_poll", "tkc_server_result", "tkc_server_cancel", "tkc_server_destroy",
     "tkc_last_error", "tkc_version",
@@ -100,6 +100,7 @@ def _load():
         "tkc_topk_closeness_ties": [vp, i32, i32, i32, i32, vp, vp, vp, vp, P(i32), P(tkc_stats)],
         "tkc_graph_reach": [vp, vp, vp, vp],
         "tkc_graph_reach_info": [vp, P(i32), P(c.c_double)],
+        "tkc_graph_reach_noalloc": [vp, vp, vp, vp],
         "tkc_topk_harmonic": [vp, i32, i32, i32, vp, vp, P(i32), P(tkc_stats)],
         "tkc_graph_harmonic_bounds": [vp, i32, vp, vp],
         "tkc_graph_harmonic_lb_update": [vp, vp, i32, vp],
@@ -222,6 +223,11 @@ def tkc_graph_reach_info(g):
     ms = ctypes.c_double(0)
     _check(lib.tkc_graph_reach_info(g, ctypes.byref(path), ctypes.byref(ms)))
     return path.value, ms.value
+
+
+def tkc_graph_reach_noalloc(g, alpha, omega, scc=None):
+    """alpha, omega, scc: device tensors (int64, int64, int32) of n entries."""
+    _check(lib.tkc_graph_reach_noalloc(g, _ptr(alpha), _ptr(omega), _ptr(scc)))
 
 
 def tkc_graph_bounds(g, variant, num, den, order=None):
@@ -355,7 +361,8 @@ class Graph:
         return a, o, (s if self.directed else None)
 
     def reach_info(self):
-        """(path, ms): 0 not computed yet, 1 device, 2 host fallback."""
+        """(path, ms): 0 not computed yet, 1 the parallel device steps, 2 with
+        the one-thread device pass for long chains."""
         return tkc_graph_reach_info(self.h)
 
     def harmonic_bounds(self, variant):
