@@ -258,18 +258,35 @@ TKC_DEV void pull_shared(int32_t eb, int32_t len, const Mask<NW>& miss, const ui
         c_acc[lane * NW + j] = 0;
     }
     __builtin_amdgcn_wave_barrier();
-    for (int32_t t = lane; t < tot; t += 64) {
-        int32_t lo = 0, hi = 64;   // owner: last vertex whose range starts at or before t
+    // each lane takes four consecutive arcs per pass: one owner search, then
+    // four index loads and four frontier loads in flight together
+    for (int32_t t0 = lane * 4; t0 < tot; t0 += 256) {
+        int32_t lo = 0, hi = 64;   // owner: last vertex whose range starts at or before t0
         while (hi - lo > 1) {
             const int32_t mid = (lo + hi) >> 1;
-            if (c_pre[mid] <= t) lo = mid; else hi = mid;
+            if (c_pre[mid] <= t0) lo = mid; else hi = mid;
         }
-        const int32_t u = rci[c_beg[lo] + (t - c_pre[lo])];
-        (*scanned)++;
+        int32_t own[4], u[4];
 #pragma unroll
-        for (int j = 0; j < NW; j++) {
-            const uint64_t f = Fc[(int64_t)u * NW + j] & c_miss[lo * NW + j];
-            if (f) atomicOr((unsigned long long*)&c_acc[lo * NW + j], (unsigned long long)f);
+        for (int q = 0; q < 4; q++) {
+            const int32_t t = t0 + q;
+            own[q] = -1;
+            u[q] = 0;
+            if (t < tot) {
+                while (lo < 63 && c_pre[lo + 1] <= t) lo++;
+                own[q] = lo;
+                u[q] = rci[c_beg[lo] + (t - c_pre[lo])];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            if (own[q] < 0) continue;
+            (*scanned)++;
+#pragma unroll
+            for (int j = 0; j < NW; j++) {
+                const uint64_t f = Fc[(int64_t)u[q] * NW + j] & c_miss[own[q] * NW + j];
+                if (f) atomicOr((unsigned long long*)&c_acc[own[q] * NW + j], (unsigned long long)f);
+            }
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -551,10 +568,12 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 uint64_t m = __ballot(s_st[l] == 1);
                 if (lane == 0) s_act[l >> 6] = m;
             }
-            if (tid == 0) {
+            if (tid >= BB - 64) {   // the last wave: this level's out-degree sum over active lanes
                 int64_t mv = 0;
-                for (int l = 0; l < nsel; l++) if (s_st[l] == 1) mv += s_mf[l];
-                s_scal[0] = mv;
+                for (int l = lane; l < nsel; l += 64)
+                    if (s_st[l] == 1) mv += s_mf[l];
+                mv = wave_sum_i64(mv);
+                if (lane == 0) s_scal[0] = mv;
             }
             __syncthreads();
             Mask<NW> act;
@@ -604,10 +623,11 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             // frontier word and folds it into its visited word, then per
             // out-arc the index, the target's visited and frontier words and
             // its next word; pull reads every vertex's row, frontier and
-            // visited words, and per scanned in-arc the index and a frontier
-            // word (counted in my_scan)
+            // visited words, writes the visited words of frontier vertices,
+            // and per scanned in-arc reads the index and a frontier word
+            // (counted in my_scan)
             bytes += (ol_len + oh_len) * (4 + 8 * NW) +
-                     (bu ? (int64_t)n * (8 + 16 * NW) + (fl_len + fh_len) * (4 + 24 * NW)
+                     (bu ? (int64_t)n * (8 + 16 * NW) + (fl_len + fh_len) * (8 * NW)
                          : (fl_len + fh_len) * (8 + 24 * NW) + udeg * (4 + 24 * NW));
             // (1) F_{D-1} is no longer read: clear its words through L_{D-1}
             {
@@ -763,23 +783,12 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                     }
                 }
             } else {
-                // pull: the level list's vertices fold F_D into their visited
-                // words (readers use vis | F_D, so the fold's timing does not
-                // matter); light vertices (few in-arcs) scan their in-arcs, in
-                // groups of four (four independent index loads, then four
-                // independent frontier loads), until every missing active
-                // lane is found
-                for (int64_t i = gtid; i < fl_len + fh_len; i += nthreads) {
-                    const int32_t u = i < fl_len ? fl[i] : fh[i - fl_len];
-                    bool done = true;
-#pragma unroll
-                    for (int j = 0; j < NW; j++) {
-                        const uint64_t vn = vis[(int64_t)u * NW + j] | Fc[(int64_t)u * NW + j];
-                        vis[(int64_t)u * NW + j] = vn;
-                        done &= (act.w[j] & ~vn) == 0;
-                    }
-                    if (done) my_dd += deg[u];
-                }
+                // pull: one lane per vertex.  A frontier vertex folds F_D into
+                // its visited words here (readers use vis | F_D, so the
+                // fold's timing does not matter).  Light vertices (few
+                // in-arcs) scan their in-arcs, in groups of four (four
+                // independent index loads, then four independent frontier
+                // loads), until every missing active lane is found
                 PHASE(1);
                 for (int64_t base = gwave * 64; base < n; base += nwaves * 64) {
                     const int32_t w = (int32_t)(base + lane);
@@ -790,9 +799,20 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
 #pragma unroll
                     for (int j = 0; j < NW; j++) { acc.w[j] = 0; miss.w[j] = 0; }
                     if (w < n) {
+                        uint64_t vn[NW];
+                        bool inF = false;
 #pragma unroll
-                        for (int j = 0; j < NW; j++)
-                            miss.w[j] = act.w[j] & ~(vis[(int64_t)w * NW + j] | Fc[(int64_t)w * NW + j]);
+                        for (int j = 0; j < NW; j++) {
+                            const uint64_t fw = Fc[(int64_t)w * NW + j];
+                            vn[j] = vis[(int64_t)w * NW + j] | fw;
+                            inF |= fw != 0;
+                            miss.w[j] = act.w[j] & ~vn[j];
+                        }
+                        if (inF) {
+#pragma unroll
+                            for (int j = 0; j < NW; j++) vis[(int64_t)w * NW + j] = vn[j];
+                            if (!miss.any()) my_dd += deg[w];
+                        }
                         eb = a.g.rrp[w];
                         const int32_t d_in = a.g.rrp[w + 1] - eb;
                         if (d_in <= HEAVY_DEG && miss.any()) len = d_in;
@@ -984,12 +1004,16 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 // filled during level D+2; chunk tail D%3 was read after
                 // level D-1 and is next filled during level D+2.
                 const int q3 = (int)((D + 2) % 3);
-                for (int l = 0; l < W; l++) { ctr[C_CNT(q3, l)] = 0; ctr[C_DEG(q3, l)] = 0; }
                 ctr[C_UDEG(q3)] = 0;
                 ctr[C_DDONE(q3)] = 0;
                 ctr[C_LT(sO, 0)] = 0;
                 ctr[C_LT(sO, 1)] = 0;
                 ctr[C_CT(D % 3)] = 0;
+            }
+            if (blockIdx.x == 0 && tid < W) {   // the per-lane counters of that parity
+                const int q3 = (int)((D + 2) % 3);
+                ctr[C_CNT(q3, tid)] = 0;
+                ctr[C_DEG(q3, tid)] = 0;
             }
             D++;
             __syncthreads();
