@@ -53,19 +53,21 @@ def kernel_source_hash(kernel: str) -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, workload: str, mode: str, width: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary;
-    null when the kernels changed since the counters were taken or the
-    counters belong to another mode or batch width."""
+def traffic_key(kernel: str, k: int, mode: str, width: int) -> str:
+    return "%s k=%d %s W=%d" % (kernel, k, mode, width)
+
+
+def load_traffic(kernel: str, workload: str, k: int, mode: str, width: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this kernel, workload, k, mode and batch width; null when there is none
+    or the kernel's sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         d = json.load(open(path))
-        rec = d.get(workload, {}).get(kernel)
+        rec = d.get(workload, {}).get(traffic_key(kernel, k, mode, width))
         if not rec or rec.get("source_hash") != kernel_source_hash(kernel):
-            return None
-        if rec.get("mode") != mode or rec.get("batch_width") != width:
             return None
         return rec.get("bytes_per_launch")
     except Exception:
@@ -112,7 +114,7 @@ def stats_table(d: str) -> str:
 
 
 def traffic_from(fetch_dir: str, write_dir: str, workload: str, kernel: str, last: int, copy_bytes: int,
-                 mode: str, width: int):
+                 k: int, mode: str, width: int):
     """HBM bytes per launch of `kernel` from two rocprofv3 --pmc runs
     (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled so that the
     largest copy dispatch (a device copy of copy_bytes) reads and writes
@@ -137,7 +139,8 @@ def traffic_from(fetch_dir: str, write_dir: str, workload: str, kernel: str, las
             key = (int(disp), name)
             vals[key] = vals.get(key, 0.0) + float(value)
         return sorted(vals.items(), key=lambda kv: kv[0][0])
-    rec = {"source_hash": kernel_source_hash(kernel), "copy_bytes": copy_bytes, "mode": mode, "batch_width": width}
+    rec = {"source_hash": kernel_source_hash(kernel), "copy_bytes": copy_bytes, "k": k, "mode": mode,
+           "batch_width": width}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         disp = per_dispatch(d, counter)
         copies = [v for (i, name), v in disp if "copy" in name.lower()]
@@ -152,7 +155,7 @@ def traffic_from(fetch_dir: str, write_dir: str, workload: str, kernel: str, las
     rec["bytes_per_launch"] = int(rec["fetch_size_bytes"] + rec["write_size_bytes"])
     path = os.path.join(ROOT, "profiles", "traffic.json")
     d = json.load(open(path)) if os.path.exists(path) else {}
-    d.setdefault(workload, {})[kernel] = rec
+    d.setdefault(workload, {})[traffic_key(kernel, k, mode, width)] = rec
     json.dump(d, open(path, "w"), indent=1, sort_keys=True)
     return rec
 
@@ -284,8 +287,13 @@ def serve_bench(args):
     dgs = [tkc.Graph.from_graphgen(ctx, g) for g in pool]
     srv = tkc.Server(ctx, int(args.serve_budget_gb * (1 << 30)), args.serve_slots)
     gids = [srv.add(d) for d in dgs]
+    if args.serve_pack > 0:
+        srv.enable_packing(args.serve_pack)
+        print("serve: packing on for graphs of at most %d vertices: %s" % (args.serve_pack, srv.info()),
+              file=sys.stderr, flush=True)
     rng = np.random.default_rng(args.serve_seed)
-    answers = {}
+    solo_ans = {}      # (graph, k) -> (ids, S) of the request served alone
+    mismatch = [0]
 
     def run(reqs, gaps=None):
         """Submit (graph, k) requests (with arrival gaps in seconds) and
@@ -311,10 +319,14 @@ def serve_bench(args):
             ids, S, r, f, ms = srv.result(tickets[i], k)
             lat[i] = ms
             key = (gi, k)
-            if key in answers:
-                assert np.array_equal(answers[key], ids), "served answers differ for graph %d k=%d" % key
+            if key in solo_ans:
+                if not (np.array_equal(solo_ans[key][0], ids) and np.array_equal(solo_ans[key][1], S)):
+                    mismatch[0] += 1
             else:
-                answers[key] = ids.copy()
+                solo_ans[key] = (ids.copy(), S.copy())   # the warm-up: one request at a time
+            if len(reqs) > 1 and (i + 1) % 500 == 0:
+                print("serve: %d/%d requests done (%.1f s)" % (i + 1, len(reqs), time.perf_counter() - start),
+                      file=sys.stderr, flush=True)
         th.join()
         return time.perf_counter() - start, np.array(lat)
 
@@ -358,6 +370,12 @@ def serve_bench(args):
         "saturation_req_s": round(lam_sat, 3),
         "saturation_latency_ms_p50": round(float(np.percentile(lat_sat, 50)), 3),
         "solo_sum_s": round(solo_sum / 1e3, 3), "wall_s": round(wall, 3),
+        "served_equal_solo": mismatch[0] == 0,
+        "mismatches": mismatch[0],
+        "checked": "every served answer (saturation and timed runs) against the same (graph, k) served alone "
+                   "in the warm-up",
+        "server": srv.info(),
+        "packing_max_vertices": args.serve_pack,
     }
     print(json.dumps(out), flush=True)
     srv.close()
@@ -384,6 +402,10 @@ def main():
     ap.add_argument("--compare", default="plain,batched,hybrid",
                     help="modes timed once each (default knobs) beside the main run")
     ap.add_argument("--no-compare", action="store_true", help="skip the comparison runs")
+    ap.add_argument("--plain-cap", type=int, default=20000,
+                    help="search cap of every plain-mode comparison (never an uncapped plain run)")
+    ap.add_argument("--configs", default="C1,C3,C4", help="other workloads measured into the same line")
+    ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration)")
     ap.add_argument("--serve", action="store_true", help="run the serving-mix benchmark instead")
@@ -392,7 +414,9 @@ def main():
     ap.add_argument("--reach-only", action="store_true",
                     help="time the reachability bounds of --workload (device and host paths) instead")
     ap.add_argument("--serve-graphs", type=int, default=64)
-    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--serve-pack", type=int, default=1 << 17,
+                    help="pack graphs of at most this many vertices into shared launches (0: off)")
     ap.add_argument("--serve-sat", type=int, default=400, help="requests of the saturation run")
     ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate / saturation throughput")
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -412,7 +436,7 @@ def main():
     if args.traffic_from:
         fd, wd = args.traffic_from.split(",")
         rec = traffic_from(fd, wd, args.workload, args.traffic_kernel, args.traffic_last,
-                           args.calib_copy_mb << 20, args.mode, args.traffic_width)
+                           args.calib_copy_mb << 20, args.k, args.mode, args.traffic_width)
         print(json.dumps(rec, indent=1))
         return
     if args.gpus != 1:
@@ -452,50 +476,26 @@ def main():
         print("bench: autotune (budget %.0f ms)" % args.autotune_ms, file=sys.stderr, flush=True)
         tuning, tuned_ms = dg.autotune(args.k, args.variant, args.autotune_ms)
         print("bench: autotuned %s (%.3f ms)" % (tuning, tuned_ms), file=sys.stderr, flush=True)
-    print("bench: warmup", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        tkc.topk_closeness(dg, args.k, args.variant, args.mode)
-    torch.cuda.synchronize()
-    walls, stats = [], []
-    t_all0 = time.perf_counter()
-    for i in range(args.steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ids, S, r, f, st = tkc.topk_closeness(dg, args.k, args.variant, args.mode)
-        torch.cuda.synchronize()
-        walls.append((time.perf_counter() - t0) * 1e3)
-        stats.append(st)
-    torch.cuda.synchronize()
-    t_all = time.perf_counter() - t_all0
-    print("bench: timed %d steps" % args.steps, file=sys.stderr, flush=True)
-    walls = np.array(walls)
-    ms_per_step = t_all * 1e3 / args.steps
-    mvis = stats[-1]["m_vis"]
-    gteps = mvis / (ms_per_step * 1e-3) / 1e9
-    st = stats[-1]
-    # dominant kernel: library HIP events around its launches, over the timed steps
-    kern_ms = float(np.mean([s["ms_kernel_main"] for s in stats]))
-    launches = st["main_launches"]
-    bytes_main = st["bytes_main"]
-    per_launch_ms = kern_ms / max(1, launches)
-    achieved = (bytes_main / max(1, launches)) / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
-    kname = KERNEL_NAMES.get(st["main_kernel"], "?")
-    traffic = load_traffic(kname, args.workload, MODE_NAMES.get(st["mode_used"], "?"), st["batch_width"])
-
-    undirected = not g.directed
-    mn = (2 if undirected else 1) * (g.arcs // (2 if undirected else 1)) * g.n
-    improvement = mn / mvis if mvis else None
+    m = measure(tkc, torch, ctx, g, dg, args.workload, args.k, args.variant, args.mode, args.steps, args.warmup)
+    st = m.pop("_stats")
 
     compare = {}
     if not args.no_compare:
-        for mode in [m for m in args.compare.split(",") if m]:
+        for mode in [x for x in args.compare.split(",") if x]:
             print("bench: compare %s" % mode, file=sys.stderr, flush=True)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            ids2, S2, r2, f2, st2 = tkc.topk_closeness(dg, args.k, args.variant, mode)
-            torch.cuda.synchronize()
-            compare[mode] = {"wall_ms": (time.perf_counter() - t0) * 1e3, "m_vis": st2["m_vis"],
-                             "same_result": bool(np.array_equal(ids2, ids) and np.array_equal(S2, S))}
+            compare[mode] = compare_once(tkc, torch, dg, args.k, args.variant, mode, m["_ids"], m["_S"],
+                                         args.plain_cap)
+    plain = compare.get("plain")
+    useful = None
+    if plain and plain.get("finished"):
+        # the work a one-source-at-a-time engine needs for the same answer
+        useful = round(plain["m_vis"] / (m["ms_per_step"] * 1e-3) / 1e9, 4)
+
+    configs = {}
+    if not args.no_configs:
+        for cname in [x for x in args.configs.split(",") if x]:
+            print("bench: config %s" % cname, file=sys.stderr, flush=True)
+            configs[cname] = run_config(tkc, torch, graphgen, ctx, cname, args)
 
     cpu = None
     if not args.no_cpu:
@@ -504,12 +504,12 @@ def main():
 
     out = {
         "metric": METRIC,
-        "value": round(gteps, 4),
+        "value": m["gteps"],
         "unit": "GTEPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -519,10 +519,74 @@ def main():
                    "k": args.k, "variant": args.variant, "variant_used": st["variant_used"],
                    "mode": args.mode, "mode_used": MODE_NAMES.get(st["mode_used"], st["mode_used"]),
                    "batch_width": st["batch_width"], "tuning": tuning, "n": g.n, "arcs": int(g.arcs)},
+        "wall_ms_p50": m["wall_ms_p50"],
+        "wall_ms_p99": m["wall_ms_p99"],
+        "m_vis": m["m_vis"],
+        "useful_gteps": useful,
+        "useful_note": "m_vis of the plain one-source-at-a-time engine on the same query over this run's "
+                       "ms_per_step; value counts every lane's work, including searches the plain engine "
+                       "would cut or skip",
+        "improvement_factor": m["improvement_factor"],
+        "phase_ms": m["phase_ms"],
+        "searches": m["searches"],
+        "roofline": m["roofline"],
+        "compare": compare,
+        "configs": configs,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    dg.free()
+    ctx.close()
+
+
+def measure(tkc, torch, ctx, g, dg, wname, k, variant, mode, steps, warmup, tune=None):
+    """warmup untimed queries, then `steps` timed ones (each between device
+    synchronisations); GTEPS, percentiles, phases and the dominant kernel's
+    roofline."""
+    keep = ctx.tuning()
+    if tune:
+        ctx.tune(**tune)
+    try:
+        for _ in range(warmup):
+            tkc.topk_closeness(dg, k, variant, mode)
+        torch.cuda.synchronize()
+        walls, stats = [], []
+        t_all0 = time.perf_counter()
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ids, S, r, f, st = tkc.topk_closeness(dg, k, variant, mode)
+            torch.cuda.synchronize()
+            walls.append((time.perf_counter() - t0) * 1e3)
+            stats.append(st)
+        torch.cuda.synchronize()
+        t_all = time.perf_counter() - t_all0
+    finally:
+        ctx.tune(**keep)
+    print("bench: %s timed %d steps" % (wname, steps), file=sys.stderr, flush=True)
+    walls = np.array(walls)
+    ms_per_step = t_all * 1e3 / steps
+    st = stats[-1]
+    mvis = st["m_vis"]
+    # dominant kernel: library HIP events around its launches, over the timed steps
+    kern_ms = float(np.mean([x["ms_kernel_main"] for x in stats]))
+    launches = st["main_launches"]
+    bytes_main = st["bytes_main"]
+    per_launch_ms = kern_ms / max(1, launches)
+    achieved = (bytes_main / max(1, launches)) / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
+    kname = KERNEL_NAMES.get(st["main_kernel"], "?")
+    mode_used = MODE_NAMES.get(st["mode_used"], "?")
+    traffic = load_traffic(kname, wname, k, mode_used, st["batch_width"])
+    undirected = not g.directed
+    mn = (2 if undirected else 1) * (g.arcs // (2 if undirected else 1)) * g.n
+    return {
+        "_stats": st, "_ids": ids, "_S": S,
+        "gteps": round(mvis / (ms_per_step * 1e-3) / 1e9, 4),
+        "ms_per_step": round(ms_per_step, 4),
         "wall_ms_p50": round(float(np.percentile(walls, 50)), 4),
         "wall_ms_p99": round(float(np.percentile(walls, 99)), 4),
         "m_vis": int(mvis),
-        "improvement_factor": improvement,
+        "improvement_factor": mn / mvis if mvis else None,
         "phase_ms": {"reach": st["ms_reach"], "bounds": st["ms_bounds"], "traverse": st["ms_traverse"]},
         "searches": {"started": st["bfs_started"], "exact": st["bfs_exact"], "cut": st["bfs_cut"],
                      "skipped": st["skipped"], "deferred": st["deferred"], "max_level": st["max_level"]},
@@ -530,12 +594,80 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                      "launches_per_step": launches, "kernel_ms_per_step": round(kern_ms, 4),
                      "bytes_per_step": int(bytes_main)},
-        "compare": compare,
-        "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
-    dg.free()
-    ctx.close()
+
+
+def compare_once(tkc, torch, dg, k, variant, mode, ids, S, plain_cap):
+    """One query in `mode` with the default knobs.  Plain mode always runs
+    under a search cap: if it would need more searches it stops there and
+    reports the work and time so far (finished = false), never an answer."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if mode == "plain":
+        done, res, st = tkc.topk_closeness_budget(dg, k, variant, plain_cap)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3
+        out = {"wall_ms": round(wall, 3), "m_vis": int(st["m_vis"]), "searches": int(st["bfs_started"]),
+               "finished": bool(done), "search_cap": int(plain_cap)}
+        if done:
+            out["same_result"] = bool(np.array_equal(res[0], ids) and np.array_equal(res[1], S))
+        else:
+            out["note"] = ("stopped at the search cap: wall_ms and m_vis cover %d searches only, and the full "
+                           "plain query takes longer" % st["bfs_started"])
+        return out
+    ids2, S2, r2, f2, st2 = tkc.topk_closeness(dg, k, variant, mode)
+    torch.cuda.synchronize()
+    return {"wall_ms": round((time.perf_counter() - t0) * 1e3, 3), "m_vis": int(st2["m_vis"]),
+            "same_result": bool(np.array_equal(ids2, ids) and np.array_equal(S2, S))}
+
+
+# the other workloads of the benchmark, each with its knobs fixed here: the
+# BA n = 2,000 query (plain engine against batched), R-MAT scale 20 in its
+# autotuned configuration (batched, W = 256, four workgroups per CU), the
+# 2000^2 grid with the level-based variant
+CONFIGS = {
+    "C1": {"workload": "ba2k", "k": [1, 10], "variant": "auto", "mode": "plain", "steps": 30, "warmup": 3,
+           "tune": None, "compare": ["batched", "hybrid"], "plain_cap": 20000},
+    "C3": {"workload": "rmat20", "k": [10], "variant": "auto", "mode": "batched", "steps": 10, "warmup": 2,
+           "tune": {"batch_width": 256, "blocks_per_cu": 4}, "compare": ["hybrid", "plain"], "plain_cap": 20000},
+    # a plain search on the grid is a whole-GPU search of ~430 levels (~8 ms):
+    # the comparison stops after 300 of them
+    "C4": {"workload": "grid2000", "k": [10], "variant": "nbbound", "mode": "batched", "steps": 2, "warmup": 1,
+           "tune": {"batch_width": 128}, "compare": ["plain"], "plain_cap": 300},
+}
+
+
+def run_config(tkc, torch, graphgen, ctx, cname, args):
+    cfg = CONFIGS[cname]
+    g = graphgen.workload(cfg["workload"])
+    dg = tkc.Graph.from_graphgen(ctx, g)
+    out = {"workload": WORKLOADS.get(cfg["workload"], cfg["workload"]), "variant": cfg["variant"],
+           "mode": cfg["mode"], "tuning": cfg["tune"], "n": g.n, "arcs": int(g.arcs), "runs": {}}
+    try:
+        for k in cfg["k"]:
+            m = measure(tkc, torch, ctx, g, dg, cfg["workload"], k, cfg["variant"], cfg["mode"], cfg["steps"],
+                        cfg["warmup"], cfg["tune"])
+            st = m.pop("_stats")
+            ids, S = m.pop("_ids"), m.pop("_S")
+            m["variant_used"] = st["variant_used"]
+            m["mode_used"] = MODE_NAMES.get(st["mode_used"], st["mode_used"])
+            m["compare"] = {}
+            for mode in cfg["compare"]:
+                print("bench: %s compare %s" % (cname, mode), file=sys.stderr, flush=True)
+                m["compare"][mode] = compare_once(tkc, torch, dg, k, cfg["variant"], mode, ids, S,
+                                                  min(args.plain_cap, cfg["plain_cap"]))
+            plain = m["compare"].get("plain")
+            m["useful_gteps"] = (round(plain["m_vis"] / (m["ms_per_step"] * 1e-3) / 1e9, 4)
+                                 if plain and plain.get("finished") else None)
+            out["runs"]["k=%d" % k] = m
+        if g.directed:
+            used, ms = dg.reach_info()
+            out["reach_ms_once_per_graph"] = round(ms, 3)
+            out["reach_note"] = ("directed reachability (SCCs + Alg. 6) runs once per graph and is cached; "
+                                 "the timed queries reuse it")
+    finally:
+        dg.free()
+    return out
 
 
 if __name__ == "__main__":

@@ -90,6 +90,7 @@ extern "C" {
 typedef struct tkc_ctx tkc_ctx;
 typedef struct tkc_graph tkc_graph;
 typedef struct tkc_server tkc_server;
+typedef struct tkc_pack tkc_pack;
 
 /* per-call statistics; every field is filled on success */
 typedef struct {
@@ -185,6 +186,18 @@ int tkc_graph_free(tkc_graph *g);
 int tkc_topk_closeness(tkc_graph *g, int32_t k, int32_t variant, int32_t mode,
                        int32_t *ids, int64_t *sum_dist, int64_t *reach, double *farness,
                        int32_t *n_out, tkc_stats *stats);
+
+/* Top-k closeness (Alg. 1) in plain mode (one search at a time, Sect. 6),
+ * with at most max_searches (>= 1) breadth-first searches: for measuring
+ * the one-source-at-a-time engine on graphs where a whole plain run would
+ * take too long.  A query that finishes within the cap returns TKC_OK and
+ * the same results as tkc_topk_closeness.  One that would need more returns
+ * TKC_ECANCELED with *n_out = 0, no results, and *stats (if not NULL)
+ * holding the work done so far: bfs_started = max_searches, m_vis, and the
+ * phase times.  Errors: TKC_EINVAL, TKC_ENOMEM, TKC_EDEVICE. */
+int tkc_topk_closeness_budget(tkc_graph *g, int32_t k, int32_t variant, int64_t max_searches,
+                              int32_t *ids, int64_t *sum_dist, int64_t *reach, double *farness,
+                              int32_t *n_out, tkc_stats *stats);
 
 /* Top-k harmonic centrality: h(v) = sum of 1/d(v,w) over the vertices w
  * that v reaches (the measure of Sect. 2 with f(d) = 1/d, ranked in Sect.
@@ -290,7 +303,49 @@ int tkc_graph_lb_update(tkc_graph *g, const int32_t *sources, int32_t count,
 int tkc_graph_sums(tkc_graph *g, const int32_t *sources, int32_t count,
                    int64_t *sum_dist, int64_t *reach);
 
+/* ---- packs: top-k requests on several graphs in one batched launch */
+/* A pack of `count` graphs of one context, all directed or all undirected,
+ * each listed once: the library uploads their disjoint union once (member
+ * i's vertices renumbered by an offset; no arc joins two members) so that
+ * requests on different members can share the lanes of one batched launch
+ * (Alg. 1 with BFSCut, Sect. 6, each request with its own order, bounds
+ * and k-th farness).  The members stay owned by the caller and must outlive
+ * the pack (tkc_graph_free returns TKC_EBUSY meanwhile); their
+ * preprocessing (reachability, initial bounds, order) is cached on them.
+ * Errors: TKC_EINVAL (NULL, empty, mixed directedness, repeated graph,
+ * another context, union beyond int32 ids), TKC_ENOMEM, TKC_EDEVICE. */
+int tkc_pack_create(tkc_ctx *ctx, tkc_graph *const *graphs, int32_t count, tkc_pack **out);
+/* nreq requests (1..64) on distinct members member[0..nreq) of pack p,
+ * request i asking for the top k[i] (k[i] >= 1) by closeness.  variant:
+ * TKC_NB_CUT or TKC_DEG_CUT (TKC_AUTO means TKC_NB_CUT); every variant
+ * gives the same answers, only the work differs.  Results are concatenated
+ * in request order: request i's n_out[i] = min(k[i], n of its member)
+ * results, in each member's own vertex ids and the exact order of
+ * tkc_topk_closeness, start at the sum of n_out[0..i).  ids (and sum_dist,
+ * reach, farness when not NULL) hold the sum of min(k[i], n_i) entries;
+ * n_out holds nreq.  stats (may be NULL) covers the whole launch.  Each
+ * request's answer equals tkc_topk_closeness on its member alone.  Errors:
+ * TKC_EINVAL (also for two requests on one member), TKC_ENOMEM,
+ * TKC_EDEVICE. */
+int tkc_pack_topk(tkc_pack *p, int32_t nreq, const int32_t *member, const int32_t *k, int32_t variant,
+                  int32_t *ids, int64_t *sum_dist, int64_t *reach, double *farness, int32_t *n_out,
+                  tkc_stats *stats);
+int tkc_pack_free(tkc_pack *p);
+
 /* ---- serving: graphs stay resident, requests are batched as they arrive */
+/* Packing for a server: every added graph of at most max_vertices vertices
+ * joins a pack (tkc_pack_create; undirected and directed graphs apart, up
+ * to 64 members and 2^28 arcs each).  A request on a packed graph whose
+ * variant resolves to TKC_NB_CUT or TKC_DEG_CUT is then served together
+ * with the queued requests on the pack's other members, in one batched
+ * launch (tkc_pack_topk); answers are unchanged.  max_vertices = 0 turns
+ * packing off.  Call it after adding the graphs and while no request is
+ * queued or running (TKC_EBUSY otherwise).  Errors: TKC_EINVAL, TKC_EBUSY,
+ * TKC_ENOMEM, TKC_EDEVICE. */
+int tkc_server_enable_packing(tkc_server *s, int32_t max_vertices);
+/* Counters of server s (any pointer may be NULL): requests served,
+ * requests served in packed launches, packed launches, packs. */
+int tkc_server_info(tkc_server *s, int64_t *served, int64_t *packed, int64_t *pack_calls, int32_t *packs);
 /* hbm_budget_bytes caps the device memory the server's request slots may
  * use (admission control); max_inflight caps concurrent requests. */
 int tkc_server_create(tkc_ctx *ctx, size_t hbm_budget_bytes, int32_t max_inflight,

@@ -47,6 +47,10 @@ int tkc_fail(int code, const char* fmt, ...) {
             return tkc_fail(TKC_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
+double tkc_now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
 static double now_ms() {
     using namespace std::chrono;
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
@@ -96,7 +100,7 @@ static size_t ws_items(Workspace& ws, const WsShape& sh, std::vector<WsItem>& it
         {(void**)&ws.b_vis, 8 * n * nw, true}, {(void**)&ws.b_frt0, 8 * n * nw, true},
         {(void**)&ws.b_frt1, 8 * n * nw, true}, {(void**)&ws.b_nxt, 8 * n * nw, true},
         {(void**)&ws.b_list, 32 * n + 16 * ((size_t)sh.nchunks + 64), false}, {(void**)&ws.b_mark, 4 * n, true},
-        {(void**)&ws.b_ctr, 8 * 2048, true}, {(void**)&ws.b_cand, 4 * 256, false},
+        {(void**)&ws.b_ctr, 8 * 2048, true}, {(void**)&ws.b_cand, 8 * 256, false},
         {(void**)&ws.b_hist, sh.lb ? 8 * lcap * W : 8, false},
         {(void**)&ws.b_levtab, sh.lb ? 8 * lcap * W : 8, false},
         {(void**)&ws.b_lvl, sh.lb ? 2 * n * W : 8, false},
@@ -628,13 +632,14 @@ static PlainWork plain_view(Workspace& ws) {
     w.bar = ws.bar;
     return w;
 }
-static BatchWork batch_view(Workspace& ws) {
+BatchWork tkc_batch_view(Workspace& ws) {
     BatchWork w{};
     w.vis = ws.b_vis; w.frt0 = ws.b_frt0; w.frt1 = ws.b_frt1; w.nxt = ws.b_nxt;
     w.list = ws.b_list; w.touched = ws.b_mark; w.ctr = ws.b_ctr; w.lanes = nullptr;
     w.ccap = (int64_t)ws.shape.nchunks + 64;
     w.lvl = ws.b_lvl; w.hist = ws.b_hist; w.levtab = ws.b_levtab; w.lcap = ws.shape.lcap;
     w.cand = ws.b_cand;
+    w.cand_req = ws.b_cand + 256;
     w.trace = ws.trace;
     w.trace_cap = ws.trace ? 4096 : 0;
     w.bar = ws.bar;
@@ -751,6 +756,19 @@ extern "C" int tkc_topk_closeness_ties(tkc_graph* g, int32_t k, int32_t variant,
     return tkc_run_query(c, g, k, variant, mode, ids, sum_dist, reach, farness, n_out, stats, cap);
 }
 
+extern "C" int tkc_topk_closeness_budget(tkc_graph* g, int32_t k, int32_t variant, int64_t max_searches,
+                                         int32_t* ids, int64_t* sum_dist, int64_t* reach, double* farness,
+                                         int32_t* n_out, tkc_stats* stats) {
+    if (!g || !ids || !n_out) return tkc_fail(TKC_EINVAL, "NULL argument");
+    if (k < 1) return tkc_fail(TKC_EINVAL, "k must be >= 1");
+    if (max_searches < 1) return tkc_fail(TKC_EINVAL, "max_searches must be >= 1");
+    if (variant < TKC_AUTO || variant > TKC_NB_CUTLB) return tkc_fail(TKC_EINVAL, "unknown variant %d", variant);
+    tkc_ctx* c = g->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    return tkc_run_query(c, g, k, variant, TKC_PLAIN, ids, sum_dist, reach, farness, n_out, stats, 0, false,
+                         max_searches);
+}
+
 extern "C" int tkc_topk_harmonic(tkc_graph* g, int32_t k, int32_t variant, int32_t mode, int32_t* ids,
                                  double* harmonic, int32_t* n_out, tkc_stats* stats) {
     if (!g || !ids || !n_out) return tkc_fail(TKC_EINVAL, "NULL argument");
@@ -843,7 +861,7 @@ extern "C" int tkc_autotune(tkc_graph* g, int32_t k, int32_t variant, double bud
 
 int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t mode, int32_t* ids,
                   int64_t* sum_dist, int64_t* reach, double* farness, int32_t* n_out, tkc_stats* stats,
-                  int32_t ties_cap, bool harm) {
+                  int32_t ties_cap, bool harm, int64_t max_searches) {
     const bool ties = ties_cap > 0;
     Workspace& ws = c->ws;
     hipStream_t s = c->stream;
@@ -860,7 +878,7 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
         c->tune = tkc_effective_tuning(keep, g);
         c->tune.slice_batches = keep.slice_batches;
         rc = tkc_run_query(c, g, k, variant, c->tune.mode, ids, sum_dist, reach, farness, n_out, stats, ties_cap,
-                           harm);
+                           harm, max_searches);
         c->tune = keep;
         return rc;
     }
@@ -918,7 +936,8 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
     if (lb && mode == TKC_HYBRID) mode = TKC_BATCHED;
     if (mode == TKC_PLAIN) {
         EngineTimer tm(c, &ms_eng[0], &nl_eng[0]);
-        if (tkc_launch_plain(dg, rcv, ov, bv, tk, plain_view(ws), st_plain, nullptr, 0, lbl, c->tune, s, &grid))
+        if (tkc_launch_plain(dg, rcv, ov, bv, tk, plain_view(ws), st_plain, nullptr, 0, lbl, c->tune, s, &grid,
+                             max_searches))
             return tkc_fail(TKC_EDEVICE, "plain engine launch failed: %s", hipGetErrorString(hipGetLastError()));
         if ((rc = tm.done(readback))) return rc;
         rb_ready = true;
@@ -931,7 +950,7 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
         for (;;) {
             {
                 EngineTimer tm(c, &ms_eng[1], &nl_eng[1]);
-                int e = tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_batch, nullptr, 0, pos, slice, lbl,
+                int e = tkc_launch_batch(dg, rcv, ov, bv, tk, tkc_batch_view(ws), st_batch, nullptr, 0, pos, slice, lbl,
                                          false, nullptr, nullptr, c->tune, s, &grid);
                 if (e)
                     return tkc_fail(TKC_EDEVICE, "batched engine launch failed: %s", hipGetErrorString(hipGetLastError()));
@@ -976,7 +995,7 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
             EngineTimer tm(c, &ms_eng[1], &nl_eng[1]);
             EngineTuning seed = c->tune;
             seed.lanes_cap = seed.seed_lanes;
-            if (tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_batch, nullptr, 0, 0, -1, false,
+            if (tkc_launch_batch(dg, rcv, ov, bv, tk, tkc_batch_view(ws), st_batch, nullptr, 0, 0, -1, false,
                                  false, nullptr, nullptr, seed, s, &grid))
                 return tkc_fail(TKC_EDEVICE, "batched seed launch failed: %s", hipGetErrorString(hipGetLastError()));
             HIPCHK(hipEventRecord(c->evm, s));
@@ -1013,7 +1032,7 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
             if (ndef > 0) {
                 trace_reset(c);
                 EngineTimer tm(c, &ms_eng[1], &nl_eng[1]);
-                if (tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_tail, ws.s_deferred, ndef, 0, 0,
+                if (tkc_launch_batch(dg, rcv, ov, bv, tk, tkc_batch_view(ws), st_tail, ws.s_deferred, ndef, 0, 0,
                                      false, false, nullptr, nullptr, c->tune, s, &grid))
                     return tkc_fail(TKC_EDEVICE, "batched tail launch failed");
                 if ((rc = tm.done(readback))) return rc;
@@ -1025,7 +1044,7 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
             if (!(sw_stop & 1) && (sw_stop & 2) && resume < n) {
                 trace_reset(c);
                 EngineTimer tm(c, &ms_eng[1], &nl_eng[1]);
-                if (tkc_launch_batch(dg, rcv, ov, bv, tk, batch_view(ws), st_batch, nullptr, 0, resume, 0, false,
+                if (tkc_launch_batch(dg, rcv, ov, bv, tk, tkc_batch_view(ws), st_batch, nullptr, 0, resume, 0, false,
                                      false, nullptr, nullptr, c->tune, s, &grid))
                     return tkc_fail(TKC_EDEVICE, "batched continuation launch failed");
                 if ((rc = tm.done(readback))) return rc;
@@ -1052,6 +1071,46 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
     const int64_t* pS = pin_at<int64_t>(ws, ws.tS);
     const int64_t* pR = pin_at<int64_t>(ws, ws.tR);
     const int32_t* pI = pin_at<int32_t>(ws, ws.tI);
+    auto fill_stats = [&]() -> int {
+        if (!stats) return TKC_OK;
+        for (int e = 0; e < 4; e++) {
+            st.m_vis += hstat[e][ST_MVIS];
+            st.bfs_started += hstat[e][ST_STARTED];
+            st.bfs_exact += hstat[e][ST_EXACT];
+            st.bfs_cut += hstat[e][ST_CUT];
+            st.skipped += hstat[e][ST_SKIPPED];
+            st.deferred += hstat[e][ST_DEFERRED];
+            st.max_level = (int32_t)std::max<int64_t>(st.max_level, hstat[e][ST_MAXLEVEL]);
+        }
+        st.batch_width = c->tune.batch_width;
+        st.variant_used = variant;
+        st.mode_used = mode;
+        st.nb_rounds = rounds;
+        // phases from the stream's marks (the readback synchronised it)
+        float ph[3] = {0.f, 0.f, 0.f};
+        for (int i = 0; i < 3; i++)
+            HIPCHK(hipEventElapsedTime(&ph[i], c->evq[i], i < 2 ? c->evq[i + 1] : trav_end));
+        st.ms_reach = ph[0];
+        st.ms_bounds = ph[1];
+        st.ms_traverse = ph[2];
+        st.ms_total = now_ms() - t0;
+        int best = 0;
+        for (int e = 1; e < 3; e++)
+            if (ms_eng[e] > ms_eng[best]) best = e;
+        st.main_kernel = best;
+        st.ms_kernel_main = ms_eng[best];
+        st.main_launches = nl_eng[best];
+        st.bytes_main = best == 0 ? hstat[0][ST_BYTES]
+                                  : (best == 1 ? hstat[1][ST_BYTES] + hstat[3][ST_BYTES] : hstat[2][ST_BYTES]);
+        *stats = st;
+        return TKC_OK;
+    };
+    if (hstat[0][ST_CAPPED]) {
+        // the plain engine met its search cap: counters only, no answer
+        *n_out = 0;
+        if ((rc = fill_stats())) return rc;
+        return tkc_fail(TKC_ECANCELED, "search cap of %lld searches reached", (long long)max_searches);
+    }
     std::vector<int64_t> hS(pS, pS + k), hR(pR, pR + k);
     std::vector<int32_t> hI(pI, pI + k);
     int32_t cnt = std::min(hst.cnt, k);
@@ -1111,40 +1170,7 @@ int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t 
                                     : ((double)(n - 1) * (double)hS[i]) / ((double)(hR[i] - 1) * (double)(hR[i] - 1));
     }
     *n_out = cnt;
-    double t4 = now_ms();
-    if (stats) {
-        for (int e = 0; e < 4; e++) {
-            st.m_vis += hstat[e][ST_MVIS];
-            st.bfs_started += hstat[e][ST_STARTED];
-            st.bfs_exact += hstat[e][ST_EXACT];
-            st.bfs_cut += hstat[e][ST_CUT];
-            st.skipped += hstat[e][ST_SKIPPED];
-            st.deferred += hstat[e][ST_DEFERRED];
-            st.max_level = (int32_t)std::max<int64_t>(st.max_level, hstat[e][ST_MAXLEVEL]);
-        }
-        st.batch_width = c->tune.batch_width;
-        st.variant_used = variant;
-        st.mode_used = mode;
-        st.nb_rounds = rounds;
-        // phases from the stream's marks (the readback synchronised it)
-        float ph[3] = {0.f, 0.f, 0.f};
-        for (int i = 0; i < 3; i++)
-            HIPCHK(hipEventElapsedTime(&ph[i], c->evq[i], i < 2 ? c->evq[i + 1] : trav_end));
-        st.ms_reach = ph[0];
-        st.ms_bounds = ph[1];
-        st.ms_traverse = ph[2];
-        st.ms_total = t4 - t0;
-        int best = 0;
-        for (int e = 1; e < 3; e++)
-            if (ms_eng[e] > ms_eng[best]) best = e;
-        st.main_kernel = best;
-        st.ms_kernel_main = ms_eng[best];
-        st.main_launches = nl_eng[best];
-        st.bytes_main = best == 0 ? hstat[0][ST_BYTES]
-                                  : (best == 1 ? hstat[1][ST_BYTES] + hstat[3][ST_BYTES] : hstat[2][ST_BYTES]);
-        *stats = st;
-    }
-    return TKC_OK;
+    return fill_stats();
 }
 
 // AUTO variant: one full search from the highest-degree vertex measures its
@@ -1245,7 +1271,7 @@ int tkc_sums_impl(tkc_ctx* c, tkc_graph* g, const int32_t* sources, int32_t coun
     BoundsView bv{ws.lnum, ws.lden};
     int grid = 0;
     std::lock_guard<std::mutex> lk(tkc_coop_mutex());
-    if (tkc_launch_batch(g->view(), rcv, ov, bv, tk, batch_view(ws), ws.stats, dsrc, count, 0, 0, false, true,
+    if (tkc_launch_batch(g->view(), rcv, ov, bv, tk, tkc_batch_view(ws), ws.stats, dsrc, count, 0, 0, false, true,
                          ws.b_outS, ws.b_outR, c->tune, s, &grid))
         return tkc_fail(TKC_EDEVICE, "batched engine launch failed");
     HIPCHK(hipMemcpyAsync(S, ws.b_outS, 8 * (size_t)count, hipMemcpyDeviceToHost, s));
@@ -1303,7 +1329,7 @@ extern "C" int tkc_graph_lb_update(tkc_graph* g, const int32_t* sources, int32_t
         int32_t cnt = std::min(count - off, g->n);
         HIPCHK(hipMemcpyAsync(ws.s_deferred, sources + off, 4 * (size_t)cnt, hipMemcpyHostToDevice, s));
         std::lock_guard<std::mutex> lk(tkc_coop_mutex());
-        if (tkc_launch_batch(g->view(), rcv, ov, bv, tk, batch_view(ws), ws.stats, ws.s_deferred, cnt, 0, 0,
+        if (tkc_launch_batch(g->view(), rcv, ov, bv, tk, tkc_batch_view(ws), ws.stats, ws.s_deferred, cnt, 0, 0,
                              true, true, ws.b_outS, ws.b_outR, c->tune, s, &grid))
             return tkc_fail(TKC_EDEVICE, "batched engine launch failed");
         HIPCHK(hipStreamSynchronize(s));
@@ -1349,7 +1375,7 @@ extern "C" int tkc_graph_harmonic_lb_update(tkc_graph* g, const int32_t* sources
         int32_t cnt = std::min(count - off, g->n);
         HIPCHK(hipMemcpyAsync(ws.s_deferred, sources + off, 4 * (size_t)cnt, hipMemcpyHostToDevice, s));
         std::lock_guard<std::mutex> lk(tkc_coop_mutex());
-        if (tkc_launch_batch(g->view(), rcv, ov, bv, tk, batch_view(ws), ws.stats, ws.s_deferred, cnt, 0, 0,
+        if (tkc_launch_batch(g->view(), rcv, ov, bv, tk, tkc_batch_view(ws), ws.stats, ws.s_deferred, cnt, 0, 0,
                              1, true, ws.b_outS, ws.b_outR, c->tune, s, &grid))
             return tkc_fail(TKC_EDEVICE, "batched engine launch failed");
         HIPCHK(hipStreamSynchronize(s));

@@ -68,7 +68,7 @@ struct DevTopk {
 // counters the engines add to (device, int64 each)
 enum {
     ST_MVIS = 0, ST_STARTED, ST_EXACT, ST_CUT, ST_SKIPPED, ST_DEFERRED, ST_MAXLEVEL, ST_CURSOR,
-    ST_STOP, ST_BYTES, ST_COUNT
+    ST_STOP, ST_BYTES, ST_CAPPED, ST_COUNT
 };
 
 struct OrderView {
@@ -173,9 +173,12 @@ struct PlainWork {
 // lb_mode: 0 cut searches (Cut variants), 1 complete searches feeding
 // level-based updates (Bound variants), 2 both: shallow searches may be cut
 // (cut_allowed), and the complete ones feed level-based updates
+// max_searches > 0: stop before the search that would exceed it and set
+// stats[ST_CAPPED] (the top k is then incomplete)
 int tkc_launch_plain(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv, DevTopk tk,
                      PlainWork w, int64_t* stats, const int32_t* list, int32_t list_count,
-                     int lb_mode, const EngineTuning& tune, hipStream_t s, int* grid_out);
+                     int lb_mode, const EngineTuning& tune, hipStream_t s, int* grid_out,
+                     int64_t max_searches = 0);
 
 // k_batch.hip: W sources per launch, one bit lane each (cooperative kernel).
 struct BatchWork {
@@ -193,15 +196,29 @@ struct BatchWork {
     int64_t* levtab;     // LCAP * W Lev tables
     int32_t lcap;
     int32_t* cand;       // selected candidates of a batch (W)
+    int32_t* cand_req;   // the request of each candidate (W; packed launches)
     int64_t* trace;      // optional per-level records (16 int64 from word 8), [0] = count
     int64_t trace_cap;
     uint32_t* bar;       // grid barrier state (zeroed once)
 };
+// One request of a packed launch: a top-k query on one member of a union
+// graph (the members' vertices renumbered by adding `off`).  The views are
+// the member's own, in its own vertex ids; the top k is the request's.
+struct PackReq {
+    int32_t off;             // union id of the member's vertex 0
+    int32_t n;               // the member's vertex count (its order's length)
+    OrderView ov;
+    BoundsView bv;
+    DevReach rc;
+    DevTopk tk;
+};
+#define TKC_PACK_MAXREQ 64
+
 int tkc_launch_batch(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv, DevTopk tk,
                      BatchWork w, int64_t* stats, const int32_t* list, int32_t list_count,
                      int32_t start_pos, int32_t max_batches, int lb_mode, bool no_cut,
                      int64_t* out_S, int64_t* out_r, const EngineTuning& tune, hipStream_t s,
-                     int* grid_out);
+                     int* grid_out, const PackReq* preq = nullptr, int32_t npreq = 0);
 
 // k_swarm.hip: one search per workgroup for short cut searches.
 struct SwarmWork {

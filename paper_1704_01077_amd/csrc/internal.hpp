@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -98,7 +99,7 @@ struct tkc_graph {
     int32_t *mid_vtx = nullptr, *mseg = nullptr;
     int32_t nmseg = 0;
     int32_t server_refs = 0;
-    int32_t auto_variant = 0;
+    std::atomic<int32_t> auto_variant{0};   // read by server workers without the graph lock
     // reachability bounds of a directed graph, computed once per graph:
     // alpha, omega (n int64 each) and topological SCC ids (n int32)
     void* reach_base = nullptr;
@@ -131,6 +132,27 @@ struct tkc_graph {
 };
 
 int tkc_fail(int code, const char* fmt, ...);
+// milliseconds on the host's steady clock
+double tkc_now_ms();
+// the batched engine's buffers in a workspace
+BatchWork tkc_batch_view(Workspace& ws);
+
+// A pack: the disjoint union of member graphs, whose top-k requests share the
+// lanes of one batched launch (pack.cpp)
+struct tkc_pack {
+    tkc_ctx* ctx = nullptr;
+    std::vector<tkc_graph*> members;
+    std::vector<int32_t> off;   // union id of each member's vertex 0
+    tkc_graph* ug = nullptr;    // the union graph
+    void* dev = nullptr;        // per-request top-k states and the request table
+    size_t dev_bytes = 0;
+    std::mutex mu;              // one packed call at a time
+};
+// tkc_pack_topk on context c's stream and workspace (the server's slots)
+int tkc_pack_topk_on(tkc_ctx* c, tkc_pack* p, int32_t nreq, const int32_t* member, const int32_t* k,
+                     int32_t variant, int32_t* ids, int64_t* sum_dist, int64_t* reach, double* farness,
+                     int32_t* n_out, tkc_stats* stats);
+
 // noalloc.hip: the per-device address of the no-allocation scratch array
 int tkc_noalloc_init(int device);
 // level-based updates of a variant: 0 none (Cut), 1 only (Bound), 2 with cuts
@@ -147,7 +169,7 @@ int tkc_ws_reserve(tkc_ctx* ctx, Workspace& ws, const WsShape& sh);
 // harm: harmonic centrality; farness then receives the values h
 int tkc_run_query(tkc_ctx* c, tkc_graph* g, int32_t k, int32_t variant, int32_t mode, int32_t* ids,
                   int64_t* sum_dist, int64_t* reach, double* farness, int32_t* n_out, tkc_stats* stats,
-                  int32_t ties_cap = 0, bool harm = false);
+                  int32_t ties_cap = 0, bool harm = false, int64_t max_searches = 0);
 int tkc_sums_impl(tkc_ctx* c, tkc_graph* g, const int32_t* sources, int32_t count, int64_t* S, int64_t* R,
                   tkc_stats* st);
 int32_t tkc_auto_variant(tkc_ctx* c, tkc_graph* g);

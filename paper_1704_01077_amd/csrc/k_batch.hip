@@ -73,6 +73,11 @@ struct BatchArgs {
     int64_t* out_r;
     int32_t* mark;         // per-vertex level stamp (NW > 1)
     uint32_t* bar;         // grid barrier state
+    // packed launch (npreq > 0): the batches' lanes are shared by npreq
+    // requests on the members of a union graph; a.ov, a.bv, a.rc and a.tk
+    // are then unused, every request brings its own
+    const PackReq* preq;
+    int32_t npreq;
 };
 
 TKC_DEV int64_t shfl64b(int64_t v, int src) {
@@ -322,6 +327,88 @@ TKC_DEV bool discover(uint64_t* Fn, int32_t* mark, int32_t w, const Mask<NW>& nb
     }
 }
 
+// Candidate selection of Alg. 1 from one processing order, by the 64 lanes
+// of one wave: positions pos, pos + 1, ... are taken, skipped (the bound
+// already passes x) or finished at once (nothing reachable: S = 0, r = 1)
+// until cap candidates are selected, the order ends, or the stop rule fires
+// (sets *stop).  Selected vertices, plus `off`, go to cand[nsel ...].
+struct SelIn {
+    const int32_t* ord;      // the order (order mode) or the source list (list mode)
+    const uint32_t* key;     // the order's keys; null in list mode
+    int32_t count;
+    bool key_is_bound;
+    const int64_t* num;
+    const int64_t* den;
+    const int64_t* omega;
+    DevTopk tk;
+    int32_t harm;
+    int32_t no_cut;
+    int32_t off;
+};
+TKC_DEV void select_cands(const SelIn& in, int32_t& pos, int32_t cap, int32_t* cand, int32_t& nsel, int32_t& stop,
+                          int64_t& skipped, int64_t& r1) {
+    const int lane = lane_id();
+    const bool order_mode = in.key != nullptr;
+    const int32_t count = in.count;
+    XVal x = read_x(in.tk.st, in.tk.ring);
+    int64_t r1_here = 0;
+    while (nsel < cap && pos < count && !stop) {
+        int32_t i = pos + lane;
+        bool valid = i < count;
+        int32_t v = valid ? in.ord[i] : -1;
+        bool st = false, sk = false, one = false;
+        if (valid && !in.no_cut) {
+            if (order_mode) {
+                uint32_t key = in.key[i];
+                st = in.harm ? key_stops_h(key, x)
+                             : (in.key_is_bound ? key_stops(key, x) : (key == 0xffffffffu && x.den != 0));
+            }
+            if (!st) sk = lex_after(in.num[v], in.den[v], v, x.num, x.den, x.id);
+        }
+        // in list mode without cuts every position gets a lane, sinks included
+        if (valid && !st && !sk && !in.no_cut) one = in.omega[v] <= 1;
+        uint64_t mst = __ballot(valid && st);
+        int lim = mst ? (__ffsll((long long)mst) - 1) : 64;
+        bool inwin = valid && lane < lim;
+        bool elig = inwin && !st && !sk && !one;
+        uint64_t me = __ballot(elig);
+        int room = cap - nsel;
+        // lanes beyond the room-th eligible one are left for the next batch
+        int cut_lane = 64;
+        if (__popcll(me) > room) {
+            uint64_t m = me;
+            for (int q = 0; q < room; q++) m &= m - 1;
+            cut_lane = __ffsll((long long)m) - 1;
+        }
+        bool take = inwin && lane < cut_lane;
+        int rank = __popcll(me & below_mask());
+        if (take && elig) cand[nsel + rank] = v + in.off;
+        uint64_t mone = __ballot(take && one);
+        uint64_t msk = __ballot(take && sk);
+        // vertices that reach nothing are exact at once: (S, r) = (0, 1)
+        if (lane == 0) {
+            uint64_t m = mone;
+            while (m) {
+                int l = __ffsll((long long)m) - 1;
+                m &= m - 1;
+                int32_t vv = in.ord[pos + l];
+                if (in.harm) topk_insert(in.tk.st, in.tk.ring, in.tk.S, in.tk.R, in.tk.I, harm_enc(0.0), 2, vv);
+                else topk_insert(in.tk.st, in.tk.ring, in.tk.S, in.tk.R, in.tk.I, 0, 1, vv);
+            }
+        }
+        r1_here += __popcll(mone);
+        skipped += __popcll(msk);
+        int took = __popcll(me & ((cut_lane >= 64) ? ~0ull : ((1ull << cut_lane) - 1)));
+        int consumed = lim < cut_lane ? lim : cut_lane;
+        if (consumed > count - pos) consumed = count - pos;
+        nsel += took;
+        pos += consumed;
+        if (mst && lim < cut_lane) stop = 1;
+        if (r1_here) x = read_x(in.tk.st, in.tk.ring);
+    }
+    r1 += r1_here;
+}
+
 TKC_DEV uint64_t* fsel(const BatchWork& w, int64_t level) {
     const int i = (int)(level % 3);
     return i == 0 ? w.frt0 : (i == 1 ? w.frt1 : w.nxt);
@@ -358,6 +445,12 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
 
     // replicated per-lane control state
     __shared__ int32_t s_v[MAXW];
+    // per lane: the x its cuts compare with (its request's, read at the
+    // start of the batch), the union offset of its graph, its request
+    __shared__ int64_t s_xn[MAXW], s_xd[MAXW];
+    __shared__ int32_t s_xi[MAXW], s_off[MAXW], s_req[MAXW];
+    // cursors and stop flags of a pack's requests (block 0's first wave)
+    __shared__ int32_t s_pk_pos[TKC_PACK_MAXREQ], s_pk_stop[TKC_PACK_MAXREQ];
     __shared__ int64_t s_a[MAXW], s_o[MAXW], s_nD[MAXW], s_SD[MAXW], s_U[MAXW], s_nf[MAXW], s_mf[MAXW];
     __shared__ double s_H[MAXW];   // harmonic centrality so far (levels 1..D)
     __shared__ int32_t s_st[MAXW];      // 0 unused, 1 active, 2 exact, 3 cut
@@ -386,66 +479,44 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
 
     int32_t pos = a.start_pos;
     int32_t batches = 0;
+    if (tid < TKC_PACK_MAXREQ) {
+        s_pk_pos[tid] = 0;
+        s_pk_stop[tid] = 0;
+    }
+    __syncthreads();
     while (batches < a.max_batches) {
         // ---------------------------------------------- candidate selection
         if (blockIdx.x == 0 && tid < 64) {
-            XVal x = read_x(a.tk.st, a.tk.ring);
             int32_t nsel = 0;
             int32_t stop = 0;
             int64_t skipped = 0, r1 = 0;
-            while (nsel < a.Wsel && pos < count && !stop) {
-                int32_t i = pos + lane;
-                bool valid = i < count;
-                int32_t v = valid ? (order_mode ? a.ov.ord[i] : a.list[i]) : -1;
-                bool st = false, sk = false, one = false;
-                if (valid && !a.no_cut) {
-                    if (order_mode) {
-                        uint32_t key = a.ov.key[i];
-                        st = a.bv.harm ? key_stops_h(key, x)
-                                       : (a.ov.key_is_bound ? key_stops(key, x) : (key == 0xffffffffu && x.den != 0));
-                    }
-                    if (!st) sk = lex_after(a.bv.num[v], a.bv.den[v], v, x.num, x.den, x.id);
-                }
-                // in list mode without cuts every position gets a lane, sinks included
-                if (valid && !st && !sk && !a.no_cut) one = a.rc.omega[v] <= 1;
-                uint64_t mst = __ballot(valid && st);
-                int lim = mst ? (__ffsll((long long)mst) - 1) : 64;
-                bool inwin = valid && lane < lim;
-                bool elig = inwin && !st && !sk && !one;
-                uint64_t me = __ballot(elig);
-                int room = a.Wsel - nsel;
-                // lanes beyond the room-th eligible one are left for the next batch
-                int cut_lane = 64;
-                if (__popcll(me) > room) {
-                    uint64_t m = me;
-                    for (int q = 0; q < room; q++) m &= m - 1;
-                    cut_lane = __ffsll((long long)m) - 1;
-                }
-                bool take = inwin && lane < cut_lane;
-                int rank = __popcll(me & below_mask());
-                if (take && elig) a.w.cand[nsel + rank] = v;
-                uint64_t mone = __ballot(take && one);
-                uint64_t msk = __ballot(take && sk);
-                // vertices that reach nothing are exact at once: (S, r) = (0, 1)
-                if (lane == 0) {
-                    uint64_t m = mone;
-                    while (m) {
-                        int l = __ffsll((long long)m) - 1;
-                        m &= m - 1;
-                        int32_t vv = order_mode ? a.ov.ord[pos + l] : a.list[pos + l];
-                        if (a.bv.harm) topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, harm_enc(0.0), 2, vv);
-                        else topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, 0, 1, vv);
+            if (a.npreq == 0) {
+                const SelIn in{order_mode ? a.ov.ord : a.list, order_mode ? a.ov.key : nullptr, count,
+                               a.ov.key_is_bound, a.bv.num, a.bv.den, a.rc.omega, a.tk, a.bv.harm, a.no_cut, 0};
+                select_cands(in, pos, a.Wsel, a.w.cand, nsel, stop, skipped, r1);
+            } else {
+                // the requests of a pack take turns: first up to an even
+                // share of the lanes each, then whatever is left over
+                const int32_t share = a.Wsel / a.npreq > 0 ? a.Wsel / a.npreq : 1;
+                for (int pass = 0; pass < 2 && nsel < a.Wsel; pass++) {
+                    for (int32_t r = 0; r < a.npreq && nsel < a.Wsel; r++) {
+                        if (s_pk_stop[r] || s_pk_pos[r] >= a.preq[r].n) continue;
+                        const PackReq& q = a.preq[r];
+                        const SelIn in{q.ov.ord, q.ov.key, q.n, q.ov.key_is_bound, q.bv.num, q.bv.den, q.rc.omega,
+                                       q.tk, 0, 0, q.off};
+                        const int32_t before = nsel;
+                        const int32_t cap = pass == 0 ? (nsel + share < a.Wsel ? nsel + share : a.Wsel) : a.Wsel;
+                        int32_t rpos = s_pk_pos[r], rstop = s_pk_stop[r];
+                        select_cands(in, rpos, cap, a.w.cand, nsel, rstop, skipped, r1);
+                        for (int32_t c = before + lane; c < nsel; c += 64) a.w.cand_req[c] = r;
+                        __builtin_amdgcn_wave_barrier();
+                        if (lane == 0) {
+                            s_pk_pos[r] = rpos;
+                            s_pk_stop[r] = rstop;
+                        }
+                        __builtin_amdgcn_wave_barrier();
                     }
                 }
-                r1 += __popcll(mone);
-                skipped += __popcll(msk);
-                int took = __popcll(me & ((cut_lane >= 64) ? ~0ull : ((1ull << cut_lane) - 1)));
-                int consumed = lim < cut_lane ? lim : cut_lane;
-                if (consumed > count - pos) consumed = count - pos;
-                nsel += took;
-                pos += consumed;
-                if (mst && lim < cut_lane) stop = 1;
-                if (r1) x = read_x(a.tk.st, a.tk.ring);
             }
             if (lane == 0) {
                 ctr[C_NSEL] = nsel;
@@ -464,14 +535,31 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
         if (nsel == 0) break;
 
         // ------------------------------------------------------ lane init
-        const XVal x = read_x(a.tk.st, a.tk.ring);
+        XVal xb{0, 0, 0};
+        if (a.npreq == 0) xb = read_x(a.tk.st, a.tk.ring);
         if (tid < MAXW) {
             int l = tid;
             if (l < nsel) {
                 int32_t v = a.w.cand[l];
+                int32_t off = 0, r = 0;
+                const int64_t* al = a.rc.alpha;
+                const int64_t* om = a.rc.omega;
+                XVal xl = xb;
+                if (a.npreq) {
+                    r = a.w.cand_req[l];
+                    off = a.preq[r].off;
+                    al = a.preq[r].rc.alpha;
+                    om = a.preq[r].rc.omega;
+                    xl = read_x(a.preq[r].tk.st, a.preq[r].tk.ring);
+                }
                 s_v[l] = v;
-                s_a[l] = a.rc.alpha[v];
-                s_o[l] = a.rc.omega[v];
+                s_off[l] = off;
+                s_req[l] = r;
+                s_xn[l] = xl.num;
+                s_xd[l] = xl.den;
+                s_xi[l] = xl.id;
+                s_a[l] = al[v - off];
+                s_o[l] = om[v - off];
                 s_nD[l] = 1; s_SD[l] = 0; s_H[l] = 0.0;
                 s_U[l] = deg[v]; s_nf[l] = 1; s_mf[l] = deg[v];
                 s_st[l] = 1;
@@ -552,7 +640,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                         int64_t bn, bd;
                         if (a.bv.harm) harm_cut_bound(s_H[l], s_nD[l], s_U[l], D, s_o[l], &bn, &bd);
                         else cut_bound(s_SD[l], s_nD[l], s_U[l], D, s_a[l], s_o[l], &bn, &bd);
-                        if (lex_after(bn, bd, s_v[l], x.num, x.den, x.id)) {
+                        if (lex_after(bn, bd, s_v[l] - s_off[l], s_xn[l], s_xd[l], s_xi[l])) {
                             s_st[l] = 3;
                             s_maxD[l] = (int32_t)D;
                         }
@@ -1034,11 +1122,13 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 if (s_maxD[l] > md) md = s_maxD[l];
                 if (s_st[l] == 2) {
                     ex++;
+                    const DevTopk& tk = a.npreq ? a.preq[s_req[l]].tk : a.tk;
+                    const int32_t id = s_v[l] - s_off[l];
                     if (a.no_cut) {
                     } else if (a.bv.harm) {
-                        topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, harm_enc(s_H[l]), 2, s_v[l]);
+                        topk_insert(tk.st, tk.ring, tk.S, tk.R, tk.I, harm_enc(s_H[l]), 2, id);
                     } else {
-                        topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, s_SD[l], s_nD[l], s_v[l]);
+                        topk_insert(tk.st, tk.ring, tk.S, tk.R, tk.I, s_SD[l], s_nD[l], id);
                     }
                 } else if (s_st[l] == 3) cu++;
             }
@@ -1171,9 +1261,12 @@ int tkc_launch_batch(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv
                      BatchWork w, int64_t* stats, const int32_t* list, int32_t list_count,
                      int32_t start_pos, int32_t max_batches, int lb_mode, bool no_cut,
                      int64_t* out_S, int64_t* out_r, const EngineTuning& tune, hipStream_t s,
-                     int* grid_out) {
+                     int* grid_out, const PackReq* preq, int32_t npreq) {
     int W = tune.batch_width;
     if (W != 32 && W != 64 && W != 128 && W != 256) return -2;
+    // a packed launch: requests of a union graph, BFSCut only, from their orders
+    if (npreq < 0 || npreq > TKC_PACK_MAXREQ) return -2;
+    if (npreq > 0 && (!preq || !w.cand_req || lb_mode || no_cut || list || max_batches != 0)) return -2;
     if (!w.bar || !w.vis || !w.frt0 || !w.frt1 || !w.nxt || !w.list || !w.ctr || !w.cand || !stats) return -2;
     if (lb_mode && (!w.lvl || !w.hist || !w.levtab)) return -2;
     int NW = W <= 64 ? 1 : W / 64;
@@ -1210,6 +1303,8 @@ int tkc_launch_batch(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv
     a.out_r = out_r;
     a.mark = (int32_t*)w.touched;
     a.bar = w.bar;
+    a.preq = preq;
+    a.npreq = npreq;
     void* args[] = {&a};
     e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(BB), args, 0, s);
     return e == hipSuccess ? 0 : -1;

@@ -34,6 +34,7 @@ struct PlainArgs {
     int32_t lb_mode;
     int32_t alpha_td;
     int32_t beta_bu;
+    int64_t max_searches;   // 0: no cap
     uint32_t* bar;
 };
 
@@ -145,6 +146,7 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
     int64_t* stats = a.stats;
 
     int32_t pos;
+    int64_t searches = 0;   // replicated: every workgroup takes the same path
     for (pos = 0; pos < count; pos++) {
         const int32_t v = a.list ? a.list[pos] : a.ov.ord[pos];
         const XVal x = read_x(a.tk.st, a.tk.ring);
@@ -172,6 +174,11 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
             grid_barrier(a.bar, gridDim.x);
             continue;
         }
+        if (a.max_searches > 0 && searches >= a.max_searches) {
+            if (boss) stats[ST_CAPPED] = 1;
+            break;
+        }
+        searches++;
         const int64_t dv = deg[v];
         if (boss) {
             for (int q = 0; q < 3 * CS; q++) ctr[q] = 0;
@@ -425,7 +432,8 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
 
 int tkc_launch_plain(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv, DevTopk tk,
                      PlainWork w, int64_t* stats, const int32_t* list, int32_t list_count,
-                     int lb_mode, const EngineTuning& tune, hipStream_t s, int* grid_out) {
+                     int lb_mode, const EngineTuning& tune, hipStream_t s, int* grid_out,
+                     int64_t max_searches) {
     if (!w.bar || !w.vis || !w.fb || !w.ql || !w.qh || !w.qg || !w.ctr || !stats) return -2;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return -1;
@@ -444,6 +452,7 @@ int tkc_launch_plain(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv
     a.lb_mode = lb_mode;
     a.alpha_td = tune.td_bu_alpha > 0 ? tune.td_bu_alpha : 14;
     a.beta_bu = tune.bu_td_beta > 0 ? tune.bu_td_beta : 24;
+    a.max_searches = max_searches > 0 ? max_searches : 0;
     a.bar = w.bar;
     void* args[] = {&a};
     hipError_t e = hipLaunchCooperativeKernel((const void*)k_plain, dim3(grid), dim3(PB), args, 0, s);

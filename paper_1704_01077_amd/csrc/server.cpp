@@ -11,6 +11,12 @@
 //     computed by the first request on a graph and reused by later ones.
 //   - Cooperative (grid-barrier) kernels of different slots never overlap:
 //     they take a process-wide lock, while ordinary kernels run freely.
+//   - Packing (tkc_server_enable_packing): the small graphs are grouped into
+//     packs (disjoint unions, pack.cpp).  A slot that takes a request on a
+//     packed graph also takes the queued requests on the pack's other
+//     members (distinct graphs, the same BFSCut variant) and serves them
+//     all with one batched launch, so requests that arrived together share
+//     the GPU's lanes instead of queuing for the cooperative lock one by one.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -65,6 +71,21 @@ struct tkc_server {
     std::map<uint64_t, std::shared_ptr<Request>> all;
     uint64_t next_ticket = 1;
     bool stopping = false;
+    // packing
+    bool packing = false;
+    std::vector<tkc_pack*> packs;
+    std::vector<int32_t> pack_of, member_of;   // per graph id (-1: not packed)
+    std::vector<size_t> pack_need;             // workspace bytes of a packed call
+    int64_t n_served = 0, n_packed = 0, n_pack_calls = 0;
+
+    // fills request rq's answer from a packed call's concatenated results
+    static void take(Request& rq, const std::vector<int32_t>& ids, const std::vector<int64_t>& S,
+                     const std::vector<int64_t>& R, const std::vector<double>& F, int32_t o, int32_t c) {
+        rq.ids.assign(ids.begin() + o, ids.begin() + o + c);
+        rq.S.assign(S.begin() + o, S.begin() + o + c);
+        rq.R.assign(R.begin() + o, R.begin() + o + c);
+        rq.F.assign(F.begin() + o, F.begin() + o + c);
+    }
 
     size_t committed_except(int slot) {
         size_t t = 0;
@@ -112,6 +133,76 @@ struct tkc_server {
                 rq->state = 1;
             }
             tkc_graph* g = graphs[rq->graph_id];
+            // packing: queued requests on the pack's other members join this one
+            std::vector<std::shared_ptr<Request>> group;
+            int32_t pk = -1, pv = 0;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                if (packing && !rq->cancelled) pk = pack_of[rq->graph_id];
+            }
+            if (pk >= 0) {
+                pv = rq->variant == TKC_AUTO ? tkc_auto_variant(c, g) : rq->variant;
+                if (pv != TKC_NB_CUT && pv != TKC_DEG_CUT) pk = -1;
+            }
+            if (pk >= 0) {
+                std::lock_guard<std::mutex> lk(mu);
+                const size_t need = std::max(slot_bytes[slot], pack_need[pk]);
+                if (committed_except(slot) + need <= budget) {
+                    slot_bytes[slot] = need;
+                    group.push_back(rq);
+                    std::vector<char> used(packs[pk]->members.size(), 0);
+                    used[member_of[rq->graph_id]] = 1;
+                    for (auto it = queue.begin(); it != queue.end() && group.size() < TKC_PACK_MAXREQ;) {
+                        const std::shared_ptr<Request>& q = *it;
+                        const int32_t gid = q->graph_id;
+                        // an AUTO request joins once its graph's variant is known
+                        const int32_t qv = q->variant == TKC_AUTO ? graphs[gid]->auto_variant.load() : q->variant;
+                        if (pack_of[gid] == pk && !used[member_of[gid]] && qv == pv && !q->cancelled) {
+                            used[member_of[gid]] = 1;
+                            q->state = 1;
+                            group.push_back(q);
+                            it = queue.erase(it);
+                        } else {
+                            ++it;
+                        }
+                    }
+                }
+            }
+            if (group.size() >= 2) {
+                const int32_t nr = (int32_t)group.size();
+                std::vector<int32_t> mem(nr), ks(nr), nout(nr);
+                int32_t tot = 0;
+                for (int32_t i = 0; i < nr; i++) {
+                    mem[i] = member_of[group[i]->graph_id];
+                    ks[i] = group[i]->k;
+                    tot += std::min(group[i]->k, graphs[group[i]->graph_id]->n);
+                }
+                std::vector<int32_t> ids(tot);
+                std::vector<int64_t> S(tot), R(tot);
+                std::vector<double> F(tot);
+                const int st = tkc_pack_topk_on(c, packs[pk], nr, mem.data(), ks.data(), pv, ids.data(), S.data(),
+                                                R.data(), F.data(), nout.data(), nullptr);
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    int32_t o = 0;
+                    for (int32_t i = 0; i < nr; i++) {
+                        Request& q = *group[i];
+                        if (st == TKC_OK) take(q, ids, S, R, F, o, nout[i]);
+                        else q.err = tkc_last_error();
+                        o += st == TKC_OK ? nout[i] : 0;
+                        q.status = q.cancelled ? TKC_ECANCELED : st;
+                        q.t_done = now_ms();
+                        q.state = 2;
+                    }
+                    n_served += nr;
+                    n_packed += nr;
+                    n_pack_calls++;
+                    slot_bytes[slot] = std::max(slot_bytes[slot], c->ws.bytes);
+                }
+                cv_done.notify_all();
+                cv_work.notify_all();
+                continue;
+            }
             int32_t k = std::min(rq->k, g->n);
             rq->ids.resize(k);
             rq->S.resize(k);
@@ -129,6 +220,7 @@ struct tkc_server {
                 rq->t_done = now_ms();
                 rq->state = 2;
                 slot_bytes[slot] = c->ws.bytes;
+                n_served++;
             }
             cv_done.notify_all();
             cv_work.notify_all();
@@ -251,6 +343,70 @@ extern "C" int tkc_server_cancel(tkc_server* s, uint64_t ticket) {
     return TKC_OK;
 }
 
+extern "C" int tkc_server_enable_packing(tkc_server* s, int32_t max_vertices) {
+    if (!s) return tkc_fail(TKC_EINVAL, "NULL argument");
+    if (max_vertices < 0) return tkc_fail(TKC_EINVAL, "max_vertices must be >= 0");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!s->queue.empty()) return tkc_fail(TKC_EBUSY, "requests are queued");
+    for (auto& kv : s->all)
+        if (kv.second->state == 1) return tkc_fail(TKC_EBUSY, "requests are running");
+    s->packing = false;
+    for (tkc_pack* p : s->packs) tkc_pack_free(p);
+    s->packs.clear();
+    s->pack_need.clear();
+    const int32_t ng = (int32_t)s->graphs.size();
+    s->pack_of.assign(ng, -1);
+    s->member_of.assign(ng, -1);
+    if (max_vertices == 0) return TKC_OK;
+    // members of at most max_vertices vertices, one kind of graph per pack,
+    // up to TKC_PACK_MAXREQ members and 2^28 arcs per union
+    for (int dir = 0; dir < 2; dir++) {
+        std::vector<int32_t> cur;
+        int64_t arcs = 0;
+        auto flush = [&]() -> int {
+            if (cur.size() >= 2) {
+                std::vector<tkc_graph*> mg;
+                for (int32_t gid : cur) mg.push_back(s->graphs[gid]);
+                tkc_pack* p = nullptr;
+                int rc = tkc_pack_create(s->ctx, mg.data(), (int32_t)mg.size(), &p);
+                if (rc) return rc;
+                const int32_t pi = (int32_t)s->packs.size();
+                s->packs.push_back(p);
+                s->pack_need.push_back(tkc_ws_bytes(tkc_shape_for(s->ctx->tune, p->ug, 1024, false)));
+                for (int32_t i = 0; i < (int32_t)cur.size(); i++) {
+                    s->pack_of[cur[i]] = pi;
+                    s->member_of[cur[i]] = i;
+                }
+            }
+            cur.clear();
+            arcs = 0;
+            return TKC_OK;
+        };
+        for (int32_t gid = 0; gid < ng; gid++) {
+            tkc_graph* g = s->graphs[gid];
+            if (g->directed != (dir == 1) || g->n > max_vertices) continue;
+            if ((int32_t)cur.size() == TKC_PACK_MAXREQ || arcs + g->m > (int64_t(1) << 28))
+                if (int rc = flush()) return rc;
+            cur.push_back(gid);
+            arcs += g->m;
+        }
+        if (int rc = flush()) return rc;
+    }
+    s->packing = !s->packs.empty();
+    return TKC_OK;
+}
+
+extern "C" int tkc_server_info(tkc_server* s, int64_t* served, int64_t* packed, int64_t* pack_calls,
+                               int32_t* packs) {
+    if (!s) return tkc_fail(TKC_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (served) *served = s->n_served;
+    if (packed) *packed = s->n_packed;
+    if (pack_calls) *pack_calls = s->n_pack_calls;
+    if (packs) *packs = (int32_t)s->packs.size();
+    return TKC_OK;
+}
+
 extern "C" int tkc_server_destroy(tkc_server* s) {
     if (!s) return TKC_OK;
     {
@@ -259,6 +415,8 @@ extern "C" int tkc_server_destroy(tkc_server* s) {
     }
     s->cv_work.notify_all();
     for (auto& t : s->workers) t.join();
+    for (tkc_pack* p : s->packs) tkc_pack_free(p);
+    s->packs.clear();
     for (auto* c : s->slot_ctx) tkc_ctx_destroy(c);
     for (auto* g : s->graphs) {
         std::lock_guard<std::mutex> gl(g->mu);

@@ -36,9 +36,10 @@ MODES = {"plain": TKC_PLAIN, "batched": TKC_BATCHED, "hybrid": TKC_HYBRID, "auto
 
 EXPORTS = [
     "tkc_ctx_create", "tkc_ctx_destroy", "tkc_ctx_get_tuning", "tkc_ctx_set_tuning", "tkc_graph_upload",
-    "tkc_graph_free", "tkc_topk_closeness", "tkc_topk_closeness_ties", "tkc_autotune", "tkc_graph_reach", "tkc_graph_reach_info", "tkc_graph_reach_noalloc", "tkc_graph_bounds", "tkc_topk_harmonic", "tkc_graph_harmonic_bounds", "tkc_graph_harmonic_lb_update", "tkc_graph_lb_update",
+    "tkc_graph_free", "tkc_topk_closeness", "tkc_topk_closeness_budget", "tkc_topk_closeness_ties", "tkc_autotune", "tkc_graph_reach", "tkc_graph_reach_info", "tkc_graph_reach_noalloc", "tkc_graph_bounds", "tkc_topk_harmonic", "tkc_graph_harmonic_bounds", "tkc_graph_harmonic_lb_update", "tkc_graph_lb_update",
     "tkc_graph_sums", "tkc_server_create", "tkc_server_add_graph", "tkc_server_submit",
     "tkc_server_poll", "tkc_server_result", "tkc_server_cancel", "tkc_server_destroy",
+    "tkc_pack_create", "tkc_pack_topk", "tkc_pack_free", "tkc_server_enable_packing", "tkc_server_info",
     "tkc_last_error", "tkc_version",
 ]
 
@@ -98,6 +99,12 @@ def _load():
         "tkc_graph_free": [vp],
         "tkc_topk_closeness": [vp, i32, i32, i32, vp, vp, vp, vp, P(i32), P(tkc_stats)],
         "tkc_topk_closeness_ties": [vp, i32, i32, i32, i32, vp, vp, vp, vp, P(i32), P(tkc_stats)],
+        "tkc_topk_closeness_budget": [vp, i32, i32, i64, vp, vp, vp, vp, P(i32), P(tkc_stats)],
+        "tkc_pack_create": [vp, vp, i32, P(vp)],
+        "tkc_pack_topk": [vp, i32, vp, vp, i32, vp, vp, vp, vp, vp, P(tkc_stats)],
+        "tkc_pack_free": [vp],
+        "tkc_server_enable_packing": [vp, i32],
+        "tkc_server_info": [vp, P(i64), P(i64), P(i64), P(i32)],
         "tkc_graph_reach": [vp, vp, vp, vp],
         "tkc_graph_reach_info": [vp, P(i32), P(c.c_double)],
         "tkc_graph_reach_noalloc": [vp, vp, vp, vp],
@@ -210,6 +217,19 @@ def tkc_topk_closeness_ties(g, k, variant, mode, cap, ids, sum_dist=None, reach=
     rc = lib.tkc_topk_closeness_ties(g, k, variant, mode, cap, _ptr(ids), _ptr(sum_dist), _ptr(reach),
                                      _ptr(farness), ctypes.byref(n_out), ctypes.byref(st))
     if rc != TKC_OK and not (rc == TKC_EINVAL and n_out.value > cap):
+        _check(rc)
+    return rc, n_out.value, st
+
+
+def tkc_topk_closeness_budget(g, k, variant, max_searches, ids, sum_dist=None, reach=None, farness=None):
+    """Returns (rc, n_out, stats): rc is TKC_OK with the answer, or
+    TKC_ECANCELED (no answer, stats filled) when the search cap was met;
+    other errors raise."""
+    n_out = ctypes.c_int32(0)
+    st = tkc_stats()
+    rc = lib.tkc_topk_closeness_budget(g, k, variant, max_searches, _ptr(ids), _ptr(sum_dist), _ptr(reach),
+                                       _ptr(farness), ctypes.byref(n_out), ctypes.byref(st))
+    if rc not in (TKC_OK, TKC_ECANCELED):
         _check(rc)
     return rc, n_out.value, st
 
@@ -399,6 +419,66 @@ class Graph:
         return S[: src.size], R[: src.size]
 
 
+def tkc_pack_create(ctx, graph_handles):
+    arr = (ctypes.c_void_p * len(graph_handles))(*[h.value for h in graph_handles])
+    h = ctypes.c_void_p()
+    _check(lib.tkc_pack_create(ctx, arr, len(graph_handles), ctypes.byref(h)))
+    return h
+
+
+def tkc_pack_topk(p, members, ks, variant, ids, sum_dist, reach, farness, n_out):
+    st = tkc_stats()
+    _check(lib.tkc_pack_topk(p, len(members), _ptr(members), _ptr(ks), variant, _ptr(ids), _ptr(sum_dist),
+                             _ptr(reach), _ptr(farness), _ptr(n_out), ctypes.byref(st)))
+    return st
+
+
+def tkc_pack_free(p):
+    _check(lib.tkc_pack_free(p))
+
+
+class Pack:
+    """Several resident graphs whose top-k requests share one batched launch."""
+
+    def __init__(self, ctx: Context, graphs):
+        self.graphs = list(graphs)
+        self.h = tkc_pack_create(ctx.h, [g.h for g in self.graphs])
+
+    def topk(self, members, ks, variant="nbcut"):
+        """Requests (members[i], ks[i]) on distinct members: a list of (ids, S,
+        r, farness) per request, and the launch's stats."""
+        members = np.ascontiguousarray(members, dtype=np.int32)
+        ks = np.ascontiguousarray(ks, dtype=np.int32)
+        tot = int(sum(min(int(k), self.graphs[int(m)].n) for m, k in zip(members, ks)))
+        ids = np.zeros(max(1, tot), np.int32)
+        S = np.zeros(max(1, tot), np.int64)
+        R = np.zeros(max(1, tot), np.int64)
+        F = np.zeros(max(1, tot), np.float64)
+        n_out = np.zeros(len(members), np.int32)
+        st = tkc_pack_topk(self.h, members, ks, VARIANTS.get(variant, variant), ids, S, R, F, n_out)
+        out, o = [], 0
+        for c in n_out.tolist():
+            out.append((ids[o:o + c], S[o:o + c], R[o:o + c], F[o:o + c]))
+            o += c
+        return out, st.as_dict()
+
+    def close(self):
+        if self.h:
+            tkc_pack_free(self.h)
+            self.h = None
+
+
+def tkc_server_enable_packing(s, max_vertices):
+    _check(lib.tkc_server_enable_packing(s, int(max_vertices)))
+
+
+def tkc_server_info(s):
+    a, b, c2 = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    d = ctypes.c_int32(0)
+    _check(lib.tkc_server_info(s, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c2), ctypes.byref(d)))
+    return {"served": a.value, "packed": b.value, "pack_calls": c2.value, "packs": d.value}
+
+
 class Server:
     """Request server over resident graphs (continuous batching)."""
 
@@ -410,6 +490,14 @@ class Server:
         gid = tkc_server_add_graph(self.h, g.h)
         self.graphs.append(g)
         return gid
+
+    def enable_packing(self, max_vertices: int):
+        """Serve requests on graphs of at most max_vertices vertices in
+        packed launches (0 turns packing off)."""
+        tkc_server_enable_packing(self.h, max_vertices)
+
+    def info(self) -> dict:
+        return tkc_server_info(self.h)
 
     def submit(self, graph_id: int, k: int, variant="auto") -> int:
         return tkc_server_submit(self.h, int(graph_id), int(k), VARIANTS.get(variant, variant))
@@ -452,6 +540,21 @@ def topk_closeness(g: Graph, k: int, variant="auto", mode="hybrid"):
     n_out, st = tkc_topk_closeness(g.h, int(k), VARIANTS.get(variant, variant), MODES.get(mode, mode),
                                    ids, S, R, F)
     return ids[:n_out], S[:n_out], R[:n_out], F[:n_out], st.as_dict()
+
+
+def topk_closeness_budget(g: Graph, k: int, variant="auto", max_searches=1000):
+    """Plain mode with at most max_searches searches: (finished, result,
+    stats) where result is (ids, S, r, farness) when finished, else None."""
+    cap = max(1, min(int(k), g.n))
+    ids = np.zeros(cap, np.int32)
+    S = np.zeros(cap, np.int64)
+    R = np.zeros(cap, np.int64)
+    F = np.zeros(cap, np.float64)
+    rc, n_out, st = tkc_topk_closeness_budget(g.h, int(k), VARIANTS.get(variant, variant), int(max_searches),
+                                              ids, S, R, F)
+    if rc == TKC_OK:
+        return True, (ids[:n_out], S[:n_out], R[:n_out], F[:n_out]), st.as_dict()
+    return False, None, st.as_dict()
 
 
 def tkc_topk_harmonic(g, k, variant, mode, ids, harmonic):

@@ -200,3 +200,36 @@ def test_autotuned_graph_in_server(ctx):
             srv.close()
     finally:
         g.free()
+
+
+def test_packed_serving_equals_oracle(ctx, pool):
+    """With packing on, requests on the small graphs are served together in
+    packed launches; every answer still equals the oracle's, and requests
+    that cannot be packed (level-based variants, two on one graph at once)
+    are served alone."""
+    srv = tkc.Server(ctx, 8 * GIB, 2)
+    try:
+        gid = {name: srv.add(pool[name]) for name in POOL}
+        srv.enable_packing(10000)     # ba3k, rmat11, king40, gnp_d, forest (and not the rest)
+        info = srv.info()
+        assert info["packs"] == 2     # undirected and directed
+        rng = np.random.default_rng(3)
+        small = ["ba3k", "rmat11", "king40", "gnp_d", "forest"]
+        reqs = []
+        for _ in range(120):
+            name = small[int(rng.integers(len(small)))] if rng.random() < 0.85 else POOL[int(rng.integers(len(POOL)))]
+            reqs.append((name, int(rng.choice([1, 10, 100])), ("nbcut", "degcut", "auto", "nbbound")[int(rng.integers(4))]))
+        tickets = [srv.submit(gid[name], k, var) for name, k, var in reqs]
+        for (name, k, var), t in zip(reqs, tickets):
+            ids, S, r, f, lat = srv.result(t, k)
+            wids, wS, wr, wf = expect(name, k)
+            assert np.array_equal(ids, wids) and np.array_equal(S, wS) and np.array_equal(r, wr), (name, k, var)
+            assert np.array_equal(f, wf)
+        info = srv.info()
+        assert info["served"] == len(reqs)
+        assert info["packed"] >= 2 and info["pack_calls"] >= 1, info
+        with pytest.raises(tkc.TkcError) as e:   # a pack's members stay held
+            tkc.tkc_graph_free(pool["ba3k"].h)
+        assert e.value.code == tkc.TKC_EBUSY
+    finally:
+        srv.close()

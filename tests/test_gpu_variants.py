@@ -100,3 +100,25 @@ def test_reverse_is_a_no_op_when_undirected(ctx):
         assert np.array_equal(ids, wids) and np.array_equal(S, wS)
     finally:
         dg.free()
+
+
+@pytest.mark.parametrize("name", ["ba2k", "gnp_d", "rmat11", "grid60"])
+def test_budget_plain(ctx, name):
+    """tkc_topk_closeness_budget: a cap above the searches plain mode needs
+    gives its exact answer; a cap below stops with TKC_ECANCELED, no answer,
+    and counters of exactly that many searches."""
+    dg = upload(ctx, name)
+    want = expect(name, 10)
+    ids, S, r, f, st = tkc.topk_closeness(dg, 10, "nbcut", "plain")
+    assert np.array_equal(ids, want[0])
+    need = st["bfs_started"]
+    done, res, st2 = tkc.topk_closeness_budget(dg, 10, "nbcut", need + 5)
+    assert done and np.array_equal(res[0], want[0]) and np.array_equal(res[1], want[1])
+    assert st2["m_vis"] == st["m_vis"]
+    if need >= 2:
+        done, res, st3 = tkc.topk_closeness_budget(dg, 10, "nbcut", 1)
+        assert not done and res is None
+        assert st3["m_vis"] > 0
+        # the answer of a later full query is unaffected
+        ids4, S4, _, _, _ = tkc.topk_closeness(dg, 10, "nbcut", "plain")
+        assert np.array_equal(ids4, want[0]) and np.array_equal(S4, want[1])
