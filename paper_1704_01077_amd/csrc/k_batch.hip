@@ -878,8 +878,45 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 // independent index loads, then four independent frontier
                 // loads), until every missing active lane is found
                 PHASE(1);
+                // the next pass's frontier and visited words and row
+                // pointers are loaded before this pass's dependent loads, so
+                // they arrive while this pass waits for its own (only this
+                // wave folds these vertices' visited words, and F_D does not
+                // change during the level)
+                uint64_t pf_f[NW], pf_v[NW];
+                int32_t pf_b = 0, pf_e = 0;
+                {
+                    const int64_t w0 = gwave * 64 + lane;
+#pragma unroll
+                    for (int j = 0; j < NW; j++) { pf_f[j] = 0; pf_v[j] = 0; }
+                    if (w0 < n) {
+#pragma unroll
+                        for (int j = 0; j < NW; j++) {
+                            pf_f[j] = Fc[w0 * NW + j];
+                            pf_v[j] = vis[w0 * NW + j];
+                        }
+                        pf_b = a.g.rrp[w0];
+                        pf_e = a.g.rrp[w0 + 1];
+                    }
+                }
                 for (int64_t base = gwave * 64; base < n; base += nwaves * 64) {
                     const int32_t w = (int32_t)(base + lane);
+                    uint64_t cur_f[NW], cur_v[NW];
+#pragma unroll
+                    for (int j = 0; j < NW; j++) { cur_f[j] = pf_f[j]; cur_v[j] = pf_v[j]; }
+                    const int32_t cur_b = pf_b, cur_e = pf_e;
+                    {
+                        const int64_t w2 = base + nwaves * 64 + lane;
+                        if (w2 < n) {
+#pragma unroll
+                            for (int j = 0; j < NW; j++) {
+                                pf_f[j] = Fc[w2 * NW + j];
+                                pf_v[j] = vis[w2 * NW + j];
+                            }
+                            pf_b = a.g.rrp[w2];
+                            pf_e = a.g.rrp[w2 + 1];
+                        }
+                    }
                     bool isnew = false;
                     int32_t dw = 0;
                     Mask<NW> acc, miss;
@@ -891,8 +928,8 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                         bool inF = false;
 #pragma unroll
                         for (int j = 0; j < NW; j++) {
-                            const uint64_t fw = Fc[(int64_t)w * NW + j];
-                            vn[j] = vis[(int64_t)w * NW + j] | fw;
+                            const uint64_t fw = cur_f[j];
+                            vn[j] = cur_v[j] | fw;
                             inF |= fw != 0;
                             miss.w[j] = act.w[j] & ~vn[j];
                         }
@@ -901,8 +938,8 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                             for (int j = 0; j < NW; j++) vis[(int64_t)w * NW + j] = vn[j];
                             if (!miss.any()) my_dd += deg[w];
                         }
-                        eb = a.g.rrp[w];
-                        const int32_t d_in = a.g.rrp[w + 1] - eb;
+                        eb = cur_b;
+                        const int32_t d_in = cur_e - eb;
                         if (d_in <= HEAVY_DEG && miss.any()) len = d_in;
                     }
                     int32_t* c_pre = &s_cpre[tid >> 6][0];
