@@ -402,6 +402,8 @@ def main():
     ap.add_argument("--compare", default="plain,batched,hybrid",
                     help="modes timed once each (default knobs) beside the main run")
     ap.add_argument("--no-compare", action="store_true", help="skip the comparison runs")
+    ap.add_argument("--tune", nargs="*", default=[],
+                    help="context knobs for the main run, e.g. batch_width=128 blocks_per_cu=4")
     ap.add_argument("--plain-cap", type=int, default=20000,
                     help="search cap of every plain-mode comparison (never an uncapped plain run)")
     ap.add_argument("--configs", default="C1,C3,C4", help="other workloads measured into the same line")
@@ -476,7 +478,11 @@ def main():
         print("bench: autotune (budget %.0f ms)" % args.autotune_ms, file=sys.stderr, flush=True)
         tuning, tuned_ms = dg.autotune(args.k, args.variant, args.autotune_ms)
         print("bench: autotuned %s (%.3f ms)" % (tuning, tuned_ms), file=sys.stderr, flush=True)
-    m = measure(tkc, torch, ctx, g, dg, args.workload, args.k, args.variant, args.mode, args.steps, args.warmup)
+    knobs = dict((kv.split("=")[0], int(kv.split("=")[1])) for kv in args.tune) or None
+    if knobs:
+        tuning = knobs
+    m = measure(tkc, torch, ctx, g, dg, args.workload, args.k, args.variant, args.mode, args.steps, args.warmup,
+                knobs)
     st = m.pop("_stats")
 
     compare = {}

@@ -37,3 +37,26 @@ def test_stored_traffic_records_are_well_formed():
             assert len(rec["source_hash"]) == 16
             assert rec["bytes_per_launch"] == int(rec["fetch_size_bytes"] + rec["write_size_bytes"])
             assert len(rec["fetch_size_kib"]) == len(rec["write_size_kib"]) > 0
+
+
+def test_traffic_records_apply_only_to_their_key(tmp_path, monkeypatch):
+    """A stored counter record is used only for the same kernel, workload,
+    k, mode and batch width, and only while the kernel's sources hash to
+    the value stored with it."""
+    sys.path.insert(0, ROOT)
+    import bench
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    key = bench.traffic_key("k_batch", 10, "hybrid", 64)
+    rec = {"source_hash": bench.kernel_source_hash("k_batch"), "bytes_per_launch": 1234,
+           "k": 10, "mode": "hybrid", "batch_width": 64}
+    (prof / "traffic.json").write_text(json.dumps({"ba1m": {key: rec}}))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda k: rec["source_hash"])
+    assert bench.load_traffic("k_batch", "ba1m", 10, "hybrid", 64) == 1234
+    assert bench.load_traffic("k_batch", "ba1m", 100, "hybrid", 64) is None
+    assert bench.load_traffic("k_batch", "ba1m", 10, "batched", 64) is None
+    assert bench.load_traffic("k_batch", "ba1m", 10, "hybrid", 128) is None
+    assert bench.load_traffic("k_batch", "rmat20", 10, "hybrid", 64) is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda k: "0" * 16)
+    assert bench.load_traffic("k_batch", "ba1m", 10, "hybrid", 64) is None
