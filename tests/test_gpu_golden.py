@@ -150,7 +150,7 @@ def test_medium_harmonic(ctx, name, variant):
 
 
 # full size, in the configurations bench.py times: BA 2^20 in hybrid mode
-# with the default knobs, R-MAT scale 20 batched at W = 128 and four
+# with the default knobs, R-MAT scale 20 batched at W = 256 and four
 # workgroups per CU
 @pytest.mark.parametrize("k", [1, 10, 100])
 def test_full_ba1m_exact(ctx, k):
@@ -164,7 +164,7 @@ def test_full_rmat20_exact(ctx, k):
     dg = dev(ctx, "rmat20")
     keep = ctx.tuning()
     try:
-        ctx.tune(batch_width=128, blocks_per_cu=4)
+        ctx.tune(batch_width=256, blocks_per_cu=4)
         ids, S, r, f, _ = tkc.topk_closeness(dg, k, "auto", "batched")
         check("rmat20", k, ids, S, r, f)
     finally:
