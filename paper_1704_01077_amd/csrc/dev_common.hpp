@@ -114,17 +114,86 @@ static inline size_t tkc_bar_words(uint32_t nblocks) { return (size_t)(nblocks +
 // ------------------------------------------------------------ wave helpers
 TKC_DEV int lane_id() { return (int)__lane_id(); }
 
+// Wave reductions.  With every lane of the wave active they run on DPP
+// moves inside each row of 16 lanes (quad permutations, then the half-row
+// and row mirrors), join the four rows with the row broadcasts of lanes 15
+// and 31, and read the total from lane 63: VALU work, no trip through the
+// LDS crossbar.  In divergent code they fall back to butterfly shuffles.
+#define TKC_DPP_XOR1 0xB1        // quad_perm [1,0,3,2]
+#define TKC_DPP_XOR2 0x4E        // quad_perm [2,3,0,1]
+#define TKC_DPP_QREV 0x1B        // quad_perm [3,2,1,0]
+#define TKC_DPP_HMIRROR 0x141    // lane i of each 8 reads lane 7 - i
+#define TKC_DPP_MIRROR 0x140     // lane i of each row reads lane 15 - i
+#define TKC_DPP_ROR8 0x128       // lane i of each row reads lane i ^ 8
+#define TKC_DPP_BCAST15 0x142    // lane 15 of each row into the next row
+#define TKC_DPP_BCAST31 0x143    // lane 31 into rows 2 and 3
+TKC_DEV bool wave_full() { return __builtin_amdgcn_read_exec() == ~0ull; }
+template <int CTRL>
+TKC_DEV uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+// the value of lane 15 (rows 1, 3) or 31 (rows 2, 3); `idv` elsewhere
+template <int CTRL, int ROWS>
+TKC_DEV uint32_t dpp_bcast_u32(uint32_t idv, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)idv, (int)v, CTRL, ROWS, 0xF, false);
+}
+TKC_DEV uint32_t readlane63(uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, 63); }
+
 TKC_DEV int64_t wave_sum_i64(int64_t v) {
+    if (wave_full()) {
+        uint64_t x = (uint64_t)v;
+#define TKC_STEP64(MOVE)                                                              \
+        {                                                                             \
+            const uint64_t y = (uint64_t)MOVE((uint32_t)x) | ((uint64_t)MOVE((uint32_t)(x >> 32)) << 32); \
+            x += y;                                                                   \
+        }
+        TKC_STEP64(dpp_u32<TKC_DPP_XOR1>)
+        TKC_STEP64(dpp_u32<TKC_DPP_XOR2>)
+        TKC_STEP64(dpp_u32<TKC_DPP_HMIRROR>)
+        TKC_STEP64(dpp_u32<TKC_DPP_MIRROR>)
+#undef TKC_STEP64
+        {
+            const uint64_t y = (uint64_t)dpp_bcast_u32<TKC_DPP_BCAST15, 0xA>(0u, (uint32_t)x) |
+                               ((uint64_t)dpp_bcast_u32<TKC_DPP_BCAST15, 0xA>(0u, (uint32_t)(x >> 32)) << 32);
+            x += y;
+        }
+        {
+            const uint64_t y = (uint64_t)dpp_bcast_u32<TKC_DPP_BCAST31, 0xC>(0u, (uint32_t)x) |
+                               ((uint64_t)dpp_bcast_u32<TKC_DPP_BCAST31, 0xC>(0u, (uint32_t)(x >> 32)) << 32);
+            x += y;
+        }
+        return (int64_t)((uint64_t)readlane63((uint32_t)x) | ((uint64_t)readlane63((uint32_t)(x >> 32)) << 32));
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 TKC_DEV int32_t wave_sum_i32(int32_t v) {
+    if (wave_full()) {
+        uint32_t x = (uint32_t)v;
+        x += dpp_u32<TKC_DPP_XOR1>(x);
+        x += dpp_u32<TKC_DPP_XOR2>(x);
+        x += dpp_u32<TKC_DPP_HMIRROR>(x);
+        x += dpp_u32<TKC_DPP_MIRROR>(x);
+        x += dpp_bcast_u32<TKC_DPP_BCAST15, 0xA>(0u, x);
+        x += dpp_bcast_u32<TKC_DPP_BCAST31, 0xC>(0u, x);
+        return (int32_t)readlane63(x);
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 TKC_DEV int32_t wave_max_i32(int32_t v) {
+    if (wave_full()) {
+        int32_t x = v, y;
+        y = (int32_t)dpp_u32<TKC_DPP_XOR1>((uint32_t)x); x = y > x ? y : x;
+        y = (int32_t)dpp_u32<TKC_DPP_XOR2>((uint32_t)x); x = y > x ? y : x;
+        y = (int32_t)dpp_u32<TKC_DPP_HMIRROR>((uint32_t)x); x = y > x ? y : x;
+        y = (int32_t)dpp_u32<TKC_DPP_MIRROR>((uint32_t)x); x = y > x ? y : x;
+        y = (int32_t)dpp_bcast_u32<TKC_DPP_BCAST15, 0xA>(0x80000000u, (uint32_t)x); x = y > x ? y : x;
+        y = (int32_t)dpp_bcast_u32<TKC_DPP_BCAST31, 0xC>(0x80000000u, (uint32_t)x); x = y > x ? y : x;
+        return (int32_t)readlane63((uint32_t)x);
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         int32_t y = __shfl_xor(v, o, 64);
@@ -133,9 +202,68 @@ TKC_DEV int32_t wave_max_i32(int32_t v) {
     return v;
 }
 TKC_DEV uint64_t wave_or_u64(uint64_t v) {
+    if (wave_full()) {
+        uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+        lo |= dpp_u32<TKC_DPP_XOR1>(lo);    hi |= dpp_u32<TKC_DPP_XOR1>(hi);
+        lo |= dpp_u32<TKC_DPP_XOR2>(lo);    hi |= dpp_u32<TKC_DPP_XOR2>(hi);
+        lo |= dpp_u32<TKC_DPP_HMIRROR>(lo); hi |= dpp_u32<TKC_DPP_HMIRROR>(hi);
+        lo |= dpp_u32<TKC_DPP_MIRROR>(lo);  hi |= dpp_u32<TKC_DPP_MIRROR>(hi);
+        lo |= dpp_bcast_u32<TKC_DPP_BCAST15, 0xA>(0u, lo); hi |= dpp_bcast_u32<TKC_DPP_BCAST15, 0xA>(0u, hi);
+        lo |= dpp_bcast_u32<TKC_DPP_BCAST31, 0xC>(0u, lo); hi |= dpp_bcast_u32<TKC_DPP_BCAST31, 0xC>(0u, hi);
+        return (uint64_t)readlane63(lo) | ((uint64_t)readlane63(hi) << 32);
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
     return v;
+}
+// 64 x 64 bit-matrix transpose across the wave, called by all 64 lanes: on
+// entry lane r holds row r, on return lane c holds column c (bit r of the
+// result is bit c of row r).  Stage s exchanges, between lanes r and r ^ s,
+// the bits whose column index differs from the row index in bit s; the six
+// stages commute.  Stages 32 and 16 cross rows of 16 lanes and take one
+// 32-bit shuffle each (a lane sends exactly the half of its bits the
+// partner keeps); stages 8, 4, 2 and 1 use DPP moves.
+TKC_DEV uint64_t wave_transpose64(uint64_t x) {
+    const uint32_t lane = (uint32_t)lane_id();
+    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    {   // s = 32: columns 32-63 of rows 0-31 trade with columns 0-31 of rows 32-63
+        const bool up = lane & 32u;
+        const uint32_t got = (uint32_t)__shfl_xor((int)(up ? lo : hi), 32, 64);
+        if (up) lo = got; else hi = got;
+    }
+    {   // s = 16, in both 32-bit halves at once: a lower lane keeps the low
+        // 16 bits of each half and takes the partner's low 16 bits into its
+        // high 16; an upper lane the other way round
+        const bool up = lane & 16u;
+        const uint32_t send = up ? ((lo & 0xFFFFu) | (hi << 16)) : ((lo >> 16) | (hi & 0xFFFF0000u));
+        const uint32_t got = (uint32_t)__shfl_xor((int)send, 16, 64);
+        if (up) {
+            lo = (lo & 0xFFFF0000u) | (got & 0xFFFFu);
+            hi = (hi & 0xFFFF0000u) | (got >> 16);
+        } else {
+            lo = (lo & 0xFFFFu) | (got << 16);
+            hi = (hi & 0xFFFFu) | (got & 0xFFFF0000u);
+        }
+    }
+#define TKC_TSTAGE(S, M, YLO, YHI)                                                 \
+    {                                                                              \
+        const uint32_t ylo = YLO, yhi = YHI;                                       \
+        if (lane & (S)) {                                                          \
+            lo = (lo & ~(M)) | ((ylo >> (S)) & (M));                               \
+            hi = (hi & ~(M)) | ((yhi >> (S)) & (M));                               \
+        } else {                                                                   \
+            lo = (lo & (M)) | ((ylo << (S)) & ~(M));                               \
+            hi = (hi & (M)) | ((yhi << (S)) & ~(M));                               \
+        }                                                                          \
+    }
+    TKC_TSTAGE(8u, 0x00FF00FFu, dpp_u32<TKC_DPP_ROR8>(lo), dpp_u32<TKC_DPP_ROR8>(hi))
+    // lane i ^ 4: the half-row mirror (7 - i) after the quad reversal (3 - i)
+    TKC_TSTAGE(4u, 0x0F0F0F0Fu, dpp_u32<TKC_DPP_HMIRROR>(dpp_u32<TKC_DPP_QREV>(lo)),
+               dpp_u32<TKC_DPP_HMIRROR>(dpp_u32<TKC_DPP_QREV>(hi)))
+    TKC_TSTAGE(2u, 0x33333333u, dpp_u32<TKC_DPP_XOR2>(lo), dpp_u32<TKC_DPP_XOR2>(hi))
+    TKC_TSTAGE(1u, 0x55555555u, dpp_u32<TKC_DPP_XOR1>(lo), dpp_u32<TKC_DPP_XOR1>(hi))
+#undef TKC_TSTAGE
+    return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 // exclusive prefix of a 0/1 predicate within the wave, plus the wave total
 TKC_DEV int wave_rank(bool pred, int* total) {

@@ -185,40 +185,48 @@ TKC_DEV void tally_bits(const Mask<NW>& nb, int32_t dw, int32_t* cnt, int64_t* d
         }
     }
 }
-// Dense masks (pull, one vertex per lane): the wave transposes its bit
-// matrix lane by lane; called by all 64 lanes.
+// Dense masks (pull, one vertex per lane), called by all 64 lanes: the
+// wave transposes each word's 64 x 64 bit matrix, so lane l holds the
+// vertices that search lane j * 64 + l reached; their count is a popcount
+// and their out-degree sum is taken bit slice by bit slice of the degrees
+// (one ballot per slice).  One LDS add per lane and word.
 template <int NW>
-TKC_DEV void tally_wave(const Mask<NW>& nb, int32_t dw, int32_t* cnt, int64_t* dsum) {
+TKC_DEV void tally_dense(const Mask<NW>& nb, int32_t dw, int32_t* cnt, int64_t* dsum) {
+    const int lane = lane_id();
+    uint64_t col[NW];
+    int64_t ds[NW];
 #pragma unroll
     for (int j = 0; j < NW; j++) {
-        uint64_t here = wave_or_u64(nb.w[j]);
-        while (here) {
-            int l = __ffsll((long long)here) - 1;
-            here &= here - 1;
-            const bool has = (nb.w[j] >> l) & 1ull;
-            const int c = __popcll(__ballot(has));
-            const int64_t d = wave_sum_i64(has ? (int64_t)dw : 0);
-            if (lane_id() == 0) {
-                atomicAdd(&cnt[j * 64 + l], c);
-                atomicAdd((unsigned long long*)&dsum[j * 64 + l], (unsigned long long)d);
-            }
+        col[j] = __ballot(nb.w[j] != 0) ? wave_transpose64(nb.w[j]) : 0;
+        ds[j] = 0;
+    }
+    const uint32_t d = (uint32_t)dw;
+    for (int b = 0; b < 32; b++) {
+        const uint64_t slice = __ballot((d >> b) & 1u);
+        if (!__ballot((d >> b) != 0u)) break;   // wave-uniform
+#pragma unroll
+        for (int j = 0; j < NW; j++) ds[j] += (int64_t)__popcll(col[j] & slice) << b;
+    }
+#pragma unroll
+    for (int j = 0; j < NW; j++) {
+        const int c = __popcll(col[j]);
+        if (c) {
+            atomicAdd(&cnt[j * 64 + lane], c);
+            atomicAdd((unsigned long long*)&dsum[j * 64 + lane], (unsigned long long)ds[j]);
         }
     }
 }
-// Called by all 64 lanes: the wave picks the cheaper way.  Many vertices
-// per distinct lane (dense bit matrix) -> transposition; few -> each thread
-// adds its own bits; no new bits -> nothing.
+// Called by all 64 lanes: the wave picks the cheaper way from two ballots.
+// No new bits -> nothing; a lane with more than four new bits -> the
+// transposition (fixed cost); otherwise each thread adds its own bits (at
+// most four LDS adds per thread and counter kind).
 template <int NW>
 TKC_DEV void tally(const Mask<NW>& nb, int32_t dw, int32_t* cnt, int64_t* dsum) {
-    int32_t lanes = 0, bits = 0;
+    int32_t bits = 0;
 #pragma unroll
-    for (int j = 0; j < NW; j++) {
-        lanes += __popcll(wave_or_u64(nb.w[j]));
-        bits += __popcll(nb.w[j]);
-    }
-    if (lanes == 0) return;   // wave-uniform
-    bits = wave_sum_i32(bits);
-    if (lanes * 8 <= bits) tally_wave<NW>(nb, dw, cnt, dsum);
+    for (int j = 0; j < NW; j++) bits += __popcll(nb.w[j]);
+    if (!__ballot(bits != 0)) return;   // wave-uniform
+    if (__ballot(bits > 4)) tally_dense<NW>(nb, dw, cnt, dsum);
     else tally_bits<NW>(nb, dw, cnt, dsum);
 }
 
