@@ -201,6 +201,14 @@ TKC_DEV int32_t wave_max_i32(int32_t v) {
     }
     return v;
 }
+TKC_DEV int64_t wave_max_i64(int64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t y = __shfl_xor(v, o, 64);
+        v = y > v ? y : v;
+    }
+    return v;
+}
 TKC_DEV uint64_t wave_or_u64(uint64_t v) {
     if (wave_full()) {
         uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);

@@ -48,6 +48,7 @@
 #define C_NSEL (C_BASE + 24)
 #define C_POS (C_BASE + 25)
 #define C_STOP (C_BASE + 26)
+#define C_XDONE (C_BASE + 27)   // until_x: x became finite in this batch
 #define C_TOTAL (C_BASE + 32)
 
 struct BatchArgs {
@@ -993,8 +994,12 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 }
                 PHASE(2);
                 // pull, mid in-degree vertices: packed segments of about
-                // MID_ARCS in-arcs, one wave each, edge-balanced
-                for (int64_t sg = gwave; sg < a.g.nmseg; sg += nwaves) {
+                // MID_ARCS in-arcs, one wave each, edge-balanced.  Segments,
+                // then hub chunks, are dealt from the last wave down: low
+                // vertex ids tend to have high degrees (preferential
+                // attachment, R-MAT), so the first waves' light blocks are
+                // the heaviest ones
+                for (int64_t sg = nwaves - 1 - gwave; sg < a.g.nmseg; sg += nwaves) {
                     const int32_t v0 = a.g.mseg[sg], v1 = a.g.mseg[sg + 1];
                     const int32_t idx = v0 + lane;
                     int32_t w = 0, eb = 0, len = 0;
@@ -1026,8 +1031,10 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                     if (isnew) my_ud += dw;
                     list_append(isnew, w, dw, nl, stg);
                 }
-                // pull, hubs: one wave per chunk of their in-arcs
-                for (int64_t c = gwave; c < a.g.bnchunks; c += nwaves) {
+                // pull, hubs: one wave per chunk of their in-arcs; chunk c
+                // goes to wave nwaves - 1 - (nmseg + c) mod nwaves
+                for (int64_t c = ((nwaves - 1 - gwave - a.g.nmseg) % nwaves + nwaves) % nwaves; c < a.g.bnchunks;
+                     c += nwaves) {
                     const int32_t w = a.g.bch_vtx[c];
                     Mask<NW> miss, acc;
 #pragma unroll
@@ -1161,28 +1168,97 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             if (tid == 0 && s_blk[0]) fadd_rlx(&stats[ST_BYTES], s_blk[0] * (int64_t)(4 + 8 * NW));
         }
         // ----------------------------------------------------- batch results
-        if (boss) {
-            int64_t ex = 0, cu = 0, md = stats[ST_MAXLEVEL];
-            for (int l = 0; l < nsel; l++) {
-                if (s_maxD[l] > md) md = s_maxD[l];
+        // The exact lanes' results go into their request's top k (Alg. 1).
+        // Only the k best of a request's results in this batch can be among
+        // its k best overall, so wave 0 of workgroup 0 ranks them per
+        // request (by farness, then id, then lane), and one thread inserts
+        // the ranks below k best first: an entry that no entry before it
+        // follows is placed after one comparison.  In all-ties mode every
+        // exact result goes in, in lane order, so the tie buffer sees what
+        // the top k refuses.  (The pull's per-wave LDS scratch is free here.)
+        if (blockIdx.x == 0 && tid < 64) {
+            int32_t* r_rank = &s_cpre[0][0];
+            int32_t* r_id = &s_cbeg[0][0];
+            int64_t* r_num = (int64_t*)&s_cmiss[0][0];
+            int64_t* r_den = (int64_t*)&s_cacc[0][0];
+            int64_t ex = 0, cu = 0, md = 0;
+            for (int l = lane; l < nsel; l += 64) {
+                md = s_maxD[l] > md ? s_maxD[l] : md;
+                r_rank[l] = -1;
                 if (s_st[l] == 2) {
                     ex++;
-                    const DevTopk& tk = a.npreq ? a.preq[s_req[l]].tk : a.tk;
-                    const int32_t id = s_v[l] - s_off[l];
-                    if (a.no_cut) {
-                    } else if (a.bv.harm) {
-                        topk_insert(tk.st, tk.ring, tk.S, tk.R, tk.I, harm_enc(s_H[l]), 2, id);
+                    r_id[l] = s_v[l] - s_off[l];
+                    if (a.bv.harm) {
+                        r_num[l] = harm_enc(s_H[l]);
+                        r_den[l] = 1;
                     } else {
-                        topk_insert(tk.st, tk.ring, tk.S, tk.R, tk.I, s_SD[l], s_nD[l], id);
+                        r_num[l] = s_SD[l];
+                        r_den[l] = s_nD[l] <= 1 ? 0 : sq64(s_nD[l] - 1);
                     }
-                } else if (s_st[l] == 3) cu++;
+                } else if (s_st[l] == 3) {
+                    cu++;
+                }
             }
-            stats[ST_STARTED] += nsel;
-            stats[ST_EXACT] += ex;
-            stats[ST_CUT] += cu;
-            stats[ST_MVIS] += mvis;
-            fadd_rlx(&stats[ST_BYTES], bytes);
-            stats[ST_MAXLEVEL] = md;
+            ex = wave_sum_i64(ex);
+            cu = wave_sum_i64(cu);
+            md = wave_max_i64(md);
+            __builtin_amdgcn_wave_barrier();
+            if (ex > 0 && !a.no_cut) {
+                for (int l = lane; l < nsel; l += 64) {
+                    if (s_st[l] != 2) continue;
+                    const DevTopk& tk = a.npreq ? a.preq[s_req[l]].tk : a.tk;
+                    if (ld_rlx(&tk.st->ties)) {
+                        r_rank[l] = -2;
+                        continue;
+                    }
+                    int32_t rk = 0;
+                    for (int q = 0; q < nsel; q++) {
+                        if (q == l || s_st[q] != 2 || s_req[q] != s_req[l]) continue;
+                        if (lex_after(r_num[l], r_den[l], r_id[l], r_num[q], r_den[q], r_id[q]) ||
+                            (q < l && !lex_after(r_num[q], r_den[q], r_id[q], r_num[l], r_den[l], r_id[l])))
+                            rk++;
+                    }
+                    r_rank[l] = rk < ld_rlx(&tk.st->k) ? rk : -1;
+                }
+                __builtin_amdgcn_wave_barrier();
+                // insertion order: by rank, then lane (each request's own
+                // entries arrive in rank order)
+                int32_t* r_ord = &s_stage[0][0];
+                int32_t nins = 0;
+                for (int l = lane; l < nsel; l += 64) {
+                    if (r_rank[l] < 0) continue;
+                    int32_t g = 0;
+                    for (int q = 0; q < nsel; q++)
+                        g += r_rank[q] >= 0 && (r_rank[q] < r_rank[l] || (r_rank[q] == r_rank[l] && q < l));
+                    r_ord[g] = l;
+                    nins++;
+                }
+                nins = wave_sum_i32(nins);
+                __builtin_amdgcn_wave_barrier();
+                if (lane == 0) {
+                    for (int32_t g = 0; g < nins; g++) {
+                        const int l = r_ord[g];
+                        const DevTopk& tk = a.npreq ? a.preq[s_req[l]].tk : a.tk;
+                        topk_insert(tk.st, tk.ring, tk.S, tk.R, tk.I, r_num[l], a.bv.harm ? 2 : s_nD[l], r_id[l]);
+                    }
+                    // all-ties mode: every exact result, in lane order
+                    for (int l = 0; l < nsel; l++) {
+                        if (r_rank[l] != -2) continue;
+                        const DevTopk& tk = a.npreq ? a.preq[s_req[l]].tk : a.tk;
+                        topk_insert(tk.st, tk.ring, tk.S, tk.R, tk.I, r_num[l], a.bv.harm ? 2 : s_nD[l], r_id[l]);
+                    }
+                }
+            }
+            if (lane == 0) {
+                // the until_x decision, taken once so every workgroup makes it alike
+                if (a.until_x) ctr[C_XDONE] = ld_acq(&a.tk.st->seq) >= 0 ? 1 : 0;
+                fadd_rlx(&stats[ST_STARTED], (int64_t)nsel);
+                fadd_rlx(&stats[ST_EXACT], ex);
+                fadd_rlx(&stats[ST_CUT], cu);
+                fadd_rlx(&stats[ST_MVIS], mvis);
+                fadd_rlx(&stats[ST_BYTES], bytes);
+                __hip_atomic_fetch_max(&stats[ST_MAXLEVEL], md, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
         if (a.no_cut && blockIdx.x == 0 && tid < nsel) {
             a.out_S[pos - nsel + tid] = s_SD[tid];
@@ -1281,8 +1357,12 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                 }
             }
         }
-        grid_barrier(a.bar, gridDim.x);
-        // clear the batch's words for the next batch
+        // Clear the batch's words for the next batch.  Nothing reads them
+        // after the last level's barrier except the level-based update, so
+        // only that (and the until_x decision) needs a barrier first; the
+        // next batch's selection barrier orders the clear before its level 0
+        // (and the kernel's end before the host reads anything)
+        if (a.lb_mode || a.until_x) grid_barrier(a.bar, gridDim.x);
         {
             int64_t tot = (int64_t)n * NW;
             for (int64_t q = gtid; q < tot; q += nthreads) {
@@ -1294,10 +1374,9 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             if (NW > 1)
                 for (int64_t q = gtid; q < n; q += nthreads) a.mark[q] = 0;
         }
-        grid_barrier(a.bar, gridDim.x);
         batches++;
         if (stop_now) break;
-        if (a.until_x && ld_acq(&a.tk.st->seq) >= 0) break;
+        if (a.until_x && ld_rlx(&ctr[C_XDONE]) != 0) break;
     }
     if (boss) stats[ST_CURSOR] = pos;
 }

@@ -51,14 +51,6 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
     }
     return v;
 }
-__device__ __forceinline__ int64_t wave_max_i64(int64_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const int64_t y = __shfl_xor(v, o, 64);
-        v = y > v ? y : v;
-    }
-    return v;
-}
 
 // Reductions and appends to one global address are aggregated per block
 // (grid-strided over at most RB blocks): same-address atomics serialise,
