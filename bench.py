@@ -53,20 +53,21 @@ def kernel_source_hash(kernel: str) -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_key(kernel: str, k: int, mode: str, width: int) -> str:
-    return "%s k=%d %s W=%d" % (kernel, k, mode, width)
+def traffic_key(kernel: str, k: int, mode: str, width: int, relabel: bool = False) -> str:
+    return "%s k=%d %s W=%d%s" % (kernel, k, mode, width, " relabelled" if relabel else "")
 
 
-def load_traffic(kernel: str, workload: str, k: int, mode: str, width: int):
+def load_traffic(kernel: str, workload: str, k: int, mode: str, width: int, relabel: bool = False):
     """HBM bytes per launch from the committed rocprofv3 counter summary of
-    this kernel, workload, k, mode and batch width; null when there is none
-    or the kernel's sources changed since the counters were taken."""
+    this kernel, workload, k, mode, batch width and vertex order; null when
+    there is none or the kernel's sources changed since the counters were
+    taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         d = json.load(open(path))
-        rec = d.get(workload, {}).get(traffic_key(kernel, k, mode, width))
+        rec = d.get(workload, {}).get(traffic_key(kernel, k, mode, width, relabel))
         if not rec or rec.get("source_hash") != kernel_source_hash(kernel):
             return None
         return rec.get("bytes_per_launch")
@@ -114,7 +115,7 @@ def stats_table(d: str) -> str:
 
 
 def traffic_from(fetch_dir: str, write_dir: str, workload: str, kernel: str, last: int, copy_bytes: int,
-                 k: int, mode: str, width: int):
+                 k: int, mode: str, width: int, relabel: bool = False):
     """HBM bytes per launch of `kernel` from two rocprofv3 --pmc runs
     (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled so that the
     largest copy dispatch (a device copy of copy_bytes) reads and writes
@@ -140,7 +141,7 @@ def traffic_from(fetch_dir: str, write_dir: str, workload: str, kernel: str, las
             vals[key] = vals.get(key, 0.0) + float(value)
         return sorted(vals.items(), key=lambda kv: kv[0][0])
     rec = {"source_hash": kernel_source_hash(kernel), "copy_bytes": copy_bytes, "k": k, "mode": mode,
-           "batch_width": width}
+           "batch_width": width, "relabel": bool(relabel)}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         disp = per_dispatch(d, counter)
         copies = [v for (i, name), v in disp if "copy" in name.lower()]
@@ -155,7 +156,7 @@ def traffic_from(fetch_dir: str, write_dir: str, workload: str, kernel: str, las
     rec["bytes_per_launch"] = int(rec["fetch_size_bytes"] + rec["write_size_bytes"])
     path = os.path.join(ROOT, "profiles", "traffic.json")
     d = json.load(open(path)) if os.path.exists(path) else {}
-    d.setdefault(workload, {})[traffic_key(kernel, k, mode, width)] = rec
+    d.setdefault(workload, {})[traffic_key(kernel, k, mode, width, relabel)] = rec
     json.dump(d, open(path, "w"), indent=1, sort_keys=True)
     return rec
 
@@ -431,6 +432,8 @@ def main():
     ap.add_argument("--traffic-kernel", default="k_batch")
     ap.add_argument("--traffic-last", type=int, default=3)
     ap.add_argument("--traffic-width", type=int, default=64, help="batch width of the profiled runs")
+    ap.add_argument("--relabel", action="store_true",
+                    help="upload the main line's graph with TKC_RELABEL (vertices by decreasing out-degree)")
     args = ap.parse_args()
     if args.stats_from:
         print(stats_table(args.stats_from))
@@ -438,7 +441,7 @@ def main():
     if args.traffic_from:
         fd, wd = args.traffic_from.split(",")
         rec = traffic_from(fd, wd, args.workload, args.traffic_kernel, args.traffic_last,
-                           args.calib_copy_mb << 20, args.k, args.mode, args.traffic_width)
+                           args.calib_copy_mb << 20, args.k, args.mode, args.traffic_width, args.relabel)
         print(json.dumps(rec, indent=1))
         return
     if args.gpus != 1:
@@ -464,7 +467,7 @@ def main():
     print("bench: generating %s" % args.workload, file=sys.stderr, flush=True)
     g = graphgen.workload(args.workload)
     ctx = tkc.Context(0)
-    dg = tkc.Graph.from_graphgen(ctx, g)
+    dg = tkc.Graph.from_graphgen(ctx, g, relabel=args.relabel)
     torch.cuda.synchronize()
 
     if args.calib_copy_mb:
@@ -482,7 +485,7 @@ def main():
     if knobs:
         tuning = knobs
     m = measure(tkc, torch, ctx, g, dg, args.workload, args.k, args.variant, args.mode, args.steps, args.warmup,
-                knobs)
+                knobs, args.relabel)
     st = m.pop("_stats")
 
     compare = {}
@@ -524,7 +527,8 @@ def main():
         "config": {"workload": "%s, top-k k=%d" % (WORKLOADS.get(args.workload, args.workload), args.k),
                    "k": args.k, "variant": args.variant, "variant_used": st["variant_used"],
                    "mode": args.mode, "mode_used": MODE_NAMES.get(st["mode_used"], st["mode_used"]),
-                   "batch_width": st["batch_width"], "tuning": tuning, "n": g.n, "arcs": int(g.arcs)},
+                   "batch_width": st["batch_width"], "tuning": tuning, "relabel": bool(args.relabel), "n": g.n,
+                   "arcs": int(g.arcs)},
         "wall_ms_p50": m["wall_ms_p50"],
         "wall_ms_p99": m["wall_ms_p99"],
         "m_vis": m["m_vis"],
@@ -545,7 +549,7 @@ def main():
     ctx.close()
 
 
-def measure(tkc, torch, ctx, g, dg, wname, k, variant, mode, steps, warmup, tune=None):
+def measure(tkc, torch, ctx, g, dg, wname, k, variant, mode, steps, warmup, tune=None, relabel=False):
     """warmup untimed queries, then `steps` timed ones (each between device
     synchronisations); GTEPS, percentiles, phases and the dominant kernel's
     roofline."""
@@ -582,7 +586,7 @@ def measure(tkc, torch, ctx, g, dg, wname, k, variant, mode, steps, warmup, tune
     achieved = (bytes_main / max(1, launches)) / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
     kname = KERNEL_NAMES.get(st["main_kernel"], "?")
     mode_used = MODE_NAMES.get(st["mode_used"], "?")
-    traffic = load_traffic(kname, wname, k, mode_used, st["batch_width"])
+    traffic = load_traffic(kname, wname, k, mode_used, st["batch_width"], relabel)
     undirected = not g.directed
     mn = (2 if undirected else 1) * (g.arcs // (2 if undirected else 1)) * g.n
     return {
@@ -634,8 +638,11 @@ def compare_once(tkc, torch, dg, k, variant, mode, ids, S, plain_cap):
 CONFIGS = {
     "C1": {"workload": "ba2k", "k": [1, 10], "variant": "auto", "mode": "plain", "steps": 30, "warmup": 3,
            "tune": None, "compare": ["batched", "hybrid"], "plain_cap": 20000},
+    # C3's graph is uploaded with TKC_RELABEL (vertices by decreasing
+    # out-degree): the skewed R-MAT degrees then pack the hubs' words together
     "C3": {"workload": "rmat20", "k": [10], "variant": "auto", "mode": "batched", "steps": 10, "warmup": 2,
-           "tune": {"batch_width": 256, "blocks_per_cu": 4}, "compare": ["hybrid", "plain"], "plain_cap": 20000},
+           "tune": {"batch_width": 256, "blocks_per_cu": 4}, "compare": ["hybrid", "plain"], "plain_cap": 20000,
+           "relabel": True},
     # a plain search on the grid is a whole-GPU search of ~430 levels (~8 ms):
     # the comparison stops after 300 of them
     "C4": {"workload": "grid2000", "k": [10], "variant": "nbbound", "mode": "batched", "steps": 2, "warmup": 1,
@@ -646,13 +653,15 @@ CONFIGS = {
 def run_config(tkc, torch, graphgen, ctx, cname, args):
     cfg = CONFIGS[cname]
     g = graphgen.workload(cfg["workload"])
-    dg = tkc.Graph.from_graphgen(ctx, g)
+    relabel = bool(cfg.get("relabel"))
+    dg = tkc.Graph.from_graphgen(ctx, g, relabel=relabel)
     out = {"workload": WORKLOADS.get(cfg["workload"], cfg["workload"]), "variant": cfg["variant"],
-           "mode": cfg["mode"], "tuning": cfg["tune"], "n": g.n, "arcs": int(g.arcs), "runs": {}}
+           "mode": cfg["mode"], "tuning": cfg["tune"], "relabel": relabel, "n": g.n, "arcs": int(g.arcs),
+           "runs": {}}
     try:
         for k in cfg["k"]:
             m = measure(tkc, torch, ctx, g, dg, cfg["workload"], k, cfg["variant"], cfg["mode"], cfg["steps"],
-                        cfg["warmup"], cfg["tune"])
+                        cfg["warmup"], cfg["tune"], relabel)
             st = m.pop("_stats")
             ids, S = m.pop("_ids"), m.pop("_S")
             m["variant_used"] = st["variant_used"]

@@ -86,6 +86,16 @@ extern "C" {
                                i.e. out-closeness of the reversed graph
                                (the reversed-graph case study, Sect. 10);
                                no effect on undirected graphs              */
+#define TKC_RELABEL 16u     /* store the graph with its vertices renumbered
+                               by decreasing out-degree (ties by id), which
+                               packs the heavy vertices' words together for
+                               skewed graphs; every result, tie-break and
+                               per-vertex output still uses the caller's
+                               ids.  Such a graph serves the top-k queries,
+                               tkc_autotune, tkc_graph_reach and servers
+                               (without packing); the other step functions,
+                               tkc_graph_reach_noalloc and tkc_pack_create
+                               return TKC_EINVAL for it                    */
 
 typedef struct tkc_ctx tkc_ctx;
 typedef struct tkc_graph tkc_graph;

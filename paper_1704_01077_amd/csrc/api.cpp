@@ -362,11 +362,39 @@ extern "C" int tkc_graph_upload(tkc_ctx* c, int32_t n, int64_t m, const int32_t*
             return tkc_fail(TKC_EINVAL, "undirected CSR is not symmetric");
         }
     }
+    // TKC_RELABEL: vertices renumbered by decreasing out-degree (ties by id),
+    // rows sorted; oid[new] = caller's id, nid[caller's id] = new
+    std::vector<int32_t> oid, nid;
+    if (flags & TKC_RELABEL) {
+        oid.resize(n);
+        nid.resize(n);
+        for (int32_t v = 0; v < n; v++) oid[v] = v;
+        std::stable_sort(oid.begin(), oid.end(), [&](int32_t a, int32_t b) {
+            return hrp[a + 1] - hrp[a] > hrp[b + 1] - hrp[b];
+        });
+        for (int32_t v = 0; v < n; v++) nid[oid[v]] = v;
+        auto permute = [&](std::vector<int32_t>& rp, std::vector<int32_t>& ci) {
+            std::vector<int32_t> rp2(n + 1), ci2(m);
+            rp2[0] = 0;
+            for (int32_t v = 0; v < n; v++) {
+                const int32_t o = oid[v];
+                int32_t at = rp2[v];
+                for (int32_t e = rp[o]; e < rp[o + 1]; e++) ci2[at++] = nid[ci[e]];
+                std::sort(ci2.begin() + rp2[v], ci2.begin() + at);
+                rp2[v + 1] = at;
+            }
+            rp.swap(rp2);
+            ci.swap(ci2);
+        };
+        permute(hrp, hci);
+        if (directed) permute(hrrp, hrci);
+    }
     tkc_graph* g = new tkc_graph();
     g->ctx = c;
     g->n = n;
     g->m = m;
     g->directed = directed;
+    g->relabeled = (flags & TKC_RELABEL) != 0;
     // heavy vertices and their arc chunks (ascending ids: deterministic), for
     // the out-arcs and (directed) the in-arcs
     std::vector<int32_t> hv, hcb(1, 0), cb, ce, cv, rcb, rce, rcv;
@@ -431,6 +459,7 @@ extern "C" int tkc_graph_upload(tkc_ctx* c, int32_t n, int64_t m, const int32_t*
                    4 * hcb.size() + 12 * (cb.size() + 1) + 12 * (rcb.size() + 1) + 12 * (bcb.size() + 1) +
                    4 * (mvtx.size() + 1) + 4 * mseg.size() + 16 * 256;
     if (directed) bytes += 4 * (size_t)(n + 1) + 4 * (size_t)(m ? m : 1);
+    if (g->relabeled) bytes += 8 * (size_t)n + 512;
     if (hipMalloc(&g->dbase, bytes + 1024) != hipSuccess) {
         hipGetLastError();
         delete g;
@@ -467,8 +496,17 @@ extern "C" int tkc_graph_upload(tkc_ctx* c, int32_t n, int64_t m, const int32_t*
         g->rrp = g->rp;
         g->rci = g->ci;
     }
+    if (g->relabeled) {
+        g->d_oid = (int32_t*)take(4 * (size_t)n);
+        g->d_nid = (int32_t*)take(4 * (size_t)n);
+    }
     hipStream_t s = c->stream;
     int rc = TKC_OK;
+    if (g->relabeled &&
+        (hipMemcpyAsync(g->d_oid, oid.data(), 4 * (size_t)n, hipMemcpyHostToDevice, s) != hipSuccess ||
+         hipMemcpyAsync(g->d_nid, nid.data(), 4 * (size_t)n, hipMemcpyHostToDevice, s) != hipSuccess))
+        rc = tkc_fail(TKC_EDEVICE, "vertex map copy failed");
+    if (g->relabeled) g->h_nid = nid;
     if (hipMemcpyAsync(g->rp, hrp.data(), 4 * (size_t)(n + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
         (m && hipMemcpyAsync(g->ci, hci.data(), 4 * (size_t)m, hipMemcpyHostToDevice, s) != hipSuccess))
         rc = tkc_fail(TKC_EDEVICE, "graph copy failed");
@@ -1203,6 +1241,23 @@ extern "C" int tkc_graph_reach(tkc_graph* g, int64_t* alpha, int64_t* omega, int
     if (rc) return rc;
     rc = tkc_step_reach(c, g, c->ws);
     if (rc) return rc;
+    if (g->relabeled) {
+        // device arrays by stored vertex, outputs by the caller's id
+        const size_t n = (size_t)g->n;
+        std::vector<int64_t> ha(n), ho(n);
+        std::vector<int32_t> hs(g->directed && scc ? n : 0);
+        HIPCHK(hipMemcpyAsync(ha.data(), c->ws.alpha, 8 * n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(ho.data(), c->ws.omega, 8 * n, hipMemcpyDeviceToHost, c->stream));
+        if (hs.size()) HIPCHK(hipMemcpyAsync(hs.data(), c->ws.scc, 4 * n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (size_t v = 0; v < n; v++) {
+            const int32_t u = g->h_nid[v];
+            alpha[v] = ha[u];
+            omega[v] = ho[u];
+            if (hs.size()) scc[v] = hs[u];
+        }
+        return TKC_OK;
+    }
     HIPCHK(hipMemcpyAsync(alpha, c->ws.alpha, 8 * (size_t)g->n, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipMemcpyAsync(omega, c->ws.omega, 8 * (size_t)g->n, hipMemcpyDeviceToHost, c->stream));
     if (scc && g->directed)
@@ -1213,6 +1268,7 @@ extern "C" int tkc_graph_reach(tkc_graph* g, int64_t* alpha, int64_t* omega, int
 
 extern "C" int tkc_graph_harmonic_bounds(tkc_graph* g, int32_t variant, double* ub, int32_t* order) {
     if (!g || !ub) return tkc_fail(TKC_EINVAL, "NULL argument");
+    if (g->relabeled) return tkc_fail(TKC_EINVAL, "not available for a graph uploaded with TKC_RELABEL");
     if (variant < TKC_DEG_CUT || variant > TKC_NB_CUTLB) return tkc_fail(TKC_EINVAL, "bad variant");
     tkc_ctx* c = g->ctx;
     HIPCHK(hipSetDevice(c->device));
@@ -1236,6 +1292,7 @@ extern "C" int tkc_graph_harmonic_bounds(tkc_graph* g, int32_t variant, double* 
 
 extern "C" int tkc_graph_bounds(tkc_graph* g, int32_t variant, int64_t* num, int64_t* den, int32_t* order) {
     if (!g || !num || !den) return tkc_fail(TKC_EINVAL, "NULL argument");
+    if (g->relabeled) return tkc_fail(TKC_EINVAL, "not available for a graph uploaded with TKC_RELABEL");
     if (variant < TKC_DEG_CUT || variant > TKC_NB_CUTLB) return tkc_fail(TKC_EINVAL, "bad variant");
     tkc_ctx* c = g->ctx;
     HIPCHK(hipSetDevice(c->device));
@@ -1291,6 +1348,7 @@ int tkc_sums_impl(tkc_ctx* c, tkc_graph* g, const int32_t* sources, int32_t coun
 
 extern "C" int tkc_graph_sums(tkc_graph* g, const int32_t* sources, int32_t count, int64_t* S, int64_t* R) {
     if (!g || !sources || !S || !R || count < 0) return tkc_fail(TKC_EINVAL, "bad argument");
+    if (g->relabeled) return tkc_fail(TKC_EINVAL, "not available for a graph uploaded with TKC_RELABEL");
     for (int32_t i = 0; i < count; i++)
         if (sources[i] < 0 || sources[i] >= g->n) return tkc_fail(TKC_EINVAL, "source %d out of range", sources[i]);
     HIPCHK(hipSetDevice(g->ctx->device));
@@ -1306,6 +1364,7 @@ extern "C" int tkc_graph_sums(tkc_graph* g, const int32_t* sources, int32_t coun
 extern "C" int tkc_graph_lb_update(tkc_graph* g, const int32_t* sources, int32_t count, int64_t* num,
                                    int64_t* den) {
     if (!g || !sources || !num || !den || count < 0) return tkc_fail(TKC_EINVAL, "bad argument");
+    if (g->relabeled) return tkc_fail(TKC_EINVAL, "not available for a graph uploaded with TKC_RELABEL");
     for (int32_t i = 0; i < count; i++)
         if (sources[i] < 0 || sources[i] >= g->n) return tkc_fail(TKC_EINVAL, "source %d out of range", sources[i]);
     tkc_ctx* c = g->ctx;
@@ -1342,6 +1401,7 @@ extern "C" int tkc_graph_lb_update(tkc_graph* g, const int32_t* sources, int32_t
 
 extern "C" int tkc_graph_harmonic_lb_update(tkc_graph* g, const int32_t* sources, int32_t count, double* ub) {
     if (!g || !sources || !ub || count < 0) return tkc_fail(TKC_EINVAL, "bad argument");
+    if (g->relabeled) return tkc_fail(TKC_EINVAL, "not available for a graph uploaded with TKC_RELABEL");
     for (int32_t i = 0; i < count; i++)
         if (sources[i] < 0 || sources[i] >= g->n) return tkc_fail(TKC_EINVAL, "source %d out of range", sources[i]);
     for (int32_t v = 0; v < g->n; v++)

@@ -44,7 +44,13 @@ struct DevGraph {
     const int32_t* mid_vtx;
     const int32_t* mseg;
     int32_t nmseg;
+    // relabelled graphs (TKC_RELABEL): the caller's id of each vertex and
+    // the vertex of each caller id; null otherwise (ids are the caller's)
+    const int32_t* oid = nullptr;
+    const int32_t* nid = nullptr;
 };
+// the caller's id of vertex v (ties of the exact order break on it)
+#define TKC_OID(g, v) ((g).oid ? (g).oid[v] : (v))
 #define HEAVY_DEG 64
 #define CHUNK_ARCS 512
 #define HUB_IN_DEG 1024

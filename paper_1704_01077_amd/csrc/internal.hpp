@@ -98,6 +98,10 @@ struct tkc_graph {
     int32_t bnchunks = 0;
     int32_t *mid_vtx = nullptr, *mseg = nullptr;
     int32_t nmseg = 0;
+    // TKC_RELABEL: vertex v is the caller's vertex oid[v]; nid is the inverse
+    bool relabeled = false;
+    int32_t *d_oid = nullptr, *d_nid = nullptr;
+    std::vector<int32_t> h_nid;
     int32_t server_refs = 0;
     std::atomic<int32_t> auto_variant{0};   // read by server workers without the graph lock
     // reachability bounds of a directed graph, computed once per graph:
@@ -127,6 +131,8 @@ struct tkc_graph {
         g.rch_vtx = rch_vtx; g.rch_beg = rch_beg; g.rch_end = rch_end; g.rnchunks = rnchunks;
         g.bch_vtx = bch_vtx; g.bch_beg = bch_beg; g.bch_end = bch_end; g.bnchunks = bnchunks;
         g.mid_vtx = mid_vtx; g.mseg = mseg; g.nmseg = nmseg;
+        g.oid = relabeled ? d_oid : nullptr;
+        g.nid = relabeled ? d_nid : nullptr;
         return g;
     }
 };

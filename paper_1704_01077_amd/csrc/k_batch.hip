@@ -353,6 +353,7 @@ struct SelIn {
     int32_t harm;
     int32_t no_cut;
     int32_t off;
+    const int32_t* oid;      // relabelled graph: the caller's ids (ties), else null
 };
 TKC_DEV void select_cands(const SelIn& in, int32_t& pos, int32_t cap, int32_t* cand, int32_t& nsel, int32_t& stop,
                           int64_t& skipped, int64_t& r1) {
@@ -372,7 +373,7 @@ TKC_DEV void select_cands(const SelIn& in, int32_t& pos, int32_t cap, int32_t* c
                 st = in.harm ? key_stops_h(key, x)
                              : (in.key_is_bound ? key_stops(key, x) : (key == 0xffffffffu && x.den != 0));
             }
-            if (!st) sk = lex_after(in.num[v], in.den[v], v, x.num, x.den, x.id);
+            if (!st) sk = lex_after(in.num[v], in.den[v], in.oid ? in.oid[v] : v, x.num, x.den, x.id);
         }
         // in list mode without cuts every position gets a lane, sinks included
         if (valid && !st && !sk && !in.no_cut) one = in.omega[v] <= 1;
@@ -401,6 +402,7 @@ TKC_DEV void select_cands(const SelIn& in, int32_t& pos, int32_t cap, int32_t* c
                 int l = __ffsll((long long)m) - 1;
                 m &= m - 1;
                 int32_t vv = in.ord[pos + l];
+                if (in.oid) vv = in.oid[vv];
                 if (in.harm) topk_insert(in.tk.st, in.tk.ring, in.tk.S, in.tk.R, in.tk.I, harm_enc(0.0), 2, vv);
                 else topk_insert(in.tk.st, in.tk.ring, in.tk.S, in.tk.R, in.tk.I, 0, 1, vv);
             }
@@ -501,7 +503,8 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
             int64_t skipped = 0, r1 = 0;
             if (a.npreq == 0) {
                 const SelIn in{order_mode ? a.ov.ord : a.list, order_mode ? a.ov.key : nullptr, count,
-                               a.ov.key_is_bound, a.bv.num, a.bv.den, a.rc.omega, a.tk, a.bv.harm, a.no_cut, 0};
+                               a.ov.key_is_bound, a.bv.num, a.bv.den, a.rc.omega, a.tk, a.bv.harm, a.no_cut, 0,
+                               a.g.oid};
                 select_cands(in, pos, a.Wsel, a.w.cand, nsel, stop, skipped, r1);
             } else {
                 // the requests of a pack take turns: first up to an even
@@ -512,7 +515,7 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                         if (s_pk_stop[r] || s_pk_pos[r] >= a.preq[r].n) continue;
                         const PackReq& q = a.preq[r];
                         const SelIn in{q.ov.ord, q.ov.key, q.n, q.ov.key_is_bound, q.bv.num, q.bv.den, q.rc.omega,
-                                       q.tk, 0, 0, q.off};
+                                       q.tk, 0, 0, q.off, nullptr};
                         const int32_t before = nsel;
                         const int32_t cap = pass == 0 ? (nsel + share < a.Wsel ? nsel + share : a.Wsel) : a.Wsel;
                         int32_t rpos = s_pk_pos[r], rstop = s_pk_stop[r];
@@ -562,7 +565,10 @@ __global__ void __launch_bounds__(BB) k_batch(BatchArgs a) {
                     xl = read_x(a.preq[r].tk.st, a.preq[r].tk.ring);
                 }
                 s_v[l] = v;
-                s_off[l] = off;
+                // s_v[l] - s_off[l] is the source's id as the caller numbers
+                // it: the member's own id in a pack, the caller's id in a
+                // relabelled graph (ties of the exact order break on it)
+                s_off[l] = a.g.oid ? v - a.g.oid[v] : off;
                 s_req[l] = r;
                 s_xn[l] = xl.num;
                 s_xd[l] = xl.den;

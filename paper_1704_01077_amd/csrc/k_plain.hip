@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
                 break;
             }
         }
-        if (lex_after(a.bv.num[v], a.bv.den[v], v, x.num, x.den, x.id)) {
+        if (lex_after(a.bv.num[v], a.bv.den[v], TKC_OID(a.g, v), x.num, x.den, x.id)) {
             if (boss) stats[ST_SKIPPED]++;
             continue;
         }
@@ -168,8 +168,8 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
             if (boss) {
                 stats[ST_STARTED]++;
                 stats[ST_EXACT]++;
-                if (a.bv.harm) topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, harm_enc(0.0), 2, v);
-                else topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, 0, 1, v);
+                if (a.bv.harm) topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, harm_enc(0.0), 2, TKC_OID(a.g, v));
+                else topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, 0, 1, TKC_OID(a.g, v));
             }
             grid_barrier(a.bar, gridDim.x);
             continue;
@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
                 int64_t bn, bd;
                 if (a.bv.harm) harm_cut_bound(H, nD, U, D, ov, &bn, &bd);
                 else cut_bound(SD, nD, U, D, av, ov, &bn, &bd);
-                if (lex_after(bn, bd, v, x.num, x.den, x.id)) { status = 2; break; }
+                if (lex_after(bn, bd, TKC_OID(a.g, v), x.num, x.den, x.id)) { status = 2; break; }
             }
             // direction (Beamer): pull when the frontier's arcs outweigh the
             // unexplored ones, push again once the frontier is small
@@ -419,8 +419,8 @@ __global__ void __launch_bounds__(PB) k_plain(PlainArgs a) {
             if (maxD > stats[ST_MAXLEVEL]) stats[ST_MAXLEVEL] = maxD;
             if (status == 1) {
                 stats[ST_EXACT]++;
-                if (a.bv.harm) topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, harm_enc(H), 2, v);
-                else topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, SD, nD, v);
+                if (a.bv.harm) topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, harm_enc(H), 2, TKC_OID(a.g, v));
+                else topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, SD, nD, TKC_OID(a.g, v));
             } else {
                 stats[ST_CUT]++;
             }

@@ -367,8 +367,10 @@ __global__ void k_comp_of(int32_t n, const int32_t* scc, const int32_t* cid, int
     const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v < n) comp[v] = cid[scc[v]];
 }
+// minid: the smallest caller's id in each component (oid: the caller's id of
+// each vertex of a relabelled graph, or null)
 __global__ void __launch_bounds__(SB) k_comp_stats(int32_t n, const int32_t* comp, int32_t pivot, int32_t* wt,
-                                                   int32_t* minid) {
+                                                   int32_t* minid, const int32_t* oid) {
     // the pivot's component holds most vertices: one atomic per block for it
     __shared__ int64_t sh[SB / 64];
     __shared__ unsigned long long shm[SB / 64];
@@ -377,13 +379,14 @@ __global__ void __launch_bounds__(SB) k_comp_stats(int32_t n, const int32_t* com
     unsigned long long hm = 0;   // 0xffffffff - smallest id of the hot component seen
     for (int64_t v = (int64_t)blockIdx.x * SB + threadIdx.x; v < n; v += (int64_t)gridDim.x * SB) {
         const int32_t c = comp[v];
+        const int32_t id = oid ? oid[v] : (int32_t)v;
         if (c == hot) {
             hc++;
-            const unsigned long long k = 0xffffffffull - (uint32_t)v;
+            const unsigned long long k = 0xffffffffull - (uint32_t)id;
             hm = k > hm ? k : hm;
         } else {
             atomicAdd(&wt[c], 1);
-            atomicMin(&minid[c], (int32_t)v);
+            atomicMin(&minid[c], id);
         }
     }
     hc = block_sum_i64(hc, sh);
@@ -406,9 +409,10 @@ __global__ void __launch_bounds__(SB) k_comp_big(int32_t nc, const int32_t* wt, 
     if (threadIdx.x == 0 && key) atomicMax(best, key);
 }
 
-__global__ void k_set_big(const int32_t* comp, int32_t bmin, int32_t* tob, int32_t* frb, int32_t* out) {
+__global__ void k_set_big(const int32_t* comp, int32_t bmin, const int32_t* nid, int32_t* tob, int32_t* frb,
+                          int32_t* out) {
     if (threadIdx.x == 0) {
-        const int32_t c = comp[bmin];
+        const int32_t c = comp[nid ? nid[bmin] : bmin];
         tob[c] = 1;
         frb[c] = 1;
         *out = c;
@@ -1131,7 +1135,7 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
         hipLaunchKernelGGL(k_comp_of, dim3(gb), dim3(SB), 0, s, n, scc, cid, comp);
         DEV_OK(hipMemsetAsync(wt, 0, 4 * (size_t)nc, s));
         DEV_OK(hipMemsetAsync(minid, 0x7f, 4 * (size_t)nc, s));
-        hipLaunchKernelGGL(k_comp_stats, dim3(rblk(n)), dim3(SB), 0, s, n, comp, pivot, wt, minid);
+        hipLaunchKernelGGL(k_comp_stats, dim3(rblk(n)), dim3(SB), 0, s, n, comp, pivot, wt, minid, g.oid);
         DEV_OK(hipMemsetAsync(big_key, 0, 8, s));
         hipLaunchKernelGGL(k_comp_big, dim3(rblk(nc)), dim3(SB), 0, s, nc, wt, minid, big_key);
         phase("ids", nc, 0);
@@ -1174,8 +1178,8 @@ int tkc_device_alpha_omega(const DevGraph& g, int64_t* alpha, int64_t* omega, in
         DEV_OK(hipMemsetAsync(hgt, 0, 4 * (size_t)nc, s));
         DEV_OK(hipMemsetAsync(tob, 0, 4 * (size_t)nc, s));
         DEV_OK(hipMemsetAsync(frb, 0, 4 * (size_t)nc, s));
-        // the largest component is the one holding vertex bmin
-        hipLaunchKernelGGL(k_set_big, dim3(1), dim3(64), 0, s, comp, (int32_t)bmin, tob, frb, small + 9);
+        // the largest component is the one holding the caller's vertex bmin
+        hipLaunchKernelGGL(k_set_big, dim3(1), dim3(64), 0, s, comp, (int32_t)bmin, g.nid, tob, frb, small + 9);
         const int32_t big = read_i32(small + 9, pin, s);
         if (big < 0) { fail(-1); goto done; }
         bool deep = false;

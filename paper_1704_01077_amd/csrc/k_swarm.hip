@@ -118,12 +118,12 @@ __global__ void __launch_bounds__(SB) k_swarm(SwarmArgs a) {
                 bool stop = a.bv.harm ? key_stops_h(key, x)
                                       : (a.ov.key_is_bound ? key_stops(key, x) : (key == 0xffffffffu && x.den != 0));
                 if (stop) { for_rlx(a.w.stop, 1); s_dec = 1; }
-                else if (lex_after(a.bv.num[v], a.bv.den[v], v, x.num, x.den, x.id)) { s_dec = 2; st_skip++; }
+                else if (lex_after(a.bv.num[v], a.bv.den[v], TKC_OID(a.g, v), x.num, x.den, x.id)) { s_dec = 2; st_skip++; }
                 else if (a.rc.omega[v] <= 1) {
                     s_dec = 3;
                     st_started++; st_exact++;
-                    if (a.bv.harm) topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, harm_enc(0.0), 2, v);
-                    else topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, 0, 1, v);
+                    if (a.bv.harm) topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, harm_enc(0.0), 2, TKC_OID(a.g, v));
+                    else topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, 0, 1, TKC_OID(a.g, v));
                 }
             } else {
                 s_dec = 1;
@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(SB) k_swarm(SwarmArgs a) {
                 int64_t bn, bd;
                 if (a.bv.harm) harm_cut_bound(H, nD, U, D, ov, &bn, &bd);
                 else cut_bound(SD, nD, U, D, av, ov, &bn, &bd);
-                if (lex_after(bn, bd, v, s_x[0], s_x[1], (int32_t)s_x[2])) { status = 2; break; }
+                if (lex_after(bn, bd, TKC_OID(a.g, v), s_x[0], s_x[1], (int32_t)s_x[2])) { status = 2; break; }
             }
             if (s_closed) { status = 3; break; }
             // expand level D: frontier q[ls, le), edge-balanced in chunks of SB vertices
@@ -241,8 +241,8 @@ __global__ void __launch_bounds__(SB) k_swarm(SwarmArgs a) {
             if (md > st_maxl) st_maxl = md;
             if (status == 1) {
                 st_exact++;
-                if (a.bv.harm) topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, harm_enc(H), 2, v);
-                else topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, SD, nD, v);
+                if (a.bv.harm) topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, harm_enc(H), 2, TKC_OID(a.g, v));
+                else topk_insert(a.tk.st, a.tk.ring, a.tk.S, a.tk.R, a.tk.I, SD, nD, TKC_OID(a.g, v));
             } else if (status == 2) {
                 st_cut++;
             } else {

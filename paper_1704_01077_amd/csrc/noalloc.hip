@@ -42,6 +42,7 @@ int tkc_noalloc_init(int device) {
 
 extern "C" int tkc_graph_reach_noalloc(tkc_graph* g, int64_t* alpha, int64_t* omega, int32_t* scc) {
     if (!g || !alpha || !omega) return tkc_fail(TKC_EINVAL, "NULL argument");
+    if (g->relabeled) return tkc_fail(TKC_EINVAL, "not available for a graph uploaded with TKC_RELABEL");
     tkc_ctx* c = g->ctx;
     if (c->device < 0 || c->device >= kMaxDevices) return tkc_fail(TKC_EINVAL, "device out of range");
     if (hipSetDevice(c->device) != hipSuccess) return tkc_fail(TKC_EDEVICE, "hipSetDevice failed");

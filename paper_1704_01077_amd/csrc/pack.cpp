@@ -49,6 +49,7 @@ extern "C" int tkc_pack_create(tkc_ctx* ctx, tkc_graph* const* graphs, int32_t c
         if (!g) return tkc_fail(TKC_EINVAL, "graph %d is NULL", i);
         if (g->ctx != ctx) return tkc_fail(TKC_EINVAL, "graph %d belongs to another context", i);
         if (g->directed != directed) return tkc_fail(TKC_EINVAL, "members must be all directed or all undirected");
+        if (g->relabeled) return tkc_fail(TKC_EINVAL, "graph %d was uploaded with TKC_RELABEL", i);
         for (int32_t j = 0; j < i; j++)
             if (graphs[j] == g) return tkc_fail(TKC_EINVAL, "graph %d is listed twice", i);
         N += g->n;

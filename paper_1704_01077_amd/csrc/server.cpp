@@ -384,7 +384,7 @@ extern "C" int tkc_server_enable_packing(tkc_server* s, int32_t max_vertices) {
         };
         for (int32_t gid = 0; gid < ng; gid++) {
             tkc_graph* g = s->graphs[gid];
-            if (g->directed != (dir == 1) || g->n > max_vertices) continue;
+            if (g->directed != (dir == 1) || g->n > max_vertices || g->relabeled) continue;
             if ((int32_t)cur.size() == TKC_PACK_MAXREQ || arcs + g->m > (int64_t(1) << 28))
                 if (int rc = flush()) return rc;
             cur.push_back(gid);

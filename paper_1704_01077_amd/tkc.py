@@ -27,7 +27,7 @@ TKC_ECANCELED = -6
 TKC_AUTO, TKC_DEG_CUT, TKC_NB_CUT, TKC_DEG_BOUND, TKC_NB_BOUND = 0, 1, 2, 3, 4
 TKC_DEG_CUTLB, TKC_NB_CUTLB = 5, 6
 TKC_PLAIN, TKC_BATCHED, TKC_HYBRID, TKC_MODE_AUTO = 0, 1, 2, 3
-TKC_DIRECTED, TKC_VALIDATE, TKC_DEVICE_PTRS, TKC_REVERSE = 1, 2, 4, 8
+TKC_DIRECTED, TKC_VALIDATE, TKC_DEVICE_PTRS, TKC_REVERSE, TKC_RELABEL = 1, 2, 4, 8, 16
 
 VARIANTS = {"auto": TKC_AUTO, "degcut": TKC_DEG_CUT, "nbcut": TKC_NB_CUT,
             "degbound": TKC_DEG_BOUND, "nbbound": TKC_NB_BOUND,
@@ -338,7 +338,7 @@ class Graph:
     """A graph resident on the device (CSR copied at construction)."""
 
     def __init__(self, ctx: Context, n, row_ptr, col_idx, rrow_ptr=None, rcol_idx=None,
-                 validate=False, device_ptrs=False, reverse=False):
+                 validate=False, device_ptrs=False, reverse=False, relabel=False):
         row_ptr = _as_i32(row_ptr)
         col_idx = _as_i32(col_idx)
         flags = (TKC_DIRECTED if rrow_ptr is not None else 0) | (TKC_VALIDATE if validate else 0)
@@ -347,6 +347,8 @@ class Graph:
             flags |= TKC_DEVICE_PTRS
         if reverse:
             flags |= TKC_REVERSE
+        if relabel:
+            flags |= TKC_RELABEL
         if rrow_ptr is not None:
             rrow_ptr, rcol_idx = _as_i32(rrow_ptr), _as_i32(rcol_idx)
         self.n = int(n)
@@ -356,14 +358,17 @@ class Graph:
         self.h = tkc_graph_upload(ctx.h, self.n, self.m, row_ptr, col_idx, rrow_ptr, rcol_idx, flags)
 
     @classmethod
-    def from_csr(cls, ctx, row_ptr, col_idx, rrow_ptr=None, rcol_idx=None, validate=False, reverse=False):
+    def from_csr(cls, ctx, row_ptr, col_idx, rrow_ptr=None, rcol_idx=None, validate=False, reverse=False,
+                 relabel=False):
         """From int32 CSR arrays (numpy, or torch tensors on the host or the
         GPU); the reverse CSR is given iff the graph is directed."""
-        return cls(ctx, len(row_ptr) - 1, row_ptr, col_idx, rrow_ptr, rcol_idx, validate=validate, reverse=reverse)
+        return cls(ctx, len(row_ptr) - 1, row_ptr, col_idx, rrow_ptr, rcol_idx, validate=validate, reverse=reverse,
+                   relabel=relabel)
 
     @classmethod
-    def from_graphgen(cls, ctx, g, validate=False, reverse=False):
-        return cls(ctx, g.n, g.row_ptr, g.col_idx, g.rrow_ptr, g.rcol_idx, validate=validate, reverse=reverse)
+    def from_graphgen(cls, ctx, g, validate=False, reverse=False, relabel=False):
+        return cls(ctx, g.n, g.row_ptr, g.col_idx, g.rrow_ptr, g.rcol_idx, validate=validate, reverse=reverse,
+                   relabel=relabel)
 
     def free(self):
         if self.h:

@@ -58,5 +58,6 @@ def test_traffic_records_apply_only_to_their_key(tmp_path, monkeypatch):
     assert bench.load_traffic("k_batch", "ba1m", 10, "batched", 64) is None
     assert bench.load_traffic("k_batch", "ba1m", 10, "hybrid", 128) is None
     assert bench.load_traffic("k_batch", "rmat20", 10, "hybrid", 64) is None
+    assert bench.load_traffic("k_batch", "ba1m", 10, "hybrid", 64, relabel=True) is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda k: "0" * 16)
     assert bench.load_traffic("k_batch", "ba1m", 10, "hybrid", 64) is None
