@@ -75,7 +75,7 @@ static size_t ws_items(Workspace& ws, const WsShape& sh, std::vector<WsItem>& it
         {(void**)&ws.lden, 8 * n, false}, {(void**)&ws.key, 4 * n, false},
         {(void**)&ws.ord, 4 * n, false}, {(void**)&ws.tkey, 4 * n, false},
         {(void**)&ws.tval, 4 * n, false},
-        {(void**)&ws.hist, 4 * (size_t)tkc_sort_hist_words(sh.n), false},
+        {(void**)&ws.hist, 4 * (size_t)tkc_sort8_hist_words(sh.n), false},
         {(void**)&ws.mask, 64, false}, {(void**)&ws.parent, 4 * n, false},
         {(void**)&ws.csize, 8 * n + 16, false}, {(void**)&ws.gbuf, 32 * n, false},
         {(void**)&ws.nbsum, 8 * n, false}, {(void**)&ws.nbvis, 8 * n, false},
@@ -646,7 +646,7 @@ int tkc_step_bounds(tkc_ctx* c, tkc_graph* g, Workspace& ws, bool nb, int32_t* r
         if (tkc_launch_deg_bounds(dg, ws.omega, ws.lnum, ws.lden, ws.key, ws.ord, s))
             return tkc_fail(TKC_EDEVICE, "degree bound kernel failed");
     }
-    if (tkc_sort_pairs(ws.key, ws.ord, ws.tkey, ws.tval, n, ws.hist, (uint32_t*)ws.mask,
+    if (tkc_sort_pairs8(ws.key, ws.ord, ws.tkey, ws.tval, n, ws.hist, (uint32_t*)ws.mask,
                        (uint32_t*)c->pinned, s))
         return tkc_fail(TKC_EDEVICE, "sort failed");
     return TKC_OK;

@@ -113,6 +113,12 @@ static inline int tkc_grid_for(int cus, int per, int32_t n) {
     return (int)(want < full ? want : full);
 }
 
+// k_topk.hip: the current device's compute units, and how many workgroups
+// of `block` threads of kernel fn fit on one of them (both asked of the
+// runtime once per device and kernel, then cached); -1 on error
+int tkc_cu_count();
+int tkc_occupancy(const void* fn, int block);
+
 // k_prep.hip
 int tkc_launch_degrees(const DevGraph& g, hipStream_t s);
 // size holds n+2 int64; in_giant n bytes; sample_host is unused (the
@@ -151,6 +157,12 @@ int64_t tkc_sort_hist_words(int32_t n);
 int tkc_sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* tmp_keys, int32_t* tmp_vals,
                    int32_t n, int32_t* hist, uint32_t* mask_dev, uint32_t* mask_host,
                    hipStream_t s);
+// the same with 8-bit digits (the processing order): hist holds
+// tkc_sort8_hist_words(n) int32
+int64_t tkc_sort8_hist_words(int32_t n);
+int tkc_sort_pairs8(uint32_t* keys, int32_t* vals, uint32_t* tmp_keys, int32_t* tmp_vals,
+                    int32_t n, int32_t* hist, uint32_t* mask_dev, uint32_t* mask_host,
+                    hipStream_t s);
 
 // k_topk.hip
 // all-ties mode: buffers for the entries that leave or are refused by the top k

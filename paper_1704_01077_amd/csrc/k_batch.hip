@@ -1400,21 +1400,18 @@ int tkc_launch_batch(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv
     if (!w.bar || !w.vis || !w.frt0 || !w.frt1 || !w.nxt || !w.list || !w.ctr || !w.cand || !stats) return -2;
     if (lb_mode && (!w.lvl || !w.hist || !w.levtab)) return -2;
     int NW = W <= 64 ? 1 : W / 64;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return -1;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return -1;
+    const int cus = tkc_cu_count();
+    if (cus < 1) return -1;
     const bool tr = w.trace != nullptr;
     const void* fn = NW == 1 ? (tr ? (const void*)k_batch<1, true> : (const void*)k_batch<1, false>)
                    : NW == 2 ? (tr ? (const void*)k_batch<2, true> : (const void*)k_batch<2, false>)
                              : (tr ? (const void*)k_batch<4, true> : (const void*)k_batch<4, false>);
-    int occ = 0;
     hipError_t e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, BB, 0);
-    if (e != hipSuccess || occ < 1) return -1;
+    const int occ = tkc_occupancy(fn, BB);
+    if (occ < 1) return -1;
     const int want = tune.blocks_per_cu > 0 ? tune.blocks_per_cu : 2;
     int per = occ < want ? occ : want;
-    const int grid = tkc_grid_for(prop.multiProcessorCount, per, g.n);
+    const int grid = tkc_grid_for(cus, per, g.n);
     if (grid_out) *grid_out = grid;
     BatchArgs a{};
     a.g = g; a.rc = rc; a.ov = ov; a.bv = bv; a.tk = tk; a.w = w;

@@ -435,16 +435,13 @@ int tkc_launch_plain(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv
                      int lb_mode, const EngineTuning& tune, hipStream_t s, int* grid_out,
                      int64_t max_searches) {
     if (!w.bar || !w.vis || !w.fb || !w.ql || !w.qh || !w.qg || !w.ctr || !stats) return -2;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return -1;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return -1;
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_plain, PB, 0) != hipSuccess) return -1;
+    const int cus = tkc_cu_count();
+    if (cus < 1) return -1;
+    const int occ = tkc_occupancy((const void*)k_plain, PB);
     if (occ < 1) return -1;
     const int want = tune.blocks_per_cu > 0 ? tune.blocks_per_cu : 2;
     int per = occ < want ? occ : want;
-    const int grid = tkc_grid_for(prop.multiProcessorCount, per, g.n);
+    const int grid = tkc_grid_for(cus, per, g.n);
     if (grid_out) *grid_out = grid;
     PlainArgs a{};
     a.g = g; a.rc = rc; a.ov = ov; a.bv = bv; a.tk = tk; a.w = w;

@@ -270,3 +270,172 @@ int tkc_sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* tmp_keys, int32_t* t
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort with 8-bit digits, for the processing order: half
+// the passes of the 4-bit sort on keys whose varying bits span two bytes.
+// A tile is RS8_TILE items taken round-robin (item j * 256 + t is thread t's
+// j-th), so rounds in order and lanes in order visit the tile in order.
+// Per pass: per-tile digit counts; per digit, the exclusive prefix over
+// tiles and the total; the scatter, which ranks each round's items by
+// digit within each wave (a match over the digit's eight bits) and keeps
+// running per-digit counts in LDS.
+#define RS8_THREADS 256
+#define RS8_ROUNDS 8
+#define RS8_TILE (RS8_THREADS * RS8_ROUNDS)
+
+static inline int rs8_tiles(int32_t n) { return (n + RS8_TILE - 1) / RS8_TILE; }
+
+TKC_DEV uint64_t below_lanes() {
+    const int l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// lanes of the wave whose (valid) digit equals this lane's; all 64 lanes call
+TKC_DEV uint64_t rs8_match(uint32_t d, bool valid) {
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+        const uint64_t bal = __ballot((d >> b) & 1u);
+        m &= ((d >> b) & 1u) ? bal : ~bal;
+    }
+    return m;
+}
+
+// cnt[d * tiles + tile] = items of digit d in the tile
+__global__ void __launch_bounds__(RS8_THREADS) k_rs8_count(const uint32_t* __restrict__ keys, int32_t n, int shift,
+                                                            int32_t* cnt, int32_t tiles) {
+    __shared__ int32_t h[256];
+    const int t = threadIdx.x;
+    h[t] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS8_TILE;
+#pragma unroll
+    for (int j = 0; j < RS8_ROUNDS; j++) {
+        const int64_t i = base + j * RS8_THREADS + t;
+        const bool valid = i < n;
+        const uint32_t d = valid ? (keys[i] >> shift) & 255u : 0u;
+        const uint64_t m = rs8_match(d, valid);
+        if (valid && __ffsll((long long)m) - 1 == lane_id()) atomicAdd(&h[d], __popcll(m));
+    }
+    __syncthreads();
+    cnt[(int64_t)t * tiles + blockIdx.x] = h[t];
+}
+
+// workgroup d: the exclusive prefix of digit d's counts over the tiles, in
+// place, and the digit's total
+__global__ void __launch_bounds__(RS8_THREADS) k_rs8_scan(int32_t* cnt, int32_t tiles, int32_t* total) {
+    __shared__ int32_t wsum[RS8_THREADS / 64];
+    int32_t* row = cnt + (int64_t)blockIdx.x * tiles;
+    const int t = threadIdx.x;
+    const int32_t per = (tiles + RS8_THREADS - 1) / RS8_THREADS;
+    const int32_t lo = t * per, hi = lo + per < tiles ? lo + per : tiles;
+    int32_t s = 0;
+    for (int32_t q = lo; q < hi; q++) s += row[q];
+    int32_t x = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(x, o, 64);
+        if (lane_id() >= o) x += y;
+    }
+    if (lane_id() == 63) wsum[t >> 6] = x;
+    __syncthreads();
+    int32_t run = x - s;
+    for (int w = 0; w < (t >> 6); w++) run += wsum[w];
+    for (int32_t q = lo; q < hi; q++) {
+        const int32_t c = row[q];
+        row[q] = run;
+        run += c;
+    }
+    if (t == RS8_THREADS - 1) total[blockIdx.x] = run;
+}
+
+__global__ void __launch_bounds__(RS8_THREADS) k_rs8_scatter(const uint32_t* __restrict__ keys,
+                                                              const int32_t* __restrict__ vals, int32_t n, int shift,
+                                                              const int32_t* __restrict__ pre, int32_t tiles,
+                                                              const int32_t* __restrict__ total,
+                                                              uint32_t* __restrict__ okeys, int32_t* __restrict__ ovals) {
+    __shared__ int32_t start[256];   // where digit d's items of this tile go
+    __shared__ int32_t run[256];     // of which this many are placed
+    __shared__ int32_t wc[RS8_THREADS / 64][256];
+    __shared__ int32_t wsum[RS8_THREADS / 64];
+    const int t = threadIdx.x, wv = t >> 6, lane = lane_id();
+    {   // digits before d over the whole input, then this tile's prefix in d
+        const int32_t tot = total[t];
+        int32_t x = tot;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        int32_t below = x - tot;
+        for (int w = 0; w < wv; w++) below += wsum[w];
+        start[t] = below + pre[(int64_t)t * tiles + blockIdx.x];
+        run[t] = 0;
+    }
+    const int64_t base = (int64_t)blockIdx.x * RS8_TILE;
+    for (int j = 0; j < RS8_ROUNDS; j++) {
+        const int64_t i = base + j * RS8_THREADS + t;
+        const bool valid = i < n;
+        uint32_t k = 0;
+        int32_t v = 0;
+        if (valid) {
+            k = keys[i];
+            v = vals[i];
+        }
+        const uint32_t d = (k >> shift) & 255u;
+#pragma unroll
+        for (int w = 0; w < RS8_THREADS / 64; w++) wc[w][t] = 0;
+        __syncthreads();
+        const uint64_t m = rs8_match(d, valid);
+        if (valid && __ffsll((long long)m) - 1 == lane) wc[wv][d] = __popcll(m);
+        __syncthreads();
+        if (valid) {
+            int32_t pos = start[d] + run[d] + __popcll(m & below_lanes());
+            for (int w = 0; w < wv; w++) pos += wc[w][d];
+            okeys[pos] = k;
+            ovals[pos] = v;
+        }
+        __syncthreads();
+        int32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < RS8_THREADS / 64; w++) add += wc[w][t];
+        run[t] += add;
+    }
+}
+
+int64_t tkc_sort8_hist_words(int32_t n) { return 256LL * rs8_tiles(n > 0 ? n : 1) + 256 + 16; }
+
+int tkc_sort_pairs8(uint32_t* keys, int32_t* vals, uint32_t* tmp_keys, int32_t* tmp_vals, int32_t n, int32_t* hist,
+                    uint32_t* mask_dev, uint32_t* mask_host, hipStream_t s) {
+    if (n <= 1) return 0;
+    if (hipMemsetD32Async((hipDeviceptr_t)mask_dev, 0u, 1, s) != hipSuccess) return -1;
+    if (hipMemsetD32Async((hipDeviceptr_t)(mask_dev + 1), 0xffffffffu, 1, s) != hipSuccess) return -1;
+    int gb = rs_tiles(n);
+    if (gb > 256) gb = 256;
+    hipLaunchKernelGGL(k_rs_mask, dim3(gb), dim3(256), 0, s, keys, n, mask_dev);
+    if (hipMemcpyAsync(mask_host, mask_dev, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return -1;
+    if (hipStreamSynchronize(s) != hipSuccess) return -1;
+    const uint32_t vary = mask_host[0] ^ mask_host[1];
+    const int tiles = rs8_tiles(n);
+    int32_t* total = hist + 256LL * tiles;
+    uint32_t* ka = keys; int32_t* va = vals;
+    uint32_t* kb = tmp_keys; int32_t* vb = tmp_vals;
+    for (int shift = 0; shift < 32; shift += 8) {
+        if (((vary >> shift) & 255u) == 0) continue;
+        hipLaunchKernelGGL(k_rs8_count, dim3(tiles), dim3(RS8_THREADS), 0, s, ka, n, shift, hist, tiles);
+        hipLaunchKernelGGL(k_rs8_scan, dim3(256), dim3(RS8_THREADS), 0, s, hist, tiles, total);
+        hipLaunchKernelGGL(k_rs8_scatter, dim3(tiles), dim3(RS8_THREADS), 0, s, ka, va, n, shift,
+                           (const int32_t*)hist, tiles, (const int32_t*)total, kb, vb);
+        uint32_t* tk = ka; ka = kb; kb = tk;
+        int32_t* tv = va; va = vb; vb = tv;
+    }
+    if (ka != keys) {
+        hipMemcpyAsync(keys, ka, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, s);
+        hipMemcpyAsync(vals, va, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}

@@ -271,20 +271,20 @@ __global__ void __launch_bounds__(SB) k_swarm(SwarmArgs a) {
 
 int tkc_swarm_max_blocks(int block) {
     (void)block;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return -1;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return -1;
+    const int cus = tkc_cu_count();
+    if (cus < 1) return -1;
     int occ = 0;
     const int sb = swarm_sb();
     if (sb == 1024) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_swarm<1024>, 1024, 0) != hipSuccess) return -1;
+        occ = tkc_occupancy((const void*)k_swarm<1024>, 1024);
+        if (occ < 0) return -1;
         if (occ > 2) occ = 2;
     } else {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_swarm<256>, 256, 0) != hipSuccess) return -1;
+        occ = tkc_occupancy((const void*)k_swarm<256>, 256);
+        if (occ < 0) return -1;
         if (occ > 8) occ = 8;
     }
-    return prop.multiProcessorCount * (occ > 0 ? occ : 1);
+    return cus * (occ > 0 ? occ : 1);
 }
 
 int tkc_launch_swarm(const DevGraph& g, DevReach rc, OrderView ov, BoundsView bv, DevTopk tk,
