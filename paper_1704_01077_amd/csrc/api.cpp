@@ -627,17 +627,32 @@ int tkc_step_bounds(tkc_ctx* c, tkc_graph* g, Workspace& ws, bool nb, int32_t* r
     DevGraph dg = g->view();
     int32_t n = g->n;
     if (rounds) *rounds = 0;
+    // the sort's key mask, staged apart from the NB finish count in pinned memory
+    uint32_t* mask_pin = (uint32_t*)c->pinned + 64;
+    bool keyed = false;
     if (nb) {
         int32_t* nfin_dev = (int32_t*)ws.small;
+        // order keys and their mask, queued by the NB rounds before their
+        // last host wait
+        const std::function<int()> fin = [&]() -> int {
+            if (harm) {
+                if (tkc_launch_harm_bounds(dg, ws.omega, ws.nbhub, ws.lnum, ws.lden, ws.key, ws.ord, s)) return -1;
+            } else if (tkc_launch_nb_keys(n, ws.lnum, ws.lden, ws.key, ws.ord, s)) {
+                return -1;
+            }
+            return tkc_sort_mask(ws.key, n, (uint32_t*)ws.mask, mask_pin, s);
+        };
         int r = tkc_launch_nb(dg, ws.alpha, ws.omega, ws.gbuf, ws.nbsum, ws.nbvis, ws.nbflags, ws.lnum, ws.lden,
-                              ws.nbpart, nfin_dev, (int32_t*)c->pinned, s, harm ? ws.nbhub : nullptr);
+                              ws.nbpart, nfin_dev, (int32_t*)c->pinned, s, harm ? ws.nbhub : nullptr, &fin, &keyed);
         if (r < 0) return tkc_fail(TKC_EDEVICE, "NB bound kernels failed");
         if (rounds) *rounds = r;
-        if (harm) {
-            if (tkc_launch_harm_bounds(dg, ws.omega, ws.nbhub, ws.lnum, ws.lden, ws.key, ws.ord, s))
-                return tkc_fail(TKC_EDEVICE, "harmonic bound kernel failed");
-        } else if (tkc_launch_nb_keys(n, ws.lnum, ws.lden, ws.key, ws.ord, s)) {
-            return tkc_fail(TKC_EDEVICE, "key kernel failed");
+        if (!keyed) {
+            if (harm) {
+                if (tkc_launch_harm_bounds(dg, ws.omega, ws.nbhub, ws.lnum, ws.lden, ws.key, ws.ord, s))
+                    return tkc_fail(TKC_EDEVICE, "harmonic bound kernel failed");
+            } else if (tkc_launch_nb_keys(n, ws.lnum, ws.lden, ws.key, ws.ord, s)) {
+                return tkc_fail(TKC_EDEVICE, "key kernel failed");
+            }
         }
     } else if (harm) {
         if (tkc_launch_harm_bounds(dg, ws.omega, nullptr, ws.lnum, ws.lden, ws.key, ws.ord, s))
@@ -647,7 +662,7 @@ int tkc_step_bounds(tkc_ctx* c, tkc_graph* g, Workspace& ws, bool nb, int32_t* r
             return tkc_fail(TKC_EDEVICE, "degree bound kernel failed");
     }
     if (tkc_sort_pairs8(ws.key, ws.ord, ws.tkey, ws.tval, n, ws.hist, (uint32_t*)ws.mask,
-                       (uint32_t*)c->pinned, s))
+                        (uint32_t*)c->pinned, s, keyed ? mask_pin : nullptr))
         return tkc_fail(TKC_EDEVICE, "sort failed");
     return TKC_OK;
 }

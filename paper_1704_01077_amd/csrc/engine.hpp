@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
+
 struct TopkState;
 struct XRec;
 
@@ -129,9 +131,14 @@ int tkc_launch_cc(const DevGraph& g, int32_t* parent, int64_t* size, int64_t* al
 // at least n/64 int32; nfin_dev the finish counters (1,057 int32).  Returns
 // the number of rounds, -1 on error.  hub (n doubles, may be null): also
 // the walk-count upper bound on the harmonic centrality
+// fin (may be null): the caller's work on the final bounds (order keys and
+// the like), queued before the check that follows a tail round so that one
+// host wait covers both; *fin_done says whether the rounds ended at such a
+// check (else the bounds changed after fin ran, and the caller runs it again)
 int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega, int64_t* gbuf, int64_t* sum,
                   int64_t* vis, uint8_t* flags, int64_t* num, int64_t* den, uint64_t* partial,
-                  int32_t* nfin_dev, int32_t* nfin_host, hipStream_t s, double* hub = nullptr);
+                  int32_t* nfin_dev, int32_t* nfin_host, hipStream_t s, double* hub = nullptr,
+                  const std::function<int()>* fin = nullptr, bool* fin_done = nullptr);
 // harmonic centrality bounds and order keys: from hub (walk counts) when
 // given, else the degree bound
 int tkc_launch_harm_bounds(const DevGraph& g, const int64_t* omega, const double* hub, int64_t* num,
@@ -160,9 +167,14 @@ int tkc_sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* tmp_keys, int32_t* t
 // the same with 8-bit digits (the processing order): hist holds
 // tkc_sort8_hist_words(n) int32
 int64_t tkc_sort8_hist_words(int32_t n);
+// known_mask: the OR and AND of the keys already in host memory (from
+// tkc_sort_mask and a host wait), else null: the sort finds them itself
 int tkc_sort_pairs8(uint32_t* keys, int32_t* vals, uint32_t* tmp_keys, int32_t* tmp_vals,
                     int32_t n, int32_t* hist, uint32_t* mask_dev, uint32_t* mask_host,
-                    hipStream_t s);
+                    hipStream_t s, const uint32_t* known_mask = nullptr);
+// queue the OR and AND of n keys into mask_dev[0..1] and their copy to the
+// pinned mask_host[0..1] (no wait)
+int tkc_sort_mask(const uint32_t* keys, int32_t n, uint32_t* mask_dev, uint32_t* mask_host, hipStream_t s);
 
 // k_topk.hip
 // all-ties mode: buffers for the entries that leave or are refused by the top k

@@ -649,8 +649,10 @@ static void launch_nb_round(int lpv, dim3 grid, hipStream_t s, A... args) {
 // finish counters, their total, the tail list's count).
 int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega, int64_t* gbuf, int64_t* sum,
                   int64_t* vis, uint8_t* flags, int64_t* num, int64_t* den, uint64_t* partial,
-                  int32_t* nfin_dev, int32_t* nfin_host, hipStream_t s, double* hub) {
+                  int32_t* nfin_dev, int32_t* nfin_host, hipStream_t s, double* hub,
+                  const std::function<int()>* fin, bool* fin_done) {
     int32_t n = g.n;
+    if (fin_done) *fin_done = false;
     int nl = nblk(n, 256);
     int nc = nblk((int64_t)g.nchunks * 64, 256);
     int nhb = nblk(g.nheavy, 256);
@@ -762,13 +764,19 @@ int tkc_launch_nb(const DevGraph& g, const int64_t* alpha, const int64_t* omega,
                 hipLaunchKernelGGL(k_nb_tail<false>, dim3(nt), dim3(256), 0, s, (const int32_t*)tail_cnt, tail_cap,
                                    (const int32_t*)tail_list, g.rp, g.ci, g.deg, k, g1, g2, gk, alpha, omega, st,
                                    nfin_dev);
+            // a tail round usually finishes every vertex: the caller's work
+            // on the final bounds goes ahead of the check's wait
+            if (fin && (*fin)()) return -1;
             if (!check(false)) return -1;
             if (done < n) {
                 round(k, 0);
                 tail_at = (n - done) / 4;
             }
             k++;
-            if (done >= n) break;
+            if (done >= n) {
+                if (fin_done) *fin_done = fin != nullptr;
+                break;
+            }
             continue;
         }
         // two full rounds per host check (the first pair without one: the

@@ -408,18 +408,26 @@ __global__ void __launch_bounds__(RS8_THREADS) k_rs8_scatter(const uint32_t* __r
 
 int64_t tkc_sort8_hist_words(int32_t n) { return 256LL * rs8_tiles(n > 0 ? n : 1) + 256 + 16; }
 
-int tkc_sort_pairs8(uint32_t* keys, int32_t* vals, uint32_t* tmp_keys, int32_t* tmp_vals, int32_t n, int32_t* hist,
-                    uint32_t* mask_dev, uint32_t* mask_host, hipStream_t s) {
-    if (n <= 1) return 0;
+int tkc_sort_mask(const uint32_t* keys, int32_t n, uint32_t* mask_dev, uint32_t* mask_host, hipStream_t s) {
     if (hipMemsetD32Async((hipDeviceptr_t)mask_dev, 0u, 1, s) != hipSuccess) return -1;
     if (hipMemsetD32Async((hipDeviceptr_t)(mask_dev + 1), 0xffffffffu, 1, s) != hipSuccess) return -1;
-    int gb = rs_tiles(n);
+    int gb = rs_tiles(n > 0 ? n : 1);
     if (gb > 256) gb = 256;
     hipLaunchKernelGGL(k_rs_mask, dim3(gb), dim3(256), 0, s, keys, n, mask_dev);
     if (hipMemcpyAsync(mask_host, mask_dev, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
         return -1;
-    if (hipStreamSynchronize(s) != hipSuccess) return -1;
-    const uint32_t vary = mask_host[0] ^ mask_host[1];
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int tkc_sort_pairs8(uint32_t* keys, int32_t* vals, uint32_t* tmp_keys, int32_t* tmp_vals, int32_t n, int32_t* hist,
+                    uint32_t* mask_dev, uint32_t* mask_host, hipStream_t s, const uint32_t* known_mask) {
+    if (n <= 1) return 0;
+    if (!known_mask) {
+        if (tkc_sort_mask(keys, n, mask_dev, mask_host, s)) return -1;
+        if (hipStreamSynchronize(s) != hipSuccess) return -1;
+        known_mask = mask_host;
+    }
+    const uint32_t vary = known_mask[0] ^ known_mask[1];
     const int tiles = rs8_tiles(n);
     int32_t* total = hist + 256LL * tiles;
     uint32_t* ka = keys; int32_t* va = vals;
