@@ -162,3 +162,31 @@ def test_relabel_refusals(ctx):
         with pytest.raises(tkc.TkcError) as e:
             call()
         assert e.value.code == tkc.TKC_EINVAL
+
+
+def test_relabel_serving(ctx):
+    """A server holding relabelled and plain graphs: packing takes only the
+    plain ones, and every served answer is in the caller's ids."""
+    names = ["rmat11", "ba2k", "gnp_d", "forest", "rmat13"]
+    relabelled = {"rmat11", "ba2k", "rmat13"}
+    gs = {nm: tkc.Graph.from_graphgen(ctx, graph(nm), validate=True, relabel=nm in relabelled) for nm in names}
+    srv = tkc.Server(ctx, 8 << 30, 2)
+    try:
+        gid = {nm: srv.add(gs[nm]) for nm in names}
+        srv.enable_packing(10000)     # gnp_d (directed) and forest (undirected): one member each
+        rng = np.random.default_rng(5)
+        reqs = []
+        for _ in range(80):
+            nm = names[int(rng.integers(len(names)))]
+            reqs.append((nm, int(rng.choice([1, 10, 100])), ("nbcut", "degcut", "auto", "nbbound")[int(rng.integers(4))]))
+        tickets = [srv.submit(gid[nm], k, var) for nm, k, var in reqs]
+        for (nm, k, var), t in zip(reqs, tickets):
+            ids, S, r, f, _ = srv.result(t, k)
+            wids, wS, wr, wf = expect(nm, k)
+            assert np.array_equal(ids, wids) and np.array_equal(S, wS) and np.array_equal(r, wr), (nm, k, var)
+            assert np.array_equal(f, wf)
+        assert srv.info()["served"] == len(reqs)
+    finally:
+        srv.close()
+        for g in gs.values():
+            g.free()
