@@ -14,6 +14,12 @@ def pytest_configure(config):
     # build the host-side C libraries only when nothing is built yet
     import graphgen
     import oracle
+    # the mutation test runs the oracle's pins against altered copies of the
+    # oracle, each built into a library of its own
+    other = os.environ.get("ORACLE_LIB_UNDER_TEST")
+    if other:
+        oracle._LIB = other
+        oracle._lib = None
     if not os.path.exists(graphgen._LIB):
         graphgen.build(force=False)
     if not os.path.exists(oracle._LIB):

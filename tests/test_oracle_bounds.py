@@ -88,6 +88,78 @@ def test_nb_known_small_values():
     assert list(num) == [4] * 4
 
 
+def walk_counts(n, e, directed, s, kmax):
+    """gamma_1(s) .. gamma_kmax(s) counted by enumeration, as the arcs the
+    walks end on: directed, every walk of length k out of s (Eq. 3);
+    undirected, every walk that never steps straight back along the edge it
+    came by, which is what the tree recurrence of Sect. 5 (Eq. 2, Alg. 3)
+    counts.  Self-loops and repeated arcs are dropped, as in the oracle."""
+    arcs = {(int(u), int(v)) for u, v in e if u != v}
+    if not directed:
+        arcs |= {(v, u) for u, v in arcs}
+    out = {u: [] for u in range(n)}
+    for u, v in sorted(arcs):
+        out[u].append(v)
+    cur = {(s, c): 1 for c in out[s]}
+    g = []
+    for _ in range(kmax):
+        g.append(sum(cur.values()))
+        nxt = {}
+        for (p, c), w in cur.items():
+            for x in out[c]:
+                if directed or x != p:
+                    nxt[(c, x)] = nxt.get((c, x), 0) + w
+        cur = nxt
+    return g
+
+
+def nb_by_enumeration(n, e, directed, s, a, o):
+    """Prop. 5.1 with alpha <= r <= omega (Sect. 8.1), by exhaustion: for
+    every integer r in [alpha, omega], place r - 1 vertices at levels 1, 2,
+    ... with at most gamma_k at level k (r is impossible when the walks die
+    out first) and keep the least S_NB(r) / (r-1)^2; None when no r >= 2 is
+    possible (+inf)."""
+    g = walk_counts(n, e, directed, s, max(1, int(o)))
+    best = None
+    for r in range(max(2, int(a)), int(o) + 1):
+        placed, S = 1, 0
+        for k, gk in enumerate(g, start=1):
+            take = min(gk, r - placed)
+            S += k * take
+            placed += take
+            if placed == r:
+                break
+        if placed < r:
+            continue
+        f = Fraction(S, (r - 1) ** 2)
+        best = f if best is None or f < best else best
+    return best
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_nb_matches_enumeration(directed):
+    """The oracle evaluates Prop. 5.1 only at alpha, omega and the level
+    boundaries between them, from the recurrence; the enumeration tries
+    every r from walks it lists one by one.  Reachability bounds: Alg. 6 on
+    digraphs, exact r, and the loose 1 <= r <= n."""
+    checks = 0
+    for seed in range(60):
+        n = 2 + seed % 13
+        e = graphgen.gnp(n, [0.08, 0.15, 0.3][seed % 3], directed, 41000 + seed)
+        S, r = oracle.sums(n, e, directed)
+        ab, ob, _ = oracle.reach_bounds(n, e, directed)
+        for a, o in ((ab, ob), (r, r), (np.ones(n, np.int64), np.full(n, n, np.int64))):
+            num, den = oracle.nb(n, e, directed, a, o)
+            for v in range(n):
+                want = nb_by_enumeration(n, e, directed, v, a[v], o[v])
+                if want is None:
+                    assert den[v] == 0, (seed, v)
+                else:
+                    assert den[v] > 0 and Fraction(int(num[v]), int(den[v])) == want, (seed, v, a[v], o[v])
+                checks += 1
+    assert checks > 1000
+
+
 @pytest.mark.parametrize("directed", [False, True])
 def test_cut_bounds_valid(directed):
     checks = 0

@@ -147,6 +147,27 @@ def test_nb_bound_exact_on_trees(seed):
     assert np.array_equal(ub, h)
 
 
+@pytest.mark.parametrize("n", [3, 4, 7, 10, 31, 64])
+def test_nb_bound_on_cycles(n):
+    """Undirected cycle: the walks that never step straight back are two of
+    each length, and up to length n/2 they end at the two distinct vertices
+    at that distance, except the one antipode of an even cycle.  Placing
+    vertices stops at omega = n, so the antipode level takes one vertex: the
+    bound is h bit for bit (the same terms in the same order), the closed
+    form of the cycle.  Directed cycle: one walk per length, h = H(n-1)."""
+    e = E([(i, (i + 1) % n) for i in range(n)])
+    h = oracle.harmonic(n, e, False)
+    ub = oracle.nb_harmonic(n, e, False)
+    assert np.array_equal(ub, h)
+    m = n // 2
+    want = 2 * H(m) if n % 2 else 2 * H(m - 1) + Fraction(1, m)
+    assert np.all([close(x, want, n) for x in ub])
+    hd = oracle.harmonic(n, e, True)
+    ubd = oracle.nb_harmonic(n, e, True)
+    assert np.array_equal(ubd, hd)
+    assert np.all([close(x, H(n - 1), n) for x in ubd])
+
+
 def test_nb_bound_forest_with_isolated_vertices():
     rng = np.random.default_rng(77)
     e1 = random_tree(30, rng)
