@@ -136,6 +136,9 @@ typedef struct {
 /* Context on HIP device `device`; hip_stream may be NULL (library stream) or
  * a hipStream_t the caller keeps alive.  Error: TKC_EDEVICE. */
 int tkc_ctx_create(int device, void *hip_stream, tkc_ctx **out);
+/* Waits for the context's stream, then frees it.  Free the servers, packs
+ * and graphs made on a context before it: they use its stream and device.
+ * (Graphs still held at process exit are simply released with the device.) */
 int tkc_ctx_destroy(tkc_ctx *ctx);
 
 /* Execution knobs of a context (performance only: results never depend on
@@ -360,6 +363,9 @@ int tkc_server_info(tkc_server *s, int64_t *served, int64_t *packed, int64_t *pa
  * use (admission control); max_inflight caps concurrent requests. */
 int tkc_server_create(tkc_ctx *ctx, size_t hbm_budget_bytes, int32_t max_inflight,
                       tkc_server **out);
+/* Adds a graph (it may be called while requests run); the graph must stay
+ * uploaded until the server is destroyed (tkc_graph_free refuses it with
+ * TKC_EBUSY until then). */
 int tkc_server_add_graph(tkc_server *s, tkc_graph *g, int32_t *graph_id);
 /* Queue a request; TKC_EBUSY if it can never fit the budget. */
 int tkc_server_submit(tkc_server *s, int32_t graph_id, int32_t k, int32_t variant,
@@ -369,7 +375,12 @@ int tkc_server_poll(tkc_server *s, uint64_t ticket, int32_t *done);
  * latency_ms = completion - submission. */
 int tkc_server_result(tkc_server *s, uint64_t ticket, int32_t *ids, int64_t *sum_dist,
                       int64_t *reach, double *farness, int32_t *n_out, double *latency_ms);
+/* A queued request is dropped at once; a running one finishes, and either
+ * way tkc_server_result then returns TKC_ECANCELED. */
 int tkc_server_cancel(tkc_server *s, uint64_t ticket);
+/* Lets the workers finish the requests they are running, drops the queued
+ * ones and frees the server.  No other call on s may run during or after
+ * it: collect or cancel every ticket first. */
 int tkc_server_destroy(tkc_server *s);
 
 const char *tkc_last_error(void);

@@ -158,6 +158,12 @@ int tkc_ws_reserve(tkc_ctx* ctx, Workspace& ws, const WsShape& sh) {
         if (hipHostMalloc((void**)&ws.pin, span, hipHostMallocDefault) != hipSuccess) {
             hipGetLastError();
             ws.pin = nullptr;
+            // give the device arena back too, so that the next call starts
+            // over instead of finding a workspace without its readback buffer
+            hipStreamSynchronize(ctx->stream);
+            hipFree(ws.base);
+            ws.base = nullptr;
+            ws.bytes = 0;
             return tkc_fail(TKC_ENOMEM, "pinned host allocation of %zu bytes failed", span);
         }
         ws.pin_bytes = span;
@@ -190,11 +196,15 @@ extern "C" int tkc_ctx_create(int device, void* hip_stream, tkc_ctx** out) {
         }
         c->own_stream = true;
     }
-    hipEventCreate(&c->ev0);
-    hipEventCreate(&c->ev1);
-    for (auto& e : c->evq) hipEventCreate(&e);
-    hipEventCreate(&c->evm);
-    hipHostMalloc((void**)&c->pinned, 4096, hipHostMallocDefault);
+    bool ok = hipEventCreate(&c->ev0) == hipSuccess && hipEventCreate(&c->ev1) == hipSuccess &&
+              hipEventCreate(&c->evm) == hipSuccess;
+    for (auto& e : c->evq) ok = ok && hipEventCreate(&e) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&c->pinned, 4096, hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        hipGetLastError();
+        tkc_ctx_destroy(c);
+        return tkc_fail(TKC_EDEVICE, "event or pinned buffer creation failed");
+    }
     *out = c;
     return TKC_OK;
 }
@@ -207,10 +217,11 @@ extern "C" int tkc_ctx_destroy(tkc_ctx* c) {
     if (c->ws.trace) hipFree(c->ws.trace);
     if (c->ws.pin) hipHostFree(c->ws.pin);
     if (c->pinned) hipHostFree(c->pinned);
-    hipEventDestroy(c->ev0);
-    hipEventDestroy(c->ev1);
-    for (auto& e : c->evq) hipEventDestroy(e);
-    hipEventDestroy(c->evm);
+    if (c->ev0) hipEventDestroy(c->ev0);
+    if (c->ev1) hipEventDestroy(c->ev1);
+    for (auto& e : c->evq)
+        if (e) hipEventDestroy(e);
+    if (c->evm) hipEventDestroy(c->evm);
     if (c->own_stream) hipStreamDestroy(c->stream);
     delete c;
     return TKC_OK;
@@ -1368,8 +1379,8 @@ extern "C" int tkc_graph_sums(tkc_graph* g, const int32_t* sources, int32_t coun
         if (sources[i] < 0 || sources[i] >= g->n) return tkc_fail(TKC_EINVAL, "source %d out of range", sources[i]);
     HIPCHK(hipSetDevice(g->ctx->device));
     // the source list shares n-sized buffers: chunks of at most n
-    for (int32_t off = 0; off < count; off += g->n) {
-        int32_t c = std::min(count - off, g->n);
+    for (int64_t off = 0; off < count; off += g->n) {
+        const int32_t c = (int32_t)std::min<int64_t>(count - off, g->n);
         int rc = tkc_sums_impl(g->ctx, g, sources + off, c, S + off, R + off, nullptr);
         if (rc) return rc;
     }
@@ -1399,8 +1410,8 @@ extern "C" int tkc_graph_lb_update(tkc_graph* g, const int32_t* sources, int32_t
     OrderView ov{ws.ord, ws.key, 0, false};
     BoundsView bv{ws.lnum, ws.lden};
     int grid = 0;
-    for (int32_t off = 0; off < count; off += g->n) {
-        int32_t cnt = std::min(count - off, g->n);
+    for (int64_t off = 0; off < count; off += g->n) {
+        const int32_t cnt = (int32_t)std::min<int64_t>(count - off, g->n);
         HIPCHK(hipMemcpyAsync(ws.s_deferred, sources + off, 4 * (size_t)cnt, hipMemcpyHostToDevice, s));
         std::lock_guard<std::mutex> lk(tkc_coop_mutex());
         if (tkc_launch_batch(g->view(), rcv, ov, bv, tk, tkc_batch_view(ws), ws.stats, ws.s_deferred, cnt, 0, 0,
@@ -1446,8 +1457,8 @@ extern "C" int tkc_graph_harmonic_lb_update(tkc_graph* g, const int32_t* sources
     BoundsView bv{ws.lnum, ws.lden};
     bv.harm = 1;
     int grid = 0;
-    for (int32_t off = 0; off < count; off += g->n) {
-        int32_t cnt = std::min(count - off, g->n);
+    for (int64_t off = 0; off < count; off += g->n) {
+        const int32_t cnt = (int32_t)std::min<int64_t>(count - off, g->n);
         HIPCHK(hipMemcpyAsync(ws.s_deferred, sources + off, 4 * (size_t)cnt, hipMemcpyHostToDevice, s));
         std::lock_guard<std::mutex> lk(tkc_coop_mutex());
         if (tkc_launch_batch(g->view(), rcv, ov, bv, tk, tkc_batch_view(ws), ws.stats, ws.s_deferred, cnt, 0, 0,

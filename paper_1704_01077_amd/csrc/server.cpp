@@ -99,6 +99,7 @@ struct tkc_server {
         hipSetDevice(c->device);
         for (;;) {
             std::shared_ptr<Request> rq;
+            tkc_graph* g = nullptr;
             {
                 std::unique_lock<std::mutex> lk(mu);
                 for (;;) {
@@ -131,10 +132,14 @@ struct tkc_server {
                     cv_work.wait(lk);
                 }
                 rq->state = 1;
+                // the graph table may grow while requests run
+                // (tkc_server_add_graph): read it under the lock only
+                g = graphs[rq->graph_id];
             }
-            tkc_graph* g = graphs[rq->graph_id];
             // packing: queued requests on the pack's other members join this one
             std::vector<std::shared_ptr<Request>> group;
+            std::vector<int32_t> mem, ks;   // the group's members and k
+            int32_t tot = 0;                // and its result count
             int32_t pk = -1, pv = 0;
             {
                 std::lock_guard<std::mutex> lk(mu);
@@ -166,17 +171,16 @@ struct tkc_server {
                             ++it;
                         }
                     }
+                    for (const std::shared_ptr<Request>& q : group) {
+                        mem.push_back(member_of[q->graph_id]);
+                        ks.push_back(q->k);
+                        tot += std::min(q->k, graphs[q->graph_id]->n);
+                    }
                 }
             }
             if (group.size() >= 2) {
                 const int32_t nr = (int32_t)group.size();
-                std::vector<int32_t> mem(nr), ks(nr), nout(nr);
-                int32_t tot = 0;
-                for (int32_t i = 0; i < nr; i++) {
-                    mem[i] = member_of[group[i]->graph_id];
-                    ks[i] = group[i]->k;
-                    tot += std::min(group[i]->k, graphs[group[i]->graph_id]->n);
-                }
+                std::vector<int32_t> nout(nr);
                 std::vector<int32_t> ids(tot);
                 std::vector<int64_t> S(tot), R(tot);
                 std::vector<double> F(tot);
@@ -210,7 +214,12 @@ struct tkc_server {
             rq->F.resize(k);
             int32_t got = 0;
             int st = TKC_OK;
-            if (!rq->cancelled)
+            bool skip;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                skip = rq->cancelled;
+            }
+            if (!skip)
                 st = tkc_run_query(c, g, k, rq->variant, TKC_MODE_AUTO, rq->ids.data(), rq->S.data(), rq->R.data(),
                                    rq->F.data(), &got, nullptr);
             {
