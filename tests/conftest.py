@@ -6,6 +6,11 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+# the mutation test runs the oracle's pins against altered copies of the
+# oracle package, each in a directory of its own
+ORACLE_COPY = os.environ.get("ORACLE_PKG_DIR")
+if ORACLE_COPY:
+    sys.path.insert(0, ORACLE_COPY)
 
 
 def pytest_configure(config):
@@ -14,12 +19,8 @@ def pytest_configure(config):
     # build the host-side C libraries only when nothing is built yet
     import graphgen
     import oracle
-    # the mutation test runs the oracle's pins against altered copies of the
-    # oracle, each built into a library of its own
-    other = os.environ.get("ORACLE_LIB_UNDER_TEST")
-    if other:
-        oracle._LIB = other
-        oracle._lib = None
+    if ORACLE_COPY and not os.path.abspath(oracle.__file__).startswith(os.path.abspath(ORACLE_COPY) + os.sep):
+        raise RuntimeError("ORACLE_PKG_DIR is set but oracle was imported from %s" % oracle.__file__)
     if not os.path.exists(graphgen._LIB):
         graphgen.build(force=False)
     if not os.path.exists(oracle._LIB):

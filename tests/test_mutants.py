@@ -1,13 +1,16 @@
 """The oracle's pins catch plausible mistakes in the oracle.
 
-Each case below plants one mistake in a copy of ``oracle/oracle.c`` (a
-dropped term, a wrong sign, weight or index, a transposed operand, a flipped
-tie rule, a missing step of Alg. 6), builds the copy into a library of its
-own, and runs the oracle's pin files against it in a fresh pytest process
-(``ORACLE_LIB_UNDER_TEST`` points the oracle package at that library).  A
-mistake passes this test only if some pin fails on it; the unaltered source,
-built the same way, must pass every pin.  Nothing here runs on a GPU, and
-the oracle's own library is never touched.
+Each case below plants one mistake in a copy of the oracle package: in
+``oracle.c`` (a dropped term, a wrong sign, weight or index, a transposed
+operand, a flipped tie rule, a missing step of Alg. 6) or in its Python
+half (the degree bound on harmonic centrality, the harmonic order, the
+default reachability brackets, outputs handed back in the wrong order).
+The copy is built in a directory of its own and the oracle's pin files run
+against it in a fresh pytest process (``ORACLE_PKG_DIR`` puts the copy
+first on the import path).  A mistake passes this test only if some pin
+fails on it; the unaltered package, copied and built the same way, must
+pass every pin.  Nothing here runs on a GPU, and the oracle's own files are
+never touched.
 """
 import concurrent.futures
 import glob
@@ -213,6 +216,57 @@ MUTANTS = [
      "int64_t t = (int64_t)j - i;"),
 ]
 
+# the same for oracle/__init__.py
+PY_MUTANTS = [
+    ("py_harmonic_order_tie_to_larger_id",
+     "order = np.lexsort((np.arange(h.size), -h))",
+     "order = np.lexsort((-np.arange(h.size), -h))"),
+    ("py_harmonic_order_ascending",
+     "order = np.lexsort((np.arange(h.size), -h))",
+     "order = np.lexsort((np.arange(h.size), h))"),
+    ("py_deg_bound_keeps_repeated_arcs",
+     "e = np.unique(e[:, 0] * max(n, 1) + e[:, 1])",
+     "e = e[:, 0] * max(n, 1) + e[:, 1]"),
+    ("py_deg_bound_keeps_self_loops",
+     "e = e[e[:, 0] != e[:, 1]]\n",
+     "e = e\n"),
+    ("py_deg_bound_undirected_one_way",
+     "e = np.concatenate([e, e[:, ::-1]])",
+     "e = np.concatenate([e, e])"),
+    ("py_deg_bound_far_weight",
+     "float(omega[v] - 1 - deg[v]) / 2.0",
+     "float(omega[v] - 1 - deg[v]) / 3.0"),
+    ("py_deg_bound_far_weight_loose",
+     "float(omega[v] - 1 - deg[v]) / 2.0",
+     "float(omega[v] - 1 - deg[v]) / 1.0"),
+    ("py_deg_bound_near_weight",
+     "out[v] = float(deg[v]) + float(omega[v] - 1 - deg[v]) / 2.0",
+     "out[v] = float(deg[v]) / 2.0 + float(omega[v] - 1 - deg[v]) / 2.0"),
+    ("py_walk_bound_stops_at_alpha",
+     "        omega = reach_bounds(n, edges, directed)[1]\n    o = np.ascontiguousarray(omega",
+     "        omega = reach_bounds(n, edges, directed)[0]\n    o = np.ascontiguousarray(omega"),
+    ("py_nb_brackets_swapped",
+     "        alpha, omega, _ = reach_bounds(n, edges, directed)",
+     "        omega, alpha, _ = reach_bounds(n, edges, directed)"),
+    ("py_sums_outputs_swapped",
+     "return S[:cnt], r[:cnt]",
+     "return r[:cnt], S[:cnt]"),
+    ("py_nb_outputs_swapped",
+     "return num[:n], den[:n]",
+     "return den[:n], num[:n]"),
+    ("py_alpha_omega_swapped",
+     "return a[:n], o[:n], comp[:n]",
+     "return o[:n], a[:n], comp[:n]"),
+    ("py_lb_harmonic_ignores_scc",
+     "        ptr = sc.ctypes.data_as(ctypes.c_void_p)\n    else:\n        sc = None\n        ptr = None\n"
+     "    r = _L().oracle_lb_harmonic",
+     "        ptr = None\n    else:\n        sc = None\n        ptr = None\n"
+     "    r = _L().oracle_lb_harmonic"),
+    ("py_closeness_farness_by_rank",
+     "far = np.array([farness(n, S[i], r[i]) for i in ids], dtype=np.float64)",
+     "far = np.array([farness(n, S[i], r[i]) for i in range(len(ids))], dtype=np.float64)"),
+]
+
 _BASE = "unaltered"
 
 
@@ -225,18 +279,19 @@ def _mutate(src, old, new):
     return src
 
 
-def _run_one(tmp, name, text):
+def _run_one(tmp, name, c_text, py_text):
     d = os.path.join(tmp, name)
-    os.makedirs(d, exist_ok=True)
-    c = os.path.join(d, "oracle.c")
-    lib = os.path.join(d, "liboracle.so")
-    with open(c, "w") as fh:
-        fh.write(text)
-    b = subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-w", "-o", lib, c],
-                       capture_output=True, text=True)
+    pkg = os.path.join(d, "oracle")
+    os.makedirs(pkg, exist_ok=True)
+    for fname, text in (("oracle.c", c_text), ("__init__.py", py_text)):
+        with open(os.path.join(pkg, fname), "w") as fh:
+            fh.write(text)
+    lib = os.path.join(pkg, "liboracle.so")
+    b = subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-w", "-o", lib,
+                        os.path.join(pkg, "oracle.c")], capture_output=True, text=True)
     if b.returncode:
         return ("build", b.stderr[-2000:])
-    env = dict(os.environ, ORACLE_LIB_UNDER_TEST=lib, OMP_NUM_THREADS="1")
+    env = dict(os.environ, ORACLE_PKG_DIR=d, OMP_NUM_THREADS="1")
     cmd = [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
            "--hypothesis-seed=0", "--timeout", "120", *PINS]
     try:
@@ -250,19 +305,24 @@ def _run_one(tmp, name, text):
 
 @pytest.fixture(scope="module")
 def outcomes(tmp_path_factory):
-    with open(os.path.join(os.path.dirname(oracle.__file__), "oracle.c")) as fh:
-        src = fh.read()
-    cases = {_BASE: src}
+    here = os.path.dirname(oracle.__file__)
+    with open(os.path.join(here, "oracle.c")) as fh:
+        c_src = fh.read()
+    with open(os.path.join(here, "__init__.py")) as fh:
+        py_src = fh.read()
+    cases = {_BASE: (c_src, py_src)}
     for name, old, new in MUTANTS:
-        cases[name] = _mutate(src, old, new)
+        cases[name] = (_mutate(c_src, old, new), py_src)
+    for name, old, new in PY_MUTANTS:
+        cases[name] = (c_src, _mutate(py_src, old, new))
     tmp = str(tmp_path_factory.mktemp("mutants"))
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
-        futs = {nm: ex.submit(_run_one, tmp, nm, text) for nm, text in cases.items()}
+        futs = {nm: ex.submit(_run_one, tmp, nm, c, py) for nm, (c, py) in cases.items()}
         return {nm: f.result() for nm, f in futs.items()}
 
 
 def test_mutant_names_unique():
-    names = [m[0] for m in MUTANTS]
+    names = [m[0] for m in MUTANTS + PY_MUTANTS]
     assert len(names) == len(set(names))
 
 
@@ -271,7 +331,7 @@ def test_unaltered_source_passes_the_pins(outcomes):
     assert rc == 0, info
 
 
-@pytest.mark.parametrize("name", [m[0] for m in MUTANTS])
+@pytest.mark.parametrize("name", [m[0] for m in MUTANTS + PY_MUTANTS])
 def test_pins_catch(outcomes, name):
     rc, info = outcomes[name]
     # 1: pytest ran and some pin failed (not a crash, a time-out or a build error)

@@ -70,3 +70,26 @@ def test_topk_edge_cases():
     r = np.array([1], np.int64)
     assert list(oracle.topk(S, r, 3)) == [0]
     assert list(oracle.topk(S, r, 0)) == []
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_closeness_topk_against_brute(directed):
+    """The oracle's whole answer (ids, S, r and the farness doubles) against
+    Floyd-Warshall: each returned double belongs to its own vertex and lies
+    within a few ulps of the exact rational (n-1) S / (r-1)^2 (the binary64
+    formula rounds three times: two products and the quotient)."""
+    for seed in range(120):
+        n = 2 + seed % 30
+        e = graphgen.gnp(n, [0.05, 0.1, 0.3][seed % 3], directed, 77000 + seed)
+        S2, r2 = brute(n, e, directed)
+        want = brute_order(n, S2, r2)
+        for k in (1, 5, n):
+            ids, S, r, far = oracle.closeness_topk(n, e, directed, k)
+            assert list(ids) == want[:k], (seed, k)
+            assert (S == S2[ids]).all() and (r == r2[ids]).all()
+            for v, f in zip(ids, far):
+                if r2[v] <= 1:
+                    assert f == float("inf")
+                    continue
+                exact = Fraction((n - 1) * int(S2[v]), int(r2[v] - 1) ** 2)
+                assert abs(Fraction(f) - exact) <= 4 * 2.0 ** -52 * exact, (seed, v, f)
