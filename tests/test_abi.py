@@ -74,3 +74,35 @@ def test_struct_layout_matches_header(struct):
     os.unlink(exe)
     assert out[0] == ctypes.sizeof(mirror)
     assert out[1:] == [getattr(mirror, f).offset for f in fields]
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without libtkc.so the binding refuses to import: there is no other
+    path to an answer."""
+    import shutil
+    import sys
+    pkg = tmp_path / "paper_1704_01077_amd"
+    pkg.mkdir()
+    shutil.copy(os.path.join(ROOT, "paper_1704_01077_amd", "tkc.py"), pkg / "tkc.py")
+    (pkg / "__init__.py").write_text("")
+    p = subprocess.run([sys.executable, "-c", "import paper_1704_01077_amd.tkc"], cwd=str(tmp_path),
+                       capture_output=True, text=True)
+    assert p.returncode != 0
+    assert "ImportError" in p.stderr and "libtkc.so is not built" in p.stderr
+
+
+def test_product_never_reaches_the_oracle():
+    """The package (binding, build script, HIP and C++ sources) names no part
+    of the oracle: no import, no include, no library, no fallback."""
+    pkg = os.path.join(ROOT, "paper_1704_01077_amd")
+    pat = re.compile(r"\boracle\b|liboracle|oracle_[a-z]+\(")
+    hits = []
+    for d, _, files in os.walk(pkg):
+        if "_build" in d or "__pycache__" in d:
+            continue
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
+                for i, line in enumerate(open(os.path.join(d, f)), 1):
+                    if pat.search(line):
+                        hits.append("%s:%d: %s" % (f, i, line.strip()))
+    assert not hits, hits
